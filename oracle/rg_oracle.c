@@ -1,0 +1,720 @@
+/*
+ * rg_oracle.c -- TEST INFRASTRUCTURE ONLY (see rg_oracle.h).
+ *
+ * Plain sequential FP64 reference of the scenario-based robust reference
+ * governor.  Build: gcc -O2 -ffp-contract=off -std=c99 (no fast-math), so every
+ * expression below is evaluated exactly as written, one IEEE rounding per
+ * operation.  Threads (orc_problem.nthreads) only split the scenario loop of one
+ * candidate evaluation; the minimum is order-free, so results do not depend on
+ * the thread count.
+ */
+#define _POSIX_C_SOURCE 200809L
+#include "rg_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ========================================================================= *
+ * Random numbers.  The paper draws N_sim disturbance sequences d_j^k,
+ * j = 0..j*, at every RG time step (Sec. II-C; Alg. 2 and Alg. 3 draw them once
+ * and reuse them for every candidate kappa).  Reading: the draws are a pure
+ * function of (seed, instance, t, k, j, component), produced by the
+ * counter-based generator Philox4x32-10 of Salmon, Moraes, Dror and Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3" (SC'11), which the GPU library
+ * implements separately from the same definition.
+ * ========================================================================= */
+
+/* Philox4x32 with 10 rounds, as defined by Salmon et al. (SC'11, Sec. 4.2):
+ * each round multiplies counter words 0 and 2 by two fixed 32-bit multipliers,
+ * forms the 64-bit products, and permutes/XORs the halves with the other words
+ * and the round key; the key is advanced by the two Weyl increments between
+ * rounds. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t MUL0 = 0xD2511F53u, MUL1 = 0xCD9E8D57u;
+    const uint32_t WEYL0 = 0x9E3779B9u, WEYL1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += WEYL0;
+            k1 += WEYL1;
+        }
+        uint64_t p0 = (uint64_t)MUL0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)MUL1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Canonical uniform draw on [lo, hi): the top 24 bits of a Philox word give
+ * u = (word >> 8) * 2^-24, exactly representable in binary32; the value is then
+ * one correctly rounded binary32 fused multiply-add, fl32(span32 * u + lo32),
+ * with lo32 = fl32(lo) and span32 = fl32(hi - lo).  Both the FP32 and FP64
+ * computations consume this binary32 value, so they see identical inputs. */
+float orc_uniform_box(uint32_t word, double lo, double hi)
+{
+    float u = (float)(word >> 8) * 0x1p-24f;
+    float lo32 = (float)lo;
+    float span32 = (float)(hi - lo);
+    return fmaf(span32, u, lo32);
+}
+
+static void orc_counter_words(const orc_problem* p, uint32_t k, uint32_t j, uint32_t t,
+                              uint32_t tag, uint32_t block, uint32_t out[4])
+{
+    uint32_t ctr[4] = {k, j, t, (tag << 16) | block};
+    uint32_t key[2] = {p->seed, p->instance};
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* Disturbance of scenario k at prediction step j of RG step t (tag 0). */
+void orc_draw_w(const orc_problem* p, uint32_t t, uint32_t k, uint32_t j, double* w)
+{
+    uint32_t words[4];
+    for (int c = 0; c < p->n_w; ++c) {
+        if ((c & 3) == 0) orc_counter_words(p, k, j, t, 0u, (uint32_t)(c >> 2), words);
+        w[c] = (double)orc_uniform_box(words[c & 3], p->w_lo[c], p->w_hi[c]);
+    }
+}
+
+/* Uncertain coefficients of scenario k at RG step t (tag 1, j = 0):
+ * theta^k = theta_nom * (1 + theta_rel * s), s uniform on [-1, 1); the factor
+ * is the canonical binary32 draw on [1 - theta_rel, 1 + theta_rel). */
+void orc_draw_theta(const orc_problem* p, uint32_t t, uint32_t k, double* theta)
+{
+    const double* nom = NULL;
+    if (p->kind == ORC_FC9) nom = p->coeffs + 90;
+    uint32_t words[4];
+    for (int q = 0; q < p->n_theta; ++q) {
+        if ((q & 3) == 0) orc_counter_words(p, k, 0u, t, 1u, (uint32_t)(q >> 2), words);
+        double factor = (double)orc_uniform_box(words[q & 3], 1.0 - p->theta_rel,
+                                                1.0 + p->theta_rel);
+        theta[q] = nom[q] * factor;
+    }
+}
+
+/* Disturbance acting on the true plant between RG steps t and t+1 (tag 2). */
+void orc_draw_true_w(const orc_problem* p, uint32_t t, double* w)
+{
+    uint32_t words[4];
+    for (int c = 0; c < p->n_w; ++c) {
+        if ((c & 3) == 0) orc_counter_words(p, 0u, 0u, t, 2u, (uint32_t)(c >> 2), words);
+        w[c] = (double)orc_uniform_box(words[c & 3], p->w_lo[c], p->w_hi[c]);
+    }
+}
+
+/* ========================================================================= *
+ * Plant.  The closed loop is x_{t+1} = f(x_t, v_t), y_t = h(x_t, v_t)
+ * (Eq. (1)); the paper discretises its continuous-time model with fixed-step
+ * fourth-order Runge-Kutta (Sec. IV-A).  Two synthetic closed loops stand in
+ * for the paper's fuel-cell model, whose equations are not in the paper.
+ * ========================================================================= */
+
+/* LQ4: xdot = A x + B v + G (x .* x) + E w. */
+static void lq4_rhs(const double* c, const double* x, double v, const double* w, double* xd)
+{
+    const double* A = c;
+    const double* B = c + 16;
+    const double* G = c + 20;
+    const double* E = c + 36;
+    for (int i = 0; i < 4; ++i) {
+        double s = B[i] * v;
+        for (int j = 0; j < 4; ++j) s += A[4 * i + j] * x[j];
+        for (int j = 0; j < 4; ++j) s += G[4 * i + j] * (x[j] * x[j]);
+        for (int j = 0; j < 2; ++j) s += E[2 * i + j] * w[j];
+        xd[i] = s;
+    }
+}
+
+/* FC9 (air-supply-like chain of six volumes p1..p6 fed by a compressor of
+ * speed w1, two auxiliary speeds w2, w3):
+ *   z = x - xbar, p7 = p_amb,
+ *   q0 = c_q0 * w1,  q_l = k_l * sqrt(max(p_l - p_{l+1}, 0)), l = 1..6,
+ *   xdot_i = -a_i z_i + sum_j W_ij tanh(z_j) + w_i + phi_i,
+ *   phi_l = q_{l-1} - q_l (l = 1..6),
+ *   phi_7 = b1 v - mu1 w1 (p1 - p1ref),  phi_8 = b2 v w1,  phi_9 = b3 v - mu2 w3 v.
+ * theta = (a[9], k[6], b[3], mu[2]). */
+static void fc9_rhs(const double* c, const double* th, const double* x, double v,
+                    const double* w, double* xd)
+{
+    const double* W = c;
+    const double* xbar = c + 81;
+    const double c_q0 = c[110], p_amb = c[111], p1ref = c[114];
+    const double* a = th;
+    const double* kq = th + 9;
+    const double* b = th + 15;
+    const double* mu = th + 18;
+    double z[9], s[9], q[7];
+    for (int i = 0; i < 9; ++i) {
+        z[i] = x[i] - xbar[i];
+        s[i] = tanh(z[i]);
+    }
+    q[0] = c_q0 * x[6];
+    for (int l = 0; l < 6; ++l) {
+        double downstream = (l < 5) ? x[l + 1] : p_amb;
+        double dp = x[l] - downstream;
+        q[l + 1] = kq[l] * sqrt(dp > 0.0 ? dp : 0.0);
+    }
+    for (int i = 0; i < 9; ++i) {
+        double acc = -a[i] * z[i];
+        for (int j = 0; j < 9; ++j) acc += W[9 * i + j] * s[j];
+        acc += w[i];
+        double phi;
+        if (i < 6) phi = q[i] - q[i + 1];
+        else if (i == 6) phi = b[0] * v - mu[0] * x[6] * (x[0] - p1ref);
+        else if (i == 7) phi = b[1] * v * x[6];
+        else phi = b[2] * v - mu[1] * x[8] * v;
+        xd[i] = acc + phi;
+    }
+}
+
+static const double* nominal_theta(const orc_problem* p)
+{
+    return (p->kind == ORC_FC9) ? p->coeffs + 90 : NULL;
+}
+
+void orc_rhs(const orc_problem* p, const double* theta, const double* x, double v,
+             const double* w, double* xdot)
+{
+    if (p->kind == ORC_LQ4) lq4_rhs(p->coeffs, x, v, w, xdot);
+    else fc9_rhs(p->coeffs, theta ? theta : nominal_theta(p), x, v, w, xdot);
+}
+
+/* Constrained outputs y = h(x, v).  LQ4: y = C x.  FC9: y1 = c_q0 w1 / (d0 + d1 v)
+ * (ratio of supplied to demanded flow, kept above a floor like the paper's
+ * oxygen excess ratio, Sec. IV-A), y2 = p1, y3 = w1. */
+void orc_output(const orc_problem* p, const double* x, double v, double* y)
+{
+    if (p->kind == ORC_LQ4) {
+        const double* C = p->coeffs + 44;
+        for (int i = 0; i < 2; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < 4; ++j) s += C[4 * i + j] * x[j];
+            y[i] = s;
+        }
+    } else {
+        const double* c = p->coeffs;
+        y[0] = c[110] * x[6] / (c[112] + c[113] * v);
+        y[1] = x[0];
+        y[2] = x[6];
+    }
+}
+
+/* Classical fourth-order Runge-Kutta step of length dt with v, w, theta held
+ * over the step (Sec. IV-A: "4th order Runge Kutta", fixed step):
+ *   k1 = f(x), k2 = f(x + dt/2 k1), k3 = f(x + dt/2 k2), k4 = f(x + dt k3),
+ *   x+ = x + dt/6 (k1 + 2 k2 + 2 k3 + k4). */
+void orc_rk4(const orc_problem* p, const double* theta, const double* x, double v,
+             const double* w, double* xn)
+{
+    const int n = p->n;
+    const double h = p->dt;
+    double k1[ORC_MAXN], k2[ORC_MAXN], k3[ORC_MAXN], k4[ORC_MAXN], xs[ORC_MAXN];
+    orc_rhs(p, theta, x, v, w, k1);
+    for (int i = 0; i < n; ++i) xs[i] = x[i] + (h / 2.0) * k1[i];
+    orc_rhs(p, theta, xs, v, w, k2);
+    for (int i = 0; i < n; ++i) xs[i] = x[i] + (h / 2.0) * k2[i];
+    orc_rhs(p, theta, xs, v, w, k3);
+    for (int i = 0; i < n; ++i) xs[i] = x[i] + h * k3[i];
+    orc_rhs(p, theta, xs, v, w, k4);
+    for (int i = 0; i < n; ++i)
+        xn[i] = x[i] + (h / 6.0) * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+}
+
+/* One prediction step under disturbance w.  ORC_INJECT_ODE: w enters the
+ * continuous dynamics, held over the step.  ORC_INJECT_POST: the literal
+ * form of Eq. (4), x+ = f(x, v) + d with d = D w added after the step
+ * (D = E for LQ4, the identity for FC9). */
+void orc_step(const orc_problem* p, const double* theta, const double* x, double v,
+              const double* w, double* xn)
+{
+    if (p->inject == ORC_INJECT_ODE) {
+        orc_rk4(p, theta, x, v, w, xn);
+        return;
+    }
+    double zero[ORC_MAXW] = {0};
+    orc_rk4(p, theta, x, v, zero, xn);
+    if (p->kind == ORC_LQ4) {
+        const double* E = p->coeffs + 36;
+        for (int i = 0; i < 4; ++i) xn[i] = xn[i] + (E[2 * i] * w[0] + E[2 * i + 1] * w[1]);
+    } else {
+        for (int i = 0; i < p->n; ++i) xn[i] = xn[i] + w[i];
+    }
+}
+
+/* Constraint margin of y for Y = {y : F y <= g} (Sec. II-A: y_t in Y, Y convex):
+ * m = min_r (g_r - F_r y); m >= 0 iff y in Y.  r_arg = first minimising row. */
+double orc_margin(const orc_problem* p, const double* y, int32_t* r_arg)
+{
+    double best = INFINITY;
+    int32_t arg = 0;
+    for (int r = 0; r < p->n_c; ++r) {
+        double fy = 0.0;
+        for (int i = 0; i < p->n_y; ++i) fy += p->F[r * p->n_y + i] * y[i];
+        double m = p->g[r] - fy;
+        if (isnan(m)) m = -INFINITY;
+        if (r == 0 || m < best) {
+            best = m;
+            arg = r;
+        }
+    }
+    if (r_arg) *r_arg = arg;
+    return best;
+}
+
+/* ========================================================================= *
+ * Prediction and verdict (Eq. (3); Alg. 1 lines 5-7; Alg. 3 parallel steps 1-3).
+ * ========================================================================= */
+
+/* Candidate set-point, Eq. (2): v = v_{t-1} + kappa (r_t - v_{t-1}).
+ * Reading: at kappa = 1 the candidate is r_t itself (Alg. 1 stops there). */
+double orc_candidate_v(double kappa, double r, double v_prev)
+{
+    if (kappa == 1.0) return r;
+    return v_prev + kappa * (r - v_prev);
+}
+
+static int all_finite(const double* x, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!isfinite(x[i])) return 0;
+    return 1;
+}
+
+/* Worst constraint margin of one scenario rollout: xhat_0 = x_t,
+ * xhat_{j+1} = step(xhat_j, v, d_j^k), margins checked at j = 0..j* (Eq. (3)
+ * constraint rows; Alg. 3 parallel step 2-3).  Returns min_j m_j with the
+ * first minimising (j, r); a non-finite state or margin returns -inf at the
+ * first such j.  traj (nullable) receives the (H+1) x n states. */
+double orc_rollout(const orc_problem* p, const double* x0, double v, uint32_t t, uint32_t k,
+                   int32_t* j_arg, int32_t* r_arg, double* traj)
+{
+    const int n = p->n;
+    double x[ORC_MAXN], xn[ORC_MAXN], y[ORC_MAXY], w[ORC_MAXW], theta[ORC_MAXTH];
+    if (p->n_theta > 0) orc_draw_theta(p, t, k, theta);
+    memcpy(x, x0, sizeof(double) * (size_t)n);
+    double best = INFINITY;
+    int32_t bj = 0, br = 0;
+    for (int32_t j = 0; j <= p->H; ++j) {
+        if (traj) memcpy(traj + (size_t)j * (size_t)n, x, sizeof(double) * (size_t)n);
+        int32_t r = 0;
+        double m;
+        if (!all_finite(x, n)) {
+            m = -INFINITY;
+        } else {
+            orc_output(p, x, v, y);
+            m = orc_margin(p, y, &r);
+            if (!isfinite(m) && m != INFINITY) m = -INFINITY;
+        }
+        if (m < best || j == 0) {
+            best = m;
+            bj = j;
+            br = r;
+        }
+        if (best == -INFINITY) break;
+        if (j == p->H) break;
+        orc_draw_w(p, t, k, (uint32_t)j, w);
+        orc_step(p, theta, x, v, w, xn);
+        memcpy(x, xn, sizeof(double) * (size_t)n);
+    }
+    if (j_arg) *j_arg = bj;
+    if (r_arg) *r_arg = br;
+    return best;
+}
+
+/* Dense solve of J d = b by Gaussian elimination with partial pivoting.
+ * Returns 0 on success, -1 if a pivot vanishes. */
+static int dense_solve(int n, double* J, double* b)
+{
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(J[r * n + c]) > fabs(J[piv * n + c])) piv = r;
+        if (!(fabs(J[piv * n + c]) > 1e-300)) return -1;
+        if (piv != c) {
+            for (int q = 0; q < n; ++q) {
+                double tmp = J[c * n + q];
+                J[c * n + q] = J[piv * n + q];
+                J[piv * n + q] = tmp;
+            }
+            double tmp = b[c];
+            b[c] = b[piv];
+            b[piv] = tmp;
+        }
+        for (int r = c + 1; r < n; ++r) {
+            double f = J[r * n + c] / J[c * n + c];
+            for (int q = c; q < n; ++q) J[r * n + q] -= f * J[c * n + q];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int c = n - 1; c >= 0; --c) {
+        double s = b[c];
+        for (int q = c + 1; q < n; ++q) s -= J[c * n + q] * b[q];
+        b[c] = s / J[c * n + c];
+    }
+    return 0;
+}
+
+/* Jacobian df/dx of the continuous dynamics at (x, v), nominal theta, w = 0. */
+static void orc_jacobian(const orc_problem* p, const double* x, double v, double* J)
+{
+    if (p->kind == ORC_LQ4) {
+        const double* A = p->coeffs;
+        const double* G = p->coeffs + 20;
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) J[4 * i + j] = A[4 * i + j] + 2.0 * G[4 * i + j] * x[j];
+        return;
+    }
+    const double* c = p->coeffs;
+    const double* W = c;
+    const double* xbar = c + 81;
+    const double* th = c + 90;
+    const double* a = th;
+    const double* kq = th + 9;
+    const double* b = th + 15;
+    const double* mu = th + 18;
+    const double c_q0 = c[110], p_amb = c[111], p1ref = c[114];
+    (void)b;
+    for (int i = 0; i < 9; ++i) {
+        for (int j = 0; j < 9; ++j) {
+            double sj = tanh(x[j] - xbar[j]);
+            J[9 * i + j] = W[9 * i + j] * (1.0 - sj * sj);
+        }
+        J[9 * i + i] += -a[i];
+    }
+    /* dq_l/dp: q_l = k_l sqrt(max(dp_l, 0)); derivative 0 where dp_l <= 0. */
+    double dq_up[6], dq_dn[6];
+    for (int l = 0; l < 6; ++l) {
+        double downstream = (l < 5) ? x[l + 1] : p_amb;
+        double dp = x[l] - downstream;
+        double d = (dp > 0.0) ? kq[l] / (2.0 * sqrt(dp)) : 0.0;
+        dq_up[l] = d;   /* d q_{l+1} / d p_l       */
+        dq_dn[l] = -d;  /* d q_{l+1} / d p_{l+1}   */
+    }
+    /* phi_1 = q0 - q1; phi_l = q_{l-1} - q_l */
+    J[9 * 0 + 6] += c_q0;
+    for (int l = 0; l < 6; ++l) {
+        /* -q_{l+1} in phi_l */
+        J[9 * l + l] += -dq_up[l];
+        if (l < 5) J[9 * l + (l + 1)] += -dq_dn[l];
+        /* +q_{l+1} in phi_{l+1} */
+        if (l < 5) {
+            J[9 * (l + 1) + l] += dq_up[l];
+            J[9 * (l + 1) + (l + 1)] += dq_dn[l];
+        }
+    }
+    /* phi_7 = b1 v - mu1 w1 (p1 - p1ref) */
+    J[9 * 6 + 6] += -mu[0] * (x[0] - p1ref);
+    J[9 * 6 + 0] += -mu[0] * x[6];
+    /* phi_8 = b2 v w1 */
+    J[9 * 7 + 6] += b[1] * v;
+    /* phi_9 = b3 v - mu2 w3 v */
+    J[9 * 8 + 8] += -mu[1] * v;
+}
+
+/* Tightened steady-state test (Sec. II-A): y_ss(v) in (1 - eps) Y.  The
+ * equilibrium manifold is "assumed known"; reading: y_ss(v) = h(x_ss, v) with
+ * x_ss the equilibrium f(x_ss, v, w = 0, theta_nom) = 0 reached by Newton's
+ * method from x = -A^{-1} B v (LQ4, the linear part's DC solution) or x = xbar
+ * (FC9), stopped at ||f||_inf <= 1e-12 within 50 iterations; failure gives
+ * -inf.  (1 - eps) Y is read row-wise as g_r - eps |g_r| - F_r y >= 0, which
+ * equals (1 - eps) g_r - F_r y whenever 0 is in Y.  ss_check = 0 returns +inf. */
+double orc_steady_margin(const orc_problem* p, double v, double* x_ss, int32_t* iters)
+{
+    const int n = p->n;
+    double x[ORC_MAXN], f[ORC_MAXN], J[ORC_MAXN * ORC_MAXN], zero[ORC_MAXW] = {0};
+    if (iters) *iters = 0;
+    if (!p->ss_check) return INFINITY;
+    if (p->kind == ORC_LQ4) {
+        double A[16];
+        memcpy(A, p->coeffs, sizeof A);
+        for (int i = 0; i < 4; ++i) x[i] = -(p->coeffs[16 + i] * v);
+        if (dense_solve(4, A, x) != 0) return -INFINITY;
+    } else {
+        memcpy(x, p->coeffs + 81, sizeof(double) * 9);
+    }
+    int converged = 0;
+    for (int it = 0; it <= 50; ++it) {
+        orc_rhs(p, NULL, x, v, zero, f);
+        double nrm = 0.0;
+        for (int i = 0; i < n; ++i) {
+            if (!isfinite(f[i])) return -INFINITY;
+            if (fabs(f[i]) > nrm) nrm = fabs(f[i]);
+        }
+        if (nrm <= 1e-12) {
+            converged = 1;
+            if (iters) *iters = it;
+            break;
+        }
+        if (it == 50) break;
+        orc_jacobian(p, x, v, J);
+        for (int i = 0; i < n; ++i) f[i] = -f[i];
+        if (dense_solve(n, J, f) != 0) return -INFINITY;
+        for (int i = 0; i < n; ++i) x[i] += f[i];
+    }
+    if (!converged) return -INFINITY;
+    if (x_ss) memcpy(x_ss, x, sizeof(double) * (size_t)n);
+    double y[ORC_MAXY];
+    orc_output(p, x, v, y);
+    double best = INFINITY;
+    for (int r = 0; r < p->n_c; ++r) {
+        double fy = 0.0;
+        for (int i = 0; i < p->n_y; ++i) fy += p->F[r * p->n_y + i] * y[i];
+        double m = (p->g[r] - p->eps * fabs(p->g[r])) - fy;
+        if (isnan(m)) m = -INFINITY;
+        if (m < best) best = m;
+    }
+    return best;
+}
+
+typedef struct {
+    const orc_problem* p;
+    const double* x0;
+    double v;
+    uint32_t t;
+    int32_t k_begin, k_end;
+    double* per_scen;
+} orc_chunk;
+
+static void* orc_chunk_run(void* arg)
+{
+    orc_chunk* c = (orc_chunk*)arg;
+    for (int32_t k = c->k_begin; k < c->k_end; ++k)
+        c->per_scen[k] = orc_rollout(c->p, c->x0, c->v, c->t, (uint32_t)k, NULL, NULL, NULL);
+    return NULL;
+}
+
+/* Candidate worst margin M(v) = min( min_k m^k(v), m_ss(v) ); the candidate is
+ * admissible iff M(v) >= 0 (Alg. 2 line 7 / Alg. 3 step 3: robust means every
+ * sampled scenario).  per_scen (nullable) receives m^k; k_arg the first
+ * minimising scenario; m_ss_out the steady-state margin. */
+double orc_candidate(const orc_problem* p, const double* x0, double v, uint32_t t,
+                     double* per_scen, int32_t* k_arg, double* m_ss_out)
+{
+    const int32_t N = p->N;
+    double* m = per_scen;
+    double* owned = NULL;
+    if (!m) {
+        owned = (double*)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+        m = owned;
+    }
+    int T = p->nthreads > 1 ? p->nthreads : 1;
+    if (T > N) T = N > 0 ? N : 1;
+    if (T == 1) {
+        for (int32_t k = 0; k < N; ++k)
+            m[k] = orc_rollout(p, x0, v, t, (uint32_t)k, NULL, NULL, NULL);
+    } else {
+        pthread_t th[256];
+        orc_chunk ch[256];
+        if (T > 256) T = 256;
+        for (int i = 0; i < T; ++i) {
+            ch[i].p = p; ch[i].x0 = x0; ch[i].v = v; ch[i].t = t;
+            ch[i].k_begin = (int32_t)(((int64_t)N * i) / T);
+            ch[i].k_end = (int32_t)(((int64_t)N * (i + 1)) / T);
+            ch[i].per_scen = m;
+            pthread_create(&th[i], NULL, orc_chunk_run, &ch[i]);
+        }
+        for (int i = 0; i < T; ++i) pthread_join(th[i], NULL);
+    }
+    double worst = INFINITY;
+    int32_t ka = 0;
+    for (int32_t k = 0; k < N; ++k) {
+        if (k == 0 || m[k] < worst) {
+            worst = m[k];
+            ka = k;
+        }
+    }
+    double mss = orc_steady_margin(p, v, NULL, NULL);
+    if (m_ss_out) *m_ss_out = mss;
+    if (k_arg) *k_arg = ka;
+    free(owned);
+    return worst < mss ? worst : mss;
+}
+
+/* ========================================================================= *
+ * Kappa searches.
+ * ========================================================================= */
+
+/* Alg. 1 (bisection) applied to the robust verdict M(v) >= 0 over all
+ * scenarios.  N_kappa = K + 1 candidate evaluations at most: kappa = 1 first
+ * (stop if admissible), then K halvings of [kappa_lo, kappa_hi]; the result is
+ * the last admissible candidate (0 if none).  Reading of the iteration count:
+ * K counts the halvings after the kappa = 1 probe, so the bracket closes to
+ * 2^-K.  Alg. 2 computes the same value under feasibility monotone in kappa
+ * (the min over scenarios commutes with the dyadic floor); orc_alg2 is its
+ * literal per-scenario form. */
+orc_result orc_bisect(const orc_problem* p, const double* x0, double r, double v_prev,
+                      uint32_t t, int32_t K, double* trace_kappa, double* trace_margin)
+{
+    orc_result res = {0.0, v_prev, -INFINITY, 0, 1};
+    double lo = 0.0, hi = 1.0, kappa = 1.0, kopt = 0.0;
+    int found = 0;
+    double worst_at_opt = -INFINITY;
+    for (int32_t i = 1; i <= K + 1; ++i) {
+        double v = orc_candidate_v(kappa, r, v_prev);
+        double M = orc_candidate(p, x0, v, t, NULL, NULL, NULL);
+        if (trace_kappa) trace_kappa[i - 1] = kappa;
+        if (trace_margin) trace_margin[i - 1] = M;
+        res.passes = i;
+        if (M >= 0.0) {
+            kopt = kappa;
+            found = 1;
+            worst_at_opt = M;
+            if (kappa == 1.0) break;
+            lo = kappa;
+        } else {
+            hi = kappa;
+        }
+        kappa = (lo + hi) / 2.0;
+    }
+    res.kappa = kopt;
+    res.v = found ? orc_candidate_v(kopt, r, v_prev) : v_prev;
+    res.worst = worst_at_opt;
+    res.status = found ? 0 : 1;
+    return res;
+}
+
+/* Alg. 2 literally: for each scenario k run Alg. 1 with the verdict of
+ * scenario k alone (and the steady-state test), then take the minimum over k. */
+orc_result orc_alg2(const orc_problem* p, const double* x0, double r, double v_prev,
+                    uint32_t t, int32_t K)
+{
+    orc_result res = {1.0, r, -INFINITY, 0, 0};
+    double kopt = 1.0;
+    int any_infeasible = 0;
+    for (int32_t k = 0; k < p->N; ++k) {
+        double lo = 0.0, hi = 1.0, kappa = 1.0, kk = 0.0;
+        int found = 0;
+        for (int32_t i = 1; i <= K + 1; ++i) {
+            double v = orc_candidate_v(kappa, r, v_prev);
+            double mk = orc_rollout(p, x0, v, t, (uint32_t)k, NULL, NULL, NULL);
+            double ms = orc_steady_margin(p, v, NULL, NULL);
+            res.passes++;
+            if (mk >= 0.0 && ms >= 0.0) {
+                kk = kappa;
+                found = 1;
+                if (kappa == 1.0) break;
+                lo = kappa;
+            } else {
+                hi = kappa;
+            }
+            kappa = (lo + hi) / 2.0;
+        }
+        if (!found) any_infeasible = 1;
+        if (kk < kopt) kopt = kk;
+    }
+    res.kappa = kopt;
+    res.status = (kopt == 0.0 && any_infeasible) ? 1 : 0;
+    res.v = res.status ? v_prev : orc_candidate_v(kopt, r, v_prev);
+    return res;
+}
+
+/* Alg. 3 / Eq. (5): grid kappa_i = (i-1)/(M-1), P_ik = 1 iff scenario k and
+ * the steady-state test admit kappa_i, i* = the largest row of all ones (even
+ * if a smaller row fails), kappa_opt = kappa_{i*}; then `refine` bisection
+ * halvings inside [kappa_{i*}, kappa_{i*+1}] (0 for the plain Alg. 3).  No
+ * admissible row returns kappa = 0 with status 1.  Pmat (nullable) receives the
+ * M x N boolean array P. */
+orc_result orc_grid(const orc_problem* p, const double* x0, double r, double v_prev,
+                    uint32_t t, int32_t M, int32_t refine, uint8_t* Pmat)
+{
+    orc_result res = {0.0, v_prev, -INFINITY, 0, 1};
+    double* m = (double*)malloc(sizeof(double) * (size_t)(p->N > 0 ? p->N : 1));
+    int32_t istar = -1;
+    double worst_star = -INFINITY;
+    for (int32_t i = 0; i < M; ++i) {
+        double kappa = (M > 1) ? (double)i / (double)(M - 1) : 1.0;
+        double v = orc_candidate_v(kappa, r, v_prev);
+        double mss = 0.0;
+        double W = orc_candidate(p, x0, v, t, m, NULL, &mss);
+        res.passes++;
+        int row_ok = 1;
+        for (int32_t k = 0; k < p->N; ++k) {
+            int ok = (m[k] >= 0.0 && mss >= 0.0);
+            if (Pmat) Pmat[(size_t)i * (size_t)p->N + (size_t)k] = (uint8_t)ok;
+            if (!ok) row_ok = 0;
+        }
+        if (p->N == 0 && !(mss >= 0.0)) row_ok = 0;
+        if (row_ok) {
+            istar = i;
+            worst_star = W;
+        }
+    }
+    free(m);
+    if (istar < 0) return res;
+    double kappa = (M > 1) ? (double)istar / (double)(M - 1) : 1.0;
+    double worst = worst_star;
+    if (istar < M - 1 && refine > 0) {
+        double lo = kappa, hi = (double)(istar + 1) / (double)(M - 1);
+        for (int32_t s = 0; s < refine; ++s) {
+            double mid = (lo + hi) / 2.0;
+            double W = orc_candidate(p, x0, orc_candidate_v(mid, r, v_prev), t, NULL, NULL, NULL);
+            res.passes++;
+            if (W >= 0.0) {
+                lo = mid;
+                worst = W;
+            } else {
+                hi = mid;
+            }
+        }
+        kappa = lo;
+    }
+    res.kappa = kappa;
+    res.v = orc_candidate_v(kappa, r, v_prev);
+    res.worst = worst;
+    res.status = 0;
+    return res;
+}
+
+/* ========================================================================= *
+ * Closed loop (Fig. 1): the RG picks v_t from (x_t, v_{t-1}, r_t), the plant
+ * advances one step under v_t and the true disturbance (Eq. (4)).
+ * ========================================================================= */
+
+/* True plant: one step of the nominal model under the tag-2 disturbance. */
+void orc_plant_step(const orc_problem* p, const double* x, double v, uint32_t t, double* xn)
+{
+    double w[ORC_MAXW];
+    orc_draw_true_w(p, t, w);
+    orc_step(p, NULL, x, v, w, xn);
+}
+
+/* T closed-loop steps from (x0, v0) at RG step t0.  search: 0 = bisection
+ * (K halvings), 1 = grid (M points, `refine` halvings), 2 = Alg. 2.  x_out
+ * receives (T+1) x n states.  Returns the number of steps whose search found
+ * no admissible candidate. */
+int32_t orc_closed_loop(const orc_problem* p, const double* x0, double v0, const double* r_seq,
+                        int32_t T, uint32_t t0, int32_t search, int32_t K, int32_t M,
+                        int32_t refine, double* v_out, double* kappa_out, double* x_out)
+{
+    const int n = p->n;
+    double x[ORC_MAXN], xn[ORC_MAXN];
+    memcpy(x, x0, sizeof(double) * (size_t)n);
+    if (x_out) memcpy(x_out, x, sizeof(double) * (size_t)n);
+    double v_prev = v0;
+    int32_t infeasible = 0;
+    for (int32_t s = 0; s < T; ++s) {
+        uint32_t t = t0 + (uint32_t)s;
+        orc_result res;
+        if (search == 1) res = orc_grid(p, x, r_seq[s], v_prev, t, M, refine, NULL);
+        else if (search == 2) res = orc_alg2(p, x, r_seq[s], v_prev, t, K);
+        else res = orc_bisect(p, x, r_seq[s], v_prev, t, K, NULL, NULL);
+        if (res.status) infeasible++;
+        if (v_out) v_out[s] = res.v;
+        if (kappa_out) kappa_out[s] = res.kappa;
+        orc_plant_step(p, x, res.v, t, xn);
+        memcpy(x, xn, sizeof(double) * (size_t)n);
+        if (x_out) memcpy(x_out + (size_t)(s + 1) * (size_t)n, x, sizeof(double) * (size_t)n);
+        v_prev = res.v;
+    }
+    return infeasible;
+}
