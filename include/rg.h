@@ -1,0 +1,247 @@
+/*
+ * rg.h -- C ABI of the MI355X (gfx950) scenario-based robust reference governor.
+ *
+ * The method is that of Ossareh, Shayne and Chevalier, "CPU- and GPU-Based
+ * Parallelization of the Robust Reference Governor" (arXiv 2510.08288):
+ *
+ *   * the closed loop x_{t+1} = f(x_t, v_t) (+ d_t), y_t = h(x_t, v_t)
+ *     (Eq. (1), Eq. (4)) is integrated with fixed-step fourth-order Runge-Kutta
+ *     (Sec. IV-A);
+ *   * a candidate kappa in [0, 1] gives the set-point v = v_{t-1} +
+ *     kappa (r_t - v_{t-1}) (Eq. (2)); it is admissible when, for every one of N
+ *     sampled disturbance scenarios, the predicted outputs stay in Y over
+ *     j = 0..H and the steady-state output lies in (1 - eps) Y (Eq. (3); Alg. 2;
+ *     Alg. 3 parallel steps 1-3);
+ *   * the governor returns the largest admissible kappa found by bisection
+ *     (Alg. 1, Alg. 2) or by the grid search of Alg. 3 / Eq. (5).
+ *
+ * Conventions for every entry point:
+ *   - All pointers are HOST pointers unless stated otherwise.  Input arrays are
+ *     copied before the call returns; the caller keeps ownership.
+ *   - Every function returns an int status: RG_OK (0), a positive status that
+ *     comes with valid outputs, or a negative error, in which case no output
+ *     was written.  No function throws or aborts across the ABI.
+ *   - Calls that produce results are blocking: they enqueue work on the
+ *     handle's stream and synchronise that stream before returning.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Constraint sets are polytopes Y = {y : F y <= g}; a margin is
+ *     min_r (g_r - F_r y), >= 0 iff y is in Y (Sec. II-A).
+ */
+#ifndef RG_H
+#define RG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define RG_OK 0
+#define RG_S_INFEASIBLE 1  /* valid output: no evaluated candidate was admissible;
+                              kappa = 0 and v = v_prev (Alg. 1 starts from kappa_opt = 0) */
+#define RG_S_FALLBACK 2    /* valid output: the Newton search fell back to bisection */
+#define RG_E_INVAL (-1)    /* null pointer, non-positive size, non-finite input, bad shape */
+#define RG_E_NOMEM (-2)    /* device or host allocation failed / workspace too small */
+#define RG_E_HIP (-3)      /* a HIP runtime call failed (message in rg_last_error) */
+#define RG_E_NOTSUP (-4)   /* valid request outside what this build supports */
+#define RG_E_STATE (-5)    /* call not allowed in the handle's current state */
+
+/* ---- enumerations --------------------------------------------------------- */
+enum rg_plant_kind {
+    RG_PLANT_LQ4 = 1, /* n=4, n_w=2, n_y=2, n_theta=0; coeffs A[16] B[4] G[16] E[8] C[8]:
+                         xdot = A x + B v + G (x.*x) + E w,  y = C x */
+    RG_PLANT_FC9 = 2  /* n=9, n_w=9, n_y=3, n_theta=20; coeffs W[81] xbar[9] theta_nom[20]
+                         c_q0 p_amb d0 d1 p1ref (115 values); with z = x - xbar, p7 = p_amb,
+                         theta = (a[9], k[6], b[3], mu[2]), q0 = c_q0 x7,
+                         q_l = k_l sqrt(max(x_l - x_{l+1}, 0)) (l = 1..6, x_7 read as p7):
+                           xdot_i = -a_i z_i + (W tanh z)_i + w_i + phi_i,
+                           phi_l = q_{l-1} - q_l (l = 1..6),
+                           phi_7 = b1 v - mu1 x7 (x1 - p1ref), phi_8 = b2 v x7,
+                           phi_9 = b3 v - mu2 x9 v;
+                           y = (c_q0 x7 / (d0 + d1 v), x1, x7)  (1-based indices) */
+};
+enum rg_inject {
+    RG_INJECT_ODE = 0, /* w enters the continuous dynamics, held over each RK4 step */
+    RG_INJECT_POST = 1 /* Eq. (4): x+ = RK4(x, v) + D w (D = E for LQ4, I for FC9) */
+};
+enum rg_rng_mode {
+    RG_RNG_STREAM = 0, /* draws generated once per RG step into device memory, read coalesced */
+    RG_RNG_INLINE = 1  /* draws regenerated inside the rollout kernel from the counter */
+};
+enum rg_precision {
+    RG_PREC_F32_RECHECK = 0, /* FP32 rollouts; lanes with |margin| < band re-simulated in FP64 */
+    RG_PREC_F64 = 1          /* FP64 rollouts throughout */
+};
+enum rg_search {
+    RG_SEARCH_BISECT = 0, /* Alg. 1 on the worst margin: kappa = 1 probe, then K halvings */
+    RG_SEARCH_GRID = 1,   /* Alg. 3 / Eq. (5): M-point grid, then `refine` halvings */
+    RG_SEARCH_NEWTON = 2  /* safeguarded Newton on the worst margin (reserved) */
+};
+
+/* ---- descriptors -------------------------------------------------------------- */
+typedef struct rg_plant {
+    int32_t kind;          /* enum rg_plant_kind */
+    int32_t n, n_w, n_y;   /* must match the kind */
+    int32_t n_theta;       /* uncertain coefficients: 0 (LQ4) or 20 (FC9) */
+    const double* coeffs;  /* n_coeffs values, layout per kind */
+    int32_t n_coeffs;
+} rg_plant;
+
+/* Scenario distribution (Sec. II-C: N_sim sequences drawn at each time step).
+ * Draw c of scenario k at prediction step j of RG step t is the Philox4x32-10
+ * word (counter (k, j, t, (0<<16) | c/4), key (seed, instance)), word c%4,
+ * mapped to fl32(fl32(hi-lo) * ((word>>8) 2^-24) + fl32(lo)) by one binary32
+ * fused multiply-add.  Per-scenario coefficients use tag 1 (j = 0) and the box
+ * [1 - theta_rel, 1 + theta_rel) as a factor on theta_nom; the true-plant
+ * disturbance of the closed loop uses tag 2 with k = j = 0. */
+typedef struct rg_scenarios {
+    int32_t N;             /* scenarios, >= 1 */
+    uint32_t seed;         /* key word 0 */
+    uint32_t instance;     /* key word 1 */
+    const double* w_lo;    /* [n_w] lower box corner */
+    const double* w_hi;    /* [n_w] upper box corner (>= w_lo) */
+    double theta_rel;      /* relative spread of theta, in [0, 1) */
+    int32_t inject;        /* enum rg_inject */
+    int32_t rng_mode;      /* enum rg_rng_mode */
+} rg_scenarios;
+
+typedef struct rg_constraints {
+    int32_t n_c;           /* rows, 1..4 */
+    const double* F;       /* [n_c x n_y] row-major */
+    const double* g;       /* [n_c] */
+    double eps;            /* steady-state tightening: rows g_r - eps |g_r| - F_r y_ss >= 0 */
+    int32_t ss_check;      /* 0 disables the steady-state test */
+} rg_constraints;
+
+typedef struct rg_options {
+    int32_t precision;     /* enum rg_precision (default F32_RECHECK) */
+    double band;           /* recheck band on |FP32 margin| (default 1e-4) */
+    int32_t K;             /* halvings after the kappa = 1 probe (default 12) */
+    int32_t search;        /* enum rg_search (default BISECT) */
+    int32_t depth;         /* bisection levels evaluated per device round (1..6; 0 = auto) */
+    int32_t M;             /* grid points for RG_SEARCH_GRID (2..127) */
+    int32_t refine;        /* halvings after the grid */
+    int32_t early_exit;    /* 1: a candidate stops once one lane is below -band */
+    int32_t block;         /* threads per workgroup for rollouts (64..256, multiple of 64; 0 = auto) */
+    int32_t max_T;         /* closed-loop steps kept on the device per chunk (default 256) */
+} rg_options;
+
+typedef struct rg_step_info {
+    double kappa;          /* chosen kappa */
+    double v;              /* chosen set-point */
+    double worst_margin;   /* M(kappa) of the chosen candidate (-inf if none admissible) */
+    int32_t status;        /* RG_OK or RG_S_INFEASIBLE */
+    int32_t rounds;        /* device rounds executed */
+    int32_t candidates;    /* candidate evaluations executed (incl. speculative ones) */
+    int32_t rechecks;      /* (candidate, scenario) pairs re-simulated in FP64 */
+    int32_t bisect_passes; /* candidate evaluations plain sequential Alg. 1 would make */
+    uint32_t t;            /* RG step counter used for the draws */
+    uint64_t lane_steps;   /* RK4 steps executed by FP32/FP64 rollout lanes (speculative
+                              candidates and early exits included; rechecks excluded) */
+} rg_step_info;
+
+/* Kernel timing collected while profiling is on (rg_set_profiling). */
+typedef struct rg_profile {
+    int64_t rollout_launches;  /* rollout kernel launches timed */
+    double rollout_ms;         /* summed HIP-event time of those launches */
+    uint64_t lane_steps;       /* RK4 steps executed by those launches */
+    int64_t steps;             /* RG steps covered */
+} rg_profile;
+
+typedef struct rg_handle rg_handle;
+
+/* ---- lifecycle ---------------------------------------------------------------- */
+
+/* Fill *opt with defaults.  Returns RG_E_INVAL if opt is NULL. */
+int rg_default_options(rg_options* opt);
+
+/* Create a governor for one problem (Eq. (3) fixes f, h, Y, eps and j* = H;
+ * Sec. II-C fixes N_sim and the distribution).  H >= 1 steps of length dt > 0.
+ * opt may be NULL (defaults).  All descriptor arrays are copied.  No device
+ * memory is allocated here: see rg_workspace_size / rg_bind_workspace. */
+int rg_create(const rg_plant* plant, const rg_scenarios* scen, const rg_constraints* cons,
+              int32_t H, double dt, const rg_options* opt, rg_handle** out);
+
+/* Release the handle and whatever device memory the library allocated itself.
+ * A bound workspace is not freed.  Accepts NULL. */
+int rg_destroy(rg_handle* h);
+
+/* Bytes of device memory one handle needs. */
+int rg_workspace_size(const rg_handle* h, size_t* bytes);
+
+/* Give the handle caller-owned device memory (e.g. a torch tensor), >= the size
+ * above and 256-byte aligned; it must outlive the handle.  Without a bound
+ * workspace the first compute call allocates one with hipMalloc. */
+int rg_bind_workspace(rg_handle* h, void* device_ptr, size_t bytes);
+
+/* Stream (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream) that
+ * all work of this handle is enqueued on; NULL = the default stream. */
+int rg_set_stream(rg_handle* h, void* hip_stream);
+
+/* RG step counter t (selects fresh scenario draws, Sec. II-C).  rg_step and
+ * rg_closed_loop advance it by one per step; setting it allows exact resume. */
+int rg_set_step(rg_handle* h, uint32_t t);
+int rg_get_step(const rg_handle* h, uint32_t* t);
+
+/* ---- the governor --------------------------------------------------------------- */
+
+/* One RG update (Alg. 1-3 inputs x_t, v_{t-1}, r_t; output kappa_opt, v_t).
+ * x: [n].  v_out required; kappa_out and info nullable.  Advances t.  Returns
+ * RG_OK or RG_S_INFEASIBLE (then kappa = 0, v = v_prev). */
+int rg_step(rg_handle* h, const double* x, double r, double v_prev, double* v_out,
+            double* kappa_out, rg_step_info* info);
+
+/* Worst margins of explicit candidates without searching (Alg. 3 step 5 for a
+ * given list): margins[i] = min(min_k m^k(v_i), m_ss(v_i)) with v_i from
+ * kappa[i] (each in [0, 1]), full horizon, t unchanged.  per_scenario
+ * (nullable) receives the [M x N] FP32 (or FP64-rounded, in F64 precision)
+ * rollout margins before any recheck; per_scenario_j (nullable) the first step
+ * attaining each.  In F32_RECHECK precision, margins[] uses the FP64 value of
+ * every lane with |m32| < band. */
+int rg_margin(rg_handle* h, const double* x, double r, double v_prev, const double* kappa,
+              int32_t M, double* margins, float* per_scenario, int32_t* per_scenario_j);
+
+/* T closed-loop steps on the device with no host round trip (Fig. 1): at step
+ * s the governor picks v_s from (x_s, v_{s-1}, r_seq[s]), then the true plant
+ * advances x_{s+1} = RK4(x_s, v_s) under the tag-2 disturbance.  x0: [n];
+ * r_seq: [T]; v_out, kappa_out: [T]; x_out: [(T+1) x n]; info_out: [T];
+ * outputs nullable except v_out.  Advances t by T.  use_graph = 1 captures one
+ * RG step as a HIP graph (once per handle and stream) and replays it T times;
+ * profiling forces plain launches. */
+int rg_closed_loop(rg_handle* h, const double* x0, double v0, const double* r_seq, int32_t T,
+                   double* v_out, double* kappa_out, double* x_out, rg_step_info* info_out,
+                   int32_t use_graph);
+
+/* Profiling: with enable = 1, every rollout launch is bracketed by HIP events
+ * on the handle's stream and the totals accumulate until reset (enable = 1
+ * again resets).  rg_get_profile copies the totals. */
+int rg_set_profiling(rg_handle* h, int32_t enable);
+int rg_get_profile(const rg_handle* h, rg_profile* out);
+
+/* ---- inspection ----------------------------------------------------------------- */
+
+/* Scenario draws as the device sees them: w_out[(j - j0) * nk * n_w + (k - k0) * n_w + c]
+ * for k in [k0, k0+nk), j in [j0, j0+nj), at RG step t; theta_out (nullable)
+ * [nk x n_theta] per-scenario coefficients (FP64 value theta_nom * factor). */
+int rg_draws(rg_handle* h, uint32_t t, int32_t k0, int32_t nk, int32_t j0, int32_t nj,
+             float* w_out, double* theta_out);
+
+/* Predicted states of scenarios k_list[0..nk) under set-point v at the current
+ * t, starting from x: traj[(i * (H + 1) + j) * n + s].  precision selects the
+ * FP32 or FP64 rollout code path of the governor's kernels. */
+int rg_trajectory(rg_handle* h, const double* x, double v, const int32_t* k_list, int32_t nk,
+                  int32_t precision, double* traj);
+
+/* Static text for a status code. */
+const char* rg_status_string(int status);
+
+/* Last error message of a handle (empty string if none); NULL handle gives the
+ * last error of a failed rg_create in this thread. */
+const char* rg_last_error(const rg_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RG_H */

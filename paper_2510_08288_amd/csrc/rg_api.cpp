@@ -1,0 +1,651 @@
+// Host side of the C ABI declared in include/rg.h: argument validation,
+// workspace layout, and the enqueue order of one RG step (see rg_kernels.hip).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstddef>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rg.h"
+#include "rg_internal.hpp"
+
+using namespace rg;
+
+struct rg_handle {
+  Problem pr;
+  rg_options opt;
+  LaunchCfg cfg;
+  // device memory
+  hipStream_t stream = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+  bool ws_ready = false;
+  DevBuffers b{};
+  // host mirrors
+  uint32_t t = 0;
+  long long gen_t = -1;  // RG step whose draws are in the streamed buffer
+  std::string err;
+  // one captured closed-loop RG step, replayed per step
+  hipGraphExec_t step_graph = nullptr;
+  // profiling
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  rg_profile prof{};
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int fail(rg_handle* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+int fail_hip(rg_handle* h, const char* what, hipError_t e) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(h, RG_E_HIP, m);
+}
+
+#define HIPCHK(h, call)                              \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return fail_hip(h, #call, e_); \
+  } while (0)
+
+bool finite_array(const double* a, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace layout: offsets of each buffer inside one allocation.
+struct Layout {
+  size_t st, srch, res, r_seq, x_hist, wbuf, thbuf, rlist, per_m, per_j, scratch, total;
+};
+
+Layout layout_of(const rg_handle* h) {
+  const Problem& pr = h->pr;
+  const size_t N = (size_t)pr.s.N;
+  const size_t T = (size_t)h->opt.max_T;
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  L.st = take(sizeof(DevState));
+  L.srch = take(sizeof(DevSearch));
+  L.res = take(sizeof(DevResult) * T);
+  L.r_seq = take(sizeof(double) * T);
+  L.x_hist = take(sizeof(double) * (T + 1) * kMaxN);
+  L.wbuf = take(pr.s.rng_mode == RG_RNG_STREAM ? sizeof(float) * (size_t)pr.H * pr.p.nw * N : 0);
+  L.thbuf = take(pr.s.rng_mode == RG_RNG_STREAM ? sizeof(float) * (size_t)pr.p.nth * N : 0);
+  L.rlist = take(sizeof(int2) * (size_t)kCMax * N);
+  L.per_m = take(sizeof(float) * (size_t)kCMax * N);
+  L.per_j = take(sizeof(int32_t) * (size_t)kCMax * N);
+  L.scratch = take(sizeof(double) * kCMax * 4);
+  L.total = off;
+  return L;
+}
+
+int depth_for(const rg_handle* h) {
+  if (h->opt.depth > 0) return h->opt.depth;
+  // Enough candidates per round to give every SIMD of the chip about two
+  // wavefronts, then the smallest depth that needs no more rounds.
+  const int goal = h->opt.search == RG_SEARCH_GRID ? h->opt.refine : h->opt.K;
+  const double lanes_budget = 2.0 * 256 * 4 * 64;
+  int dmax = 1;
+  while (dmax < 6 && ((1 << (dmax + 1)) - 1) * (double)h->pr.s.N <= lanes_budget) ++dmax;
+  if (goal <= 0) return 1;
+  const int rounds = (goal + dmax - 1) / dmax;
+  return (goal + rounds - 1) / rounds;
+}
+
+void plan(rg_handle* h) {
+  const int d = depth_for(h);
+  h->opt.depth = d;
+  LaunchCfg c;
+  c.block = h->opt.block > 0 ? h->opt.block : 256;
+  const int tree = (1 << d) - 1;
+  if (h->opt.search == RG_SEARCH_GRID) {
+    c.cmax_round = h->opt.M > tree ? h->opt.M : tree;
+    c.rounds = 1 + (h->opt.refine + d - 1) / d;
+  } else {
+    const int d0 = h->opt.K < d ? h->opt.K : d;
+    const int r0 = 1 << d0;
+    c.cmax_round = r0 > tree ? r0 : tree;
+    c.rounds = 1 + (h->opt.K - d0 + d - 1) / d;
+  }
+  h->cfg = c;
+}
+
+int ensure_workspace(rg_handle* h) {
+  if (h->ws_ready) return RG_OK;
+  const Layout L = layout_of(h);
+  if (!h->ws) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, L.total);
+    if (e != hipSuccess) return fail(h, RG_E_NOMEM, std::string("hipMalloc workspace: ") + hipGetErrorString(e));
+    h->ws = p;
+    h->ws_bytes = L.total;
+    h->ws_owned = true;
+  }
+  char* base = (char*)h->ws;
+  DevBuffers& b = h->b;
+  b.st = (DevState*)(base + L.st);
+  b.srch = (DevSearch*)(base + L.srch);
+  b.res = (DevResult*)(base + L.res);
+  b.r_seq = (double*)(base + L.r_seq);
+  b.x_hist = (double*)(base + L.x_hist);
+  b.wbuf = (float*)(base + L.wbuf);
+  b.thbuf = (float*)(base + L.thbuf);
+  b.rlist = (int2*)(base + L.rlist);
+  b.per_m = (float*)(base + L.per_m);
+  b.per_j = (int32_t*)(base + L.per_j);
+  b.scratch = (double*)(base + L.scratch);
+  b.scratch_bytes = sizeof(double) * kCMax * 4;
+  // Search configuration.
+  DevSearch* S = new (std::nothrow) DevSearch;
+  if (!S) return fail(h, RG_E_NOMEM, "host allocation");
+  memset(S, 0, sizeof(DevSearch));
+  S->mode = h->opt.search == RG_SEARCH_GRID ? kGrid : kBisect;
+  S->K = h->opt.K;
+  S->depth = h->opt.depth;
+  S->M = h->opt.M;
+  S->refine = h->opt.refine;
+  S->precision = h->opt.precision;
+  S->ss_check = h->pr.c.ss_check;
+  S->n_c = h->pr.c.n_c;
+  S->ny = h->pr.p.ny;
+  S->eps = h->pr.c.eps;
+  for (int r = 0; r < kNC; ++r) S->g[r] = h->pr.c.g[r];
+  for (int i = 0; i < kNC * kMaxY; ++i) S->F[i] = h->pr.c.F[i];
+  S->done = 1;
+  hipError_t e = hipMemcpyAsync(b.srch, S, sizeof(DevSearch), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  delete S;
+  if (e != hipSuccess) return fail_hip(h, "upload search configuration", e);
+  h->ws_ready = true;
+  return RG_OK;
+}
+
+int upload_state(rg_handle* h, const double* x, double r, double v_prev) {
+  DevState s;
+  memset(&s, 0, sizeof(s));
+  for (int i = 0; i < h->pr.p.n; ++i) s.x[i] = x[i];
+  s.v_prev = v_prev;
+  s.r = r;
+  s.t = h->t;
+  s.cl_index = 0;
+  HIPCHK(h, hipMemcpyAsync(h->b.st, &s, sizeof(s), hipMemcpyHostToDevice, h->stream));
+  // The copy reads a stack object: wait for it before returning.
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return RG_OK;
+}
+
+// Draws for the current t into the streamed buffer (no-op in inline mode or if current).
+int ensure_draws(rg_handle* h) {
+  if (h->pr.s.rng_mode != RG_RNG_STREAM) return RG_OK;
+  if (h->gen_t == (long long)h->t) return RG_OK;
+  HIPCHK(h, launch_gen(h->pr, h->b, h->stream));
+  h->gen_t = (long long)h->t;
+  return RG_OK;
+}
+
+hipError_t next_event(rg_handle* h, hipEvent_t* ev) {
+  if (h->ev_used == h->ev_pool.size()) {
+    hipEvent_t e;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return err;
+    h->ev_pool.push_back(e);
+  }
+  *ev = h->ev_pool[h->ev_used++];
+  return hipSuccess;
+}
+
+// Read back the event pairs recorded since the last harvest.
+hipError_t harvest_events(rg_handle* h) {
+  for (size_t i = 0; i + 1 < h->ev_used; i += 2) {
+    float ms = 0.f;
+    hipError_t e = hipEventElapsedTime(&ms, h->ev_pool[i], h->ev_pool[i + 1]);
+    if (e != hipSuccess) return e;
+    h->prof.rollout_ms += ms;
+    h->prof.rollout_launches += 1;
+  }
+  h->ev_used = 0;
+  return hipSuccess;
+}
+
+// Enqueue one RG step: draws, round-0 setup, the rounds, the result record.
+hipError_t enqueue_step(rg_handle* h, int closed_loop) {
+  hipError_t e;
+  const int prec = h->opt.precision;
+  const double band = prec == RG_PREC_F32_RECHECK ? h->opt.band : 0.0;
+  if (h->pr.s.rng_mode == RG_RNG_STREAM && (e = launch_gen(h->pr, h->b, h->stream)) != hipSuccess)
+    return e;
+  if ((e = launch_setup(h->pr, h->b, closed_loop, h->stream)) != hipSuccess) return e;
+  for (int r = 0; r < h->cfg.rounds; ++r) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->profiling) {
+      if ((e = next_event(h, &e0)) != hipSuccess || (e = next_event(h, &e1)) != hipSuccess) return e;
+      if ((e = hipEventRecord(e0, h->stream)) != hipSuccess) return e;
+    }
+    if ((e = launch_rollout(h->pr, band, prec, h->opt.early_exit, 0, h->cfg, h->b, h->stream)) !=
+        hipSuccess)
+      return e;
+    if (h->profiling && (e = hipEventRecord(e1, h->stream)) != hipSuccess) return e;
+    if (prec == RG_PREC_F32_RECHECK &&
+        (e = launch_recheck(h->pr, h->opt.early_exit, h->cfg, h->b, h->stream)) != hipSuccess)
+      return e;
+    if ((e = launch_decide(h->pr, h->b, h->stream)) != hipSuccess) return e;
+  }
+  return launch_finalize(h->pr, closed_loop, h->b, h->stream);
+}
+
+void fill_info(const DevResult& R, rg_step_info* info) {
+  if (!info) return;
+  info->kappa = R.kappa;
+  info->v = R.v;
+  info->worst_margin = R.worst;
+  info->status = R.status;
+  info->rounds = R.rounds;
+  info->candidates = R.candidates;
+  info->rechecks = R.rechecks;
+  info->bisect_passes = R.passes_alg1;
+  info->t = R.t;
+  info->lane_steps = R.lane_steps;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rg_default_options(rg_options* opt) {
+  if (!opt) return RG_E_INVAL;
+  opt->precision = RG_PREC_F32_RECHECK;
+  opt->band = 1e-4;
+  opt->K = 12;
+  opt->search = RG_SEARCH_BISECT;
+  opt->depth = 0;
+  opt->M = 64;
+  opt->refine = 6;
+  opt->early_exit = 1;
+  opt->block = 0;
+  opt->max_T = 256;
+  return RG_OK;
+}
+
+int rg_create(const rg_plant* plant, const rg_scenarios* scen, const rg_constraints* cons,
+              int32_t H, double dt, const rg_options* opt, rg_handle** out) {
+  if (!out) return fail(nullptr, RG_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!plant || !scen || !cons) return fail(nullptr, RG_E_INVAL, "NULL descriptor");
+  rg_options o;
+  rg_default_options(&o);
+  if (opt) o = *opt;
+  // plant
+  int n, nw, ny, nth, ncoef;
+  if (plant->kind == RG_PLANT_LQ4) {
+    n = 4; nw = 2; ny = 2; nth = 0; ncoef = 52;
+  } else if (plant->kind == RG_PLANT_FC9) {
+    n = 9; nw = 9; ny = 3; nth = 20; ncoef = 115;
+  } else {
+    return fail(nullptr, RG_E_INVAL, "unknown plant kind");
+  }
+  if (plant->n != n || plant->n_w != nw || plant->n_y != ny || plant->n_theta != nth)
+    return fail(nullptr, RG_E_INVAL, "plant dimensions do not match the kind");
+  if (!plant->coeffs || plant->n_coeffs != ncoef)
+    return fail(nullptr, RG_E_INVAL, "plant coefficient count does not match the kind");
+  if (!finite_array(plant->coeffs, ncoef)) return fail(nullptr, RG_E_INVAL, "non-finite coefficient");
+  // scenarios
+  if (scen->N < 1) return fail(nullptr, RG_E_INVAL, "N must be >= 1");
+  if ((size_t)scen->N * kCMax > (size_t)INT32_MAX) return fail(nullptr, RG_E_NOTSUP, "N too large");
+  if (!scen->w_lo || !scen->w_hi) return fail(nullptr, RG_E_INVAL, "NULL disturbance box");
+  if (!finite_array(scen->w_lo, nw) || !finite_array(scen->w_hi, nw))
+    return fail(nullptr, RG_E_INVAL, "non-finite disturbance box");
+  for (int c = 0; c < nw; ++c)
+    if (scen->w_hi[c] < scen->w_lo[c]) return fail(nullptr, RG_E_INVAL, "w_hi < w_lo");
+  if (!(scen->theta_rel >= 0.0 && scen->theta_rel < 1.0))
+    return fail(nullptr, RG_E_INVAL, "theta_rel must be in [0, 1)");
+  if (scen->inject != RG_INJECT_ODE && scen->inject != RG_INJECT_POST)
+    return fail(nullptr, RG_E_INVAL, "bad inject mode");
+  if (scen->rng_mode != RG_RNG_STREAM && scen->rng_mode != RG_RNG_INLINE)
+    return fail(nullptr, RG_E_INVAL, "bad rng mode");
+  // constraints
+  if (cons->n_c < 1) return fail(nullptr, RG_E_INVAL, "n_c must be >= 1");
+  if (cons->n_c > kNC) return fail(nullptr, RG_E_NOTSUP, "at most 4 constraint rows");
+  if (!cons->F || !cons->g) return fail(nullptr, RG_E_INVAL, "NULL constraint arrays");
+  if (!finite_array(cons->F, cons->n_c * ny) || !finite_array(cons->g, cons->n_c))
+    return fail(nullptr, RG_E_INVAL, "non-finite constraint data");
+  if (!(cons->eps >= 0.0 && cons->eps < 1.0)) return fail(nullptr, RG_E_INVAL, "eps must be in [0, 1)");
+  // horizon and options
+  if (H < 1) return fail(nullptr, RG_E_INVAL, "H must be >= 1");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(nullptr, RG_E_INVAL, "dt must be > 0");
+  if (o.precision != RG_PREC_F32_RECHECK && o.precision != RG_PREC_F64)
+    return fail(nullptr, RG_E_INVAL, "bad precision");
+  if (!(o.band >= 0.0) || !std::isfinite(o.band)) return fail(nullptr, RG_E_INVAL, "bad band");
+  if (o.K < 0 || o.K > 40) return fail(nullptr, RG_E_INVAL, "K must be in [0, 40]");
+  if (o.search == RG_SEARCH_NEWTON) return fail(nullptr, RG_E_NOTSUP, "Newton search not in this build");
+  if (o.search != RG_SEARCH_BISECT && o.search != RG_SEARCH_GRID)
+    return fail(nullptr, RG_E_INVAL, "bad search");
+  if (o.depth < 0 || o.depth > 6) return fail(nullptr, RG_E_INVAL, "depth must be in [0, 6]");
+  if (o.search == RG_SEARCH_GRID && (o.M < 2 || o.M > kCMax - 1))
+    return fail(nullptr, RG_E_INVAL, "M must be in [2, 127]");
+  if (o.refine < 0 || o.refine > 40) return fail(nullptr, RG_E_INVAL, "refine must be in [0, 40]");
+  if (o.block != 0 && (o.block < 64 || o.block > 256 || (o.block & 63)))
+    return fail(nullptr, RG_E_INVAL, "block must be a multiple of 64 in [64, 256]");
+  if (o.max_T < 1 || o.max_T > 65536) return fail(nullptr, RG_E_INVAL, "max_T must be in [1, 65536]");
+
+  rg_handle* h = new (std::nothrow) rg_handle;
+  if (!h) return fail(nullptr, RG_E_NOMEM, "host allocation");
+  memset(&h->pr, 0, sizeof(h->pr));
+  PlantDesc& p = h->pr.p;
+  p.kind = plant->kind; p.n = n; p.nw = nw; p.ny = ny; p.nth = nth;
+  for (int i = 0; i < ncoef; ++i) p.coeffs[i] = plant->coeffs[i];
+  ScenDesc& s = h->pr.s;
+  s.N = scen->N; s.seed = scen->seed; s.instance = scen->instance;
+  for (int c = 0; c < nw; ++c) { s.wlo[c] = scen->w_lo[c]; s.whi[c] = scen->w_hi[c]; }
+  s.theta_rel = scen->theta_rel; s.inject = scen->inject; s.rng_mode = scen->rng_mode;
+  ConsDesc& c = h->pr.c;
+  c.n_c = cons->n_c;
+  for (int r = 0; r < kNC; ++r) {
+    for (int i = 0; i < ny; ++i) c.F[r * ny + i] = r < cons->n_c ? cons->F[r * ny + i] : 0.0;
+    c.g[r] = r < cons->n_c ? cons->g[r] : INFINITY;
+  }
+  c.eps = cons->eps; c.ss_check = cons->ss_check ? 1 : 0;
+  h->pr.H = H;
+  h->pr.dt = dt;
+  h->opt = o;
+  plan(h);
+  *out = h;
+  return RG_OK;
+}
+
+int rg_destroy(rg_handle* h) {
+  if (!h) return RG_OK;
+  if (h->step_graph) (void)hipGraphExecDestroy(h->step_graph);
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  if (h->ws_owned && h->ws) (void)hipFree(h->ws);
+  delete h;
+  return RG_OK;
+}
+
+int rg_workspace_size(const rg_handle* h, size_t* bytes) {
+  if (!h || !bytes) return RG_E_INVAL;
+  *bytes = layout_of(h).total;
+  return RG_OK;
+}
+
+int rg_bind_workspace(rg_handle* h, void* device_ptr, size_t bytes) {
+  if (!h || !device_ptr) return RG_E_INVAL;
+  if (h->ws) return fail(h, RG_E_STATE, "workspace already present");
+  if (((uintptr_t)device_ptr & 255) != 0) return fail(h, RG_E_INVAL, "workspace not 256-byte aligned");
+  if (bytes < layout_of(h).total) return fail(h, RG_E_NOMEM, "workspace too small");
+  h->ws = device_ptr;
+  h->ws_bytes = bytes;
+  h->ws_owned = false;
+  return RG_OK;
+}
+
+int rg_set_stream(rg_handle* h, void* hip_stream) {
+  if (!h) return RG_E_INVAL;
+  if (h->stream != (hipStream_t)hip_stream && h->step_graph) {
+    (void)hipGraphExecDestroy(h->step_graph);
+    h->step_graph = nullptr;
+  }
+  h->stream = (hipStream_t)hip_stream;
+  return RG_OK;
+}
+
+int rg_set_step(rg_handle* h, uint32_t t) {
+  if (!h) return RG_E_INVAL;
+  h->t = t;
+  return RG_OK;
+}
+
+int rg_get_step(const rg_handle* h, uint32_t* t) {
+  if (!h || !t) return RG_E_INVAL;
+  *t = h->t;
+  return RG_OK;
+}
+
+int rg_step(rg_handle* h, const double* x, double r, double v_prev, double* v_out,
+            double* kappa_out, rg_step_info* info) {
+  if (!h) return RG_E_INVAL;
+  if (!x || !v_out) return fail(h, RG_E_INVAL, "NULL x or v_out");
+  if (!finite_array(x, h->pr.p.n) || !std::isfinite(r) || !std::isfinite(v_prev))
+    return fail(h, RG_E_INVAL, "non-finite input");
+  int rc = ensure_workspace(h);
+  if (rc) return rc;
+  if ((rc = upload_state(h, x, r, v_prev))) return rc;
+  hipError_t e = enqueue_step(h, 0);
+  if (e != hipSuccess) return fail_hip(h, "enqueue RG step", e);
+  h->gen_t = (long long)h->t;
+  DevResult R;
+  HIPCHK(h, hipMemcpyAsync(&R, h->b.res, sizeof(R), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (h->profiling) {
+    HIPCHK(h, harvest_events(h));
+    h->prof.lane_steps += R.lane_steps;
+    h->prof.steps += 1;
+  }
+  h->t += 1;
+  *v_out = R.v;
+  if (kappa_out) *kappa_out = R.kappa;
+  fill_info(R, info);
+  return R.status == 0 ? RG_OK : RG_S_INFEASIBLE;
+}
+
+int rg_margin(rg_handle* h, const double* x, double r, double v_prev, const double* kappa,
+              int32_t M, double* margins, float* per_scenario, int32_t* per_scenario_j) {
+  if (!h) return RG_E_INVAL;
+  if (!x || !kappa || !margins || M < 1) return fail(h, RG_E_INVAL, "bad arguments");
+  if (!finite_array(x, h->pr.p.n) || !std::isfinite(r) || !std::isfinite(v_prev))
+    return fail(h, RG_E_INVAL, "non-finite input");
+  for (int i = 0; i < M; ++i)
+    if (!(kappa[i] >= 0.0 && kappa[i] <= 1.0)) return fail(h, RG_E_INVAL, "kappa outside [0, 1]");
+  int rc = ensure_workspace(h);
+  if (rc) return rc;
+  if ((rc = upload_state(h, x, r, v_prev))) return rc;
+  if ((rc = ensure_draws(h))) return rc;
+  const int prec = h->opt.precision;
+  const double band = prec == RG_PREC_F32_RECHECK ? h->opt.band : 0.0;
+  const size_t N = (size_t)h->pr.s.N;
+  std::vector<double> out(kCMax);
+  for (int base = 0; base < M; base += kCMax) {
+    const int m = (M - base) < kCMax ? (M - base) : kCMax;
+    HIPCHK(h, hipMemcpyAsync((char*)h->b.srch + offsetof(DevSearch, kappa), kappa + base, sizeof(double) * m,
+                             hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, launch_setup_list(h->pr, h->b, m, h->stream));
+    LaunchCfg cfg = h->cfg;
+    cfg.cmax_round = m;
+    HIPCHK(h, launch_rollout(h->pr, band, prec, 0, 1, cfg, h->b, h->stream));
+    if (prec == RG_PREC_F32_RECHECK) HIPCHK(h, launch_recheck(h->pr, 0, cfg, h->b, h->stream));
+    HIPCHK(h, launch_collect(h->b, m, h->b.scratch, h->stream));
+    HIPCHK(h, hipMemcpyAsync(out.data(), h->b.scratch, sizeof(double) * m, hipMemcpyDeviceToHost,
+                             h->stream));
+    if (per_scenario)
+      HIPCHK(h, hipMemcpyAsync(per_scenario + (size_t)base * N, h->b.per_m, sizeof(float) * m * N,
+                               hipMemcpyDeviceToHost, h->stream));
+    if (per_scenario_j)
+      HIPCHK(h, hipMemcpyAsync(per_scenario_j + (size_t)base * N, h->b.per_j,
+                               sizeof(int32_t) * m * N, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int i = 0; i < m; ++i) margins[base + i] = out[i];
+  }
+  return RG_OK;
+}
+
+int rg_closed_loop(rg_handle* h, const double* x0, double v0, const double* r_seq, int32_t T,
+                   double* v_out, double* kappa_out, double* x_out, rg_step_info* info_out,
+                   int32_t use_graph) {
+  if (!h) return RG_E_INVAL;
+  if (!x0 || !r_seq || !v_out || T < 1) return fail(h, RG_E_INVAL, "bad arguments");
+  if (!finite_array(x0, h->pr.p.n) || !std::isfinite(v0) || !finite_array(r_seq, T))
+    return fail(h, RG_E_INVAL, "non-finite input");
+  int rc = ensure_workspace(h);
+  if (rc) return rc;
+  const int n = h->pr.p.n;
+  const bool graph = use_graph && !h->profiling;
+  if ((rc = upload_state(h, x0, r_seq[0], v0))) return rc;
+  if (x_out)
+    for (int i = 0; i < n; ++i) x_out[i] = x0[i];
+  if (graph && !h->step_graph) {
+    hipGraph_t g = nullptr;
+    HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_step(h, 1);
+    hipError_t e2 = hipStreamEndCapture(h->stream, &g);
+    if (e != hipSuccess) return fail_hip(h, "capture closed-loop step", e);
+    if (e2 != hipSuccess) return fail_hip(h, "hipStreamEndCapture", e2);
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail_hip(h, "hipGraphInstantiate", e);
+    h->step_graph = ge;
+  }
+  std::vector<DevResult> R;
+  std::vector<double> xs;
+  int32_t done = 0;
+  while (done < T) {
+    const int chunk = (T - done) < h->opt.max_T ? (T - done) : h->opt.max_T;
+    const int32_t zero = 0;
+    HIPCHK(h, hipMemcpyAsync(h->b.r_seq, r_seq + done, sizeof(double) * chunk,
+                             hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync((char*)h->b.st + offsetof(DevState, cl_index), &zero, sizeof(zero),
+                             hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int s = 0; s < chunk; ++s) {
+      hipError_t e = graph ? hipGraphLaunch(h->step_graph, h->stream) : enqueue_step(h, 1);
+      if (e != hipSuccess) return fail_hip(h, "enqueue closed-loop step", e);
+    }
+    R.resize(chunk);
+    xs.resize((size_t)(chunk + 1) * n);
+    HIPCHK(h, hipMemcpyAsync(R.data(), h->b.res, sizeof(DevResult) * chunk, hipMemcpyDeviceToHost,
+                             h->stream));
+    HIPCHK(h, hipMemcpyAsync(xs.data(), h->b.x_hist, sizeof(double) * (chunk + 1) * n,
+                             hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (h->profiling) HIPCHK(h, harvest_events(h));
+    for (int s = 0; s < chunk; ++s) {
+      v_out[done + s] = R[s].v;
+      if (kappa_out) kappa_out[done + s] = R[s].kappa;
+      if (info_out) fill_info(R[s], info_out + done + s);
+      if (x_out)
+        for (int i = 0; i < n; ++i) x_out[(size_t)(done + s + 1) * n + i] = xs[(size_t)(s + 1) * n + i];
+      if (h->profiling) {
+        h->prof.lane_steps += R[s].lane_steps;
+        h->prof.steps += 1;
+      }
+    }
+    done += chunk;
+    h->t += (uint32_t)chunk;
+  }
+  h->gen_t = (long long)h->t - 1;
+  return RG_OK;
+}
+
+int rg_set_profiling(rg_handle* h, int32_t enable) {
+  if (!h) return RG_E_INVAL;
+  h->profiling = enable != 0;
+  h->prof = rg_profile{};
+  h->ev_used = 0;
+  return RG_OK;
+}
+
+int rg_get_profile(const rg_handle* h, rg_profile* out) {
+  if (!h || !out) return RG_E_INVAL;
+  *out = h->prof;
+  return RG_OK;
+}
+
+int rg_draws(rg_handle* h, uint32_t t, int32_t k0, int32_t nk, int32_t j0, int32_t nj,
+             float* w_out, double* theta_out) {
+  if (!h) return RG_E_INVAL;
+  if (!w_out || k0 < 0 || nk < 1 || j0 < 0 || nj < 1) return fail(h, RG_E_INVAL, "bad arguments");
+  int rc = ensure_workspace(h);
+  if (rc) return rc;
+  const size_t wb = sizeof(float) * (size_t)nk * nj * h->pr.p.nw;
+  const size_t tb = sizeof(double) * (size_t)nk * (h->pr.p.nth > 0 ? h->pr.p.nth : 1);
+  float* wd = nullptr;
+  double* td = nullptr;
+  HIPCHK(h, hipMalloc(&wd, wb));
+  hipError_t e = hipMalloc(&td, tb);
+  if (e != hipSuccess) {
+    (void)hipFree(wd);
+    return fail_hip(h, "hipMalloc", e);
+  }
+  e = launch_draws(h->pr, t, k0, nk, j0, nj, wd, theta_out ? td : nullptr, h->b, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(w_out, wd, wb, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess && theta_out && h->pr.p.nth > 0)
+    e = hipMemcpyAsync(theta_out, td, sizeof(double) * (size_t)nk * h->pr.p.nth,
+                       hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(wd);
+  (void)hipFree(td);
+  if (e != hipSuccess) return fail_hip(h, "rg_draws", e);
+  return RG_OK;
+}
+
+int rg_trajectory(rg_handle* h, const double* x, double v, const int32_t* k_list, int32_t nk,
+                  int32_t precision, double* traj) {
+  if (!h) return RG_E_INVAL;
+  if (!x || !k_list || !traj || nk < 1) return fail(h, RG_E_INVAL, "bad arguments");
+  if (precision != RG_PREC_F32_RECHECK && precision != RG_PREC_F64)
+    return fail(h, RG_E_INVAL, "bad precision");
+  if (!finite_array(x, h->pr.p.n) || !std::isfinite(v)) return fail(h, RG_E_INVAL, "non-finite input");
+  for (int i = 0; i < nk; ++i)
+    if (k_list[i] < 0 || k_list[i] >= h->pr.s.N) return fail(h, RG_E_INVAL, "scenario out of range");
+  int rc = ensure_workspace(h);
+  if (rc) return rc;
+  if ((rc = upload_state(h, x, v, v))) return rc;
+  if ((rc = ensure_draws(h))) return rc;
+  const size_t tb = sizeof(double) * (size_t)nk * (h->pr.H + 1) * h->pr.p.n;
+  double* td = nullptr;
+  int32_t* kd = nullptr;
+  HIPCHK(h, hipMalloc(&td, tb));
+  hipError_t e = hipMalloc(&kd, sizeof(int32_t) * nk);
+  if (e != hipSuccess) {
+    (void)hipFree(td);
+    return fail_hip(h, "hipMalloc", e);
+  }
+  e = hipMemcpyAsync(kd, k_list, sizeof(int32_t) * nk, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = launch_trajectory(h->pr, v, kd, nk, precision, td, h->b, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(traj, td, tb, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(td);
+  (void)hipFree(kd);
+  if (e != hipSuccess) return fail_hip(h, "rg_trajectory", e);
+  return RG_OK;
+}
+
+const char* rg_status_string(int status) {
+  switch (status) {
+    case RG_OK: return "ok";
+    case RG_S_INFEASIBLE: return "no admissible candidate (kappa = 0, v = v_prev)";
+    case RG_S_FALLBACK: return "Newton search fell back to bisection";
+    case RG_E_INVAL: return "invalid argument";
+    case RG_E_NOMEM: return "out of memory";
+    case RG_E_HIP: return "HIP runtime error";
+    case RG_E_NOTSUP: return "not supported";
+    case RG_E_STATE: return "invalid handle state";
+    default: return "unknown status";
+  }
+}
+
+const char* rg_last_error(const rg_handle* h) {
+  if (!h) return g_create_error.c_str();
+  return h->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,351 @@
+// Device arithmetic of the governor: counter-based draws, the two plants,
+// the RK4 step, constraint margins and ordered reduction keys.
+#pragma once
+
+#include <math.h>
+
+#include "rg_internal.hpp"
+
+namespace rg {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// multiplies whose high halves are XORed with the other counter words and the
+// round key; the key advances by the golden-ratio / sqrt(3) Weyl constants.
+// ---------------------------------------------------------------------------
+struct Words {
+  uint32_t v[4];
+};
+
+__device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t y0 = hi1 ^ c1 ^ k0;
+    const uint32_t y2 = hi0 ^ c3 ^ k1;
+    c0 = y0;
+    c1 = lo1;
+    c2 = y2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  Words w;
+  w.v[0] = c0;
+  w.v[1] = c1;
+  w.v[2] = c2;
+  w.v[3] = c3;
+  return w;
+}
+
+// Canonical box draw: u = top 24 bits * 2^-24 (exact in binary32), then one
+// correctly rounded binary32 FMA span * u + lo.
+__device__ __forceinline__ float box_draw(uint32_t word, float lo32, float span32) {
+  const float u = (float)(word >> 8) * 0x1p-24f;
+  return __fmaf_rn(span32, u, lo32);
+}
+
+// ---------------------------------------------------------------------------
+// Ordered keys: unsigned integers whose order is the order of the floats, so
+// a device-wide minimum is a single integer atomicMin (exact and order-free).
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ uint32_t ord32(float f) {
+  uint32_t b;
+  __builtin_memcpy(&b, &f, 4);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__host__ __device__ __forceinline__ float unord32(uint32_t o) {
+  const uint32_t b = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+  float f;
+  __builtin_memcpy(&f, &b, 4);
+  return f;
+}
+__host__ __device__ __forceinline__ unsigned long long ord64(double d) {
+  unsigned long long b;
+  __builtin_memcpy(&b, &d, 8);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__host__ __device__ __forceinline__ double unord64(unsigned long long o) {
+  const unsigned long long b = (o >> 63) ? (o & 0x7fffffffffffffffull) : ~o;
+  double d;
+  __builtin_memcpy(&d, &b, 8);
+  return d;
+}
+
+// Margin reduction key of one lane: FP32 rollouts carry the scenario index in
+// the low word (ties resolve to the lowest scenario); FP64 rollouts use the
+// full ordered double.
+__device__ __forceinline__ unsigned long long lane_key(float m, int k) {
+  return ((unsigned long long)ord32(m) << 32) | (uint32_t)k;
+}
+__device__ __forceinline__ unsigned long long lane_key(double m, int) { return ord64(m); }
+__device__ __forceinline__ double key_margin(unsigned long long key, int precision) {
+  return precision == 0 ? (double)unord32((uint32_t)(key >> 32)) : unord64(key);
+}
+
+template <class T>
+__device__ __forceinline__ T t_inf() {
+  return (T)INFINITY;
+}
+
+__device__ __forceinline__ float t_tanh(float z) { return tanhf(z); }
+__device__ __forceinline__ double t_tanh(double z) { return tanh(z); }
+__device__ __forceinline__ float t_sqrt(float z) { return __builtin_sqrtf(z); }
+__device__ __forceinline__ double t_sqrt(double z) { return sqrt(z); }
+__device__ __forceinline__ float t_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double t_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// ---------------------------------------------------------------------------
+// Plants.  Coef holds the uniform coefficients (kernel arguments, so scalar
+// registers); Lane holds what is fixed for one rollout (set-point, sampled
+// coefficients).  force() is the part of the derivative that is constant over
+// one RK4 step.
+// ---------------------------------------------------------------------------
+template <int KIND, class T>
+struct Plant;
+
+// LQ4: xdot = A x + B v + G (x.*x) + E w,  y = C x.
+template <class T>
+struct Plant<1, T> {
+  static constexpr int n = 4, nw = 2, ny = 2, nth = 0;
+  struct Coef {
+    T A[16], B[4], G[16], E[8], C[8];
+  };
+  struct Lane {
+    T bv[4];
+  };
+  __host__ __device__ static const T* nominal_theta(const Coef&) { return nullptr; }
+  static void load(Coef& c, const double* s) {
+    for (int i = 0; i < 16; ++i) c.A[i] = (T)s[i];
+    for (int i = 0; i < 4; ++i) c.B[i] = (T)s[16 + i];
+    for (int i = 0; i < 16; ++i) c.G[i] = (T)s[20 + i];
+    for (int i = 0; i < 8; ++i) c.E[i] = (T)s[36 + i];
+    for (int i = 0; i < 8; ++i) c.C[i] = (T)s[44 + i];
+  }
+  __device__ static void lane_init(const Coef& c, const T*, T v, Lane& L) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) L.bv[i] = c.B[i] * v;
+  }
+  __device__ static void force(const Coef& c, const Lane& L, const T* w, T* s) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s[i] = t_fma(c.E[2 * i + 1], w[1], t_fma(c.E[2 * i], w[0], L.bv[i]));
+  }
+  __device__ static void force0(const Coef&, const Lane& L, T* s) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s[i] = L.bv[i];
+  }
+  __device__ static void deriv(const Coef& c, const Lane&, const T* s, const T* x, T* xd) {
+    T q[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) q[j] = x[j] * x[j];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      T a = s[i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a = t_fma(c.A[4 * i + j], x[j], a);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a = t_fma(c.G[4 * i + j], q[j], a);
+      xd[i] = a;
+    }
+  }
+  __device__ static void post(const Coef& c, const T* w, T* x) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] = x[i] + (c.E[2 * i] * w[0] + c.E[2 * i + 1] * w[1]);
+  }
+  __device__ static void output(const Coef& c, const Lane&, const T* x, T* y) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      T a = c.C[4 * i] * x[0];
+#pragma unroll
+      for (int j = 1; j < 4; ++j) a = t_fma(c.C[4 * i + j], x[j], a);
+      y[i] = a;
+    }
+  }
+  // Equilibrium helpers (FP64 only): initial guess solves A x = -B v.
+  __device__ static void eq_guess(const Coef& c, T v, T* x, T* J) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) J[i] = c.A[i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] = -(c.B[i] * v);
+  }
+  __device__ static bool eq_guess_needs_solve() { return true; }
+  __device__ static void jacobian(const Coef& c, const T* x, T, T* J) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) J[4 * i + j] = c.A[4 * i + j] + 2 * c.G[4 * i + j] * x[j];
+  }
+};
+
+// FC9: volumes p1..p6 (x0..x5) fed by compressor speed w1 (x6), speeds w2, w3
+// (x7, x8):  z = x - xbar, p7 = p_amb,
+//   q0 = c_q0 w1,  q_l = k_l sqrt(max(p_l - p_{l+1}, 0)),
+//   xdot_i = -a_i z_i + (W tanh z)_i + w_i + phi_i,
+//   phi_l = q_{l-1} - q_l (l = 1..6), phi_7 = b1 v - mu1 w1 (p1 - p1ref),
+//   phi_8 = b2 v w1, phi_9 = b3 v - mu2 w3 v;
+//   y = (c_q0 w1 / (d0 + d1 v), p1, w1).
+template <class T>
+struct Plant<2, T> {
+  static constexpr int n = 9, nw = 9, ny = 3, nth = 20;
+  struct Coef {
+    T W[81], xbar[9], thnom[20];
+    T c_q0, p_amb, d0, d1, p1ref;
+  };
+  struct Lane {
+    T a[9], kq[6], b[3], mu[2];
+    T v, y1s;
+  };
+  __host__ __device__ static const T* nominal_theta(const Coef& c) { return c.thnom; }
+  static void load(Coef& c, const double* s) {
+    for (int i = 0; i < 81; ++i) c.W[i] = (T)s[i];
+    for (int i = 0; i < 9; ++i) c.xbar[i] = (T)s[81 + i];
+    for (int i = 0; i < 20; ++i) c.thnom[i] = (T)s[90 + i];
+    c.c_q0 = (T)s[110];
+    c.p_amb = (T)s[111];
+    c.d0 = (T)s[112];
+    c.d1 = (T)s[113];
+    c.p1ref = (T)s[114];
+  }
+  __device__ static void lane_init(const Coef& c, const T* th, T v, Lane& L) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) L.a[i] = th[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) L.kq[i] = th[9 + i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) L.b[i] = th[15 + i];
+    L.mu[0] = th[18];
+    L.mu[1] = th[19];
+    L.v = v;
+    L.y1s = c.c_q0 / (c.d0 + c.d1 * v);
+  }
+  __device__ static void force(const Coef&, const Lane&, const T* w, T* s) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) s[i] = w[i];
+  }
+  __device__ static void force0(const Coef&, const Lane&, T* s) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) s[i] = (T)0;
+  }
+  __device__ static void deriv(const Coef& c, const Lane& L, const T* s, const T* x, T* xd) {
+    T z[9], tz[9], q[7];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      z[j] = x[j] - c.xbar[j];
+      tz[j] = t_tanh(z[j]);
+    }
+    q[0] = c.c_q0 * x[6];
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+      const T dn = (l < 5) ? x[l + 1] : c.p_amb;
+      const T dp = x[l] - dn;
+      q[l + 1] = L.kq[l] * t_sqrt(dp > (T)0 ? dp : (T)0);
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      T a = t_fma(-L.a[i], z[i], s[i]);
+#pragma unroll
+      for (int j = 0; j < 9; ++j) a = t_fma(c.W[9 * i + j], tz[j], a);
+      T phi;
+      if (i < 6) phi = q[i] - q[i + 1];
+      else if (i == 6) phi = L.b[0] * L.v - L.mu[0] * x[6] * (x[0] - c.p1ref);
+      else if (i == 7) phi = L.b[1] * L.v * x[6];
+      else phi = L.b[2] * L.v - L.mu[1] * x[8] * L.v;
+      xd[i] = a + phi;
+    }
+  }
+  __device__ static void post(const Coef&, const T* w, T* x) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) x[i] = x[i] + w[i];
+  }
+  __device__ static void output(const Coef&, const Lane& L, const T* x, T* y) {
+    y[0] = L.y1s * x[6];
+    y[1] = x[0];
+    y[2] = x[6];
+  }
+  __device__ static void eq_guess(const Coef& c, T, T* x, T*) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) x[i] = c.xbar[i];
+  }
+  __device__ static bool eq_guess_needs_solve() { return false; }
+  // df/dx at nominal theta, w = 0.
+  __device__ static void jacobian(const Coef& c, const T* x, T v, T* J) {
+    const T* a = c.thnom;
+    const T* kq = c.thnom + 9;
+    const T* b = c.thnom + 15;
+    const T* mu = c.thnom + 18;
+    for (int j = 0; j < 9; ++j) {
+      const T tj = t_tanh(x[j] - c.xbar[j]);
+      const T dj = 1 - tj * tj;
+      for (int i = 0; i < 9; ++i) J[9 * i + j] = c.W[9 * i + j] * dj;
+    }
+    for (int i = 0; i < 9; ++i) J[9 * i + i] -= a[i];
+    J[0 * 9 + 6] += c.c_q0;  // q0 enters phi_1
+    for (int l = 0; l < 6; ++l) {
+      const T dn = (l < 5) ? x[l + 1] : c.p_amb;
+      const T dp = x[l] - dn;
+      const T d = dp > 0 ? kq[l] / (2 * t_sqrt(dp)) : (T)0;  // dq_{l+1}/dp_l
+      J[9 * l + l] -= d;
+      if (l < 5) {
+        J[9 * l + l + 1] += d;
+        J[9 * (l + 1) + l] += d;
+        J[9 * (l + 1) + l + 1] -= d;
+      }
+    }
+    J[9 * 6 + 6] -= mu[0] * (x[0] - c.p1ref);
+    J[9 * 6 + 0] -= mu[0] * x[6];
+    J[9 * 7 + 6] += b[1] * v;
+    J[9 * 8 + 8] -= mu[1] * v;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Classical RK4 step with the step forcing s held: the stage increments are
+// accumulated as k1 + 2 k2 + 2 k3 + k4.
+// ---------------------------------------------------------------------------
+template <int KIND, class T>
+__device__ __forceinline__ void rk4_step(const typename Plant<KIND, T>::Coef& c,
+                                         const typename Plant<KIND, T>::Lane& L, const T* s,
+                                         T h, T hh, T h6, T* x) {
+  using P = Plant<KIND, T>;
+  T k[P::n], acc[P::n], xs[P::n];
+  P::deriv(c, L, s, x, k);
+#pragma unroll
+  for (int i = 0; i < P::n; ++i) {
+    acc[i] = k[i];
+    xs[i] = t_fma(hh, k[i], x[i]);
+  }
+  P::deriv(c, L, s, xs, k);
+#pragma unroll
+  for (int i = 0; i < P::n; ++i) {
+    acc[i] = t_fma((T)2, k[i], acc[i]);
+    xs[i] = t_fma(hh, k[i], x[i]);
+  }
+  P::deriv(c, L, s, xs, k);
+#pragma unroll
+  for (int i = 0; i < P::n; ++i) {
+    acc[i] = t_fma((T)2, k[i], acc[i]);
+    xs[i] = t_fma(h, k[i], x[i]);
+  }
+  P::deriv(c, L, s, xs, k);
+#pragma unroll
+  for (int i = 0; i < P::n; ++i) x[i] = t_fma(h6, acc[i] + k[i], x[i]);
+}
+
+// Margin over kNC padded rows (padding rows: F = 0, g = +inf).
+template <int NY, class T>
+__device__ __forceinline__ T margin_rows(const T* F, const T* g, const T* y) {
+  T best = t_inf<T>();
+#pragma unroll
+  for (int r = 0; r < kNC; ++r) {
+    T fy = F[r * NY] * y[0];
+#pragma unroll
+    for (int i = 1; i < NY; ++i) fy = t_fma(F[r * NY + i], y[i], fy);
+    const T m = g[r] - fy;
+    best = (m < best || m != m) ? m : best;  // a NaN row stays NaN (caller maps it to -inf)
+  }
+  return best;
+}
+
+}  // namespace rg

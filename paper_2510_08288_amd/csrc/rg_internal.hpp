@@ -1,0 +1,139 @@
+// Internal layout shared by the HIP kernels and the host side of librg.
+// Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rg {
+
+constexpr int kCMax = 128;   // candidates per device round
+constexpr int kMaxN = 9;     // state dimension
+constexpr int kMaxW = 9;     // disturbance dimension
+constexpr int kMaxY = 3;     // output dimension
+constexpr int kNC = 4;       // constraint rows evaluated per step (unused rows padded)
+constexpr int kMaxTh = 20;   // uncertain coefficients
+constexpr int kMaxCoef = 115;
+
+enum Mode { kBisect = 0, kGrid = 1 };
+
+// Per-handle control state kept in device memory so that whole RG steps (and
+// closed loops) can be enqueued or graph-captured without host round trips.
+struct DevState {
+  double x[kMaxN];      // x_t
+  double v_prev;        // v_{t-1}
+  double r;             // r_t
+  uint32_t t;           // RG step counter (selects the draws)
+  int32_t cl_index;     // closed loop: index of the current step in the chunk
+};
+
+// Search state of one RG step.  Candidate c of the current round has set-point
+// v[c]; tree nodes of a speculative bisection round keep their bracket in
+// a_lo/a_hi so that node kappa = (a_lo + a_hi) / 2 reproduces the arithmetic
+// of sequential bisection exactly.
+struct DevSearch {
+  // configuration
+  int32_t mode, K, depth, M, refine, precision;
+  int32_t ss_check, n_c, ny;
+  double eps;
+  double g[kNC];        // constraint right-hand sides (padded rows +inf)
+  double F[kNC * kMaxY];
+  // per-step state
+  double lo, hi;
+  int32_t round, halvings, goal, done, found, status;
+  int32_t n_cand, probe, tree_base, tree_depth;
+  double kappa_res, v_res, worst_res;
+  int32_t cand_total, rechecks_total, rounds_total, passes_alg1;
+  // per candidate of the current round
+  double kappa[kCMax];
+  double v[kCMax];
+  double mss[kCMax];
+  double a_lo[kCMax], a_hi[kCMax];
+  unsigned long long key_all[kCMax];  // min over lanes of the FP32/FP64 rollout margin key
+  unsigned long long key_far[kCMax];  // same, over lanes outside the recheck band
+  unsigned long long key64[kCMax];    // min over FP64-rechecked lanes (ordered double)
+  int32_t dead[kCMax];                // a lane fell below -band or went non-finite
+  int32_t fail64[kCMax];              // a rechecked lane has an FP64 margin < 0
+  int32_t n_recheck;                  // entries in the recheck list this round
+  unsigned long long lane_steps;      // RK4 steps executed by rollout lanes this RG step
+};
+
+// Result record of one RG step.
+struct DevResult {
+  double kappa, v, worst;
+  int32_t status, rounds, candidates, rechecks, passes_alg1;
+  uint32_t t;
+  unsigned long long lane_steps;
+};
+
+struct PlantDesc {
+  int32_t kind, n, nw, ny, nth;
+  double coeffs[kMaxCoef];
+};
+
+struct ConsDesc {
+  int32_t n_c;
+  double F[kNC * kMaxY];  // row-major n_c x n_y, rows >= n_c zero
+  double g[kNC];          // rows >= n_c are +inf (never binding)
+  double eps;
+  int32_t ss_check;
+};
+
+struct ScenDesc {
+  int32_t N;
+  uint32_t seed, instance;
+  double wlo[kMaxW], whi[kMaxW];
+  double theta_rel;
+  int32_t inject, rng_mode;
+};
+
+// Device buffers of one handle (all inside one workspace allocation).
+struct DevBuffers {
+  DevState* st;
+  DevSearch* srch;
+  DevResult* res;          // [max_T] results of a closed-loop chunk (entry 0 for rg_step)
+  double* r_seq;           // [max_T]
+  double* x_hist;          // [(max_T + 1) * n]
+  float* wbuf;             // [H][nw][N] streamed draws
+  float* thbuf;            // [nth][N] per-scenario coefficient factors
+  int2* rlist;             // [cmax_round * N] recheck list (candidate, scenario)
+  float* per_m;            // [cmax_round * N] per-scenario margins (rg_margin)
+  int32_t* per_j;          // [cmax_round * N]
+  double* scratch;         // small staging area (trajectories, draws)
+  size_t scratch_bytes;
+};
+
+struct LaunchCfg {
+  int block;               // threads per rollout workgroup
+  int cmax_round;          // largest candidate count of any round
+  int rounds;              // device rounds per RG step
+};
+
+// ---- launchers implemented in rg_kernels.hip --------------------------------
+// Everything a launch needs about the problem (host copy).
+struct Problem {
+  PlantDesc p;
+  ScenDesc s;
+  ConsDesc c;
+  int H;
+  double dt;
+};
+
+hipError_t launch_gen(const Problem& pr, const DevBuffers& b, hipStream_t st);
+hipError_t launch_setup(const Problem& pr, const DevBuffers& b, int closed_loop, hipStream_t st);
+hipError_t launch_setup_list(const Problem& pr, const DevBuffers& b, int M, hipStream_t st);
+hipError_t launch_rollout(const Problem& pr, double band, int precision, int early_exit, int record,
+                          const LaunchCfg& cfg, const DevBuffers& b, hipStream_t st);
+hipError_t launch_recheck(const Problem& pr, int early_exit, const LaunchCfg& cfg,
+                          const DevBuffers& b, hipStream_t st);
+hipError_t launch_decide(const Problem& pr, const DevBuffers& b, hipStream_t st);
+hipError_t launch_finalize(const Problem& pr, int closed_loop, const DevBuffers& b,
+                           hipStream_t st);
+hipError_t launch_collect(const DevBuffers& b, int M, double* out_dev, hipStream_t st);
+hipError_t launch_draws(const Problem& pr, uint32_t t, int k0, int nk, int j0, int nj,
+                        float* w_dev, double* th_dev, const DevBuffers& b, hipStream_t st);
+hipError_t launch_trajectory(const Problem& pr, double v, const int32_t* k_list_dev, int nk,
+                             int precision, double* traj_dev, const DevBuffers& b,
+                             hipStream_t st);
+
+}  // namespace rg

@@ -1,0 +1,870 @@
+// HIP kernels of the robust reference governor for gfx950 (wave64).
+//
+// Per RG step the host enqueues (or replays from a graph):
+//   gen       scenario draws d_j^k for this step into device memory (Sec. II-C:
+//             one draw set per time step, shared by every candidate)
+//   setup     round-0 candidates: kappa = 1 and the first levels of the
+//             bisection tree (Alg. 1), or the M-point grid (Alg. 3)
+//   R x { rollout   one lane per (candidate, scenario): RK4 prediction over
+//                   j = 0..H with the constraint margin folded into a running
+//                   minimum (Eq. (3) constraint rows; Alg. 3 parallel steps 2-3)
+//         recheck   FP64 re-simulation of lanes whose FP32 margin is within
+//                   the band of zero
+//         decide    verdicts, bracket update, next round's candidates }
+//   finalize  result record; in closed loop the true-plant step x_{t+1}
+//
+// No step reads back to the host.  All search state lives in DevSearch.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <type_traits>
+
+#include "rg_device.hpp"
+
+namespace rg {
+
+// ---------------------------------------------------------------------------
+// Argument blocks
+// ---------------------------------------------------------------------------
+template <int KIND, class T>
+struct RollArgs {
+  using P = Plant<KIND, T>;
+  typename P::Coef pc;
+  T F[kNC * P::ny];
+  T g[kNC];
+  T h, hh, h6;
+  T band;
+  int H, N;
+  int early, record, inject;
+  uint32_t seed, inst;
+  float wlo[P::nw], wspan[P::nw];
+  float thlo, thspan;
+  const float* wbuf;
+  const float* thbuf;
+  const DevState* st;
+  DevSearch* srch;
+  float* per_m;
+  int32_t* per_j;
+  int2* rlist;
+};
+
+template <int KIND>
+struct CtlArgs {
+  typename Plant<KIND, double>::Coef pc;
+  DevState* st;
+  DevSearch* srch;
+  const double* r_seq;
+  int closed_loop;
+};
+
+// ---------------------------------------------------------------------------
+// Draws
+// ---------------------------------------------------------------------------
+template <int NW>
+__device__ __forceinline__ void draw_w(uint32_t seed, uint32_t inst, uint32_t t, uint32_t tag,
+                                       uint32_t k, uint32_t j, const float* lo, const float* span,
+                                       float* w) {
+#pragma unroll
+  for (int blk = 0; blk < (NW + 3) / 4; ++blk) {
+    const Words r = philox10(k, j, t, (tag << 16) | (uint32_t)blk, seed, inst);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = 4 * blk + q;
+      if (c < NW) w[c] = box_draw(r.v[q], lo[c], span[c]);
+    }
+  }
+}
+
+template <int NTH>
+__device__ __forceinline__ void draw_theta_factor(uint32_t seed, uint32_t inst, uint32_t t,
+                                                  uint32_t k, float lo, float span, float* f) {
+#pragma unroll
+  for (int blk = 0; blk < (NTH + 3) / 4; ++blk) {
+    const Words r = philox10(k, 0u, t, (1u << 16) | (uint32_t)blk, seed, inst);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = 4 * blk + q;
+      if (c < NTH) f[c] = box_draw(r.v[q], lo, span);
+    }
+  }
+}
+
+// Streamed draws: w[(j * nw + c) * N + k] (consecutive scenarios contiguous, so
+// a wave's loads of one step coalesce), theta factors f[c * N + k].
+template <int KIND>
+__global__ void __launch_bounds__(256) k_gen(RollArgs<KIND, float> a, float* wbuf, float* thbuf) {
+  using P = Plant<KIND, float>;
+  const uint32_t t = a.st->t;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t nwork = (size_t)a.H * a.N;
+  if (gid < nwork) {
+    const int j = (int)(gid / a.N);
+    const int k = (int)(gid - (size_t)j * a.N);
+    float w[P::nw];
+    draw_w<P::nw>(a.seed, a.inst, t, 0u, (uint32_t)k, (uint32_t)j, a.wlo, a.wspan, w);
+#pragma unroll
+    for (int c = 0; c < P::nw; ++c) wbuf[((size_t)j * P::nw + c) * a.N + k] = w[c];
+  } else if (P::nth > 0 && gid < nwork + (size_t)a.N) {
+    const int k = (int)(gid - nwork);
+    float f[P::nth > 0 ? P::nth : 1];
+    draw_theta_factor<P::nth>(a.seed, a.inst, t, (uint32_t)k, a.thlo, a.thspan, f);
+#pragma unroll
+    for (int c = 0; c < P::nth; ++c) thbuf[(size_t)c * a.N + k] = f[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One scenario rollout with the fused running-minimum margin.
+// stop_flag (nullable) is polled every 32 steps; early != 0 also stops the
+// lane once its minimum is below -band.  traj (nullable) receives states.
+// ---------------------------------------------------------------------------
+template <int KIND, class T, int RNG, int INJ>
+__device__ __forceinline__ T rollout_lane(const RollArgs<KIND, T>& a, T v, int k, uint32_t t,
+                                          const int32_t* stop_flag, int& jbest, int& nsteps,
+                                          double* traj) {
+  using P = Plant<KIND, T>;
+  T th[P::nth > 0 ? P::nth : 1];
+  if constexpr (P::nth > 0) {
+    float f[P::nth];
+    if (RNG == 0) {
+#pragma unroll
+      for (int c = 0; c < P::nth; ++c) f[c] = a.thbuf[(size_t)c * a.N + k];
+    } else {
+      draw_theta_factor<P::nth>(a.seed, a.inst, t, (uint32_t)k, a.thlo, a.thspan, f);
+    }
+#pragma unroll
+    for (int c = 0; c < P::nth; ++c) th[c] = a.pc.thnom[c] * (T)f[c];
+  }
+  typename P::Lane L;
+  P::lane_init(a.pc, th, v, L);
+  T x[P::n];
+#pragma unroll
+  for (int i = 0; i < P::n; ++i) x[i] = (T)a.st->x[i];
+  T y[P::ny];
+  P::output(a.pc, L, x, y);
+  T best = margin_rows<P::ny>(a.F, a.g, y);
+  if (best != best) best = -t_inf<T>();
+  jbest = 0;
+  if (traj) {
+    for (int i = 0; i < P::n; ++i) traj[i] = (double)x[i];
+  }
+  float wc[P::nw], wn[P::nw];
+  auto load = [&](int j, float* w) {
+    if (RNG == 0) {
+#pragma unroll
+      for (int c = 0; c < P::nw; ++c) w[c] = a.wbuf[((size_t)j * P::nw + c) * a.N + k];
+    } else {
+      draw_w<P::nw>(a.seed, a.inst, t, 0u, (uint32_t)k, (uint32_t)j, a.wlo, a.wspan, w);
+    }
+  };
+  if (a.H > 0) load(0, wc);
+  int j = 0;
+  for (; j < a.H; ++j) {
+    if (j + 1 < a.H) load(j + 1, wn);
+    T s[P::n];
+    if (INJ == 0) {
+      T wt[P::nw];
+#pragma unroll
+      for (int c = 0; c < P::nw; ++c) wt[c] = (T)wc[c];
+      P::force(a.pc, L, wt, s);
+    } else {
+      P::force0(a.pc, L, s);
+    }
+    rk4_step<KIND, T>(a.pc, L, s, a.h, a.hh, a.h6, x);
+    if (INJ == 1) {
+      T wt[P::nw];
+#pragma unroll
+      for (int c = 0; c < P::nw; ++c) wt[c] = (T)wc[c];
+      P::post(a.pc, wt, x);
+    }
+    P::output(a.pc, L, x, y);
+    T m = margin_rows<P::ny>(a.F, a.g, y);
+    m = (m == m) ? m : -t_inf<T>();
+    if (m < best) {
+      best = m;
+      jbest = j + 1;
+    }
+    if (traj) {
+      for (int i = 0; i < P::n; ++i) traj[(size_t)(j + 1) * P::n + i] = (double)x[i];
+    }
+    if (a.early) {
+      if (best < -a.band) {
+        ++j;
+        break;
+      }
+      if ((j & 31) == 31 && stop_flag &&
+          __hip_atomic_load(stop_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        ++j;
+        break;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < P::nw; ++c) wc[c] = wn[c];
+  }
+  nsteps = j;
+  bool finite = true;
+#pragma unroll
+  for (int i = 0; i < P::n; ++i) finite = finite && (x[i] - x[i] == (T)0);
+  if (!finite) best = -t_inf<T>();
+  return best;
+}
+
+// Wave64 + workgroup minimum of a 64-bit key; returns the minimum in thread 0.
+__device__ __forceinline__ unsigned long long block_min_u64(unsigned long long v,
+                                                             unsigned long long* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t lo = __shfl_xor((uint32_t)v, off);
+    const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), off);
+    const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+    v = o < v ? o : v;
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 1; i < nw; ++i) v = sh[i] < v ? sh[i] : v;
+  }
+  __syncthreads();
+  return v;
+}
+
+// Main rollout kernel: blockIdx.y = candidate of the round, blockIdx.x * block
+// + threadIdx.x = scenario.
+template <int KIND, class T, int RNG, int INJ>
+__global__ void __launch_bounds__(256) k_rollout(const RollArgs<KIND, T> a) {
+  DevSearch* S = a.srch;
+  const int c = blockIdx.y;
+  if (S->done || c >= S->n_cand) return;  // uniform over the workgroup
+  __shared__ unsigned long long sh[16];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t t = a.st->t;
+  T m = t_inf<T>();
+  int jb = 0, ns = 0;
+  if (k < a.N) {
+    m = rollout_lane<KIND, T, RNG, INJ>(a, (T)S->v[c], k, t, a.early ? &S->dead[c] : nullptr,
+                                        jb, ns, nullptr);
+    if (a.record) {
+      a.per_m[(size_t)c * a.N + k] = (float)m;
+      a.per_j[(size_t)c * a.N + k] = jb;
+    }
+    if (m < -a.band) {
+      __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (m < a.band) {
+      const int idx = atomicAdd(&S->n_recheck, 1);
+      a.rlist[idx] = make_int2(c, k);
+    }
+  }
+  const unsigned long long key = lane_key(m, k);
+  const unsigned long long kall = block_min_u64(key, sh);
+  const unsigned long long kfar = block_min_u64((m >= a.band) ? key : ~0ull, sh);
+  // executed steps: wave sum, one atomic per wave
+  int wsum = ns;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off);
+  if ((threadIdx.x & 63) == 0) atomicAdd(&S->lane_steps, (unsigned long long)wsum);
+  if (threadIdx.x == 0) {
+    atomicMin(&S->key_all[c], kall);
+    if (kfar != ~0ull) atomicMin(&S->key_far[c], kfar);
+  }
+}
+
+// FP64 re-simulation of the near-band list.
+template <int KIND, int RNG, int INJ>
+__global__ void __launch_bounds__(64) k_recheck(const RollArgs<KIND, double> a) {
+  DevSearch* S = a.srch;
+  if (S->done) return;
+  const int n = S->n_recheck;
+  const uint32_t t = a.st->t;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int2 e = a.rlist[i];
+    const int c = e.x, k = e.y;
+    if (a.early && (__hip_atomic_load(&S->dead[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                    __hip_atomic_load(&S->fail64[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
+      continue;
+    int jb = 0, ns = 0;
+    const double m = rollout_lane<KIND, double, RNG, INJ>(a, S->v[c], k, t,
+                                                          a.early ? &S->fail64[c] : nullptr, jb,
+                                                          ns, nullptr);
+    atomicMin(&S->key64[c], ord64(m));
+    if (m < 0.0) __hip_atomic_store(&S->fail64[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Candidates, steady state, verdicts
+// ---------------------------------------------------------------------------
+
+// Eq. (2) with v = r exactly at kappa = 1; no fused multiply-add, so the value
+// is the two-rounding expression v_prev + kappa (r - v_prev).
+__device__ __forceinline__ double cand_v(double kappa, double r, double v_prev) {
+  if (kappa == 1.0) return r;
+  return __dadd_rn(v_prev, __dmul_rn(kappa, __dsub_rn(r, v_prev)));
+}
+
+__device__ __forceinline__ double midpoint(double a, double b) {
+  return __dmul_rn(__dadd_rn(a, b), 0.5);
+}
+
+template <int NN>
+__device__ bool dense_solve(double* J, double* b) {
+  for (int c = 0; c < NN; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < NN; ++r)
+      if (fabs(J[r * NN + c]) > fabs(J[piv * NN + c])) piv = r;
+    if (!(fabs(J[piv * NN + c]) > 1e-300)) return false;
+    if (piv != c) {
+      for (int q = 0; q < NN; ++q) {
+        const double tmp = J[c * NN + q];
+        J[c * NN + q] = J[piv * NN + q];
+        J[piv * NN + q] = tmp;
+      }
+      const double tmp = b[c];
+      b[c] = b[piv];
+      b[piv] = tmp;
+    }
+    for (int r = c + 1; r < NN; ++r) {
+      const double f = J[r * NN + c] / J[c * NN + c];
+      for (int q = c; q < NN; ++q) J[r * NN + q] -= f * J[c * NN + q];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int c = NN - 1; c >= 0; --c) {
+    double s = b[c];
+    for (int q = c + 1; q < NN; ++q) s -= J[c * NN + q] * b[q];
+    b[c] = s / J[c * NN + c];
+  }
+  return true;
+}
+
+// Tightened steady-state margin min_r (g_r - eps |g_r| - F_r y_ss(v)) with the
+// equilibrium from Newton's method (nominal coefficients, w = 0); failure to
+// reach ||f||_inf <= 1e-12 within 50 iterations gives -inf.
+template <int KIND>
+__device__ double steady_margin(const typename Plant<KIND, double>::Coef& pc, const DevSearch* S,
+                                double v) {
+  using P = Plant<KIND, double>;
+  if (!S->ss_check) return INFINITY;
+  double x[P::n], f[P::n], J[P::n * P::n], s0[P::n];
+  P::eq_guess(pc, v, x, J);
+  if (P::eq_guess_needs_solve()) {
+    if (!dense_solve<P::n>(J, x)) return -INFINITY;
+  }
+  typename P::Lane L;
+  P::lane_init(pc, P::nominal_theta(pc), v, L);
+  P::force0(pc, L, s0);
+  bool ok = false;
+  for (int it = 0; it <= 50; ++it) {
+    P::deriv(pc, L, s0, x, f);
+    double nrm = 0.0;
+    for (int i = 0; i < P::n; ++i) {
+      if (!isfinite(f[i])) return -INFINITY;
+      nrm = fmax(nrm, fabs(f[i]));
+    }
+    if (nrm <= 1e-12) {
+      ok = true;
+      break;
+    }
+    if (it == 50) break;
+    P::jacobian(pc, x, v, J);
+    for (int i = 0; i < P::n; ++i) f[i] = -f[i];
+    if (!dense_solve<P::n>(J, f)) return -INFINITY;
+    for (int i = 0; i < P::n; ++i) x[i] += f[i];
+  }
+  if (!ok) return -INFINITY;
+  double y[P::ny];
+  P::output(pc, L, x, y);
+  double best = INFINITY;
+  for (int r = 0; r < S->n_c; ++r) {
+    double fy = 0.0;
+    for (int i = 0; i < P::ny; ++i) fy += S->F[r * P::ny + i] * y[i];
+    const double gt = __dsub_rn(S->g[r], __dmul_rn(S->eps, fabs(S->g[r])));
+    const double m = gt - fy;
+    best = (m < best || m != m) ? m : best;
+  }
+  return (best == best) ? best : -INFINITY;
+}
+
+__device__ __forceinline__ bool cand_feasible(const DevSearch* S, int c) {
+  return !S->dead[c] && !S->fail64[c] && S->mss[c] >= 0.0;
+}
+
+__device__ __forceinline__ double cand_worst(const DevSearch* S, int c) {
+  double w;
+  const double kall = S->key_all[c] == ~0ull ? INFINITY : key_margin(S->key_all[c], S->precision);
+  if (S->dead[c] || S->key64[c] == ~0ull) {
+    w = kall;
+  } else {
+    const double far = S->key_far[c] == ~0ull ? INFINITY : key_margin(S->key_far[c], S->precision);
+    const double r64 = unord64(S->key64[c]);
+    w = far < r64 ? far : r64;
+  }
+  const double ms = S->mss[c];
+  return (ms < w) ? ms : w;
+}
+
+// Lay out a speculative bisection tree of `depth` levels over (lo, hi) at
+// candidates base.. (breadth-first; node q has children 2q+1 and 2q+2).
+__device__ void build_tree(DevSearch* S, int base, int depth, double lo, double hi) {
+  const int nn = (1 << depth) - 1;
+  S->a_lo[base] = lo;
+  S->a_hi[base] = hi;
+  S->kappa[base] = midpoint(lo, hi);
+  for (int q = 0; q < nn; ++q) {
+    const int c = base + q;
+    const double kq = S->kappa[c];
+    const int l = 2 * q + 1, r = 2 * q + 2;
+    if (l < nn) {
+      S->a_lo[base + l] = S->a_lo[c];
+      S->a_hi[base + l] = kq;
+      S->kappa[base + l] = midpoint(S->a_lo[c], kq);
+    }
+    if (r < nn) {
+      S->a_lo[base + r] = kq;
+      S->a_hi[base + r] = S->a_hi[c];
+      S->kappa[base + r] = midpoint(kq, S->a_hi[c]);
+    }
+  }
+  S->tree_base = base;
+  S->tree_depth = depth;
+}
+
+// Thread-parallel per-candidate preparation: set-points, steady-state margins,
+// reduction accumulators.
+template <int KIND>
+__device__ void prepare_candidates(const CtlArgs<KIND>& a) {
+  DevSearch* S = a.srch;
+  const double r = a.st->r, vp = a.st->v_prev;
+  for (int c = threadIdx.x; c < S->n_cand; c += blockDim.x) {
+    const double v = cand_v(S->kappa[c], r, vp);
+    S->v[c] = v;
+    S->mss[c] = steady_margin<KIND>(a.pc, S, v);
+    S->key_all[c] = ~0ull;
+    S->key_far[c] = ~0ull;
+    S->key64[c] = ~0ull;
+    S->dead[c] = 0;
+    S->fail64[c] = 0;
+  }
+  if (threadIdx.x == 0) S->n_recheck = 0;
+}
+
+// Start of one RG step: round-0 candidates.
+template <int KIND>
+__global__ void __launch_bounds__(128) k_setup(const CtlArgs<KIND> a) {
+  DevSearch* S = a.srch;
+  if (threadIdx.x == 0) {
+    if (a.closed_loop) a.st->r = a.r_seq[a.st->cl_index];
+    S->done = 0;
+    S->found = 0;
+    S->status = 0;
+    S->round = 0;
+    S->halvings = 0;
+    S->lo = 0.0;
+    S->hi = 1.0;
+    S->kappa_res = 0.0;
+    S->v_res = a.st->v_prev;
+    S->worst_res = -INFINITY;
+    S->cand_total = 0;
+    S->rechecks_total = 0;
+    S->rounds_total = 0;
+    S->passes_alg1 = 0;
+    S->lane_steps = 0ull;
+    if (S->mode == kGrid) {
+      const int M = S->M;
+      for (int i = 0; i < M; ++i) S->kappa[i] = (M > 1) ? (double)i / (double)(M - 1) : 1.0;
+      S->n_cand = M;
+      S->probe = 0;
+      S->tree_depth = 0;
+      S->goal = S->refine;
+    } else {
+      S->kappa[0] = 1.0;
+      S->probe = 1;
+      S->goal = S->K;
+      const int d0 = S->K < S->depth ? S->K : S->depth;
+      if (d0 > 0) build_tree(S, 1, d0, 0.0, 1.0);
+      else S->tree_depth = 0;
+      S->n_cand = 1 + ((1 << d0) - 1);
+    }
+  }
+  __syncthreads();
+  prepare_candidates<KIND>(a);
+}
+
+// rg_margin: explicit candidate list (kappa[] already uploaded).
+template <int KIND>
+__global__ void __launch_bounds__(128) k_setup_list(const CtlArgs<KIND> a, int M) {
+  DevSearch* S = a.srch;
+  if (threadIdx.x == 0) {
+    S->done = 0;
+    S->n_cand = M;
+    S->round = 0;
+  }
+  __syncthreads();
+  prepare_candidates<KIND>(a);
+}
+
+// Verdicts of the finished round, bracket update, next round.
+template <int KIND>
+__global__ void __launch_bounds__(128) k_decide(const CtlArgs<KIND> a) {
+  DevSearch* S = a.srch;
+  if (S->done) return;
+  if (threadIdx.x == 0) {
+    S->rounds_total += 1;
+    S->cand_total += S->n_cand;
+    S->rechecks_total += S->n_recheck;
+    bool finished = false;
+    if (S->mode == kGrid && S->round == 0) {
+      const int M = S->M;
+      int istar = -1;
+      for (int i = 0; i < M; ++i)
+        if (cand_feasible(S, i)) istar = i;
+      S->passes_alg1 += M;
+      if (istar < 0) {
+        finished = true;
+      } else {
+        S->found = 1;
+        S->worst_res = cand_worst(S, istar);
+        S->lo = S->kappa[istar];
+        if (istar == M - 1) {
+          finished = true;
+        } else {
+          S->hi = S->kappa[istar + 1];
+          if (S->goal <= 0) finished = true;
+        }
+      }
+    } else {
+      if (S->probe) {
+        S->passes_alg1 += 1;
+        if (cand_feasible(S, 0)) {
+          S->found = 1;
+          S->lo = 1.0;
+          S->worst_res = cand_worst(S, 0);
+          finished = true;
+        }
+      }
+      if (!finished) {
+        int node = 0;
+        for (int l = 0; l < S->tree_depth; ++l) {
+          const int c = S->tree_base + node;
+          S->passes_alg1 += 1;
+          if (cand_feasible(S, c)) {
+            S->lo = S->kappa[c];
+            S->found = 1;
+            S->worst_res = cand_worst(S, c);
+            node = 2 * node + 2;
+          } else {
+            S->hi = S->kappa[c];
+            node = 2 * node + 1;
+          }
+        }
+        S->halvings += S->tree_depth;
+        if (S->halvings >= S->goal) finished = true;
+      }
+    }
+    if (finished) {
+      S->done = 1;
+      S->status = S->found ? 0 : 1;
+      S->kappa_res = S->found ? S->lo : 0.0;
+      S->v_res = S->found ? cand_v(S->kappa_res, a.st->r, a.st->v_prev) : a.st->v_prev;
+      if (!S->found) S->worst_res = -INFINITY;
+    } else {
+      const int rem = S->goal - S->halvings;
+      const int d = rem < S->depth ? rem : S->depth;
+      S->probe = 0;
+      build_tree(S, 0, d, S->lo, S->hi);
+      S->n_cand = (1 << d) - 1;
+      S->round += 1;
+    }
+  }
+  __syncthreads();
+  if (!S->done) prepare_candidates<KIND>(a);
+}
+
+// Result record; in closed loop also the true-plant step (Eq. (4)) in FP64
+// under the tag-2 disturbance, and the hand-over v_prev <- v_t.
+template <int KIND>
+__global__ void k_finalize(const RollArgs<KIND, double> a, DevResult* res, double* x_hist,
+                           int closed_loop) {
+  using P = Plant<KIND, double>;
+  if (threadIdx.x != 0) return;
+  DevSearch* S = a.srch;
+  DevState* st = const_cast<DevState*>(a.st);
+  const int idx = closed_loop ? st->cl_index : 0;
+  DevResult R;
+  R.kappa = S->kappa_res;
+  R.v = S->v_res;
+  R.worst = S->worst_res;
+  R.status = S->status;
+  R.rounds = S->rounds_total;
+  R.candidates = S->cand_total;
+  R.rechecks = S->rechecks_total;
+  R.passes_alg1 = S->passes_alg1;
+  R.t = st->t;
+  R.lane_steps = S->lane_steps;
+  res[idx] = R;
+  if (closed_loop) {
+    float w32[P::nw];
+    draw_w<P::nw>(a.seed, a.inst, st->t, 2u, 0u, 0u, a.wlo, a.wspan, w32);
+    double w[P::nw];
+    for (int c = 0; c < P::nw; ++c) w[c] = (double)w32[c];
+    typename P::Lane L;
+    P::lane_init(a.pc, P::nominal_theta(a.pc), R.v, L);
+    double x[P::n], s[P::n];
+    for (int i = 0; i < P::n; ++i) x[i] = st->x[i];
+    if (a.inject == 0) {
+      P::force(a.pc, L, w, s);
+      rk4_step<KIND, double>(a.pc, L, s, a.h, a.hh, a.h6, x);
+    } else {
+      P::force0(a.pc, L, s);
+      rk4_step<KIND, double>(a.pc, L, s, a.h, a.hh, a.h6, x);
+      P::post(a.pc, w, x);
+    }
+    for (int i = 0; i < P::n; ++i) {
+      st->x[i] = x[i];
+      x_hist[(size_t)(idx + 1) * P::n + i] = x[i];
+    }
+    st->v_prev = R.v;
+    st->cl_index = idx + 1;
+  }
+  st->t = st->t + 1;
+}
+
+// rg_margin: worst margin of each listed candidate.
+__global__ void k_collect(const DevSearch* S, int M, double* out) {
+  for (int c = threadIdx.x; c < M; c += blockDim.x) out[c] = cand_worst(S, c);
+}
+
+struct ThetaNominal {
+  double v[kMaxTh];
+};
+
+template <int KIND>
+__global__ void k_draws(RollArgs<KIND, float> a, uint32_t t, int k0, int nk, int j0, int nj,
+                        float* w_out, double* th_out, ThetaNominal thnom) {
+  using P = Plant<KIND, float>;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid < nk * nj) {
+    const int jj = gid / nk, kk = gid - jj * nk;
+    float w[P::nw];
+    draw_w<P::nw>(a.seed, a.inst, t, 0u, (uint32_t)(k0 + kk), (uint32_t)(j0 + jj), a.wlo, a.wspan,
+                  w);
+    for (int c = 0; c < P::nw; ++c) w_out[((size_t)jj * nk + kk) * P::nw + c] = w[c];
+  } else if (P::nth > 0 && th_out && gid < nk * nj + nk) {
+    const int kk = gid - nk * nj;
+    float f[P::nth > 0 ? P::nth : 1];
+    draw_theta_factor<P::nth>(a.seed, a.inst, t, (uint32_t)(k0 + kk), a.thlo, a.thspan, f);
+    for (int c = 0; c < P::nth; ++c) th_out[(size_t)kk * P::nth + c] = thnom.v[c] * (double)f[c];
+  }
+}
+
+template <int KIND, class T, int RNG, int INJ>
+__global__ void k_traj(const RollArgs<KIND, T> a, T v, const int32_t* k_list, int nk,
+                       double* traj) {
+  using P = Plant<KIND, T>;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nk) return;
+  int jb, ns;
+  rollout_lane<KIND, T, RNG, INJ>(a, v, k_list[i], a.st->t, nullptr, jb, ns,
+                                  traj + (size_t)i * (a.H + 1) * P::n);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side argument filling and launchers
+// ---------------------------------------------------------------------------
+template <int KIND, class T>
+static RollArgs<KIND, T> make_args(const Problem& pr, double band, int early, int record,
+                                   const DevBuffers& b) {
+  using P = Plant<KIND, T>;
+  RollArgs<KIND, T> a;
+  memset(&a, 0, sizeof(a));
+  P::load(a.pc, pr.p.coeffs);
+  for (int r = 0; r < kNC; ++r) {
+    for (int i = 0; i < P::ny; ++i) a.F[r * P::ny + i] = (T)pr.c.F[r * P::ny + i];
+    a.g[r] = (T)pr.c.g[r];
+  }
+  a.h = (T)pr.dt;
+  a.hh = (T)(pr.dt * 0.5);
+  a.h6 = (T)(pr.dt / 6.0);
+  a.band = (T)band;
+  a.H = pr.H;
+  a.N = pr.s.N;
+  a.early = early;
+  a.record = record;
+  a.inject = pr.s.inject;
+  a.seed = pr.s.seed;
+  a.inst = pr.s.instance;
+  for (int c = 0; c < P::nw; ++c) {
+    a.wlo[c] = (float)pr.s.wlo[c];
+    a.wspan[c] = (float)(pr.s.whi[c] - pr.s.wlo[c]);
+  }
+  a.thlo = (float)(1.0 - pr.s.theta_rel);
+  a.thspan = (float)(2.0 * pr.s.theta_rel);
+  a.wbuf = b.wbuf;
+  a.thbuf = b.thbuf;
+  a.st = b.st;
+  a.srch = b.srch;
+  a.per_m = b.per_m;
+  a.per_j = b.per_j;
+  a.rlist = b.rlist;
+  return a;
+}
+
+template <int KIND>
+static CtlArgs<KIND> make_ctl(const Problem& pr, const DevBuffers& b, int closed_loop) {
+  CtlArgs<KIND> a;
+  memset(&a, 0, sizeof(a));
+  Plant<KIND, double>::load(a.pc, pr.p.coeffs);
+  a.st = b.st;
+  a.srch = b.srch;
+  a.r_seq = b.r_seq;
+  a.closed_loop = closed_loop;
+  return a;
+}
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+template <class F>
+static hipError_t by_kind(int kind, F&& f) {
+  if (kind == 1) return f(IC<1>{});
+  if (kind == 2) return f(IC<2>{});
+  return hipErrorInvalidValue;
+}
+template <class F>
+static hipError_t by_bit(int v, F&& f) {
+  return v ? f(IC<1>{}) : f(IC<0>{});
+}
+
+static int div_up(size_t a, size_t b) { return (int)((a + b - 1) / b); }
+
+hipError_t launch_gen(const Problem& pr, const DevBuffers& b, hipStream_t st) {
+  return by_kind(pr.p.kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    auto a = make_args<K, float>(pr, 0.0, 0, 0, b);
+    const size_t work = (size_t)pr.H * pr.s.N + (Plant<K, float>::nth > 0 ? pr.s.N : 0);
+    hipLaunchKernelGGL(k_gen<K>, dim3(div_up(work, 256)), dim3(256), 0, st, a, b.wbuf, b.thbuf);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_setup(const Problem& pr, const DevBuffers& b, int closed_loop, hipStream_t st) {
+  return by_kind(pr.p.kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    hipLaunchKernelGGL(k_setup<K>, dim3(1), dim3(128), 0, st, make_ctl<K>(pr, b, closed_loop));
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_setup_list(const Problem& pr, const DevBuffers& b, int M, hipStream_t st) {
+  return by_kind(pr.p.kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    hipLaunchKernelGGL(k_setup_list<K>, dim3(1), dim3(128), 0, st, make_ctl<K>(pr, b, 0), M);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_rollout(const Problem& pr, double band, int precision, int early_exit, int record,
+                          const LaunchCfg& cfg, const DevBuffers& b, hipStream_t st) {
+  const dim3 grid(div_up((size_t)pr.s.N, (size_t)cfg.block), cfg.cmax_round);
+  return by_kind(pr.p.kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    return by_bit(pr.s.rng_mode, [&](auto rc) {
+      constexpr int R = decltype(rc)::value;
+      return by_bit(pr.s.inject, [&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        if (precision == 0) {
+          auto a = make_args<K, float>(pr, band, early_exit, record, b);
+          hipLaunchKernelGGL((k_rollout<K, float, R, I>), grid, dim3(cfg.block), 0, st, a);
+        } else {
+          auto a = make_args<K, double>(pr, 0.0, early_exit, record, b);
+          hipLaunchKernelGGL((k_rollout<K, double, R, I>), grid, dim3(cfg.block), 0, st, a);
+        }
+        return hipGetLastError();
+      });
+    });
+  });
+}
+
+hipError_t launch_recheck(const Problem& pr, int early_exit, const LaunchCfg& cfg,
+                          const DevBuffers& b, hipStream_t st) {
+  const size_t cap = (size_t)cfg.cmax_round * pr.s.N;
+  const int blocks = div_up(cap < 65536 ? cap : 65536, 64);
+  return by_kind(pr.p.kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    return by_bit(pr.s.rng_mode, [&](auto rc) {
+      constexpr int R = decltype(rc)::value;
+      return by_bit(pr.s.inject, [&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        auto a = make_args<K, double>(pr, 0.0, early_exit, 0, b);
+        hipLaunchKernelGGL((k_recheck<K, R, I>), dim3(blocks), dim3(64), 0, st, a);
+        return hipGetLastError();
+      });
+    });
+  });
+}
+
+hipError_t launch_decide(const Problem& pr, const DevBuffers& b, hipStream_t st) {
+  return by_kind(pr.p.kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    hipLaunchKernelGGL(k_decide<K>, dim3(1), dim3(128), 0, st, make_ctl<K>(pr, b, 0));
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_finalize(const Problem& pr, int closed_loop, const DevBuffers& b,
+                           hipStream_t st) {
+  return by_kind(pr.p.kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    auto a = make_args<K, double>(pr, 0.0, 0, 0, b);
+    hipLaunchKernelGGL(k_finalize<K>, dim3(1), dim3(64), 0, st, a, b.res, b.x_hist, closed_loop);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_collect(const DevBuffers& b, int M, double* out_dev, hipStream_t st) {
+  hipLaunchKernelGGL(k_collect, dim3(1), dim3(128), 0, st, b.srch, M, out_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_draws(const Problem& pr, uint32_t t, int k0, int nk, int j0, int nj,
+                        float* w_dev, double* th_dev, const DevBuffers& b, hipStream_t st) {
+  return by_kind(pr.p.kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    auto a = make_args<K, float>(pr, 0.0, 0, 0, b);
+    ThetaNominal thn;
+    memset(&thn, 0, sizeof(thn));
+    if (K == 2)
+      for (int i = 0; i < kMaxTh; ++i) thn.v[i] = pr.p.coeffs[90 + i];
+    const size_t work = (size_t)nk * nj + nk;
+    hipLaunchKernelGGL(k_draws<K>, dim3(div_up(work, 256)), dim3(256), 0, st, a, t, k0, nk, j0, nj,
+                       w_dev, th_dev, thn);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_trajectory(const Problem& pr, double v, const int32_t* k_list_dev, int nk,
+                             int precision, double* traj_dev, const DevBuffers& b,
+                             hipStream_t st) {
+  return by_kind(pr.p.kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    return by_bit(pr.s.rng_mode, [&](auto rc) {
+      constexpr int R = decltype(rc)::value;
+      return by_bit(pr.s.inject, [&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        if (precision == 0) {
+          auto a = make_args<K, float>(pr, 0.0, 0, 0, b);
+          hipLaunchKernelGGL((k_traj<K, float, R, I>), dim3(div_up(nk, 64)), dim3(64), 0, st, a,
+                             (float)v, k_list_dev, nk, traj_dev);
+        } else {
+          auto a = make_args<K, double>(pr, 0.0, 0, 0, b);
+          hipLaunchKernelGGL((k_traj<K, double, R, I>), dim3(div_up(nk, 64)), dim3(64), 0, st, a,
+                             v, k_list_dev, nk, traj_dev);
+        }
+        return hipGetLastError();
+      });
+    });
+  });
+}
+
+}  // namespace rg

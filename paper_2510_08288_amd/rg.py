@@ -1,0 +1,278 @@
+"""Python binding of librg (include/rg.h): argument marshalling only.
+
+Every step of the governor runs in the HIP kernels of ``librg.so``.  PyTorch
+supplies the device memory (the handle's workspace is a ``torch.uint8``
+tensor) and the stream (``torch.cuda.current_stream()``).  If the library is
+missing this module raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librg.so")
+
+RG_OK = 0
+RG_S_INFEASIBLE = 1
+RG_S_FALLBACK = 2
+RG_E_INVAL = -1
+RG_E_NOMEM = -2
+RG_E_HIP = -3
+RG_E_NOTSUP = -4
+RG_E_STATE = -5
+
+PREC_F32_RECHECK = 0
+PREC_F64 = 1
+SEARCH_BISECT = 0
+SEARCH_GRID = 1
+SEARCH_NEWTON = 2
+RNG_STREAM = 0
+RNG_INLINE = 1
+
+
+class RGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"librg error {code}: {msg}")
+        self.code = code
+
+
+class rg_plant(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n", C.c_int32), ("n_w", C.c_int32), ("n_y", C.c_int32),
+                ("n_theta", C.c_int32), ("coeffs", C.POINTER(C.c_double)), ("n_coeffs", C.c_int32)]
+
+
+class rg_scenarios(C.Structure):
+    _fields_ = [("N", C.c_int32), ("seed", C.c_uint32), ("instance", C.c_uint32),
+                ("w_lo", C.POINTER(C.c_double)), ("w_hi", C.POINTER(C.c_double)),
+                ("theta_rel", C.c_double), ("inject", C.c_int32), ("rng_mode", C.c_int32)]
+
+
+class rg_constraints(C.Structure):
+    _fields_ = [("n_c", C.c_int32), ("F", C.POINTER(C.c_double)), ("g", C.POINTER(C.c_double)),
+                ("eps", C.c_double), ("ss_check", C.c_int32)]
+
+
+class rg_options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("band", C.c_double), ("K", C.c_int32),
+                ("search", C.c_int32), ("depth", C.c_int32), ("M", C.c_int32),
+                ("refine", C.c_int32), ("early_exit", C.c_int32), ("block", C.c_int32),
+                ("max_T", C.c_int32)]
+
+
+class rg_step_info(C.Structure):
+    _fields_ = [("kappa", C.c_double), ("v", C.c_double), ("worst_margin", C.c_double),
+                ("status", C.c_int32), ("rounds", C.c_int32), ("candidates", C.c_int32),
+                ("rechecks", C.c_int32), ("bisect_passes", C.c_int32), ("t", C.c_uint32),
+                ("lane_steps", C.c_uint64)]
+
+
+class rg_profile(C.Structure):
+    _fields_ = [("rollout_launches", C.c_int64), ("rollout_ms", C.c_double),
+                ("lane_steps", C.c_uint64), ("steps", C.c_int64)]
+
+
+_lib: Optional[C.CDLL] = None
+
+_dp = C.POINTER(C.c_double)
+_fp = C.POINTER(C.c_float)
+_ip = C.POINTER(C.c_int32)
+_vp = C.c_void_p
+
+
+def load_library(path: str = LIB_PATH, with_torch: bool = True) -> C.CDLL:
+    """Load librg.so.  With ``with_torch`` the HIP runtime torch already loaded is
+    the one the library binds to (one runtime per process)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build()")
+    if with_torch:
+        import torch  # noqa: F401  (loads torch's HIP runtime first)
+    L = C.CDLL(path)
+    L.rg_default_options.argtypes = [C.POINTER(rg_options)]
+    L.rg_create.argtypes = [C.POINTER(rg_plant), C.POINTER(rg_scenarios), C.POINTER(rg_constraints),
+                            C.c_int32, C.c_double, C.POINTER(rg_options), C.POINTER(_vp)]
+    L.rg_destroy.argtypes = [_vp]
+    L.rg_workspace_size.argtypes = [_vp, C.POINTER(C.c_size_t)]
+    L.rg_bind_workspace.argtypes = [_vp, _vp, C.c_size_t]
+    L.rg_set_stream.argtypes = [_vp, _vp]
+    L.rg_set_step.argtypes = [_vp, C.c_uint32]
+    L.rg_get_step.argtypes = [_vp, C.POINTER(C.c_uint32)]
+    L.rg_step.argtypes = [_vp, _dp, C.c_double, C.c_double, _dp, _dp, C.POINTER(rg_step_info)]
+    L.rg_margin.argtypes = [_vp, _dp, C.c_double, C.c_double, _dp, C.c_int32, _dp, _fp, _ip]
+    L.rg_closed_loop.argtypes = [_vp, _dp, C.c_double, _dp, C.c_int32, _dp, _dp, _dp,
+                                 C.POINTER(rg_step_info), C.c_int32]
+    L.rg_set_profiling.argtypes = [_vp, C.c_int32]
+    L.rg_get_profile.argtypes = [_vp, C.POINTER(rg_profile)]
+    L.rg_draws.argtypes = [_vp, C.c_uint32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _fp, _dp]
+    L.rg_trajectory.argtypes = [_vp, _dp, C.c_double, _ip, C.c_int32, C.c_int32, _dp]
+    L.rg_status_string.argtypes = [C.c_int]
+    L.rg_status_string.restype = C.c_char_p
+    L.rg_last_error.argtypes = [_vp]
+    L.rg_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a: np.ndarray, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+def _info_dict(info: rg_step_info) -> dict:
+    return dict(worst=info.worst_margin, rounds=info.rounds, candidates=info.candidates,
+                rechecks=info.rechecks, bisect_passes=info.bisect_passes, t=info.t,
+                lane_steps=info.lane_steps)
+
+
+def default_options() -> rg_options:
+    o = rg_options()
+    load_library().rg_default_options(C.byref(o))
+    return o
+
+
+class Governor:
+    """One robust reference governor handle on the current CUDA (HIP) device."""
+
+    def __init__(self, problem, precision: int = PREC_F32_RECHECK, band: float = 1e-4,
+                 K: int = 12, search: int = SEARCH_BISECT, depth: int = 0, M: int = 64,
+                 refine: int = 6, early_exit: bool = True, block: int = 0, max_T: int = 256,
+                 rng_mode: int = RNG_STREAM, torch_workspace: bool = True):
+        import torch
+        self.L = load_library()
+        self.problem = problem
+        p = problem
+        self._coeffs = _f64(p.coeffs)
+        self._wlo = _f64(p.w_lo)
+        self._whi = _f64(p.w_hi)
+        self._F = _f64(np.asarray(p.F).reshape(-1))
+        self._g = _f64(p.g)
+        plant = rg_plant(p.kind, p.n, p.n_w, p.n_y, p.n_theta, _ptr(self._coeffs), self._coeffs.size)
+        scen = rg_scenarios(int(p.N), int(p.seed) & 0xFFFFFFFF, int(p.instance) & 0xFFFFFFFF,
+                            _ptr(self._wlo), _ptr(self._whi), float(p.theta_rel), int(p.inject),
+                            int(rng_mode))
+        cons = rg_constraints(int(np.asarray(p.F).shape[0]), _ptr(self._F), _ptr(self._g),
+                              float(p.eps), int(p.ss_check))
+        opt = default_options()
+        opt.precision, opt.band, opt.K, opt.search = precision, band, K, search
+        opt.depth, opt.M, opt.refine = depth, M, refine
+        opt.early_exit, opt.block, opt.max_T = int(early_exit), block, max_T
+        self.options = opt
+        h = _vp()
+        rc = self.L.rg_create(C.byref(plant), C.byref(scen), C.byref(cons), int(p.H), float(p.dt),
+                              C.byref(opt), C.byref(h))
+        if rc < 0:
+            raise RGError(rc, self.L.rg_last_error(None).decode())
+        self.h = h
+        self.workspace = None
+        if torch_workspace:
+            nbytes = C.c_size_t()
+            self._check(self.L.rg_workspace_size(self.h, C.byref(nbytes)))
+            # 256-byte alignment: torch's allocator returns at least 512-byte aligned blocks.
+            self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
+            self._check(self.L.rg_bind_workspace(self.h, C.c_void_p(self.workspace.data_ptr()),
+                                                 int(nbytes.value)))
+        # A stream of the handle's own (default priority): graph capture is not
+        # allowed on the null stream.
+        self.stream = torch.cuda.Stream()
+        self.set_stream(self.stream)
+
+    # -- plumbing --------------------------------------------------------------
+    def _check(self, rc: int) -> int:
+        if rc < 0:
+            raise RGError(rc, self.L.rg_last_error(self.h).decode())
+        return rc
+
+    def set_stream(self, stream) -> None:
+        handle = stream.cuda_stream if stream is not None else 0
+        self._check(self.L.rg_set_stream(self.h, C.c_void_p(handle)))
+
+    def set_step(self, t: int) -> None:
+        self._check(self.L.rg_set_step(self.h, int(t)))
+
+    def get_step(self) -> int:
+        t = C.c_uint32()
+        self._check(self.L.rg_get_step(self.h, C.byref(t)))
+        return int(t.value)
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            self.L.rg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- governor ----------------------------------------------------------------
+    def step(self, x, r: float, v_prev: float) -> dict:
+        x = _f64(x)
+        v = C.c_double()
+        kap = C.c_double()
+        info = rg_step_info()
+        rc = self._check(self.L.rg_step(self.h, _ptr(x), float(r), float(v_prev), C.byref(v),
+                                        C.byref(kap), C.byref(info)))
+        return dict(v=v.value, kappa=kap.value, status=rc, **_info_dict(info))
+
+    def margin(self, x, r: float, v_prev: float, kappas: Sequence[float],
+               per_scenario: bool = False) -> dict:
+        x = _f64(x)
+        k = _f64(kappas)
+        M = k.size
+        out = np.zeros(M)
+        per = np.zeros((M, self.problem.N), dtype=np.float32) if per_scenario else None
+        perj = np.zeros((M, self.problem.N), dtype=np.int32) if per_scenario else None
+        self._check(self.L.rg_margin(self.h, _ptr(x), float(r), float(v_prev), _ptr(k), M, _ptr(out),
+                                     None if per is None else _ptr(per, _fp),
+                                     None if perj is None else _ptr(perj, _ip)))
+        return dict(margins=out, per_scenario=per, per_scenario_j=perj)
+
+    def closed_loop(self, x0, v0: float, r_seq, use_graph: bool = True) -> dict:
+        x0 = _f64(x0)
+        r = _f64(r_seq)
+        T = r.size
+        v = np.zeros(T)
+        kap = np.zeros(T)
+        xs = np.zeros((T + 1, self.problem.n))
+        infos = (rg_step_info * T)()
+        self._check(self.L.rg_closed_loop(self.h, _ptr(x0), float(v0), _ptr(r), T, _ptr(v),
+                                          _ptr(kap), _ptr(xs), infos, int(use_graph)))
+        keys = ["status", "rounds", "candidates", "rechecks", "bisect_passes", "lane_steps", "t"]
+        out = {k: np.array([getattr(infos[i], k) for i in range(T)]) for k in keys}
+        out["worst"] = np.array([infos[i].worst_margin for i in range(T)])
+        out.update(v=v, kappa=kap, x=xs)
+        return out
+
+    def set_profiling(self, enable: bool) -> None:
+        self._check(self.L.rg_set_profiling(self.h, int(enable)))
+
+    def profile(self) -> dict:
+        p = rg_profile()
+        self._check(self.L.rg_get_profile(self.h, C.byref(p)))
+        return dict(rollout_launches=p.rollout_launches, rollout_ms=p.rollout_ms,
+                    lane_steps=p.lane_steps, steps=p.steps)
+
+    def draws(self, t: int, k0: int, nk: int, j0: int, nj: int, theta: bool = False):
+        w = np.zeros((nj, nk, self.problem.n_w), dtype=np.float32)
+        th = np.zeros((nk, max(self.problem.n_theta, 1))) if theta else None
+        self._check(self.L.rg_draws(self.h, int(t), k0, nk, j0, nj, _ptr(w, _fp),
+                                    None if th is None else _ptr(th)))
+        return (w, th[:, : self.problem.n_theta]) if theta else w
+
+    def trajectory(self, x, v: float, k_list, precision: int = PREC_F32_RECHECK) -> np.ndarray:
+        x = _f64(x)
+        ks = np.ascontiguousarray(np.asarray(k_list, dtype=np.int32))
+        out = np.zeros((ks.size, self.problem.H + 1, self.problem.n))
+        self._check(self.L.rg_trajectory(self.h, _ptr(x), float(v), _ptr(ks, _ip), ks.size,
+                                         int(precision), _ptr(out)))
+        return out

@@ -1,0 +1,303 @@
+"""GPU parity: the HIP governor (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (spec bar): FP32 trajectories and margins within
+1e-5 * max(1, |reference|) of the FP64 oracle; kappa within the bisection
+resolution 2^-K (in practice identical); draws bit-identical.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2510_08288_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_2510_08288_amd import rg
+    rg.load_library()
+    return rg
+
+
+@pytest.fixture(scope="module")
+def O(oracle_mod):
+    return oracle_mod
+
+
+def _gov(R, p, **kw):
+    return R.Governor(p, **kw)
+
+
+def _close32(gpu, ref, tol=TOL32):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    both_inf = np.isinf(gpu) & np.isinf(ref) & (np.sign(gpu) == np.sign(ref))
+    err = np.where(both_inf, 0.0, np.abs(gpu - ref) / np.maximum(1.0, np.abs(ref)))
+    return float(np.max(err)) if err.size else 0.0
+
+
+# ---------------------------------------------------------------------------
+# Draws
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", ["lq4", "fc9"])
+def test_draws_bit_identical(R, O, kind):
+    p = W.lq4_problem(N=300, H=50) if kind == "lq4" else W.fc9_problem(N=300, H=50)
+    g = _gov(R, p)
+    o = O.Oracle(p)
+    for t in [0, 7, 123456]:
+        w, th = g.draws(t, 0, 300, 0, 50, theta=True)
+        ref = np.array([[o.draw_w(t, k, j) for k in range(300)] for j in range(50)])
+        assert np.array_equal(w.astype(np.float64), ref)
+        if p.n_theta:
+            tref = np.array([o.draw_theta(t, k) for k in range(300)])
+            assert np.array_equal(th, tref)
+    g.close()
+
+
+# ---------------------------------------------------------------------------
+# Rollouts and margins
+# ---------------------------------------------------------------------------
+
+LQ4_CASES = [
+    dict(N=64, H=500, dt=0.01),      # one partial workgroup
+    dict(N=300, H=257, dt=0.01),     # several tiles + ragged tail
+]
+
+
+@pytest.mark.parametrize("case", LQ4_CASES)
+@pytest.mark.parametrize("inject", [W.INJECT_ODE, W.INJECT_POST])
+def test_margins_fp32_lq4(R, O, case, inject):
+    p = W.lq4_problem(inject=inject, **case)
+    o = O.Oracle(p, nthreads=8)
+    x0 = np.array([0.1, -0.05, 0.2, 0.0])
+    kap = np.array([0.0, 0.2, 0.33, 0.5, 0.75, 1.0])
+    r, vp = 1.5, 0.1
+    g = _gov(R, p)
+    out = g.margin(x0, r, vp, kap, per_scenario=True)
+    for i, k in enumerate(kap):
+        v = o.candidate_v(k, r, vp)
+        M, per, _, mss = o.candidate(x0, v, 0)
+        assert _close32(out["per_scenario"][i], per) <= TOL32
+        assert _close32([out["margins"][i]], [M]) <= TOL32
+    g.close()
+
+
+@pytest.mark.parametrize("case", LQ4_CASES)
+def test_margins_fp64_lq4(R, O, case):
+    p = W.lq4_problem(**case)
+    o = O.Oracle(p, nthreads=8)
+    x0 = np.array([0.1, -0.05, 0.2, 0.0])
+    kap = np.array([0.0, 0.4, 1.0])
+    g = _gov(R, p, precision=R.PREC_F64)
+    out = g.margin(x0, 1.5, 0.1, kap, per_scenario=True)
+    for i, k in enumerate(kap):
+        M, per, _, _ = o.candidate(x0, o.candidate_v(k, 1.5, 0.1), 0)
+        assert np.max(np.abs(out["margins"][i] - M)) < 1e-11
+    g.close()
+
+
+def test_trajectories_lq4(R, O):
+    p = W.lq4_problem(N=40, H=2000, dt=0.005)
+    o = O.Oracle(p)
+    x0 = np.array([0.2, -0.1, 0.05, 0.1])
+    ks = [0, 7, 39]
+    g = _gov(R, p)
+    for prec, tol in [(R.PREC_F32_RECHECK, TOL32), (R.PREC_F64, 1e-12)]:
+        tr = g.trajectory(x0, 1.2, ks, precision=prec)
+        for i, k in enumerate(ks):
+            _, _, _, ref = o.rollout(x0, 1.2, 0, k, traj=True)
+            err = np.max(np.abs(tr[i] - ref), axis=1) / np.maximum(1.0, np.max(np.abs(ref), axis=1))
+            assert err.max() <= tol, (prec, k, err.max())
+    g.close()
+
+
+def test_stream_and_inline_draws_give_identical_margins(R):
+    p = W.lq4_problem(N=300, H=200)
+    x0 = np.zeros(4)
+    kap = np.array([0.3, 0.6])
+    a = _gov(R, p, rng_mode=R.RNG_STREAM).margin(x0, 1.5, 0.0, kap, per_scenario=True)
+    b = _gov(R, p, rng_mode=R.RNG_INLINE).margin(x0, 1.5, 0.0, kap, per_scenario=True)
+    assert np.array_equal(a["per_scenario"], b["per_scenario"])
+    assert np.array_equal(a["margins"], b["margins"])
+
+
+# ---------------------------------------------------------------------------
+# Kappa search
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("depth", [1, 3, 6])
+def test_step_kappa_lq4_fp64_config(R, O, precision, depth):
+    wl = W.workload_lq4_fp64_single()
+    p = wl["problem"]
+    o = O.Oracle(p, nthreads=8)
+    g = _gov(R, p, precision=precision, depth=depth)
+    for (r, vp, x0) in [(wl["r"], wl["v_prev"], wl["x0"]), (-1.7, 0.2, np.array([0.05, 0, 0, -0.1])),
+                        (0.05, 0.0, np.zeros(4))]:
+        t = g.get_step()
+        res = g.step(x0, r, vp)
+        ref = o.bisect(x0, r, vp, t, 12)
+        assert abs(res["kappa"] - ref["kappa"]) <= 2.0 ** -12
+        assert res["kappa"] == ref["kappa"]
+        assert res["v"] == ref["v"]
+        assert res["status"] == ref["status"]
+        assert res["bisect_passes"] == ref["passes"]
+    g.close()
+
+
+def test_step_v_equals_r_and_single_pass_when_admissible(R):
+    p = W.lq4_problem(N=256, H=300)
+    g = _gov(R, p)
+    res = g.step(np.zeros(4), 0.05, 0.0)
+    assert res["kappa"] == 1.0 and res["v"] == 0.05 and res["bisect_passes"] == 1
+    g.close()
+
+
+def test_step_infeasible_start_keeps_v_prev(R, O):
+    p = W.lq4_problem(N=32, H=200)
+    o = O.Oracle(p)
+    # a state whose output already violates the box: every candidate fails at j = 0
+    A, B = p.coeffs[:16].reshape(4, 4), p.coeffs[44:52].reshape(2, 4)
+    x0 = 3.0 * np.linalg.pinv(B) @ np.array([1.0, 1.0])
+    assert np.max(np.abs(B @ x0)) > 1.0
+    g = _gov(R, p)
+    res = g.step(x0, 1.0, 0.3)
+    ref = o.bisect(x0, 1.0, 0.3, 0, 12)
+    assert res["status"] == R.RG_S_INFEASIBLE and ref["status"] == 1
+    assert res["kappa"] == 0.0 and res["v"] == 0.3
+    g.close()
+
+
+@pytest.mark.parametrize("N,H", [(1, 1), (1, 400), (257, 3), (513, 200)])
+def test_step_edge_sizes(R, O, N, H):
+    p = W.lq4_problem(N=N, H=H, dt=0.01)
+    o = O.Oracle(p, nthreads=8)
+    g = _gov(R, p, precision=R.PREC_F64)
+    for r in [1.5, -2.0]:
+        t = g.get_step()
+        res = g.step(np.zeros(4), r, 0.0)
+        ref = o.bisect(np.zeros(4), r, 0.0, t, 12)
+        assert res["kappa"] == ref["kappa"] and res["status"] == ref["status"]
+    g.close()
+
+
+def test_zero_width_box_all_scenarios_coincide(R, O):
+    p = W.lq4_problem(N=512, H=300, w_half=0.0)
+    g = _gov(R, p)
+    res = g.step(np.zeros(4), 1.5, 0.0)
+    ref = O.Oracle(p.replace(N=1)).bisect(np.zeros(4), 1.5, 0.0, 0, 12)
+    assert res["kappa"] == ref["kappa"]
+    g.close()
+
+
+def test_grid_search_lq4(R, O):
+    p = W.lq4_problem(N=128, H=300)
+    o = O.Oracle(p, nthreads=8)
+    for M, ref_steps in [(17, 0), (33, 4)]:
+        g = _gov(R, p, precision=R.PREC_F64, search=R.SEARCH_GRID, M=M, refine=ref_steps)
+        res = g.step(np.zeros(4), 1.5, 0.0)
+        ref = o.grid(np.zeros(4), 1.5, 0.0, 0, M, ref_steps)
+        assert res["kappa"] == ref["kappa"] and res["status"] == ref["status"]
+        assert res["bisect_passes"] == ref["passes"]
+        g.close()
+
+
+# ---------------------------------------------------------------------------
+# Closed loop
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_closed_loop_lq4(R, O, use_graph):
+    p = W.lq4_problem(N=256, H=300, dt=0.01)
+    o = O.Oracle(p, nthreads=8)
+    T = 30
+    r_seq = W.reference_sequence(3, T, switch_every=8)
+    g = _gov(R, p, K=10, max_T=16)   # two chunks
+    out = g.closed_loop(np.zeros(4), 0.0, r_seq, use_graph=use_graph)
+    assert g.get_step() == T
+    v_prev = 0.0
+    for s in range(T):
+        ref = o.bisect(out["x"][s], r_seq[s], v_prev, s, 10)
+        assert abs(out["kappa"][s] - ref["kappa"]) <= 2.0 ** -10
+        xn = o.plant_step(out["x"][s], out["v"][s], s)
+        np.testing.assert_allclose(out["x"][s + 1], xn, rtol=1e-13, atol=1e-14)
+        v_prev = out["v"][s]
+    g.close()
+
+
+def test_closed_loop_graph_equals_eager_and_resume(R):
+    p = W.lq4_problem(N=200, H=200, dt=0.01)
+    r_seq = W.reference_sequence(4, 12, switch_every=4)
+    a = _gov(R, p, K=8).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=False)
+    gb = _gov(R, p, K=8)
+    b = gb.closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    b2 = gb.closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)  # t continues: new draws
+    assert np.array_equal(a["v"], b["v"]) and np.array_equal(a["x"], b["x"])
+    gc = _gov(R, p, K=8)
+    c1 = gc.closed_loop(np.zeros(4), 0.0, r_seq[:5], use_graph=True)
+    c2 = gc.closed_loop(c1["x"][-1], c1["v"][-1], r_seq[5:], use_graph=True)
+    assert np.array_equal(np.concatenate([c1["v"], c2["v"]]), a["v"])
+    assert b2["x"].shape == b["x"].shape
+
+
+# ---------------------------------------------------------------------------
+# FC9
+# ---------------------------------------------------------------------------
+
+def test_margins_fp32_fc9(R, O):
+    p = W.fc9_problem(N=200, H=300, dt=0.002)
+    o = O.Oracle(p, nthreads=8)
+    x0 = W.FC9_XBAR.copy()
+    kap = np.array([0.0, 0.5, 1.0])
+    g = _gov(R, p)
+    out = g.margin(x0, 1.2, 0.5, kap, per_scenario=True)
+    for i, k in enumerate(kap):
+        M, per, _, mss = o.candidate(x0, o.candidate_v(k, 1.2, 0.5), 0)
+        assert _close32(out["per_scenario"][i], per) <= TOL32
+        assert _close32([out["margins"][i]], [M]) <= TOL32
+    g64 = _gov(R, p, precision=R.PREC_F64)
+    out64 = g64.margin(x0, 1.2, 0.5, kap)
+    for i, k in enumerate(kap):
+        M = o.candidate(x0, o.candidate_v(k, 1.2, 0.5), 0)[0]
+        assert abs(out64["margins"][i] - M) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Full-size workload (N=4096, H=2000), checked on sampled outputs
+# ---------------------------------------------------------------------------
+
+def test_full_size_step_sampled(R, O):
+    wl = W.workload_lq4_closed_loop(T=4)
+    p = wl["problem"]
+    o = O.Oracle(p)
+    g = _gov(R, p)
+    x0 = np.zeros(4)
+    r = 1.9
+    res = g.step(x0, r, 0.0)
+    kap = res["kappa"]
+    g.set_step(0)  # same draws as the step
+    probe = [kap, min(1.0, kap + 2.0 ** -12)]
+    out = g.margin(x0, r, 0.0, probe, per_scenario=True)
+    per = out["per_scenario"]
+    # the GPU's 8 worst scenarios at kappa agree with the oracle, one by one
+    v0 = o.candidate_v(kap, r, 0.0)
+    worst = np.argsort(per[0])[:8]
+    for k in worst:
+        m, _, _ = o.rollout(x0, v0, 0, int(k))
+        assert abs(m - per[0][k]) <= TOL32 * max(1.0, abs(m))
+        assert m >= 0.0 or kap == 0.0
+    # one step above the result is refused: witness scenario or steady state
+    if kap < 1.0:
+        v1 = o.candidate_v(probe[1], r, 0.0)
+        k1 = int(np.argmin(per[1]))
+        m1 = o.rollout(x0, v1, 0, k1)[0]
+        mss = o.steady_margin(v1)[0]
+        assert min(m1, mss) < 0.0
+    g.close()
