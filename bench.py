@@ -76,6 +76,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--depth", type=int, default=0)
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--lanes", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the scenario axis would "
@@ -95,7 +96,7 @@ def main():
     r_seq = wl["r_seq"]
     prec = rg.PREC_F32_RECHECK if args.precision == "f32" else rg.PREC_F64
     g = rg.Governor(p, precision=prec, band=wl["band"], K=wl["K"], depth=args.depth,
-                    max_T=max(256, T))
+                    lanes=args.lanes, max_T=max(256, T))
     x0 = np.asarray(wl["x0"], dtype=np.float64)
 
     # warmup: the first W updates of the workload (untimed)
@@ -146,7 +147,8 @@ def main():
         "config": {"workload": wl["name"], "plant": "LQ4", "N": p.N, "H": p.H, "dt": p.dt,
                    "K": wl["K"], "band": wl["band"], "rg_steps": K,
                    "precision": "fp32 rollouts + fp64 near-band recheck" if prec == 0 else "fp64",
-                   "search": f"bisection, {g.options.depth} levels per device round"},
+                   "search": f"bisection, {g.options.depth} levels per device round",
+                   "lanes_per_scenario": g.options.lanes},
         "rg_updates_per_s": K / elapsed,
         "executed_scenario_steps_per_s": executed / elapsed,
         "graph_replay": {"ms_per_step": elapsed_graph / K * 1e3,
@@ -159,7 +161,8 @@ def main():
                          "infeasible_steps": int(np.sum(out["status"] != 0))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "k_rollout<LQ4, float, stream, ode>",
+                     "kernel": ("k_rollout_lq4_quad (one scenario per 4 lanes)" if g.options.lanes == 4
+                                else "k_rollout<LQ4, float>"),
                      "launches": prof["rollout_launches"],
                      "avg_launch_ms": prof["rollout_ms"] / max(1, prof["rollout_launches"]),
                      "flop_per_scenario_step": FLOP_PER_STEP_LQ4,

@@ -59,8 +59,8 @@ enum rg_plant_kind {
                            xdot_i = -a_i z_i + (W tanh z)_i + w_i + phi_i,
                            phi_l = q_{l-1} - q_l (l = 1..6),
                            phi_7 = b1 v - mu1 x7 (x1 - p1ref), phi_8 = b2 v x7,
-                           phi_9 = b3 v - mu2 x9 v;
-                           y = (c_q0 x7 / (d0 + d1 v), x1, x7)  (1-based indices) */
+                           phi_9 = b3 v - mu2 (x9 - 1) v;
+                           y = (c_q0 x7 / (d0 + d1 x9), x1, x7)  (1-based indices) */
 };
 enum rg_inject {
     RG_INJECT_ODE = 0, /* w enters the continuous dynamics, held over each RK4 step */
@@ -126,6 +126,8 @@ typedef struct rg_options {
     int32_t early_exit;    /* 1: a candidate stops once one lane is below -band */
     int32_t block;         /* threads per workgroup for rollouts (64..256, multiple of 64; 0 = auto) */
     int32_t max_T;         /* closed-loop steps kept on the device per chunk (default 256) */
+    int32_t lanes;         /* lanes per scenario of FP32 LQ4 rollouts: 1, 4 (one scenario per
+                              quad, state split across lanes), 0 = auto */
 } rg_options;
 
 typedef struct rg_step_info {
@@ -213,6 +215,9 @@ int rg_margin(rg_handle* h, const double* x, double r, double v_prev, const doub
 int rg_closed_loop(rg_handle* h, const double* x0, double v0, const double* r_seq, int32_t T,
                    double* v_out, double* kappa_out, double* x_out, rg_step_info* info_out,
                    int32_t use_graph);
+
+/* The options in force, with auto fields (depth, lanes) resolved. */
+int rg_get_options(const rg_handle* h, rg_options* out);
 
 /* Profiling: with enable = 1, every rollout launch is bracketed by HIP events
  * on the handle's stream and the totals accumulate until reset (enable = 1

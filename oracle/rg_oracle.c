@@ -136,12 +136,13 @@ static void lq4_rhs(const double* c, const double* x, double v, const double* w,
 }
 
 /* FC9 (air-supply-like chain of six volumes p1..p6 fed by a compressor of
- * speed w1, two auxiliary speeds w2, w3):
+ * speed w1, an auxiliary speed w2 and a fast demand state w3):
  *   z = x - xbar, p7 = p_amb,
  *   q0 = c_q0 * w1,  q_l = k_l * sqrt(max(p_l - p_{l+1}, 0)), l = 1..6,
  *   xdot_i = -a_i z_i + sum_j W_ij tanh(z_j) + w_i + phi_i,
  *   phi_l = q_{l-1} - q_l (l = 1..6),
- *   phi_7 = b1 v - mu1 w1 (p1 - p1ref),  phi_8 = b2 v w1,  phi_9 = b3 v - mu2 w3 v.
+ *   phi_7 = b1 v - mu1 w1 (p1 - p1ref),  phi_8 = b2 v w1,
+ *   phi_9 = b3 v - mu2 (w3 - 1) v.
  * theta = (a[9], k[6], b[3], mu[2]). */
 static void fc9_rhs(const double* c, const double* th, const double* x, double v,
                     const double* w, double* xd)
@@ -172,7 +173,7 @@ static void fc9_rhs(const double* c, const double* th, const double* x, double v
         if (i < 6) phi = q[i] - q[i + 1];
         else if (i == 6) phi = b[0] * v - mu[0] * x[6] * (x[0] - p1ref);
         else if (i == 7) phi = b[1] * v * x[6];
-        else phi = b[2] * v - mu[1] * x[8] * v;
+        else phi = b[2] * v - mu[1] * (x[8] - 1.0) * v;
         xd[i] = acc + phi;
     }
 }
@@ -189,8 +190,8 @@ void orc_rhs(const orc_problem* p, const double* theta, const double* x, double 
     else fc9_rhs(p->coeffs, theta ? theta : nominal_theta(p), x, v, w, xdot);
 }
 
-/* Constrained outputs y = h(x, v).  LQ4: y = C x.  FC9: y1 = c_q0 w1 / (d0 + d1 v)
- * (ratio of supplied to demanded flow, kept above a floor like the paper's
+/* Constrained outputs y = h(x, v).  LQ4: y = C x.  FC9: y1 = c_q0 w1 / (d0 + d1 w3)
+ * (ratio of supplied flow to demand, kept above a floor like the paper's
  * oxygen excess ratio, Sec. IV-A), y2 = p1, y3 = w1. */
 void orc_output(const orc_problem* p, const double* x, double v, double* y)
 {
@@ -203,7 +204,8 @@ void orc_output(const orc_problem* p, const double* x, double v, double* y)
         }
     } else {
         const double* c = p->coeffs;
-        y[0] = c[110] * x[6] / (c[112] + c[113] * v);
+        (void)v;
+        y[0] = c[110] * x[6] / (c[112] + c[113] * x[8]);
         y[1] = x[0];
         y[2] = x[6];
     }
@@ -417,7 +419,7 @@ static void orc_jacobian(const orc_problem* p, const double* x, double v, double
     J[9 * 6 + 0] += -mu[0] * x[6];
     /* phi_8 = b2 v w1 */
     J[9 * 7 + 6] += b[1] * v;
-    /* phi_9 = b3 v - mu2 w3 v */
+    /* phi_9 = b3 v - mu2 (w3 - 1) v */
     J[9 * 8 + 8] += -mu[1] * v;
 }
 

@@ -99,23 +99,34 @@ Layout layout_of(const rg_handle* h) {
   return L;
 }
 
-int depth_for(const rg_handle* h) {
+int lanes_for(const rg_handle* h) {
+  const bool quad_ok = h->pr.p.kind == RG_PLANT_LQ4 && h->opt.precision == RG_PREC_F32_RECHECK;
+  if (h->opt.lanes == 4) return quad_ok ? 4 : 1;
+  if (h->opt.lanes == 1) return 1;
+  return quad_ok ? 4 : 1;
+}
+
+int depth_for(const rg_handle* h, int lanes) {
   if (h->opt.depth > 0) return h->opt.depth;
   // Enough candidates per round to give every SIMD of the chip about two
   // wavefronts, then the smallest depth that needs no more rounds.
   const int goal = h->opt.search == RG_SEARCH_GRID ? h->opt.refine : h->opt.K;
   const double lanes_budget = 2.0 * 256 * 4 * 64;
+  const double per_cand = (double)h->pr.s.N * lanes;
   int dmax = 1;
-  while (dmax < 6 && ((1 << (dmax + 1)) - 1) * (double)h->pr.s.N <= lanes_budget) ++dmax;
+  while (dmax < 6 && ((1 << (dmax + 1)) - 1) * per_cand <= lanes_budget) ++dmax;
   if (goal <= 0) return 1;
   const int rounds = (goal + dmax - 1) / dmax;
   return (goal + rounds - 1) / rounds;
 }
 
 void plan(rg_handle* h) {
-  const int d = depth_for(h);
+  const int lanes = lanes_for(h);
+  const int d = depth_for(h, lanes);
   h->opt.depth = d;
+  h->opt.lanes = lanes;
   LaunchCfg c;
+  c.lanes = lanes;
   c.block = h->opt.block > 0 ? h->opt.block : 256;
   const int tree = (1 << d) - 1;
   if (h->opt.search == RG_SEARCH_GRID) {
@@ -283,6 +294,7 @@ int rg_default_options(rg_options* opt) {
   opt->early_exit = 1;
   opt->block = 0;
   opt->max_T = 256;
+  opt->lanes = 0;
   return RG_OK;
 }
 
@@ -346,6 +358,7 @@ int rg_create(const rg_plant* plant, const rg_scenarios* scen, const rg_constrai
   if (o.block != 0 && (o.block < 64 || o.block > 256 || (o.block & 63)))
     return fail(nullptr, RG_E_INVAL, "block must be a multiple of 64 in [64, 256]");
   if (o.max_T < 1 || o.max_T > 65536) return fail(nullptr, RG_E_INVAL, "max_T must be in [1, 65536]");
+  if (o.lanes != 0 && o.lanes != 1 && o.lanes != 4) return fail(nullptr, RG_E_INVAL, "lanes must be 0, 1 or 4");
 
   rg_handle* h = new (std::nothrow) rg_handle;
   if (!h) return fail(nullptr, RG_E_NOMEM, "host allocation");
@@ -552,6 +565,12 @@ int rg_closed_loop(rg_handle* h, const double* x0, double v0, const double* r_se
     h->t += (uint32_t)chunk;
   }
   h->gen_t = (long long)h->t - 1;
+  return RG_OK;
+}
+
+int rg_get_options(const rg_handle* h, rg_options* out) {
+  if (!h || !out) return RG_E_INVAL;
+  *out = h->opt;
   return RG_OK;
 }
 

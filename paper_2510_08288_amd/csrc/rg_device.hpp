@@ -179,13 +179,13 @@ struct Plant<1, T> {
   }
 };
 
-// FC9: volumes p1..p6 (x0..x5) fed by compressor speed w1 (x6), speeds w2, w3
-// (x7, x8):  z = x - xbar, p7 = p_amb,
+// FC9: volumes p1..p6 (x0..x5) fed by compressor speed w1 (x6), auxiliary
+// speed w2 (x7), demand state w3 (x8):  z = x - xbar, p7 = p_amb,
 //   q0 = c_q0 w1,  q_l = k_l sqrt(max(p_l - p_{l+1}, 0)),
 //   xdot_i = -a_i z_i + (W tanh z)_i + w_i + phi_i,
 //   phi_l = q_{l-1} - q_l (l = 1..6), phi_7 = b1 v - mu1 w1 (p1 - p1ref),
-//   phi_8 = b2 v w1, phi_9 = b3 v - mu2 w3 v;
-//   y = (c_q0 w1 / (d0 + d1 v), p1, w1).
+//   phi_8 = b2 v w1, phi_9 = b3 v - mu2 (w3 - 1) v;
+//   y = (c_q0 w1 / (d0 + d1 w3), p1, w1).
 template <class T>
 struct Plant<2, T> {
   static constexpr int n = 9, nw = 9, ny = 3, nth = 20;
@@ -195,7 +195,7 @@ struct Plant<2, T> {
   };
   struct Lane {
     T a[9], kq[6], b[3], mu[2];
-    T v, y1s;
+    T v;
   };
   __host__ __device__ static const T* nominal_theta(const Coef& c) { return c.thnom; }
   static void load(Coef& c, const double* s) {
@@ -218,7 +218,6 @@ struct Plant<2, T> {
     L.mu[0] = th[18];
     L.mu[1] = th[19];
     L.v = v;
-    L.y1s = c.c_q0 / (c.d0 + c.d1 * v);
   }
   __device__ static void force(const Coef&, const Lane&, const T* w, T* s) {
 #pragma unroll
@@ -251,7 +250,7 @@ struct Plant<2, T> {
       if (i < 6) phi = q[i] - q[i + 1];
       else if (i == 6) phi = L.b[0] * L.v - L.mu[0] * x[6] * (x[0] - c.p1ref);
       else if (i == 7) phi = L.b[1] * L.v * x[6];
-      else phi = L.b[2] * L.v - L.mu[1] * x[8] * L.v;
+      else phi = L.b[2] * L.v - L.mu[1] * (x[8] - (T)1) * L.v;
       xd[i] = a + phi;
     }
   }
@@ -259,8 +258,8 @@ struct Plant<2, T> {
 #pragma unroll
     for (int i = 0; i < 9; ++i) x[i] = x[i] + w[i];
   }
-  __device__ static void output(const Coef&, const Lane& L, const T* x, T* y) {
-    y[0] = L.y1s * x[6];
+  __device__ static void output(const Coef& c, const Lane&, const T* x, T* y) {
+    y[0] = c.c_q0 * x[6] / t_fma(c.d1, x[8], c.d0);
     y[1] = x[0];
     y[2] = x[6];
   }

@@ -104,6 +104,7 @@ struct DevBuffers {
 };
 
 struct LaunchCfg {
+  int lanes;               // lanes per scenario in FP32 LQ4 rollouts (1 or 4)
   int block;               // threads per rollout workgroup
   int cmax_round;          // largest candidate count of any round
   int rounds;              // device rounds per RG step

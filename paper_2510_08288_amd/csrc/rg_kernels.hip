@@ -230,6 +230,15 @@ __device__ __forceinline__ unsigned long long block_min_u64(unsigned long long v
   return v;
 }
 
+// In decision mode a candidate whose FP64 steady-state test already fails is
+// refused without simulating it (the verdict needs both tests, Alg. 1 line 6).
+__device__ __forceinline__ bool refused_by_steady_state(int early, DevSearch* S, int c) {
+  if (!early || !(S->mss[c] < 0.0)) return false;
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return true;
+}
+
 // Main rollout kernel: blockIdx.y = candidate of the round, blockIdx.x * block
 // + threadIdx.x = scenario.
 template <int KIND, class T, int RNG, int INJ>
@@ -237,6 +246,7 @@ __global__ void __launch_bounds__(256) k_rollout(const RollArgs<KIND, T> a) {
   DevSearch* S = a.srch;
   const int c = blockIdx.y;
   if (S->done || c >= S->n_cand) return;  // uniform over the workgroup
+  if (refused_by_steady_state(a.early, S, c)) return;
   __shared__ unsigned long long sh[16];
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t t = a.st->t;
@@ -261,6 +271,184 @@ __global__ void __launch_bounds__(256) k_rollout(const RollArgs<KIND, T> a) {
   const unsigned long long kfar = block_min_u64((m >= a.band) ? key : ~0ull, sh);
   // executed steps: wave sum, one atomic per wave
   int wsum = ns;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off);
+  if ((threadIdx.x & 63) == 0) atomicAdd(&S->lane_steps, (unsigned long long)wsum);
+  if (threadIdx.x == 0) {
+    atomicMin(&S->key_all[c], kall);
+    if (kfar != ~0ull) atomicMin(&S->key_far[c], kfar);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LQ4 in FP32 with one scenario per quad of lanes.  Lane q of the quad holds
+// state component x_q.  Every derivative evaluation forms the contributions of
+// x_q to the four rows in lane-relative order (slot s <-> row q XOR s), so two
+// DPP butterflies (partner q^2, then q^1) leave row q's sum in lane q with no
+// selects.  The margin rows use D = F C the same way, then a quad minimum.
+// All control decisions are quad-uniform (every lane of a quad holds the same
+// margin), which the DPP exchanges require.
+// ---------------------------------------------------------------------------
+struct QuadCoef {
+  float a[4][4];  // a[q][s] = A[q^s][q]
+  float g[4][4];  // g[q][s] = G[q^s][q]
+  float d[4][4];  // d[q][s] = -(F C)[q^s][q]
+  float b[4];     // B[q]
+  float e[4][2];  // E[q][.]
+  float grow[4];  // g_q (constraint row q; +inf for padding rows)
+};
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL,
+                                                               0xf, 0xf, true));
+}
+constexpr int kSwap2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);  // quad_perm [2,3,0,1]
+constexpr int kSwap1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);  // quad_perm [1,0,3,2]
+
+struct QuadLane {
+  float a0, a1, a2, a3, g0, g1, g2, g3;
+};
+
+// Row q of f(x) = s + A x + G (x.*x), reduced over the quad.
+__device__ __forceinline__ float quad_deriv(const QuadLane& L, float s, float x) {
+  const float q = x * x;
+  float c0 = __builtin_fmaf(L.g0, q, __builtin_fmaf(L.a0, x, s));
+  float c1 = __builtin_fmaf(L.g1, q, L.a1 * x);
+  float c2 = __builtin_fmaf(L.g2, q, L.a2 * x);
+  float c3 = __builtin_fmaf(L.g3, q, L.a3 * x);
+  c0 = c0 + dpp<kSwap2>(c2);
+  c1 = c1 + dpp<kSwap2>(c3);
+  return c0 + dpp<kSwap1>(c1);
+}
+
+__device__ __forceinline__ float min2(float a, float b) { return b < a ? b : a; }
+
+template <int RNG, int INJ, int RECORD>
+__global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, float> a,
+                                                         const QuadCoef qc) {
+  constexpr int U = 4;  // steps per group: one prefetch, one exit test per group
+  DevSearch* S = a.srch;
+  const int c = blockIdx.y;
+  if (S->done || c >= S->n_cand) return;  // uniform over the workgroup
+  if (refused_by_steady_state(a.early, S, c)) return;
+  __shared__ unsigned long long sh[16];
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = gid >> 2, q = gid & 3;
+  const uint32_t t = a.st->t;
+  float best = INFINITY;
+  int jb = 0, ns = 0;
+  if (k < a.N) {  // whole quads are active or inactive together
+    QuadLane L;
+    L.a0 = qc.a[q][0]; L.a1 = qc.a[q][1]; L.a2 = qc.a[q][2]; L.a3 = qc.a[q][3];
+    L.g0 = qc.g[q][0]; L.g1 = qc.g[q][1]; L.g2 = qc.g[q][2]; L.g3 = qc.g[q][3];
+    const float d0 = qc.d[q][0], d1 = qc.d[q][1], d2 = qc.d[q][2], d3 = qc.d[q][3];
+    const float e0 = qc.e[q][0], e1 = qc.e[q][1], grow = qc.grow[q];
+    const float bv = qc.b[q] * (float)S->v[c];
+    const float h = a.h, hh = a.hh, h6 = a.h6;
+    const int H = a.H;
+    float x = (float)a.st->x[q];
+    auto margin = [&](float xv) {
+      float c0 = __builtin_fmaf(d0, xv, grow);
+      float c1 = d1 * xv, c2 = d2 * xv, c3 = d3 * xv;
+      c0 = c0 + dpp<kSwap2>(c2);
+      c1 = c1 + dpp<kSwap2>(c3);
+      float m = c0 + dpp<kSwap1>(c1);
+      m = min2(m, dpp<kSwap1>(m));
+      return min2(m, dpp<kSwap2>(m));
+    };
+    auto step = [&](float w0, float w1, int jnext) {
+      const float s = INJ == 0 ? __builtin_fmaf(e1, w1, __builtin_fmaf(e0, w0, bv)) : bv;
+      const float k1 = quad_deriv(L, s, x);
+      float acc = k1;
+      float xs = __builtin_fmaf(hh, k1, x);
+      const float k2 = quad_deriv(L, s, xs);
+      acc = __builtin_fmaf(2.f, k2, acc);
+      xs = __builtin_fmaf(hh, k2, x);
+      const float k3 = quad_deriv(L, s, xs);
+      acc = __builtin_fmaf(2.f, k3, acc);
+      xs = __builtin_fmaf(h, k3, x);
+      const float k4 = quad_deriv(L, s, xs);
+      x = __builtin_fmaf(h6, acc + k4, x);
+      if (INJ == 1) x = x + (e0 * w0 + e1 * w1);
+      const float m = margin(x);
+      if (RECORD) {
+        if (m < best) {
+          best = m;
+          jb = jnext;
+        }
+      } else {
+        best = min2(best, m);
+      }
+    };
+    // draws of steps j..j+U-1 (indices clamped into the horizon)
+    const size_t N2 = 2 * (size_t)a.N;
+    auto load_group = [&](int j, float* w) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int jj = (j + u) < H ? (j + u) : (H - 1);
+        if (RNG == 0) {
+          const float* p = a.wbuf + (size_t)jj * N2 + k;
+          w[2 * u] = p[0];
+          w[2 * u + 1] = p[a.N];
+        } else {
+          const Words r = philox10((uint32_t)k, (uint32_t)jj, t, 0u, a.seed, a.inst);
+          w[2 * u] = box_draw(r.v[0], a.wlo[0], a.wspan[0]);
+          w[2 * u + 1] = box_draw(r.v[1], a.wlo[1], a.wspan[1]);
+        }
+      }
+    };
+    best = margin(x);
+    float wcur[2 * U], wnext[2 * U];
+    load_group(0, wcur);
+    const int full = H / U;
+    int g = 0;
+    for (; g < full; ++g) {
+      load_group((g + 1) * U, wnext);
+#pragma unroll
+      for (int u = 0; u < U; ++u) step(wcur[2 * u], wcur[2 * u + 1], g * U + u + 1);
+#pragma unroll
+      for (int u = 0; u < 2 * U; ++u) wcur[u] = wnext[u];
+      if (a.early) {
+        if (best < -a.band) {
+          ++g;
+          break;
+        }
+        if ((g & 7) == 7 &&
+            __hip_atomic_load(&S->dead[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          ++g;
+          break;
+        }
+      }
+    }
+    ns = g * U;
+    if (g == full) {  // ragged tail of the horizon
+      for (int u = 0; u < H - full * U; ++u) step(wcur[2 * u], wcur[2 * u + 1], full * U + u + 1);
+      ns = H;
+    }
+    // non-finite state in any lane of the quad -> -inf
+    float bad = x - x;
+    bad = bad + dpp<kSwap1>(bad);
+    bad = bad + dpp<kSwap2>(bad);
+    if (!(bad == 0.f) || best != best) best = -INFINITY;
+  }
+  const bool lead = (q == 0) && (k < a.N);
+  if (lead) {
+    if (RECORD) {
+      a.per_m[(size_t)c * a.N + k] = best;
+      a.per_j[(size_t)c * a.N + k] = jb;
+    }
+    if (best < -a.band) {
+      __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (best < a.band) {
+      const int idx = atomicAdd(&S->n_recheck, 1);
+      a.rlist[idx] = make_int2(c, k);
+    }
+  }
+  const unsigned long long key = lead ? lane_key(best, k) : ~0ull;
+  const unsigned long long kall = block_min_u64(key, sh);
+  const unsigned long long kfar = block_min_u64((lead && best >= a.band) ? key : ~0ull, sh);
+  int wsum = lead ? ns : 0;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off);
   if ((threadIdx.x & 63) == 0) atomicAdd(&S->lane_steps, (unsigned long long)wsum);
@@ -296,15 +484,26 @@ __global__ void __launch_bounds__(64) k_recheck(const RollArgs<KIND, double> a) 
 // Candidates, steady state, verdicts
 // ---------------------------------------------------------------------------
 
-// Eq. (2) with v = r exactly at kappa = 1; no fused multiply-add, so the value
-// is the two-rounding expression v_prev + kappa (r - v_prev).
+// Eq. (2) with v = r exactly at kappa = 1.  Contraction is off here: the value
+// is the three-rounding expression v_prev + kappa (r - v_prev), never an FMA.
 __device__ __forceinline__ double cand_v(double kappa, double r, double v_prev) {
+#pragma clang fp contract(off)
   if (kappa == 1.0) return r;
-  return __dadd_rn(v_prev, __dmul_rn(kappa, __dsub_rn(r, v_prev)));
+  const double d = r - v_prev;
+  const double p = kappa * d;
+  return v_prev + p;
 }
 
 __device__ __forceinline__ double midpoint(double a, double b) {
-  return __dmul_rn(__dadd_rn(a, b), 0.5);
+#pragma clang fp contract(off)
+  return (a + b) * 0.5;
+}
+
+// Tightened right-hand side g - eps |g| (two roundings, no FMA).
+__device__ __forceinline__ double tightened_rhs(double g, double eps) {
+#pragma clang fp contract(off)
+  const double e = eps * fabs(g);
+  return g - e;
 }
 
 template <int NN>
@@ -379,7 +578,7 @@ __device__ double steady_margin(const typename Plant<KIND, double>::Coef& pc, co
   for (int r = 0; r < S->n_c; ++r) {
     double fy = 0.0;
     for (int i = 0; i < P::ny; ++i) fy += S->F[r * P::ny + i] * y[i];
-    const double gt = __dsub_rn(S->g[r], __dmul_rn(S->eps, fabs(S->g[r])));
+    const double gt = tightened_rhs(S->g[r], S->eps);
     const double m = gt - fy;
     best = (m < best || m != m) ? m : best;
   }
@@ -764,8 +963,54 @@ hipError_t launch_setup_list(const Problem& pr, const DevBuffers& b, int M, hipS
   });
 }
 
+static QuadCoef make_quad_coef(const Problem& pr) {
+  QuadCoef qc;
+  memset(&qc, 0, sizeof(qc));
+  const double* A = pr.p.coeffs;
+  const double* B = pr.p.coeffs + 16;
+  const double* G = pr.p.coeffs + 20;
+  const double* E = pr.p.coeffs + 36;
+  const double* Cm = pr.p.coeffs + 44;
+  double D[4][4];
+  for (int r = 0; r < 4; ++r)
+    for (int i = 0; i < 4; ++i) {
+      double acc = 0.0;
+      for (int y = 0; y < 2; ++y) acc += pr.c.F[r * 2 + y] * Cm[y * 4 + i];
+      D[r][i] = acc;
+    }
+  for (int q = 0; q < 4; ++q) {
+    for (int s = 0; s < 4; ++s) {
+      const int row = q ^ s;
+      qc.a[q][s] = (float)A[row * 4 + q];
+      qc.g[q][s] = (float)G[row * 4 + q];
+      qc.d[q][s] = (float)(-D[row][q]);
+    }
+    qc.b[q] = (float)B[q];
+    qc.e[q][0] = (float)E[q * 2 + 0];
+    qc.e[q][1] = (float)E[q * 2 + 1];
+    qc.grow[q] = (float)pr.c.g[q];
+  }
+  return qc;
+}
+
 hipError_t launch_rollout(const Problem& pr, double band, int precision, int early_exit, int record,
                           const LaunchCfg& cfg, const DevBuffers& b, hipStream_t st) {
+  if (cfg.lanes == 4 && precision == 0 && pr.p.kind == 1) {
+    const dim3 grid(div_up((size_t)pr.s.N * 4, (size_t)cfg.block), cfg.cmax_round);
+    const QuadCoef qc = make_quad_coef(pr);
+    auto a = make_args<1, float>(pr, band, early_exit, record, b);
+    return by_bit(pr.s.rng_mode, [&](auto rc) {
+      constexpr int R = decltype(rc)::value;
+      return by_bit(pr.s.inject, [&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        if (record)
+          hipLaunchKernelGGL((k_rollout_lq4_quad<R, I, 1>), grid, dim3(cfg.block), 0, st, a, qc);
+        else
+          hipLaunchKernelGGL((k_rollout_lq4_quad<R, I, 0>), grid, dim3(cfg.block), 0, st, a, qc);
+        return hipGetLastError();
+      });
+    });
+  }
   const dim3 grid(div_up((size_t)pr.s.N, (size_t)cfg.block), cfg.cmax_round);
   return by_kind(pr.p.kind, [&](auto kc) {
     constexpr int K = decltype(kc)::value;

@@ -60,7 +60,7 @@ class rg_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("band", C.c_double), ("K", C.c_int32),
                 ("search", C.c_int32), ("depth", C.c_int32), ("M", C.c_int32),
                 ("refine", C.c_int32), ("early_exit", C.c_int32), ("block", C.c_int32),
-                ("max_T", C.c_int32)]
+                ("max_T", C.c_int32), ("lanes", C.c_int32)]
 
 
 class rg_step_info(C.Structure):
@@ -108,6 +108,7 @@ def load_library(path: str = LIB_PATH, with_torch: bool = True) -> C.CDLL:
     L.rg_closed_loop.argtypes = [_vp, _dp, C.c_double, _dp, C.c_int32, _dp, _dp, _dp,
                                  C.POINTER(rg_step_info), C.c_int32]
     L.rg_set_profiling.argtypes = [_vp, C.c_int32]
+    L.rg_get_options.argtypes = [_vp, C.POINTER(rg_options)]
     L.rg_get_profile.argtypes = [_vp, C.POINTER(rg_profile)]
     L.rg_draws.argtypes = [_vp, C.c_uint32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _fp, _dp]
     L.rg_trajectory.argtypes = [_vp, _dp, C.c_double, _ip, C.c_int32, C.c_int32, _dp]
@@ -145,7 +146,7 @@ class Governor:
     def __init__(self, problem, precision: int = PREC_F32_RECHECK, band: float = 1e-4,
                  K: int = 12, search: int = SEARCH_BISECT, depth: int = 0, M: int = 64,
                  refine: int = 6, early_exit: bool = True, block: int = 0, max_T: int = 256,
-                 rng_mode: int = RNG_STREAM, torch_workspace: bool = True):
+                 rng_mode: int = RNG_STREAM, lanes: int = 0, torch_workspace: bool = True):
         import torch
         self.L = load_library()
         self.problem = problem
@@ -164,14 +165,15 @@ class Governor:
         opt = default_options()
         opt.precision, opt.band, opt.K, opt.search = precision, band, K, search
         opt.depth, opt.M, opt.refine = depth, M, refine
-        opt.early_exit, opt.block, opt.max_T = int(early_exit), block, max_T
-        self.options = opt
+        opt.early_exit, opt.block, opt.max_T, opt.lanes = int(early_exit), block, max_T, lanes
         h = _vp()
         rc = self.L.rg_create(C.byref(plant), C.byref(scen), C.byref(cons), int(p.H), float(p.dt),
                               C.byref(opt), C.byref(h))
         if rc < 0:
             raise RGError(rc, self.L.rg_last_error(None).decode())
         self.h = h
+        self.options = rg_options()
+        self._check(self.L.rg_get_options(self.h, C.byref(self.options)))
         self.workspace = None
         if torch_workspace:
             nbytes = C.c_size_t()

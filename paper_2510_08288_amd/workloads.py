@@ -98,9 +98,13 @@ def lq4_problem(seed: int = 7, N: int = 64, H: int = 500, dt: float = 0.01,
 
 
 # FC9 nominal constants.  Layout: W[81] xbar[9] theta_nom[20] c_q0 p_amb d0 d1 p1ref.
+# theta = (a[9], k[6], b[3], mu[2]): a slow compressor (a7 = 2) and a fast
+# demand state (a9 = 12), so the supply/demand ratio y1 dips mid-transient
+# after a set-point increase, by an amount that grows with the step and
+# varies with the sampled coefficients.
 FC9_XBAR = np.array([1.6, 1.5, 1.4, 1.3, 1.2, 1.1, 1.0, 1.0, 1.0])
-FC9_THETA_NOM = np.array([3.0] * 9 + [1.0] * 6 + [1.0, 0.5, 0.5] + [0.5, 0.5])
-FC9_SCALARS = np.array([0.6, 1.0, 0.3, 0.2, 1.6])  # c_q0, p_amb, d0, d1, p1ref
+FC9_THETA_NOM = np.array([3.0] * 6 + [2.0, 3.0, 12.0] + [1.0] * 6 + [1.5, 0.5, 6.0] + [0.5, 0.5])
+FC9_SCALARS = np.array([0.7, 1.0, 0.05, 0.25, 1.6])  # c_q0, p_amb, d0, d1, p1ref
 
 
 def fc9_coeffs(seed: int, w_scale: float = 0.3) -> np.ndarray:
@@ -111,10 +115,10 @@ def fc9_coeffs(seed: int, w_scale: float = 0.3) -> np.ndarray:
 
 def fc9_problem(seed: int = 11, N: int = 1024, H: int = 1000, dt: float = 0.002,
                 w_half: float = 0.02, theta_rel: float = 0.1, eps: float = 0.05,
-                y1_min: float = 1.0, p1_max: float = 2.2, om1_max: float = 1.6,
+                y1_min: float = 2.35, p1_max: float = 2.1, om1_max: float = 2.2,
                 scen_seed: int = 4321, instance: int = 0, inject: int = INJECT_ODE,
                 ss_check: int = 1) -> Problem:
-    """Outputs y = (c_q0 w1 / (d0 + d1 v), p1, w1); constraints y1 >= y1_min,
+    """Outputs y = (c_q0 w1 / (d0 + d1 w3), p1, w1); constraints y1 >= y1_min,
     p1 <= p1_max, w1 <= om1_max written as F y <= g."""
     F = np.array([[-1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
     g = np.array([-y1_min, p1_max, om1_max])
@@ -138,10 +142,19 @@ def reference_sequence(seed: int, T: int, switch_every: int = 25, lo: float = -2
 # Named workloads
 # ---------------------------------------------------------------------------
 
+# The LQ4 workloads use plant seed 24 and a 1 % steady-state tightening: with
+# this tightening the disturbed scenario rollouts, not the steady-state test,
+# decide the admissible kappa whenever the reference is not admissible (a
+# 5 % tightening lets the steady-state test alone decide every step of these
+# overdamped plants).
+LQ4_PLANT_SEED = 24
+LQ4_EPS = 0.01
+
+
 def workload_lq4_fp64_single() -> dict:
     """Plain FP64 scenario RG, one update: LQ4, N=64, H=500, dt=0.01,
     x0=0, v_prev=0, r=1.5, 12 halvings."""
-    p = lq4_problem(N=64, H=500, dt=0.01)
+    p = lq4_problem(seed=LQ4_PLANT_SEED, N=64, H=500, dt=0.01, eps=LQ4_EPS)
     return dict(name="lq4_fp64_n64_h500", problem=p, x0=np.zeros(4), v_prev=0.0, r=1.5, K=12)
 
 
@@ -150,7 +163,7 @@ def workload_lq4_closed_loop(T: int = 200) -> dict:
     dt=0.005, closed loop over T RG steps tracking a piecewise-constant
     reference (levels U[-2, 2], new level every 25 steps), 12 halvings per
     step, recheck band 1e-4."""
-    p = lq4_problem(N=4096, H=2000, dt=0.005)
+    p = lq4_problem(seed=LQ4_PLANT_SEED, N=4096, H=2000, dt=0.005, eps=LQ4_EPS)
     return dict(name="lq4_closed_loop_n4096_h2000", problem=p, x0=np.zeros(4), v_prev=0.0,
                 r_seq=reference_sequence(2024, T), K=12, band=1e-4, T=T)
 

@@ -118,6 +118,31 @@ def test_trajectories_lq4(R, O):
     g.close()
 
 
+@pytest.mark.parametrize("H", [1, 6, 257])
+def test_one_lane_and_quad_rollouts_agree(R, O, H):
+    # the two FP32 LQ4 rollout layouts (one scenario per lane / per quad of lanes)
+    p = W.lq4_problem(N=130, H=H, dt=0.01)
+    o = O.Oracle(p, nthreads=8)
+    x0 = np.array([0.1, -0.05, 0.2, 0.0])
+    kap = np.array([0.0, 0.3, 0.7, 1.0])
+    outs = {}
+    for lanes in (1, 4):
+        g = _gov(R, p, lanes=lanes)
+        assert g.options.lanes == lanes
+        outs[lanes] = g.margin(x0, 1.5, 0.1, kap, per_scenario=True)
+        g.close()
+    for i, k in enumerate(kap):
+        _, per, _, _ = o.candidate(x0, o.candidate_v(k, 1.5, 0.1), 0)
+        for lanes in (1, 4):
+            assert _close32(outs[lanes]["per_scenario"][i], per) <= TOL32
+        assert np.array_equal(outs[1]["per_scenario_j"][i] >= 0, outs[4]["per_scenario_j"][i] >= 0)
+    for lanes in (1, 4):
+        g = _gov(R, p, lanes=lanes)
+        res = g.step(x0, 1.5, 0.1)
+        assert res["kappa"] == O.Oracle(p).bisect(x0, 1.5, 0.1, 0, 12)["kappa"]
+        g.close()
+
+
 def test_stream_and_inline_draws_give_identical_margins(R):
     p = W.lq4_problem(N=300, H=200)
     x0 = np.zeros(4)
@@ -175,11 +200,12 @@ def test_step_infeasible_start_keeps_v_prev(R, O):
     g.close()
 
 
-@pytest.mark.parametrize("N,H", [(1, 1), (1, 400), (257, 3), (513, 200)])
-def test_step_edge_sizes(R, O, N, H):
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("N,H", [(1, 1), (1, 400), (257, 3), (513, 202), (70, 5)])
+def test_step_edge_sizes(R, O, N, H, precision):
     p = W.lq4_problem(N=N, H=H, dt=0.01)
     o = O.Oracle(p, nthreads=8)
-    g = _gov(R, p, precision=R.PREC_F64)
+    g = _gov(R, p, precision=precision)
     for r in [1.5, -2.0]:
         t = g.get_step()
         res = g.step(np.zeros(4), r, 0.0)
