@@ -41,7 +41,7 @@ extern "C" {
 #define RG_OK 0
 #define RG_S_INFEASIBLE 1  /* valid output: no evaluated candidate was admissible;
                               kappa = 0 and v = v_prev (Alg. 1 starts from kappa_opt = 0) */
-#define RG_S_FALLBACK 2    /* valid output: the Newton search fell back to bisection */
+#define RG_S_FALLBACK 2    /* valid output: the Newton search took at least one midpoint step */
 #define RG_E_INVAL (-1)    /* null pointer, non-positive size, non-finite input, bad shape */
 #define RG_E_NOMEM (-2)    /* device or host allocation failed / workspace too small */
 #define RG_E_HIP (-3)      /* a HIP runtime call failed (message in rg_last_error) */
@@ -77,7 +77,13 @@ enum rg_precision {
 enum rg_search {
     RG_SEARCH_BISECT = 0, /* Alg. 1 on the worst margin: kappa = 1 probe, then K halvings */
     RG_SEARCH_GRID = 1,   /* Alg. 3 / Eq. (5): M-point grid, then `refine` halvings */
-    RG_SEARCH_NEWTON = 2  /* safeguarded Newton on the worst margin (reserved) */
+    RG_SEARCH_NEWTON = 2  /* safeguarded Newton on the worst margin M(kappa), derivative from
+                             the adjoint of the arg-min rollout (or the steady-state term):
+                             each device round tests the iterate kappa_N, kappa_N -/+ 2^-K and
+                             the bracket midpoint; a step outside the bracket or with a
+                             non-negative slope falls back to the midpoint (status
+                             RG_S_FALLBACK); stops at a bracket of 2^-K (at most K+2 rounds).
+                             FP32 precision only. */
 };
 
 /* ---- descriptors -------------------------------------------------------------- */
@@ -128,6 +134,7 @@ typedef struct rg_options {
     int32_t max_T;         /* closed-loop steps kept on the device per chunk (default 256) */
     int32_t lanes;         /* lanes per scenario of FP32 LQ4 rollouts: 1, 4 (one scenario per
                               quad, state split across lanes), 0 = auto */
+    int32_t Kc;            /* adjoint checkpoint interval in RK4 steps (default 50) */
 } rg_options;
 
 typedef struct rg_step_info {
@@ -224,6 +231,28 @@ int rg_get_options(const rg_handle* h, rg_options* out);
  * again resets).  rg_get_profile copies the totals. */
 int rg_set_profiling(rg_handle* h, int32_t enable);
 int rg_get_profile(const rg_handle* h, rg_profile* out);
+
+/* Derivatives of the candidate kappa's margins (not in the paper; they back the
+ * Newton search).  Reverse mode through the discrete RK4 map of each selected
+ * scenario: a forward pass keeps the state every Kc steps, the reverse sweep
+ * recomputes one segment at a time.  States and adjoints are FP32, parameter
+ * sums FP64, and the sum over scenarios has a fixed order (deterministic).
+ *   upstream == NULL: derivative of the worst margin M(kappa) = min(min_k m^k,
+ *     m_ss): the first minimising scenario's rollout term, or the steady-state
+ *     term (implicit-function derivative, FP64) when that is smaller;
+ *   upstream [N]: sum_k upstream[k] * d m^k, over scenarios with a nonzero weight.
+ * Outputs: margin_out (nullable) = M(kappa); dkappa_out = d/dkappa (through
+ * v = v_prev + kappa (r - v_prev)); dtheta_out (nullable, [n_theta]) =
+ * d/d(nominal coefficients) through theta^k = theta_nom * factor_k.  The margin
+ * is not differentiable where the minimiser changes; the derivative returned
+ * there is that of the first minimiser.  t is not advanced. */
+int rg_grad(rg_handle* h, const double* x, double r, double v_prev, double kappa,
+            const float* upstream, double* margin_out, double* dkappa_out, double* dtheta_out);
+
+/* Replace the nominal uncertain coefficients theta_nom ([n_theta], FC9 only);
+ * scenario k then uses theta_nom * factor_k with unchanged factors.
+ * RG_E_NOTSUP for plants without coefficients. */
+int rg_set_theta(rg_handle* h, const double* theta_nom);
 
 /* ---- inspection ----------------------------------------------------------------- */
 

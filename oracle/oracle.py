@@ -94,6 +94,15 @@ def lib() -> C.CDLL:
         L.orc_closed_loop.argtypes = [P, dp, C.c_double, dp, C.c_int32, C.c_uint32, C.c_int32,
                                       C.c_int32, C.c_int32, C.c_int32, dp, dp, dp]
         L.orc_closed_loop.restype = C.c_int32
+        L.orc_rollout_tangent.argtypes = [P, dp, C.c_double, C.c_uint32, C.c_uint32, dp, dp, ip, ip]
+        L.orc_rollout_tangent.restype = C.c_double
+        L.orc_steady_tangent.argtypes = [P, C.c_double, dp, dp]
+        L.orc_steady_tangent.restype = C.c_double
+        L.orc_candidate_grad.argtypes = [P, dp, C.c_double, C.c_double, C.c_double, C.c_uint32,
+                                         dp, dp, ip]
+        L.orc_candidate_grad.restype = C.c_double
+        L.orc_newton.argtypes = [P, dp, C.c_double, C.c_double, C.c_uint32, C.c_int32, ip, ip]
+        L.orc_newton.restype = _Result
         _lib = L
     return _lib
 
@@ -241,6 +250,41 @@ class Oracle:
         if want_P:
             out["P"] = P[:, : self.p.N]
         return out
+
+    # -- sensitivities -----------------------------------------------------------
+    def rollout_tangent(self, x0, v, t, k):
+        """(m, dm/dv, dm/dtheta_nom[n_theta], j*, r*) of scenario k."""
+        x0 = _f64(x0)
+        dv = C.c_double()
+        dth = np.zeros(MAXTH)
+        ja, ra = C.c_int32(), C.c_int32()
+        m = self.L.orc_rollout_tangent(self.ref, _dp(x0), float(v), t, k, C.byref(dv), _dp(dth),
+                                       C.byref(ja), C.byref(ra))
+        return m, dv.value, dth[: self.p.n_theta], ja.value, ra.value
+
+    def steady_tangent(self, v):
+        dv = C.c_double()
+        dth = np.zeros(MAXTH)
+        m = self.L.orc_steady_tangent(self.ref, float(v), C.byref(dv), _dp(dth))
+        return m, dv.value, dth[: self.p.n_theta]
+
+    def candidate_grad(self, x0, kappa, r, v_prev, t):
+        """(M(kappa), dM/dkappa, dM/dtheta_nom, arg-min scenario or -1 for the steady state)."""
+        x0 = _f64(x0)
+        dk = C.c_double()
+        dth = np.zeros(MAXTH)
+        ka = C.c_int32()
+        M = self.L.orc_candidate_grad(self.ref, _dp(x0), float(kappa), float(r), float(v_prev), t,
+                                      C.byref(dk), _dp(dth), C.byref(ka))
+        return M, dk.value, dth[: self.p.n_theta], ka.value
+
+    def newton(self, x0, r, v_prev, t, K):
+        x0 = _f64(x0)
+        rounds, fb = C.c_int32(), C.c_int32()
+        res = self.L.orc_newton(self.ref, _dp(x0), float(r), float(v_prev), t, K, C.byref(rounds),
+                                C.byref(fb))
+        return dict(kappa=res.kappa, v=res.v, worst=res.worst, passes=res.passes,
+                    status=res.status, rounds=rounds.value, fallbacks=fb.value)
 
     # -- closed loop ------------------------------------------------------------
     def plant_step(self, x, v, t) -> np.ndarray:

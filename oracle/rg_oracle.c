@@ -720,3 +720,359 @@ int32_t orc_closed_loop(const orc_problem* p, const double* x0, double v0, const
     }
     return infeasible;
 }
+
+/* ========================================================================= *
+ * Sensitivities (not in the paper; they back the adjoint/Newton search).
+ * Forward-mode tangents of the discrete RK4 map, propagated alongside the
+ * state: S_v = dx/dv and S_p = dx/dtheta_p (theta = the scenario's
+ * coefficients).  The margin's derivative is that of the minimising term
+ * (j*, r*) (first minimiser on ties); d/dtheta_nom = d/dtheta * factor_p.
+ * ========================================================================= */
+
+/* df/dx at (x, v, theta); w enters additively and drops out. */
+static void orc_jac_theta(const orc_problem* p, const double* th, const double* x, double v,
+                          double* J)
+{
+    if (p->kind == ORC_LQ4) {
+        orc_jacobian(p, x, v, J);
+        return;
+    }
+    /* FC9 with the scenario's theta: same structure as orc_jacobian. */
+    orc_problem q = *p;
+    for (int i = 0; i < 20; ++i) q.coeffs[90 + i] = th[i];
+    orc_jacobian(&q, x, v, J);
+}
+
+/* df/dv at (x, v, theta). */
+static void orc_dfdv(const orc_problem* p, const double* th, const double* x, double* fv)
+{
+    if (p->kind == ORC_LQ4) {
+        for (int i = 0; i < 4; ++i) fv[i] = p->coeffs[16 + i];
+        return;
+    }
+    const double* b = th + 15;
+    const double* mu = th + 18;
+    for (int i = 0; i < 9; ++i) fv[i] = 0.0;
+    fv[6] = b[0];
+    fv[7] = b[1] * x[6];
+    fv[8] = b[2] - mu[1] * (x[8] - 1.0);
+}
+
+/* df/dtheta (n x n_theta, row-major) at (x, v, theta); FC9 only. */
+static void orc_dfdtheta(const orc_problem* p, const double* th, const double* x, double v,
+                         double* Ft)
+{
+    const int n = p->n, nt = p->n_theta;
+    for (int i = 0; i < n * nt; ++i) Ft[i] = 0.0;
+    if (p->kind != ORC_FC9) return;
+    (void)th;
+    const double* xbar = p->coeffs + 81;
+    const double p_amb = p->coeffs[111], p1ref = p->coeffs[114];
+    for (int i = 0; i < 9; ++i) Ft[i * nt + i] = -(x[i] - xbar[i]);          /* a_i */
+    for (int l = 0; l < 6; ++l) {                                            /* k_l */
+        double downstream = (l < 5) ? x[l + 1] : p_amb;
+        double dp = x[l] - downstream;
+        double s = sqrt(dp > 0.0 ? dp : 0.0);
+        Ft[l * nt + 9 + l] += -s;
+        if (l < 5) Ft[(l + 1) * nt + 9 + l] += s;
+    }
+    Ft[6 * nt + 15] = v;                          /* b1 */
+    Ft[7 * nt + 16] = v * x[6];                   /* b2 */
+    Ft[8 * nt + 17] = v;                          /* b3 */
+    Ft[6 * nt + 18] = -x[6] * (x[0] - p1ref);     /* mu1 */
+    Ft[8 * nt + 19] = -(x[8] - 1.0) * v;          /* mu2 */
+}
+
+/* dy/dx (n_y x n) at x; the outputs of both plants do not depend on v. */
+static void orc_dhdx(const orc_problem* p, const double* x, double* Hx)
+{
+    const int n = p->n;
+    for (int i = 0; i < p->n_y * n; ++i) Hx[i] = 0.0;
+    if (p->kind == ORC_LQ4) {
+        for (int i = 0; i < 8; ++i) Hx[i] = p->coeffs[44 + i];
+        return;
+    }
+    const double* c = p->coeffs;
+    double den = c[112] + c[113] * x[8];
+    Hx[0 * n + 6] = c[110] / den;
+    Hx[0 * n + 8] = -c[110] * x[6] * c[113] / (den * den);
+    Hx[1 * n + 0] = 1.0;
+    Hx[2 * n + 6] = 1.0;
+}
+
+/* Tangent of one RK4 step: given x and tangent columns T (n x m), advance both. */
+static void orc_rk4_tangent(const orc_problem* p, const double* th, const double* x, double v,
+                            const double* w, double* T, int m, const double* T_force,
+                            double* xn)
+{
+    /* T_force(xs) supplies df/dparam at the stage state: column 0 = d/dv, columns
+     * 1.. = d/dtheta; recomputed inside for each stage. */
+    (void)T_force;
+    const int n = p->n;
+    const double h = p->dt;
+    double xs[ORC_MAXN], k[4][ORC_MAXN];
+    double dk[4][ORC_MAXN * (1 + ORC_MAXTH)];
+    double dxs[ORC_MAXN * (1 + ORC_MAXTH)];
+    double J[ORC_MAXN * ORC_MAXN], fv[ORC_MAXN], Ft[ORC_MAXN * ORC_MAXTH];
+    const double c[4] = {0.0, 0.5, 0.5, 1.0};
+    double zero[ORC_MAXW] = {0};
+    const double* wu = (p->inject == ORC_INJECT_ODE) ? w : zero;
+    for (int s = 0; s < 4; ++s) {
+        for (int i = 0; i < n; ++i) xs[i] = (s == 0) ? x[i] : x[i] + (c[s] * h) * k[s - 1][i];
+        for (int i = 0; i < n * m; ++i)
+            dxs[i] = (s == 0) ? T[i] : T[i] + (c[s] * h) * dk[s - 1][i];
+        orc_rhs(p, th, xs, v, wu, k[s]);
+        orc_jac_theta(p, th, xs, v, J);
+        orc_dfdv(p, th, xs, fv);
+        orc_dfdtheta(p, th, xs, v, Ft);
+        for (int i = 0; i < n; ++i) {
+            for (int col = 0; col < m; ++col) {
+                double acc = 0.0;
+                for (int q = 0; q < n; ++q) acc += J[i * n + q] * dxs[q * m + col];
+                if (col == 0) acc += fv[i];
+                else acc += Ft[i * p->n_theta + (col - 1)];
+                dk[s][i * m + col] = acc;
+            }
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        xn[i] = x[i] + (h / 6.0) * (k[0][i] + 2.0 * k[1][i] + 2.0 * k[2][i] + k[3][i]);
+    for (int i = 0; i < n * m; ++i)
+        T[i] = T[i] + (h / 6.0) * (dk[0][i] + 2.0 * dk[1][i] + 2.0 * dk[2][i] + dk[3][i]);
+    if (p->inject == ORC_INJECT_POST) {
+        if (p->kind == ORC_LQ4) {
+            const double* E = p->coeffs + 36;
+            for (int i = 0; i < 4; ++i) xn[i] = xn[i] + (E[2 * i] * w[0] + E[2 * i + 1] * w[1]);
+        } else {
+            for (int i = 0; i < n; ++i) xn[i] = xn[i] + w[i];
+        }
+    }
+}
+
+/* Worst margin of scenario k with its derivatives: dm/dv and dm/dtheta_nom
+ * (n_theta values; zero-length for LQ4).  Same margin, minimiser and
+ * non-finite rules as orc_rollout. */
+double orc_rollout_tangent(const orc_problem* p, const double* x0, double v, uint32_t t,
+                           uint32_t k, double* dm_dv, double* dm_dtheta_nom,
+                           int32_t* j_arg, int32_t* r_arg)
+{
+    const int n = p->n, nt = p->n_theta, m = 1 + nt;
+    double x[ORC_MAXN], xn[ORC_MAXN], y[ORC_MAXY], w[ORC_MAXW], theta[ORC_MAXTH];
+    double T[ORC_MAXN * (1 + ORC_MAXTH)] = {0};
+    double Hx[ORC_MAXY * ORC_MAXN];
+    double factor[ORC_MAXTH];
+    if (nt > 0) {
+        orc_draw_theta(p, t, k, theta);
+        for (int q = 0; q < nt; ++q) factor[q] = theta[q] / p->coeffs[90 + q];
+    }
+    memcpy(x, x0, sizeof(double) * (size_t)n);
+    double best = INFINITY;
+    double best_dv = 0.0, best_dth[ORC_MAXTH] = {0};
+    int32_t bj = 0, br = 0;
+    for (int32_t j = 0; j <= p->H; ++j) {
+        int32_t r = 0;
+        double mj;
+        if (!all_finite(x, n)) {
+            mj = -INFINITY;
+        } else {
+            orc_output(p, x, v, y);
+            mj = orc_margin(p, y, &r);
+            if (!isfinite(mj) && mj != INFINITY) mj = -INFINITY;
+        }
+        if (mj < best || j == 0) {
+            best = mj;
+            bj = j;
+            br = r;
+            /* dm_j/d. = -F_r Hx dx/d. */
+            orc_dhdx(p, x, Hx);
+            double g[ORC_MAXN];
+            for (int i = 0; i < n; ++i) {
+                double a = 0.0;
+                for (int yy = 0; yy < p->n_y; ++yy) a += p->F[r * p->n_y + yy] * Hx[yy * n + i];
+                g[i] = -a;
+            }
+            best_dv = 0.0;
+            for (int i = 0; i < n; ++i) best_dv += g[i] * T[i * m + 0];
+            for (int q = 0; q < nt; ++q) {
+                double a = 0.0;
+                for (int i = 0; i < n; ++i) a += g[i] * T[i * m + 1 + q];
+                best_dth[q] = a;
+            }
+        }
+        if (best == -INFINITY) break;
+        if (j == p->H) break;
+        orc_draw_w(p, t, k, (uint32_t)j, w);
+        orc_rk4_tangent(p, nt > 0 ? theta : NULL, x, v, w, T, m, NULL, xn);
+        memcpy(x, xn, sizeof(double) * (size_t)n);
+    }
+    if (dm_dv) *dm_dv = best_dv;
+    if (dm_dtheta_nom)
+        for (int q = 0; q < nt; ++q) dm_dtheta_nom[q] = best_dth[q] * factor[q];
+    if (j_arg) *j_arg = bj;
+    if (r_arg) *r_arg = br;
+    return best;
+}
+
+/* Steady-state margin with its derivatives by the implicit function theorem:
+ * f(x_ss, v, theta_nom) = 0 => dx_ss/d. = -J^{-1} df/d. */
+double orc_steady_tangent(const orc_problem* p, double v, double* dmss_dv, double* dmss_dtheta)
+{
+    const int n = p->n, nt = p->n_theta;
+    double xs[ORC_MAXN];
+    double mss = orc_steady_margin(p, v, xs, NULL);
+    if (dmss_dv) *dmss_dv = 0.0;
+    if (dmss_dtheta)
+        for (int q = 0; q < nt; ++q) dmss_dtheta[q] = 0.0;
+    if (!isfinite(mss)) return mss;
+    const double* thn = nominal_theta(p);
+    double J[ORC_MAXN * ORC_MAXN], rhs[ORC_MAXN], fv[ORC_MAXN], Ft[ORC_MAXN * ORC_MAXTH];
+    double y[ORC_MAXY], Hx[ORC_MAXY * ORC_MAXN];
+    orc_output(p, xs, v, y);
+    int r_arg = 0;
+    double best = INFINITY;
+    for (int r = 0; r < p->n_c; ++r) {
+        double fy = 0.0;
+        for (int i = 0; i < p->n_y; ++i) fy += p->F[r * p->n_y + i] * y[i];
+        double m = (p->g[r] - p->eps * fabs(p->g[r])) - fy;
+        if (r == 0 || m < best) {
+            best = m;
+            r_arg = r;
+        }
+    }
+    orc_dhdx(p, xs, Hx);
+    double gr[ORC_MAXN];
+    for (int i = 0; i < n; ++i) {
+        double a = 0.0;
+        for (int yy = 0; yy < p->n_y; ++yy) a += p->F[r_arg * p->n_y + yy] * Hx[yy * n + i];
+        gr[i] = -a;
+    }
+    orc_dfdv(p, thn, xs, fv);
+    orc_dfdtheta(p, thn, xs, v, Ft);
+    /* dx/dv */
+    orc_jacobian(p, xs, v, J);
+    for (int i = 0; i < n; ++i) rhs[i] = -fv[i];
+    if (dense_solve(n, J, rhs) != 0) return mss;
+    double dv = 0.0;
+    for (int i = 0; i < n; ++i) dv += gr[i] * rhs[i];
+    if (dmss_dv) *dmss_dv = dv;
+    if (dmss_dtheta) {
+        for (int q = 0; q < nt; ++q) {
+            orc_jacobian(p, xs, v, J);
+            for (int i = 0; i < n; ++i) rhs[i] = -Ft[i * nt + q];
+            if (dense_solve(n, J, rhs) != 0) return mss;
+            double a = 0.0;
+            for (int i = 0; i < n; ++i) a += gr[i] * rhs[i];
+            dmss_dtheta[q] = a;
+        }
+    }
+    return mss;
+}
+
+/* Candidate worst margin M(kappa) with dM/dkappa and dM/dtheta_nom: the
+ * derivative of the active term (the first minimising scenario, or the
+ * steady-state margin when it is the smaller).  dv/dkappa = r - v_prev. */
+double orc_candidate_grad(const orc_problem* p, const double* x0, double kappa, double r,
+                          double v_prev, uint32_t t, double* dM_dkappa, double* dM_dtheta,
+                          int32_t* k_arg)
+{
+    const int nt = p->n_theta;
+    double v = orc_candidate_v(kappa, r, v_prev);
+    int32_t ka = 0;
+    double mss = 0.0;
+    double* per = (double*)malloc(sizeof(double) * (size_t)(p->N > 0 ? p->N : 1));
+    double M = orc_candidate(p, x0, v, t, per, &ka, &mss);
+    double worst_roll = p->N > 0 ? per[ka] : INFINITY;
+    free(per);
+    double dv = 0.0, dth[ORC_MAXTH] = {0};
+    if (mss < worst_roll) {          /* the steady-state term is active */
+        orc_steady_tangent(p, v, &dv, dth);
+        ka = -1;
+    } else {                          /* ties go to the rollout term */
+        orc_rollout_tangent(p, x0, v, t, (uint32_t)ka, &dv, dth, NULL, NULL);
+    }
+    if (dM_dkappa) *dM_dkappa = dv * (r - v_prev);
+    if (dM_dtheta)
+        for (int q = 0; q < nt; ++q) dM_dtheta[q] = dth[q];
+    if (k_arg) *k_arg = ka;
+    return M;
+}
+
+/* ========================================================================= *
+ * Safeguarded Newton search on phi(kappa) = M(kappa) (an alternative to the
+ * bisection of Alg. 1; not in the paper).  Round 0 evaluates kappa = 1 (stop
+ * if admissible) and the midpoint 1/2.  Each later round evaluates the Newton
+ * iterate kappa_N, its neighbours kappa_N -/+ delta (delta = 2^-K) and the
+ * bracket midpoint; every verdict tightens the bracket [lo, hi] (lo admissible
+ * or 0, hi refused).  kappa_N = kappa_c - phi(kappa_c) / phi'(kappa_c) from the
+ * last iterate kappa_c (derivative of the active term); a step that is not
+ * strictly inside the bracket, or a non-negative slope, falls back to the
+ * midpoint.  Stops when hi - lo <= delta and returns lo.  The midpoint makes the
+ * bracket at least halve per round, so at most K + 1 rounds.
+ * ========================================================================= */
+orc_result orc_newton(const orc_problem* p, const double* x0, double r, double v_prev,
+                      uint32_t t, int32_t K, int32_t* rounds_out, int32_t* fallbacks_out)
+{
+    orc_result res = {0.0, v_prev, -INFINITY, 0, 1};
+    const double delta = ldexp(1.0, -K);
+    double lo = 0.0, hi = 1.0;
+    int found = 0, rounds = 0, fallbacks = 0;
+    double worst_lo = -INFINITY;
+    double kc = 1.0, phi = 0.0, dphi = 0.0;
+    /* round 0 */
+    phi = orc_candidate_grad(p, x0, 1.0, r, v_prev, t, &dphi, NULL, NULL);
+    res.passes++;
+    rounds = 1;
+    if (phi >= 0.0) {
+        res.kappa = 1.0;
+        res.v = r;
+        res.worst = phi;
+        res.status = 0;
+        if (rounds_out) *rounds_out = rounds;
+        if (fallbacks_out) *fallbacks_out = 0;
+        return res;
+    }
+    {
+        double Mm = orc_candidate(p, x0, orc_candidate_v(0.5, r, v_prev), t, NULL, NULL, NULL);
+        res.passes++;
+        if (Mm >= 0.0) { lo = 0.5; found = 1; worst_lo = Mm; }
+        else hi = 0.5;
+    }
+    while (hi - lo > delta && rounds < K + 2) {
+        double kn;
+        int newton_ok = isfinite(phi) && isfinite(dphi) && dphi < 0.0;
+        kn = newton_ok ? kc - phi / dphi : 0.5 * (lo + hi);
+        if (!(kn > lo && kn < hi)) {
+            kn = 0.5 * (lo + hi);
+            newton_ok = 0;
+        }
+        if (!newton_ok) fallbacks++;
+        double cand[4] = {kn - delta, kn, kn + delta, 0.5 * (lo + hi)};
+        double M[4];
+        double dn = 0.0;
+        for (int c = 0; c < 4; ++c) {
+            if (!(cand[c] > lo && cand[c] < hi)) { M[c] = NAN; continue; }
+            if (c == 1) M[c] = orc_candidate_grad(p, x0, cand[c], r, v_prev, t, &dn, NULL, NULL);
+            else M[c] = orc_candidate(p, x0, orc_candidate_v(cand[c], r, v_prev), t, NULL, NULL, NULL);
+            res.passes++;
+        }
+        for (int c = 0; c < 4; ++c) {
+            if (M[c] != M[c]) continue;
+            if (M[c] >= 0.0) {
+                if (cand[c] > lo) { lo = cand[c]; found = 1; worst_lo = M[c]; }
+            } else if (cand[c] < hi) {
+                hi = cand[c];
+            }
+        }
+        kc = kn;
+        phi = M[1];
+        dphi = dn;
+        rounds++;
+    }
+    res.kappa = found ? lo : 0.0;
+    res.v = found ? orc_candidate_v(lo, r, v_prev) : v_prev;
+    res.worst = worst_lo;
+    res.status = found ? 0 : 1;
+    if (rounds_out) *rounds_out = rounds;
+    if (fallbacks_out) *fallbacks_out = fallbacks;
+    return res;
+}

@@ -113,6 +113,17 @@ int32_t orc_closed_loop(const orc_problem* p, const double* x0, double v0, const
                         int32_t T, uint32_t t0, int32_t search, int32_t K, int32_t M,
                         int32_t refine, double* v_out, double* kappa_out, double* x_out);
 
+/* ---- sensitivities (back the adjoint / Newton search) ------------------ */
+double orc_rollout_tangent(const orc_problem* p, const double* x0, double v, uint32_t t,
+                           uint32_t k, double* dm_dv, double* dm_dtheta_nom,
+                           int32_t* j_arg, int32_t* r_arg);
+double orc_steady_tangent(const orc_problem* p, double v, double* dmss_dv, double* dmss_dtheta);
+double orc_candidate_grad(const orc_problem* p, const double* x0, double kappa, double r,
+                          double v_prev, uint32_t t, double* dM_dkappa, double* dM_dtheta,
+                          int32_t* k_arg);
+orc_result orc_newton(const orc_problem* p, const double* x0, double r, double v_prev,
+                      uint32_t t, int32_t K, int32_t* rounds_out, int32_t* fallbacks_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -70,7 +70,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace layout: offsets of each buffer inside one allocation.
 struct Layout {
-  size_t st, srch, res, r_seq, x_hist, wbuf, thbuf, rlist, per_m, per_j, scratch, total;
+  size_t st, srch, res, r_seq, x_hist, wbuf, thbuf, rlist, per_m, per_j, scratch;
+  size_t grad, adj_k, adj_w, adj_m, adj_dv, adj_dth, adj_ckpt, adj_seg, total;
 };
 
 Layout layout_of(const rg_handle* h) {
@@ -95,6 +96,15 @@ Layout layout_of(const rg_handle* h) {
   L.per_m = take(sizeof(float) * (size_t)kCMax * N);
   L.per_j = take(sizeof(int32_t) * (size_t)kCMax * N);
   L.scratch = take(sizeof(double) * kCMax * 4);
+  const size_t n = (size_t)pr.p.n, Kc = (size_t)h->opt.Kc;
+  L.grad = take(sizeof(DevGrad));
+  L.adj_k = take(sizeof(int32_t) * N);
+  L.adj_w = take(sizeof(float) * N);
+  L.adj_m = take(sizeof(float) * N);
+  L.adj_dv = take(sizeof(double) * N);
+  L.adj_dth = take(sizeof(double) * kMaxTh * N);
+  L.adj_ckpt = take(sizeof(float) * ((size_t)pr.H / Kc + 1) * n * N);
+  L.adj_seg = take(sizeof(float) * Kc * n * N);
   L.total = off;
   return L;
 }
@@ -129,7 +139,10 @@ void plan(rg_handle* h) {
   c.lanes = lanes;
   c.block = h->opt.block > 0 ? h->opt.block : 256;
   const int tree = (1 << d) - 1;
-  if (h->opt.search == RG_SEARCH_GRID) {
+  if (h->opt.search == RG_SEARCH_NEWTON) {
+    c.cmax_round = 4;
+    c.rounds = h->opt.K + 2;
+  } else if (h->opt.search == RG_SEARCH_GRID) {
     c.cmax_round = h->opt.M > tree ? h->opt.M : tree;
     c.rounds = 1 + (h->opt.refine + d - 1) / d;
   } else {
@@ -166,11 +179,21 @@ int ensure_workspace(rg_handle* h) {
   b.per_j = (int32_t*)(base + L.per_j);
   b.scratch = (double*)(base + L.scratch);
   b.scratch_bytes = sizeof(double) * kCMax * 4;
+  b.grad = (DevGrad*)(base + L.grad);
+  b.adj_k = (int32_t*)(base + L.adj_k);
+  b.adj_w = (float*)(base + L.adj_w);
+  b.adj_m = (float*)(base + L.adj_m);
+  b.adj_dv = (double*)(base + L.adj_dv);
+  b.adj_dth = (double*)(base + L.adj_dth);
+  b.adj_ckpt = (float*)(base + L.adj_ckpt);
+  b.adj_seg = (float*)(base + L.adj_seg);
   // Search configuration.
   DevSearch* S = new (std::nothrow) DevSearch;
   if (!S) return fail(h, RG_E_NOMEM, "host allocation");
   memset(S, 0, sizeof(DevSearch));
-  S->mode = h->opt.search == RG_SEARCH_GRID ? kGrid : kBisect;
+  S->mode = h->opt.search == RG_SEARCH_GRID ? kGrid
+            : h->opt.search == RG_SEARCH_NEWTON ? kNewton : kBisect;
+  S->delta = std::ldexp(1.0, -h->opt.K);
   S->K = h->opt.K;
   S->depth = h->opt.depth;
   S->M = h->opt.M;
@@ -246,6 +269,7 @@ hipError_t enqueue_step(rg_handle* h, int closed_loop) {
   if (h->pr.s.rng_mode == RG_RNG_STREAM && (e = launch_gen(h->pr, h->b, h->stream)) != hipSuccess)
     return e;
   if ((e = launch_setup(h->pr, h->b, closed_loop, h->stream)) != hipSuccess) return e;
+  const bool newton = h->opt.search == RG_SEARCH_NEWTON;
   for (int r = 0; r < h->cfg.rounds; ++r) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->profiling) {
@@ -259,6 +283,11 @@ hipError_t enqueue_step(rg_handle* h, int closed_loop) {
     if (prec == RG_PREC_F32_RECHECK &&
         (e = launch_recheck(h->pr, h->opt.early_exit, h->cfg, h->b, h->stream)) != hipSuccess)
       return e;
+    if (newton) {  // derivative of the Newton iterate's worst margin (adjoint)
+      if ((e = launch_grad_prepare(h->pr, h->b, -1, 1, h->stream)) != hipSuccess) return e;
+      if ((e = launch_adjoint(h->pr, h->opt.Kc, 1, h->b, -1, h->stream)) != hipSuccess) return e;
+      if ((e = launch_grad_reduce(h->b, 1, h->pr.p.nth, -1, h->stream)) != hipSuccess) return e;
+    }
     if ((e = launch_decide(h->pr, h->b, h->stream)) != hipSuccess) return e;
   }
   return launch_finalize(h->pr, closed_loop, h->b, h->stream);
@@ -295,6 +324,7 @@ int rg_default_options(rg_options* opt) {
   opt->block = 0;
   opt->max_T = 256;
   opt->lanes = 0;
+  opt->Kc = 50;
   return RG_OK;
 }
 
@@ -348,9 +378,10 @@ int rg_create(const rg_plant* plant, const rg_scenarios* scen, const rg_constrai
     return fail(nullptr, RG_E_INVAL, "bad precision");
   if (!(o.band >= 0.0) || !std::isfinite(o.band)) return fail(nullptr, RG_E_INVAL, "bad band");
   if (o.K < 0 || o.K > 40) return fail(nullptr, RG_E_INVAL, "K must be in [0, 40]");
-  if (o.search == RG_SEARCH_NEWTON) return fail(nullptr, RG_E_NOTSUP, "Newton search not in this build");
-  if (o.search != RG_SEARCH_BISECT && o.search != RG_SEARCH_GRID)
+  if (o.search != RG_SEARCH_BISECT && o.search != RG_SEARCH_GRID && o.search != RG_SEARCH_NEWTON)
     return fail(nullptr, RG_E_INVAL, "bad search");
+  if (o.search == RG_SEARCH_NEWTON && o.precision != RG_PREC_F32_RECHECK)
+    return fail(nullptr, RG_E_NOTSUP, "Newton search runs on the FP32 rollouts and adjoint");
   if (o.depth < 0 || o.depth > 6) return fail(nullptr, RG_E_INVAL, "depth must be in [0, 6]");
   if (o.search == RG_SEARCH_GRID && (o.M < 2 || o.M > kCMax - 1))
     return fail(nullptr, RG_E_INVAL, "M must be in [2, 127]");
@@ -359,6 +390,7 @@ int rg_create(const rg_plant* plant, const rg_scenarios* scen, const rg_constrai
     return fail(nullptr, RG_E_INVAL, "block must be a multiple of 64 in [64, 256]");
   if (o.max_T < 1 || o.max_T > 65536) return fail(nullptr, RG_E_INVAL, "max_T must be in [1, 65536]");
   if (o.lanes != 0 && o.lanes != 1 && o.lanes != 4) return fail(nullptr, RG_E_INVAL, "lanes must be 0, 1 or 4");
+  if (o.Kc < 1 || o.Kc > 4096) return fail(nullptr, RG_E_INVAL, "Kc must be in [1, 4096]");
 
   rg_handle* h = new (std::nothrow) rg_handle;
   if (!h) return fail(nullptr, RG_E_NOMEM, "host allocation");
@@ -457,7 +489,7 @@ int rg_step(rg_handle* h, const double* x, double r, double v_prev, double* v_ou
   *v_out = R.v;
   if (kappa_out) *kappa_out = R.kappa;
   fill_info(R, info);
-  return R.status == 0 ? RG_OK : RG_S_INFEASIBLE;
+  return R.status == 0 ? RG_OK : (R.status == 2 ? RG_S_FALLBACK : RG_S_INFEASIBLE);
 }
 
 int rg_margin(rg_handle* h, const double* x, double r, double v_prev, const double* kappa,
@@ -565,6 +597,77 @@ int rg_closed_loop(rg_handle* h, const double* x0, double v0, const double* r_se
     h->t += (uint32_t)chunk;
   }
   h->gen_t = (long long)h->t - 1;
+  return RG_OK;
+}
+
+int rg_grad(rg_handle* h, const double* x, double r, double v_prev, double kappa,
+            const float* upstream, double* margin_out, double* dkappa_out, double* dtheta_out) {
+  if (!h) return RG_E_INVAL;
+  if (!x || !dkappa_out) return fail(h, RG_E_INVAL, "NULL x or dkappa_out");
+  if (!finite_array(x, h->pr.p.n) || !std::isfinite(r) || !std::isfinite(v_prev))
+    return fail(h, RG_E_INVAL, "non-finite input");
+  if (!(kappa >= 0.0 && kappa <= 1.0)) return fail(h, RG_E_INVAL, "kappa outside [0, 1]");
+  const int N = h->pr.s.N;
+  std::vector<int32_t> ks;
+  std::vector<float> ws;
+  if (upstream) {
+    for (int k = 0; k < N; ++k) {
+      if (!std::isfinite(upstream[k])) return fail(h, RG_E_INVAL, "non-finite upstream gradient");
+      if (upstream[k] != 0.f) {
+        ks.push_back(k);
+        ws.push_back(upstream[k]);
+      }
+    }
+  }
+  int rc = ensure_workspace(h);
+  if (rc) return rc;
+  if ((rc = upload_state(h, x, r, v_prev))) return rc;
+  if ((rc = ensure_draws(h))) return rc;
+  LaunchCfg cfg = h->cfg;
+  cfg.cmax_round = 1;
+  HIPCHK(h, hipMemcpyAsync((char*)h->b.srch + offsetof(DevSearch, kappa), &kappa, sizeof(double),
+                           hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, launch_setup_list(h->pr, h->b, 1, h->stream));
+  // arg-min scenario from the FP32 rollouts (keys carry the scenario index)
+  HIPCHK(h, launch_rollout(h->pr, h->opt.band, RG_PREC_F32_RECHECK, 0, 1, cfg, h->b, h->stream));
+  HIPCHK(h, launch_recheck(h->pr, 0, cfg, h->b, h->stream));
+  int max_entries = 1;
+  if (upstream) {
+    const int32_t cnt = (int32_t)ks.size();
+    max_entries = cnt > 0 ? cnt : 1;
+    if (cnt > 0) {
+      HIPCHK(h, hipMemcpyAsync(h->b.adj_k, ks.data(), sizeof(int32_t) * cnt, hipMemcpyHostToDevice,
+                               h->stream));
+      HIPCHK(h, hipMemcpyAsync(h->b.adj_w, ws.data(), sizeof(float) * cnt, hipMemcpyHostToDevice,
+                               h->stream));
+    }
+    HIPCHK(h, hipMemcpyAsync((char*)h->b.grad + offsetof(DevGrad, n_entries), &cnt, sizeof(cnt),
+                             hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, launch_grad_prepare(h->pr, h->b, 0, 0, h->stream));
+  } else {
+    HIPCHK(h, launch_grad_prepare(h->pr, h->b, 0, 1, h->stream));
+  }
+  HIPCHK(h, launch_adjoint(h->pr, h->opt.Kc, max_entries, h->b, 0, h->stream));
+  HIPCHK(h, launch_grad_reduce(h->b, max_entries, h->pr.p.nth, 0, h->stream));
+  DevGrad G;
+  HIPCHK(h, hipMemcpyAsync(&G, h->b.grad, sizeof(G), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (margin_out) *margin_out = G.M;
+  *dkappa_out = G.dM_dkappa;
+  if (dtheta_out)
+    for (int c = 0; c < h->pr.p.nth; ++c) dtheta_out[c] = G.dM_dth[c];
+  return RG_OK;
+}
+
+int rg_set_theta(rg_handle* h, const double* theta_nom) {
+  if (!h) return RG_E_INVAL;
+  if (h->pr.p.nth == 0) return fail(h, RG_E_NOTSUP, "this plant has no uncertain coefficients");
+  if (!theta_nom || !finite_array(theta_nom, h->pr.p.nth)) return fail(h, RG_E_INVAL, "bad theta");
+  for (int c = 0; c < h->pr.p.nth; ++c) h->pr.p.coeffs[90 + c] = theta_nom[c];
+  if (h->step_graph) {  // kernel arguments changed
+    (void)hipGraphExecDestroy(h->step_graph);
+    h->step_graph = nullptr;
+  }
   return RG_OK;
 }
 

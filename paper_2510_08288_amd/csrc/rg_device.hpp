@@ -163,6 +163,26 @@ struct Plant<1, T> {
       y[i] = a;
     }
   }
+  // Reverse mode: xb = J(x)^T al, vb += al . df/dv (df/dtheta: none).
+  __device__ static void vjp(const Coef& c, const Lane&, const T* x, const T* al, T* xb,
+                             double& vb, double*) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      T acc = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc = t_fma(t_fma(2 * c.G[4 * i + j], x[j], c.A[4 * i + j]), al[i], acc);
+      xb[j] = acc;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s += (double)al[i] * (double)c.B[i];
+    vb += s;
+  }
+  // dm/dx of the margin row m = g_r - F_r h(x) (F row given).
+  __device__ static void out_grad(const Coef& c, const T* Fr, const T*, T* gx) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) gx[j] = -(Fr[0] * c.C[j] + Fr[1] * c.C[4 + j]);
+  }
   // Equilibrium helpers (FP64 only): initial guess solves A x = -B v.
   __device__ static void eq_guess(const Coef& c, T v, T* x, T* J) {
 #pragma unroll
@@ -171,6 +191,10 @@ struct Plant<1, T> {
     for (int i = 0; i < 4; ++i) x[i] = -(c.B[i] * v);
   }
   __device__ static bool eq_guess_needs_solve() { return true; }
+  __device__ static void dfdv(const Coef& c, const T*, T* fv) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) fv[i] = c.B[i];
+  }
   __device__ static void jacobian(const Coef& c, const T* x, T, T* J) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -263,6 +287,71 @@ struct Plant<2, T> {
     y[1] = x[0];
     y[2] = x[6];
   }
+  // Reverse mode: xb = J(x)^T al, vb += al . df/dv, tb += al . df/dtheta
+  // (theta = the lane's coefficients a, k, b, mu).
+  __device__ static void vjp(const Coef& c, const Lane& L, const T* x, const T* al, T* xb,
+                             double& vb, double* tb) {
+    T z[9], tz[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      z[j] = x[j] - c.xbar[j];
+      tz[j] = t_tanh(z[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      T acc = 0;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) acc = t_fma(c.W[9 * i + j], al[i], acc);
+      xb[j] = t_fma(-L.a[j], al[j], acc * (1 - tz[j] * tz[j]));
+      tb[j] += -(double)al[j] * (double)z[j];
+    }
+    // orifice flows q_{l+1} = k_l sqrt(max(dp_l, 0)): -in phi_l, +in phi_{l+1}
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+      const T dn = (l < 5) ? x[l + 1] : c.p_amb;
+      const T dp = x[l] - dn;
+      const T sq = dp > (T)0 ? t_sqrt(dp) : (T)0;
+      const T d = dp > (T)0 ? L.kq[l] / (2 * sq) : (T)0;
+      const T beta = (l < 5) ? al[l + 1] - al[l] : -al[l];
+      xb[l] += beta * d;
+      if (l < 5) xb[l + 1] -= beta * d;
+      tb[9 + l] += (double)beta * (double)sq;
+    }
+    xb[6] += al[0] * c.c_q0;  // q0 in phi_1
+    // phi_7 = b1 v - mu1 w1 (p1 - p1ref)
+    xb[6] -= al[6] * L.mu[0] * (x[0] - c.p1ref);
+    xb[0] -= al[6] * L.mu[0] * x[6];
+    // phi_8 = b2 v w1
+    xb[6] += al[7] * L.b[1] * L.v;
+    // phi_9 = b3 v - mu2 (w3 - 1) v
+    xb[8] -= al[8] * L.mu[1] * L.v;
+    const double v = (double)L.v;
+    vb += (double)al[6] * (double)L.b[0] + (double)al[7] * (double)L.b[1] * (double)x[6] +
+          (double)al[8] * ((double)L.b[2] - (double)L.mu[1] * ((double)x[8] - 1.0));
+    tb[15] += (double)al[6] * v;
+    tb[16] += (double)al[7] * v * (double)x[6];
+    tb[17] += (double)al[8] * v;
+    tb[18] += -(double)al[6] * (double)x[6] * ((double)x[0] - (double)c.p1ref);
+    tb[19] += -(double)al[8] * ((double)x[8] - 1.0) * v;
+  }
+  __device__ static void out_grad(const Coef& c, const T* Fr, const T* x, T* gx) {
+#pragma unroll
+    for (int j = 0; j < 9; ++j) gx[j] = 0;
+    const T den = t_fma(c.d1, x[8], c.d0);
+    gx[6] = -(Fr[0] * c.c_q0 / den + Fr[2]);
+    gx[8] = Fr[0] * c.c_q0 * x[6] * c.d1 / (den * den);
+    gx[0] = -Fr[1];
+  }
+  // df/dv and df/dtheta at nominal theta (FP64, steady-state sensitivities).
+  __device__ static void dfdv(const Coef& c, const T* x, T* fv) {
+    const T* b = c.thnom + 15;
+    const T* mu = c.thnom + 18;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fv[i] = 0;
+    fv[6] = b[0];
+    fv[7] = b[1] * x[6];
+    fv[8] = b[2] - mu[1] * (x[8] - 1);
+  }
   __device__ static void eq_guess(const Coef& c, T, T* x, T*) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) x[i] = c.xbar[i];
@@ -332,7 +421,72 @@ __device__ __forceinline__ void rk4_step(const typename Plant<KIND, T>::Coef& c,
   for (int i = 0; i < P::n; ++i) x[i] = t_fma(h6, acc[i] + k[i], x[i]);
 }
 
+// Reverse sweep of one RK4 step at x with forcing s: lam <- (dPhi/dx)^T lam,
+// vb += lam . dPhi/dv, tb += lam . dPhi/dtheta.  Stage states are recomputed.
+template <int KIND, class T>
+__device__ __forceinline__ void rk4_vjp(const typename Plant<KIND, T>::Coef& c,
+                                        const typename Plant<KIND, T>::Lane& L, const T* s,
+                                        T h, T hh, T h6, const T* x, T* lam, double& vb,
+                                        double* tb) {
+  using P = Plant<KIND, T>;
+  constexpr int n = P::n;
+  T x2[n], x3[n], x4[n], k[n];
+  P::deriv(c, L, s, x, k);
+#pragma unroll
+  for (int i = 0; i < n; ++i) x2[i] = t_fma(hh, k[i], x[i]);
+  P::deriv(c, L, s, x2, k);
+#pragma unroll
+  for (int i = 0; i < n; ++i) x3[i] = t_fma(hh, k[i], x[i]);
+  P::deriv(c, L, s, x3, k);
+#pragma unroll
+  for (int i = 0; i < n; ++i) x4[i] = t_fma(h, k[i], x[i]);
+  T a[n], u[n], acc[n];
+  // k4 = f(x4), weight h/6
+#pragma unroll
+  for (int i = 0; i < n; ++i) a[i] = h6 * lam[i];
+  P::vjp(c, L, x4, a, u, vb, tb);
+#pragma unroll
+  for (int i = 0; i < n; ++i) {
+    acc[i] = u[i];
+    a[i] = t_fma(h, u[i], 2 * h6 * lam[i]);  // adjoint of k3: 2h/6 lam + h u4
+  }
+  P::vjp(c, L, x3, a, u, vb, tb);
+#pragma unroll
+  for (int i = 0; i < n; ++i) {
+    acc[i] += u[i];
+    a[i] = t_fma(hh, u[i], 2 * h6 * lam[i]);  // adjoint of k2
+  }
+  P::vjp(c, L, x2, a, u, vb, tb);
+#pragma unroll
+  for (int i = 0; i < n; ++i) {
+    acc[i] += u[i];
+    a[i] = t_fma(hh, u[i], h6 * lam[i]);  // adjoint of k1
+  }
+  P::vjp(c, L, x, a, u, vb, tb);
+#pragma unroll
+  for (int i = 0; i < n; ++i) lam[i] = lam[i] + (acc[i] + u[i]);
+}
+
 // Margin over kNC padded rows (padding rows: F = 0, g = +inf).
+// Margin and its minimising row.
+template <int NY, class T>
+__device__ __forceinline__ T margin_rows_arg(const T* F, const T* g, const T* y, int& rarg) {
+  T best = t_inf<T>();
+  rarg = 0;
+#pragma unroll
+  for (int r = 0; r < kNC; ++r) {
+    T fy = F[r * NY] * y[0];
+#pragma unroll
+    for (int i = 1; i < NY; ++i) fy = t_fma(F[r * NY + i], y[i], fy);
+    const T m = g[r] - fy;
+    if (m < best || m != m) {
+      best = m;
+      rarg = r;
+    }
+  }
+  return best;
+}
+
 template <int NY, class T>
 __device__ __forceinline__ T margin_rows(const T* F, const T* g, const T* y) {
   T best = t_inf<T>();

@@ -15,7 +15,7 @@ constexpr int kNC = 4;       // constraint rows evaluated per step (unused rows 
 constexpr int kMaxTh = 20;   // uncertain coefficients
 constexpr int kMaxCoef = 115;
 
-enum Mode { kBisect = 0, kGrid = 1 };
+enum Mode { kBisect = 0, kGrid = 1, kNewton = 2 };
 
 // Per-handle control state kept in device memory so that whole RG steps (and
 // closed loops) can be enqueued or graph-captured without host round trips.
@@ -56,6 +56,11 @@ struct DevSearch {
   int32_t fail64[kCMax];              // a rechecked lane has an FP64 margin < 0
   int32_t n_recheck;                  // entries in the recheck list this round
   unsigned long long lane_steps;      // RK4 steps executed by rollout lanes this RG step
+  int32_t full[kCMax];                // 1: no early exit / steady-state refusal (Newton iterate)
+  // Newton search
+  int32_t nk_idx;                     // candidate carrying the Newton iterate this round
+  int32_t fallbacks;                  // rounds that used the midpoint instead of a Newton step
+  double delta;                       // 2^-K
 };
 
 // Result record of one RG step.
@@ -64,6 +69,17 @@ struct DevResult {
   int32_t status, rounds, candidates, rechecks, passes_alg1;
   uint32_t t;
   unsigned long long lane_steps;
+};
+
+// Gradient of a candidate's margin (rg_grad, Newton search).
+struct DevGrad {
+  int32_t n_entries;       // adjoint entries (0: the steady-state term is active)
+  int32_t k_star;          // arg-min scenario (-1: steady state)
+  double M;                // candidate worst margin
+  double dM_dv;            // derivative w.r.t. the set-point
+  double dM_dkappa;        // dM_dv * (r - v_prev)
+  double dM_dth[kMaxTh];   // derivative w.r.t. the nominal coefficients
+  int32_t j_star, r_star;  // minimising step and row of k_star
 };
 
 struct PlantDesc {
@@ -101,6 +117,15 @@ struct DevBuffers {
   int32_t* per_j;          // [cmax_round * N]
   double* scratch;         // small staging area (trajectories, draws)
   size_t scratch_bytes;
+  // adjoint
+  DevGrad* grad;           // result of the last gradient request
+  int32_t* adj_k;          // [N] scenario of each adjoint entry
+  float* adj_w;            // [N] upstream weight of each entry
+  float* adj_m;            // [N] margin of each entry
+  double* adj_dv;          // [N] weighted dm/dv of each entry
+  double* adj_dth;         // [N * kMaxTh] weighted dm/dtheta_nom of each entry
+  float* adj_ckpt;         // [(H / Kc + 1) * n * N] forward checkpoints (SoA by entry)
+  float* adj_seg;          // [Kc * n * N] recomputed segment states
 };
 
 struct LaunchCfg {
@@ -133,6 +158,12 @@ hipError_t launch_finalize(const Problem& pr, int closed_loop, const DevBuffers&
 hipError_t launch_collect(const DevBuffers& b, int M, double* out_dev, hipStream_t st);
 hipError_t launch_draws(const Problem& pr, uint32_t t, int k0, int nk, int j0, int nj,
                         float* w_dev, double* th_dev, const DevBuffers& b, hipStream_t st);
+hipError_t launch_grad_prepare(const Problem& pr, const DevBuffers& b, int cand, int use_keys,
+                               hipStream_t st);
+hipError_t launch_adjoint(const Problem& pr, int Kc, int max_entries, const DevBuffers& b,
+                          int cand, hipStream_t st);
+hipError_t launch_grad_reduce(const DevBuffers& b, int max_entries, int nth, int cand,
+                              hipStream_t st);
 hipError_t launch_trajectory(const Problem& pr, double v, const int32_t* k_list_dev, int nk,
                              int precision, double* traj_dev, const DevBuffers& b,
                              hipStream_t st);

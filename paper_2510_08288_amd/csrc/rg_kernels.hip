@@ -55,6 +55,7 @@ struct CtlArgs {
   DevSearch* srch;
   const double* r_seq;
   int closed_loop;
+  DevGrad* grad;
 };
 
 // ---------------------------------------------------------------------------
@@ -119,9 +120,9 @@ __global__ void __launch_bounds__(256) k_gen(RollArgs<KIND, float> a, float* wbu
 // lane once its minimum is below -band.  traj (nullable) receives states.
 // ---------------------------------------------------------------------------
 template <int KIND, class T, int RNG, int INJ>
-__device__ __forceinline__ T rollout_lane(const RollArgs<KIND, T>& a, T v, int k, uint32_t t,
-                                          const int32_t* stop_flag, int& jbest, int& nsteps,
-                                          double* traj) {
+__device__ __forceinline__ T rollout_lane(const RollArgs<KIND, T>& a, int early, T v, int k,
+                                          uint32_t t, const int32_t* stop_flag, int& jbest,
+                                          int& nsteps, double* traj) {
   using P = Plant<KIND, T>;
   T th[P::nth > 0 ? P::nth : 1];
   if constexpr (P::nth > 0) {
@@ -187,7 +188,7 @@ __device__ __forceinline__ T rollout_lane(const RollArgs<KIND, T>& a, T v, int k
     if (traj) {
       for (int i = 0; i < P::n; ++i) traj[(size_t)(j + 1) * P::n + i] = (double)x[i];
     }
-    if (a.early) {
+    if (early) {
       if (best < -a.band) {
         ++j;
         break;
@@ -246,15 +247,16 @@ __global__ void __launch_bounds__(256) k_rollout(const RollArgs<KIND, T> a) {
   DevSearch* S = a.srch;
   const int c = blockIdx.y;
   if (S->done || c >= S->n_cand) return;  // uniform over the workgroup
-  if (refused_by_steady_state(a.early, S, c)) return;
+  const int early = a.early && !S->full[c];
+  if (refused_by_steady_state(early, S, c)) return;
   __shared__ unsigned long long sh[16];
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t t = a.st->t;
   T m = t_inf<T>();
   int jb = 0, ns = 0;
   if (k < a.N) {
-    m = rollout_lane<KIND, T, RNG, INJ>(a, (T)S->v[c], k, t, a.early ? &S->dead[c] : nullptr,
-                                        jb, ns, nullptr);
+    m = rollout_lane<KIND, T, RNG, INJ>(a, early, (T)S->v[c], k, t,
+                                        early ? &S->dead[c] : nullptr, jb, ns, nullptr);
     if (a.record) {
       a.per_m[(size_t)c * a.N + k] = (float)m;
       a.per_j[(size_t)c * a.N + k] = jb;
@@ -331,7 +333,8 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
   DevSearch* S = a.srch;
   const int c = blockIdx.y;
   if (S->done || c >= S->n_cand) return;  // uniform over the workgroup
-  if (refused_by_steady_state(a.early, S, c)) return;
+  const int early = a.early && !S->full[c];
+  if (refused_by_steady_state(early, S, c)) return;
   __shared__ unsigned long long sh[16];
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = gid >> 2, q = gid & 3;
@@ -409,7 +412,7 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
       for (int u = 0; u < U; ++u) step(wcur[2 * u], wcur[2 * u + 1], g * U + u + 1);
 #pragma unroll
       for (int u = 0; u < 2 * U; ++u) wcur[u] = wnext[u];
-      if (a.early) {
+      if (early) {
         if (best < -a.band) {
           ++g;
           break;
@@ -468,12 +471,14 @@ __global__ void __launch_bounds__(64) k_recheck(const RollArgs<KIND, double> a) 
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int2 e = a.rlist[i];
     const int c = e.x, k = e.y;
-    if (a.early && (__hip_atomic_load(&S->dead[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
-                    __hip_atomic_load(&S->fail64[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
+    if (a.early && !S->full[c] &&
+        (__hip_atomic_load(&S->dead[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+         __hip_atomic_load(&S->fail64[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
       continue;
     int jb = 0, ns = 0;
-    const double m = rollout_lane<KIND, double, RNG, INJ>(a, S->v[c], k, t,
-                                                          a.early ? &S->fail64[c] : nullptr, jb,
+    const int early = a.early && !S->full[c];
+    const double m = rollout_lane<KIND, double, RNG, INJ>(a, early, S->v[c], k, t,
+                                                          early ? &S->fail64[c] : nullptr, jb,
                                                           ns, nullptr);
     atomicMin(&S->key64[c], ord64(m));
     if (m < 0.0) __hip_atomic_store(&S->fail64[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -589,18 +594,22 @@ __device__ __forceinline__ bool cand_feasible(const DevSearch* S, int c) {
   return !S->dead[c] && !S->fail64[c] && S->mss[c] >= 0.0;
 }
 
-__device__ __forceinline__ double cand_worst(const DevSearch* S, int c) {
+__device__ __forceinline__ double cand_worst_p(const DevSearch* S, int c, int precision) {
   double w;
-  const double kall = S->key_all[c] == ~0ull ? INFINITY : key_margin(S->key_all[c], S->precision);
+  const double kall = S->key_all[c] == ~0ull ? INFINITY : key_margin(S->key_all[c], precision);
   if (S->dead[c] || S->key64[c] == ~0ull) {
     w = kall;
   } else {
-    const double far = S->key_far[c] == ~0ull ? INFINITY : key_margin(S->key_far[c], S->precision);
+    const double far = S->key_far[c] == ~0ull ? INFINITY : key_margin(S->key_far[c], precision);
     const double r64 = unord64(S->key64[c]);
     w = far < r64 ? far : r64;
   }
   const double ms = S->mss[c];
   return (ms < w) ? ms : w;
+}
+
+__device__ __forceinline__ double cand_worst(const DevSearch* S, int c) {
+  return cand_worst_p(S, c, S->precision);
 }
 
 // Lay out a speculative bisection tree of `depth` levels over (lo, hi) at
@@ -636,6 +645,7 @@ __device__ void prepare_candidates(const CtlArgs<KIND>& a) {
   DevSearch* S = a.srch;
   const double r = a.st->r, vp = a.st->v_prev;
   for (int c = threadIdx.x; c < S->n_cand; c += blockDim.x) {
+    if (S->mode != kNewton) S->full[c] = 0;
     const double v = cand_v(S->kappa[c], r, vp);
     S->v[c] = v;
     S->mss[c] = steady_margin<KIND>(a.pc, S, v);
@@ -669,7 +679,18 @@ __global__ void __launch_bounds__(128) k_setup(const CtlArgs<KIND> a) {
     S->rounds_total = 0;
     S->passes_alg1 = 0;
     S->lane_steps = 0ull;
-    if (S->mode == kGrid) {
+    S->fallbacks = 0;
+    if (S->mode == kNewton) {
+      S->kappa[0] = 1.0;  // probe, carries the first derivative
+      S->kappa[1] = 0.5;
+      S->full[0] = 1;
+      S->full[1] = 0;
+      S->n_cand = 2;
+      S->nk_idx = 0;
+      S->probe = 1;
+      S->tree_depth = 0;
+      S->goal = S->K;
+    } else if (S->mode == kGrid) {
       const int M = S->M;
       for (int i = 0; i < M; ++i) S->kappa[i] = (M > 1) ? (double)i / (double)(M - 1) : 1.0;
       S->n_cand = M;
@@ -703,6 +724,56 @@ __global__ void __launch_bounds__(128) k_setup_list(const CtlArgs<KIND> a, int M
   prepare_candidates<KIND>(a);
 }
 
+// Safeguarded Newton on phi(kappa) = M(kappa) (see the FP64 reference for the
+// same rule): every verdict tightens [lo, hi]; the next iterate is
+// kappa_c - phi/phi' from this round's iterate (adjoint derivative), or the
+// midpoint when that step is not strictly inside the bracket or the slope is
+// not negative; candidates kappa_N -/+ delta and the midpoint go with it.
+// Returns true when hi - lo <= delta (or the round cap K + 2 is reached).
+__device__ bool newton_decide(DevSearch* S, const DevGrad* G) {
+  const double delta = S->delta;
+  S->passes_alg1 += S->n_cand;
+  if (S->round == 0 && cand_feasible(S, 0)) {
+    S->found = 1;
+    S->lo = 1.0;
+    S->worst_res = cand_worst(S, 0);
+    return true;
+  }
+  for (int c = 0; c < S->n_cand; ++c) {
+    const double kc = S->kappa[c];
+    if (cand_feasible(S, c)) {
+      if (kc > S->lo || (!S->found && kc >= S->lo)) {
+        S->lo = kc;
+        S->found = 1;
+        S->worst_res = cand_worst(S, c);
+      }
+    } else if (kc < S->hi) {
+      S->hi = kc;
+    }
+  }
+  if (S->hi - S->lo <= delta || S->round + 1 >= S->K + 2) return true;
+  const double kap_c = S->kappa[S->nk_idx];
+  const double phi = G->M, dphi = G->dM_dkappa;
+  bool ok = (phi == phi) && (dphi == dphi) && isfinite(phi) && isfinite(dphi) && dphi < 0.0;
+  double kn = ok ? kap_c - phi / dphi : 0.5 * (S->lo + S->hi);
+  if (!(kn > S->lo && kn < S->hi)) {
+    kn = 0.5 * (S->lo + S->hi);
+    ok = false;
+  }
+  if (!ok) S->fallbacks += 1;
+  const double cand[4] = {kn, kn - delta, kn + delta, 0.5 * (S->lo + S->hi)};
+  int n = 0;
+  for (int i = 0; i < 4; ++i) {
+    if (i > 0 && !(cand[i] > S->lo && cand[i] < S->hi)) continue;
+    S->kappa[n] = cand[i];
+    S->full[n] = (i == 0);
+    ++n;
+  }
+  S->n_cand = n;
+  S->nk_idx = 0;
+  return false;
+}
+
 // Verdicts of the finished round, bracket update, next round.
 template <int KIND>
 __global__ void __launch_bounds__(128) k_decide(const CtlArgs<KIND> a) {
@@ -713,7 +784,9 @@ __global__ void __launch_bounds__(128) k_decide(const CtlArgs<KIND> a) {
     S->cand_total += S->n_cand;
     S->rechecks_total += S->n_recheck;
     bool finished = false;
-    if (S->mode == kGrid && S->round == 0) {
+    if (S->mode == kNewton) {
+      finished = newton_decide(S, a.grad);
+    } else if (S->mode == kGrid && S->round == 0) {
       const int M = S->M;
       int istar = -1;
       for (int i = 0; i < M; ++i)
@@ -763,16 +836,18 @@ __global__ void __launch_bounds__(128) k_decide(const CtlArgs<KIND> a) {
     }
     if (finished) {
       S->done = 1;
-      S->status = S->found ? 0 : 1;
+      S->status = S->found ? (S->mode == kNewton && S->fallbacks > 0 ? 2 : 0) : 1;
       S->kappa_res = S->found ? S->lo : 0.0;
       S->v_res = S->found ? cand_v(S->kappa_res, a.st->r, a.st->v_prev) : a.st->v_prev;
       if (!S->found) S->worst_res = -INFINITY;
-    } else {
+    } else if (S->mode != kNewton) {
       const int rem = S->goal - S->halvings;
       const int d = rem < S->depth ? rem : S->depth;
       S->probe = 0;
       build_tree(S, 0, d, S->lo, S->hi);
       S->n_cand = (1 << d) - 1;
+      S->round += 1;
+    } else {
       S->round += 1;
     }
   }
@@ -864,8 +939,272 @@ __global__ void k_traj(const RollArgs<KIND, T> a, T v, const int32_t* k_list, in
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nk) return;
   int jb, ns;
-  rollout_lane<KIND, T, RNG, INJ>(a, v, k_list[i], a.st->t, nullptr, jb, ns,
+  rollout_lane<KIND, T, RNG, INJ>(a, 0, v, k_list[i], a.st->t, nullptr, jb, ns,
                                   traj + (size_t)i * (a.H + 1) * P::n);
+}
+
+
+// ---------------------------------------------------------------------------
+// Gradients of a candidate's margin.
+//
+// Reverse mode through the discrete RK4 map: forward pass with checkpoints
+// every Kc steps (tracking the minimiser j*, r*), then segment by segment from
+// j* back to 0: recompute the segment's states from its checkpoint, sweep them
+// in reverse with rk4_vjp.  States and adjoints in FP32, parameter sums in
+// FP64.  One lane per (scenario, upstream weight) entry.
+// ---------------------------------------------------------------------------
+struct AdjArgs {
+  int Kc;
+  int lmax;                // stride of the SoA scratch (= N)
+  int cand;                // candidate index whose v is used
+  const int32_t* k_list;
+  const float* w_list;
+  float* out_m;
+  double* out_dv;
+  double* out_dth;
+  float* ckpt;
+  float* seg;
+  DevGrad* grad;
+};
+
+template <int KIND, int RNG, int INJ>
+__global__ void __launch_bounds__(64) k_adjoint(const RollArgs<KIND, float> a, const AdjArgs g) {
+  using P = Plant<KIND, float>;
+  constexpr int n = P::n;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.grad->n_entries) return;
+  const int k = g.k_list[e];
+  const float wgt = g.w_list[e];
+  const uint32_t t = a.st->t;
+  const int cand = g.cand >= 0 ? g.cand : a.srch->nk_idx;
+  if (a.srch->done && g.cand < 0) return;
+  const float v = (float)a.srch->v[cand];
+  const size_t L = (size_t)g.lmax;
+  float th[P::nth > 0 ? P::nth : 1], fac[P::nth > 0 ? P::nth : 1];
+  if constexpr (P::nth > 0) {
+    if (RNG == 0) {
+      for (int c = 0; c < P::nth; ++c) fac[c] = a.thbuf[(size_t)c * a.N + k];
+    } else {
+      draw_theta_factor<P::nth>(a.seed, a.inst, t, (uint32_t)k, a.thlo, a.thspan, fac);
+    }
+    for (int c = 0; c < P::nth; ++c) th[c] = a.pc.thnom[c] * fac[c];
+  }
+  typename P::Lane Ln;
+  P::lane_init(a.pc, th, v, Ln);
+  auto load_w = [&](int j, float* w) {
+    if (RNG == 0) {
+      for (int c = 0; c < P::nw; ++c) w[c] = a.wbuf[((size_t)j * P::nw + c) * a.N + k];
+    } else {
+      draw_w<P::nw>(a.seed, a.inst, t, 0u, (uint32_t)k, (uint32_t)j, a.wlo, a.wspan, w);
+    }
+  };
+  auto forcing = [&](const float* w, float* s) {
+    if (INJ == 0) P::force(a.pc, Ln, w, s);
+    else P::force0(a.pc, Ln, s);
+  };
+  auto step = [&](float* x, const float* w) {
+    float s[n];
+    forcing(w, s);
+    rk4_step<KIND, float>(a.pc, Ln, s, a.h, a.hh, a.h6, x);
+    if (INJ == 1) P::post(a.pc, w, x);
+  };
+  // forward: minimiser and checkpoints
+  float x[n], xbest[n], y[P::ny], w[P::nw];
+  for (int i = 0; i < n; ++i) x[i] = (float)a.st->x[i];
+  int rb = 0, jb = 0;
+  P::output(a.pc, Ln, x, y);
+  float best = margin_rows_arg<P::ny>(a.F, a.g, y, rb);
+  for (int i = 0; i < n; ++i) {
+    xbest[i] = x[i];
+    g.ckpt[(size_t)i * L + e] = x[i];
+  }
+  for (int j = 0; j < a.H; ++j) {
+    load_w(j, w);
+    step(x, w);
+    int r = 0;
+    P::output(a.pc, Ln, x, y);
+    const float m = margin_rows_arg<P::ny>(a.F, a.g, y, r);
+    if (m < best) {
+      best = m;
+      jb = j + 1;
+      rb = r;
+      for (int i = 0; i < n; ++i) xbest[i] = x[i];
+    }
+    if ((j + 1) % g.Kc == 0 && j + 1 < a.H)
+      for (int i = 0; i < n; ++i) g.ckpt[((size_t)((j + 1) / g.Kc) * n + i) * L + e] = x[i];
+  }
+  bool finite = best == best;
+  for (int i = 0; i < n; ++i) finite = finite && (x[i] - x[i] == 0.f);
+  double vb = 0.0;
+  double tb[P::nth > 0 ? P::nth : 1];
+  for (int c = 0; c < (P::nth > 0 ? P::nth : 1); ++c) tb[c] = 0.0;
+  if (finite) {
+    float lam[n];
+    P::out_grad(a.pc, a.F + rb * P::ny, xbest, lam);
+    for (int seg = (jb - 1) / g.Kc; jb > 0 && seg >= 0; --seg) {
+      const int j0 = seg * g.Kc;
+      const int j1 = (j0 + g.Kc) < jb ? (j0 + g.Kc) : jb;
+      float xs[n];
+      for (int i = 0; i < n; ++i) xs[i] = g.ckpt[((size_t)seg * n + i) * L + e];
+      for (int j = j0; j < j1; ++j) {
+        for (int i = 0; i < n; ++i) g.seg[((size_t)(j - j0) * n + i) * L + e] = xs[i];
+        load_w(j, w);
+        step(xs, w);
+      }
+      for (int j = j1 - 1; j >= j0; --j) {
+        for (int i = 0; i < n; ++i) xs[i] = g.seg[((size_t)(j - j0) * n + i) * L + e];
+        load_w(j, w);
+        float s[n];
+        forcing(w, s);
+        rk4_vjp<KIND, float>(a.pc, Ln, s, a.h, a.hh, a.h6, xs, lam, vb, tb);
+      }
+    }
+  } else {
+    best = -INFINITY;
+  }
+  g.out_m[e] = best;
+  g.out_dv[e] = (double)wgt * vb;
+  for (int c = 0; c < P::nth; ++c) g.out_dth[(size_t)e * kMaxTh + c] = (double)wgt * tb[c] * (double)fac[c];
+  if (e == 0) {
+    g.grad->j_star = jb;
+    g.grad->r_star = rb;
+  }
+}
+
+// Steady-state margin gradient by the adjoint of the equilibrium condition:
+// f(x_ss, v) = 0, m = g_r - eps|g_r| - F_r h(x_ss):  solve J^T mu = dm/dx, then
+// dm/dv = -mu . df/dv and dm/dtheta_nom = -mu . df/dtheta (FP64).
+template <int KIND>
+__device__ double steady_grad(const typename Plant<KIND, double>::Coef& pc, const DevSearch* S,
+                              double v, double* dmdv, double* dth) {
+  using P = Plant<KIND, double>;
+  constexpr int n = P::n;
+  *dmdv = 0.0;
+  for (int c = 0; c < kMaxTh; ++c) dth[c] = 0.0;
+  if (!S->ss_check) return INFINITY;
+  double x[n], f[n], J[n * n], s0[n];
+  P::eq_guess(pc, v, x, J);
+  if (P::eq_guess_needs_solve()) {
+    if (!dense_solve<n>(J, x)) return -INFINITY;
+  }
+  typename P::Lane L;
+  P::lane_init(pc, P::nominal_theta(pc), v, L);
+  P::force0(pc, L, s0);
+  bool ok = false;
+  for (int it = 0; it <= 50; ++it) {
+    P::deriv(pc, L, s0, x, f);
+    double nrm = 0.0;
+    for (int i = 0; i < n; ++i) nrm = fmax(nrm, fabs(f[i]));
+    if (!(nrm == nrm)) return -INFINITY;
+    if (nrm <= 1e-12) {
+      ok = true;
+      break;
+    }
+    if (it == 50) break;
+    P::jacobian(pc, x, v, J);
+    for (int i = 0; i < n; ++i) f[i] = -f[i];
+    if (!dense_solve<n>(J, f)) return -INFINITY;
+    for (int i = 0; i < n; ++i) x[i] += f[i];
+  }
+  if (!ok) return -INFINITY;
+  double y[P::ny];
+  P::output(pc, L, x, y);
+  double best = INFINITY;
+  int rb = 0;
+  for (int r = 0; r < S->n_c; ++r) {
+    double fy = 0.0;
+    for (int i = 0; i < P::ny; ++i) fy += S->F[r * P::ny + i] * y[i];
+    const double m = tightened_rhs(S->g[r], S->eps) - fy;
+    if (r == 0 || m < best) {
+      best = m;
+      rb = r;
+    }
+  }
+  double Fr[P::ny], gx[n], mu[n];
+  for (int i = 0; i < P::ny; ++i) Fr[i] = S->F[rb * P::ny + i];
+  P::out_grad(pc, Fr, x, gx);
+  P::jacobian(pc, x, v, J);
+  double Jt[n * n];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Jt[i * n + j] = J[j * n + i];
+  for (int i = 0; i < n; ++i) mu[i] = gx[i];
+  if (!dense_solve<n>(Jt, mu)) return best;
+  double xb[n], vb = 0.0, tb[kMaxTh];
+  for (int c = 0; c < kMaxTh; ++c) tb[c] = 0.0;
+  P::vjp(pc, L, x, mu, xb, vb, tb);
+  *dmdv = -vb;
+  for (int c = 0; c < P::nth; ++c) dth[c] = -tb[c];
+  return best;
+}
+
+// Choose the active term of M(kappa) for candidate `cand`: the arg-min
+// scenario (one adjoint entry) or the steady-state margin (gradient here).
+// use_keys = 0 keeps the entries the host uploaded (weighted sum).
+template <int KIND>
+__global__ void k_grad_prepare(const CtlArgs<KIND> a, DevGrad* G, int32_t* adj_k, float* adj_w,
+                               int cand, int use_keys) {
+  if (threadIdx.x != 0) return;
+  DevSearch* S = a.srch;
+  if (cand < 0) {
+    if (S->done) return;
+    cand = S->nk_idx;
+  }
+  const double worst = cand_worst_p(S, cand, 0);  // gradients use the FP32 rollouts
+  G->M = worst;
+  G->dM_dv = 0.0;
+  for (int c = 0; c < kMaxTh; ++c) G->dM_dth[c] = 0.0;
+  if (!use_keys) {
+    G->k_star = -1;
+    return;
+  }
+  const unsigned long long key = S->key_all[cand];
+  const double roll = key == ~0ull ? INFINITY : key_margin(key, 0);
+  if (S->mss[cand] < roll) {
+    double dv, dth[kMaxTh];
+    steady_grad<KIND>(a.pc, S, S->v[cand], &dv, dth);
+    G->dM_dv = dv;
+    for (int c = 0; c < kMaxTh; ++c) G->dM_dth[c] = dth[c];
+    G->n_entries = 0;
+    G->k_star = -1;
+  } else {
+    const int ks = (int)(uint32_t)(key & 0xffffffffu);
+    G->n_entries = 1;
+    G->k_star = ks;
+    adj_k[0] = ks;
+    adj_w[0] = 1.f;
+  }
+}
+
+// Deterministic sum of the entries' weighted derivatives (fixed order per
+// thread, then a fixed LDS tree), then dM/dkappa = dM/dv (r - v_prev).
+__global__ void __launch_bounds__(256) k_grad_reduce(DevGrad* G, const double* dv, const double* dth,
+                                                     int nth, const DevState* st,
+                                                     const DevSearch* S, int cand) {
+  if (cand < 0 && S->done) return;  // Newton search already finished
+  __shared__ double sh[256];
+  const int n = G->n_entries;
+  const int tid = threadIdx.x;
+  for (int c = -1; c < nth; ++c) {
+    double acc = 0.0;
+    for (int e = tid; e < n; e += 256) acc += c < 0 ? dv[e] : dth[(size_t)e * kMaxTh + c];
+    sh[tid] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) sh[tid] += sh[tid + s];
+      __syncthreads();
+    }
+    if (tid == 0 && n > 0) {
+      if (c < 0) G->dM_dv += sh[0];
+      else G->dM_dth[c] += sh[0];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double kap = S->kappa[cand];
+    // v = r exactly at kappa = 1; dv/dkappa = r - v_prev on both sides
+    (void)kap;
+    G->dM_dkappa = G->dM_dv * (st->r - st->v_prev);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -918,6 +1257,7 @@ static CtlArgs<KIND> make_ctl(const Problem& pr, const DevBuffers& b, int closed
   a.srch = b.srch;
   a.r_seq = b.r_seq;
   a.closed_loop = closed_loop;
+  a.grad = b.grad;
   return a;
 }
 
@@ -1086,6 +1426,53 @@ hipError_t launch_draws(const Problem& pr, uint32_t t, int k0, int nk, int j0, i
                        w_dev, th_dev, thn);
     return hipGetLastError();
   });
+}
+
+hipError_t launch_grad_prepare(const Problem& pr, const DevBuffers& b, int cand, int use_keys,
+                               hipStream_t st) {
+  return by_kind(pr.p.kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    hipLaunchKernelGGL(k_grad_prepare<K>, dim3(1), dim3(64), 0, st, make_ctl<K>(pr, b, 0), b.grad,
+                       b.adj_k, b.adj_w, cand, use_keys);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_adjoint(const Problem& pr, int Kc, int max_entries, const DevBuffers& b,
+                          int cand, hipStream_t st) {
+  AdjArgs g;
+  g.Kc = Kc;
+  g.lmax = pr.s.N;
+  g.cand = cand;
+  g.k_list = b.adj_k;
+  g.w_list = b.adj_w;
+  g.out_m = b.adj_m;
+  g.out_dv = b.adj_dv;
+  g.out_dth = b.adj_dth;
+  g.ckpt = b.adj_ckpt;
+  g.seg = b.adj_seg;
+  g.grad = b.grad;
+  return by_kind(pr.p.kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    return by_bit(pr.s.rng_mode, [&](auto rc) {
+      constexpr int R = decltype(rc)::value;
+      return by_bit(pr.s.inject, [&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        auto a = make_args<K, float>(pr, 0.0, 0, 0, b);
+        hipLaunchKernelGGL((k_adjoint<K, R, I>), dim3(div_up(max_entries, 64)), dim3(64), 0, st, a,
+                           g);
+        return hipGetLastError();
+      });
+    });
+  });
+}
+
+hipError_t launch_grad_reduce(const DevBuffers& b, int max_entries, int nth, int cand,
+                              hipStream_t st) {
+  (void)max_entries;
+  hipLaunchKernelGGL(k_grad_reduce, dim3(1), dim3(256), 0, st, b.grad, b.adj_dv, b.adj_dth, nth,
+                     b.st, b.srch, cand);
+  return hipGetLastError();
 }
 
 hipError_t launch_trajectory(const Problem& pr, double v, const int32_t* k_list_dev, int nk,

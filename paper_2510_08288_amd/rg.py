@@ -60,7 +60,7 @@ class rg_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("band", C.c_double), ("K", C.c_int32),
                 ("search", C.c_int32), ("depth", C.c_int32), ("M", C.c_int32),
                 ("refine", C.c_int32), ("early_exit", C.c_int32), ("block", C.c_int32),
-                ("max_T", C.c_int32), ("lanes", C.c_int32)]
+                ("max_T", C.c_int32), ("lanes", C.c_int32), ("Kc", C.c_int32)]
 
 
 class rg_step_info(C.Structure):
@@ -109,6 +109,8 @@ def load_library(path: str = LIB_PATH, with_torch: bool = True) -> C.CDLL:
                                  C.POINTER(rg_step_info), C.c_int32]
     L.rg_set_profiling.argtypes = [_vp, C.c_int32]
     L.rg_get_options.argtypes = [_vp, C.POINTER(rg_options)]
+    L.rg_grad.argtypes = [_vp, _dp, C.c_double, C.c_double, C.c_double, _fp, _dp, _dp, _dp]
+    L.rg_set_theta.argtypes = [_vp, _dp]
     L.rg_get_profile.argtypes = [_vp, C.POINTER(rg_profile)]
     L.rg_draws.argtypes = [_vp, C.c_uint32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _fp, _dp]
     L.rg_trajectory.argtypes = [_vp, _dp, C.c_double, _ip, C.c_int32, C.c_int32, _dp]
@@ -146,7 +148,8 @@ class Governor:
     def __init__(self, problem, precision: int = PREC_F32_RECHECK, band: float = 1e-4,
                  K: int = 12, search: int = SEARCH_BISECT, depth: int = 0, M: int = 64,
                  refine: int = 6, early_exit: bool = True, block: int = 0, max_T: int = 256,
-                 rng_mode: int = RNG_STREAM, lanes: int = 0, torch_workspace: bool = True):
+                 rng_mode: int = RNG_STREAM, lanes: int = 0, Kc: int = 50,
+                 torch_workspace: bool = True):
         import torch
         self.L = load_library()
         self.problem = problem
@@ -166,6 +169,7 @@ class Governor:
         opt.precision, opt.band, opt.K, opt.search = precision, band, K, search
         opt.depth, opt.M, opt.refine = depth, M, refine
         opt.early_exit, opt.block, opt.max_T, opt.lanes = int(early_exit), block, max_T, lanes
+        opt.Kc = Kc
         h = _vp()
         rc = self.L.rg_create(C.byref(plant), C.byref(scen), C.byref(cons), int(p.H), float(p.dt),
                               C.byref(opt), C.byref(h))
@@ -238,6 +242,27 @@ class Governor:
                                      None if per is None else _ptr(per, _fp),
                                      None if perj is None else _ptr(perj, _ip)))
         return dict(margins=out, per_scenario=per, per_scenario_j=perj)
+
+    def grad(self, x, r: float, v_prev: float, kappa: float, upstream=None) -> dict:
+        """dM/dkappa and dM/dtheta_nom (upstream None), or the upstream-weighted sum
+        of the per-scenario margin derivatives."""
+        x = _f64(x)
+        up = None
+        if upstream is not None:
+            up = np.ascontiguousarray(np.asarray(upstream, dtype=np.float32).reshape(-1))
+            assert up.size == self.problem.N
+        M = C.c_double()
+        dk = C.c_double()
+        dth = np.zeros(max(self.problem.n_theta, 1))
+        self._check(self.L.rg_grad(self.h, _ptr(x), float(r), float(v_prev), float(kappa),
+                                   None if up is None else _ptr(up, _fp), C.byref(M), C.byref(dk),
+                                   _ptr(dth)))
+        return dict(M=M.value, dkappa=dk.value, dtheta=dth[: self.problem.n_theta])
+
+    def set_theta(self, theta_nom) -> None:
+        th = _f64(theta_nom)
+        assert th.size == self.problem.n_theta
+        self._check(self.L.rg_set_theta(self.h, _ptr(th)))
 
     def closed_loop(self, x0, v0: float, r_seq, use_graph: bool = True) -> dict:
         x0 = _f64(x0)

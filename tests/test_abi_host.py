@@ -33,7 +33,8 @@ def test_header_declares_the_boundary():
     for required in ["rg_create", "rg_destroy", "rg_step", "rg_margin", "rg_closed_loop",
                      "rg_workspace_size", "rg_bind_workspace", "rg_set_stream", "rg_set_step",
                      "rg_get_step", "rg_draws", "rg_trajectory", "rg_status_string",
-                     "rg_last_error", "rg_default_options"]:
+                     "rg_last_error", "rg_default_options", "rg_grad", "rg_set_theta",
+                     "rg_get_options", "rg_set_profiling", "rg_get_profile"]:
         assert required in names
 
 
@@ -119,7 +120,8 @@ def test_create_rejects_bad_horizon_and_options(lib):
     assert _create(lib, p, dt=float("nan"))[0] == R.RG_E_INVAL
     for field, value, code in [("K", -1, R.RG_E_INVAL), ("depth", 9, R.RG_E_INVAL),
                                ("block", 100, R.RG_E_INVAL), ("block", 512, R.RG_E_INVAL),
-                               ("precision", 4, R.RG_E_INVAL), ("search", 2, R.RG_E_NOTSUP),
+                               ("precision", 4, R.RG_E_INVAL), ("search", 3, R.RG_E_INVAL),
+                               ("Kc", 0, R.RG_E_INVAL), ("lanes", 2, R.RG_E_INVAL),
                                ("band", float("inf"), R.RG_E_INVAL), ("max_T", 0, R.RG_E_INVAL)]:
         o = R.rg_options()
         lib.rg_default_options(C.byref(o))
@@ -129,6 +131,13 @@ def test_create_rejects_bad_horizon_and_options(lib):
     lib.rg_default_options(C.byref(o))
     o.search, o.M = 1, 200
     assert _create(lib, p, opt=o)[0] == R.RG_E_INVAL
+    o = R.rg_options()
+    lib.rg_default_options(C.byref(o))
+    o.search, o.precision = 2, 1      # Newton runs on the FP32 rollouts and adjoint only
+    assert _create(lib, p, opt=o)[0] == R.RG_E_NOTSUP
+    o.precision = 0
+    rc, h = _create(lib, p, opt=o)
+    assert rc == 0 and lib.rg_destroy(h) == 0
 
 
 def test_create_rejects_nonfinite_data(lib):
@@ -157,6 +166,9 @@ def test_calls_reject_bad_arguments_before_device_work(lib):
     assert lib.rg_margin(h, x.ctypes.data_as(dp), 1.0, 0.0, kap.ctypes.data_as(dp), 2,
                          out.ctypes.data_as(dp), None, None) == R.RG_E_INVAL
     assert b"kappa" in lib.rg_last_error(h)
+    dk = C.c_double()
+    assert lib.rg_grad(h, x.ctypes.data_as(dp), 1.0, 0.0, 1.5, None, None, C.byref(dk), None) == R.RG_E_INVAL
+    assert lib.rg_set_theta(h, x.ctypes.data_as(dp)) == R.RG_E_NOTSUP   # LQ4 has no theta
     r = np.zeros(3)
     assert lib.rg_closed_loop(h, x.ctypes.data_as(dp), 0.0, r.ctypes.data_as(dp), 0,
                               out.ctypes.data_as(dp), None, None, None, 0) == R.RG_E_INVAL

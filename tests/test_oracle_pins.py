@@ -495,3 +495,134 @@ def test_closed_loop_resume_is_exact(oracle_mod):
     a = o.closed_loop(np.zeros(4), 0.0, r_seq[:5], K=8)
     b = o.closed_loop(a["x"][-1], a["v"][-1], r_seq[5:], t0=5, K=8)
     assert np.array_equal(full["v"], np.concatenate([a["v"], b["v"]]))
+
+
+# ----------------------------------------------------------------------------
+# Sensitivities (forward-mode tangents) against finite differences and the
+# linear closed form
+# ----------------------------------------------------------------------------
+
+def test_tangent_linear_closed_form(oracle_mod):
+    # G = 0, w fixed: x_j(v) = x_j(0) + v * sum_{i<j} Phi^i Psi B, so
+    # dm/dv = -F_r* C sum_{i<j*} Phi^i Psi B exactly.
+    p = _linear_problem(seed=3, N=4, H=300, dt=0.01)
+    o = oracle_mod.Oracle(p)
+    A, B, _, _, C = _lq4_mats(p)
+    Phi, Psi = _rk4_poly(A, p.dt)
+    x0 = np.array([0.1, 0.0, -0.1, 0.05])
+    for v in [0.4, -0.7]:
+        for k in range(3):
+            m, dv, _, j, r = o.rollout_tangent(x0, v, 2, k)
+            S = sum(np.linalg.matrix_power(Phi, i) for i in range(j)) @ Psi @ B if j > 0 else np.zeros(4)
+            ref = -(p.F[r] @ C @ S)
+            assert dv == pytest.approx(ref, rel=1e-9, abs=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["lq4", "fc9"])
+def test_tangent_matches_central_differences(oracle_mod, kind):
+    if kind == "lq4":
+        p = W.lq4_problem(seed=24, N=4, H=400, dt=0.005, eps=0.01)
+        x0 = np.zeros(4)
+        vs = [0.6, -0.9]
+    else:
+        p = W.fc9_problem(N=4, H=400, dt=0.002)
+        o0 = oracle_mod.Oracle(p)
+        x0 = o0.steady_margin(0.5)[1]
+        vs = [1.1, 1.4]
+    o = oracle_mod.Oracle(p)
+    h = 1e-4
+    checked = 0
+    for v in vs:
+        for k in range(p.N):
+            m, dv, dth, j, r = o.rollout_tangent(x0, v, 0, k)
+            mp, jp, rp = o.rollout(x0, v + h, 0, k)
+            mm, jm, rm = o.rollout(x0, v - h, 0, k)
+            if (jp, rp) != (j, r) or (jm, rm) != (j, r):
+                continue   # minimiser moves inside the stencil: not differentiable there
+            fd = (mp - mm) / (2 * h)
+            assert dv == pytest.approx(fd, rel=1e-6, abs=1e-9)
+            checked += 1
+            for q in range(p.n_theta):
+                cp = p.coeffs.copy(); cp[90 + q] += h * p.coeffs[90 + q]
+                cm = p.coeffs.copy(); cm[90 + q] -= h * p.coeffs[90 + q]
+                op = oracle_mod.Oracle(p.replace(coeffs=cp))
+                om = oracle_mod.Oracle(p.replace(coeffs=cm))
+                a, ja_, ra_ = op.rollout(x0, v, 0, k)
+                b, jb_, rb_ = om.rollout(x0, v, 0, k)
+                if (ja_, ra_) != (j, r) or (jb_, rb_) != (j, r):
+                    continue
+                fdq = (a - b) / (2 * h * p.coeffs[90 + q])
+                assert dth[q] == pytest.approx(fdq, rel=1e-5, abs=1e-8), q
+    assert checked >= 2
+
+
+def test_steady_tangent_matches_central_differences(oracle_mod):
+    for p, vs in [(W.lq4_problem(seed=24, N=1, H=10, eps=0.01), [0.3, -0.6]),
+                  (W.fc9_problem(N=1, H=10), [0.8, 1.3])]:
+        o = oracle_mod.Oracle(p)
+        h = 1e-5
+        for v in vs:
+            m, dv, dth = o.steady_tangent(v)
+            fd = (o.steady_margin(v + h)[0] - o.steady_margin(v - h)[0]) / (2 * h)
+            assert dv == pytest.approx(fd, rel=1e-6, abs=1e-9)
+            for q in range(p.n_theta):
+                cp = p.coeffs.copy(); cp[90 + q] += h
+                cm = p.coeffs.copy(); cm[90 + q] -= h
+                fdq = (oracle_mod.Oracle(p.replace(coeffs=cp)).steady_margin(v)[0]
+                       - oracle_mod.Oracle(p.replace(coeffs=cm)).steady_margin(v)[0]) / (2 * h)
+                assert dth[q] == pytest.approx(fdq, rel=1e-5, abs=1e-8)
+
+
+def test_candidate_grad_matches_kappa_differences(oracle_mod):
+    p = W.lq4_problem(seed=24, N=16, H=500, dt=0.005, eps=0.01)
+    o = oracle_mod.Oracle(p)
+    x0 = np.zeros(4)
+    h = 1e-5
+    for kap in [0.3, 0.45]:
+        M, dk, _, ka = o.candidate_grad(x0, kap, 1.8, 0.0, 0)
+        Mp, _, _, kp = o.candidate_grad(x0, kap + h, 1.8, 0.0, 0)
+        Mm, _, _, km = o.candidate_grad(x0, kap - h, 1.8, 0.0, 0)
+        if kp == ka == km:
+            assert dk == pytest.approx((Mp - Mm) / (2 * h), rel=1e-5, abs=1e-8)
+
+
+# ----------------------------------------------------------------------------
+# Safeguarded Newton search
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed,r", [(3, 1.5), (4, -2.0), (6, 2.5), (8, 1.0)])
+def test_newton_exact_linear_ratio(oracle_mod, seed, r):
+    # The linear plant's exact kappa*: Newton must stop within 2^-K below it.
+    p = _linear_problem(seed=seed, N=6, H=150, dt=0.01)
+    o = oracle_mod.Oracle(p)
+    K = 12
+    ks = _affine_kappa_star(o, p, np.zeros(4), r, 0.0, 0)
+    res = o.newton(np.zeros(4), r, 0.0, 0, K)
+    if ks >= 1.0:
+        assert res["kappa"] == 1.0
+    else:
+        assert ks - 2.0 ** -K - 1e-12 <= res["kappa"] <= ks + 1e-12
+    assert res["rounds"] <= K + 2
+
+
+@pytest.mark.parametrize("seed,r", [(24, 1.5), (24, -1.8), (10, 1.9), (19, -1.5), (7, 1.5)])
+def test_newton_agrees_with_bisection(oracle_mod, seed, r):
+    p = W.lq4_problem(seed=seed, N=16, H=600, dt=0.005, eps=0.01)
+    o = oracle_mod.Oracle(p, nthreads=4)
+    b = o.bisect(np.zeros(4), r, 0.0, 0, 12)
+    n = o.newton(np.zeros(4), r, 0.0, 0, 12)
+    assert abs(n["kappa"] - b["kappa"]) <= 2.0 ** -12
+    if n["kappa"] > 0:
+        assert o.candidate(np.zeros(4), o.candidate_v(n["kappa"], r, 0.0), 0)[0] >= 0
+
+
+def test_newton_fc9_bracket(oracle_mod):
+    p = W.fc9_problem(N=16, H=300, dt=0.002)
+    o = oracle_mod.Oracle(p, nthreads=4)
+    x0 = o.steady_margin(0.5)[1]
+    n = o.newton(x0, 2.0, 0.5, 0, 12)
+    b = o.bisect(x0, 2.0, 0.5, 0, 12)
+    assert 0 < n["kappa"] < 1
+    assert abs(n["kappa"] - b["kappa"]) <= 2.0 ** -12
+    assert o.candidate(x0, o.candidate_v(n["kappa"], 2.0, 0.5), 0)[0] >= 0
+    assert o.candidate(x0, o.candidate_v(n["kappa"] + 2.0 ** -12, 2.0, 0.5), 0)[0] < 0
