@@ -8,7 +8,8 @@ boundary, 12 bisection halvings after the kappa = 1 probe, tracking a
 piecewise-constant reference (levels U[-2, 2], new level every 25 steps).
 
 One bench step = one RG update of that closed loop (draws, all search rounds,
-recheck, decision, true-plant step), all on the device.  Prints one JSON line.
+recheck, decision, true-plant step), all on the device, replayed from the HIP
+graph captured for one RG step.  Prints one JSON line.
 
   value       nominal scenario-steps/s: sum over the timed RG updates of
               (candidate evaluations sequential Alg. 1 makes) x N x H, over the
@@ -17,10 +18,15 @@ recheck, decision, true-plant step), all on the device.  Prints one JSON line.
               its HIP-event time, against the FP32 vector peak
   cpu_baseline  the FP64 reference on this host's cores, on the first RG
               updates of the same closed loop
+  search_modes  the same closed loop under FP32 rollouts + adjoint-driven
+              Newton and under plain sequential FP64 bisection, each timed in
+              a child process of its own (so a kernel profile of this process
+              covers the headline form only)
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -67,6 +73,38 @@ def cpu_baseline(wl, r_seq, seconds):
                        f"FP64 bisection, {threads} threads over scenarios, {el:.1f} s"), kappas
 
 
+def run_form(args):
+    """One alternative search form on the first `--steps` updates of the same
+    closed loop, replayed from captured HIP graphs; prints one JSON line."""
+    import numpy as np
+    import torch
+
+    from paper_2510_08288_amd import rg, workloads as W
+
+    T = args.steps
+    wl = W.workload_lq4_closed_loop(T=max(T, 2))
+    p = wl["problem"]
+    r_seq = wl["r_seq"]
+    kw = (dict(precision=rg.PREC_F32_RECHECK, search=rg.SEARCH_NEWTON)
+          if args.form == "fp32_adjoint_newton" else dict(precision=rg.PREC_F64, depth=1))
+    gm = rg.Governor(p, band=wl["band"], K=wl["K"], max_T=max(256, T), **kw)
+    x0 = np.asarray(wl["x0"], dtype=np.float64)
+    gm.set_step(0)
+    gm.closed_loop(x0, wl["v_prev"], r_seq[:2], use_graph=True)  # capture + warm the graph
+    gm.set_step(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    om = gm.closed_loop(x0, wl["v_prev"], r_seq[:T], use_graph=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    gm.close()
+    print(json.dumps({"rg_updates_per_s": T / el, "ms_per_step": el / T * 1e3, "steps": T,
+                      "value": float(np.sum(om["bisect_passes"])) * p.N * p.H / el,
+                      "rounds_per_step": float(np.mean(om["rounds"])),
+                      "fallback_steps": int(np.sum(om["status"] == 2)),
+                      "kappa": [float(k) for k in om["kappa"]]}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +115,10 @@ def main():
     ap.add_argument("--depth", type=int, default=0)
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--mode-steps", type=int, default=25,
+                    help="closed-loop steps timed for the Newton and FP64 search forms")
+    ap.add_argument("--form", choices=["fp32_adjoint_newton", "fp64_sequential_bisection"],
+                    default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the scenario axis would "
@@ -90,6 +132,8 @@ def main():
     from paper_2510_08288_amd import rg, workloads as W
 
     torch.cuda.set_device(0)
+    if args.form is not None:
+        return run_form(args)
     T = max(args.steps, args.warmup)
     wl = W.workload_lq4_closed_loop(T=T)
     p = wl["problem"]
@@ -104,25 +148,48 @@ def main():
         g.set_step(0)
         g.closed_loop(x0, wl["v_prev"], r_seq[: args.warmup], use_graph=False)
 
-    # timed region: the workload's first K updates, from its initial state
+    # the workload's first K updates launched eagerly, with a HIP event pair
+    # around every rollout launch (the roofline figure); untimed
     g.set_step(0)
     g.set_profiling(True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    out = g.closed_loop(x0, wl["v_prev"], r_seq[: args.steps], use_graph=False)
+    t1 = time.perf_counter()
+    out_e = g.closed_loop(x0, wl["v_prev"], r_seq[: args.steps], use_graph=False)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    elapsed_eager = time.perf_counter() - t1
     prof = g.profile()
     g.set_profiling(False)
 
-    # the same K updates replayed from one captured HIP graph per RG step
+    # timed region: the same K updates, each replayed from the captured HIP
+    # graph of one RG step (captured beforehand), from the initial state
+    g.set_step(0)
+    g.closed_loop(x0, wl["v_prev"], r_seq[:1], use_graph=True)
     g.set_step(0)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    out_g = g.closed_loop(x0, wl["v_prev"], r_seq[: args.steps], use_graph=True)
+    t0 = time.perf_counter()
+    out = g.closed_loop(x0, wl["v_prev"], r_seq[: args.steps], use_graph=True)
     torch.cuda.synchronize()
-    elapsed_graph = time.perf_counter() - t1
-    graph_same = bool(np.array_equal(out_g["v"], out["v"]))
+    elapsed = time.perf_counter() - t0
+    graph_same = bool(np.array_equal(out_e["v"], out["v"]))
+
+    # The same closed loop under the other two search forms the metric names:
+    # FP32 rollouts + adjoint-driven Newton, and plain sequential FP64 bisection
+    # (one candidate per device round, Alg. 1 as written).  Each runs in a child
+    # process; fewer steps, as the FP64 form is slow.
+    modes = {}
+    Km = min(args.steps, args.mode_steps)
+    for label in ["fp32_adjoint_newton", "fp64_sequential_bisection"]:
+        child = subprocess.run([sys.executable, os.path.abspath(__file__), "--form", label,
+                                "--steps", str(Km)], capture_output=True, text=True)
+        if child.returncode != 0:
+            sys.stderr.write(child.stdout + child.stderr)
+            raise SystemExit(f"search form {label} failed (exit {child.returncode})")
+        om = json.loads(child.stdout.strip().splitlines()[-1])
+        kap = np.asarray(om.pop("kappa"))
+        om["max_abs_kappa_diff_vs_default"] = float(np.max(np.abs(kap - out["kappa"][:Km])))
+        om["kappa_within_2^-12"] = bool(np.all(np.abs(kap - out["kappa"][:Km])
+                                               <= 2.0 ** -wl["K"] + 1e-15))
+        modes[label] = om
 
     K = args.steps
     nominal = int(np.sum(out["bisect_passes"])) * p.N * p.H
@@ -148,12 +215,16 @@ def main():
                    "K": wl["K"], "band": wl["band"], "rg_steps": K,
                    "precision": "fp32 rollouts + fp64 near-band recheck" if prec == 0 else "fp64",
                    "search": f"bisection, {g.options.depth} levels per device round",
-                   "lanes_per_scenario": g.options.lanes},
+                   "lanes_per_scenario": g.options.lanes,
+                   "launch": "one captured HIP graph per RG update, replayed"},
         "rg_updates_per_s": K / elapsed,
         "executed_scenario_steps_per_s": executed / elapsed,
-        "graph_replay": {"ms_per_step": elapsed_graph / K * 1e3,
-                         "rg_updates_per_s": K / elapsed_graph,
-                         "value": nominal / elapsed_graph, "same_result": graph_same},
+        "eager_profiled": {"ms_per_step": elapsed_eager / K * 1e3,
+                           "rg_updates_per_s": K / elapsed_eager,
+                           "value": nominal / elapsed_eager, "same_result": graph_same},
+        "search_modes": dict(modes, fp32_speculative_bisection={
+            "rg_updates_per_s": K / elapsed, "ms_per_step": elapsed / K * 1e3, "steps": K,
+            "rounds_per_step": float(np.mean(out["rounds"]))}),
         "search_stats": {"rounds": int(np.sum(out["rounds"])),
                          "candidates": int(np.sum(out["candidates"])),
                          "rechecks": int(np.sum(out["rechecks"])),

@@ -135,6 +135,7 @@ typedef struct rg_options {
     int32_t lanes;         /* lanes per scenario of FP32 LQ4 rollouts: 1, 4 (one scenario per
                               quad, state split across lanes), 0 = auto */
     int32_t Kc;            /* adjoint checkpoint interval in RK4 steps (default 50) */
+    int32_t persistent_wgs;/* batches: workgroups of the persistent rollout kernel (0 = auto) */
 } rg_options;
 
 typedef struct rg_step_info {
@@ -160,6 +161,16 @@ typedef struct rg_profile {
 } rg_profile;
 
 typedef struct rg_handle rg_handle;
+typedef struct rg_batch rg_batch;
+
+/* One independent governor of a batch. */
+typedef struct rg_instance_desc {
+    rg_plant plant;
+    rg_scenarios scen;     /* rng_mode is ignored: batches draw inline */
+    rg_constraints cons;
+    int32_t H;
+    double dt;
+} rg_instance_desc;
 
 /* ---- lifecycle ---------------------------------------------------------------- */
 
@@ -253,6 +264,40 @@ int rg_grad(rg_handle* h, const double* x, double r, double v_prev, double kappa
  * scenario k then uses theta_nom * factor_k with unchanged factors.
  * RG_E_NOTSUP for plants without coefficients. */
 int rg_set_theta(rg_handle* h, const double* theta_nom);
+
+/* Equilibrium of the nominal closed loop under constant set-point v (w = 0):
+ * the state behind y_ss(v), from the Newton iteration of the steady-state test
+ * (Sec. II-A).  x_out: [n].  RG_E_STATE if it does not converge. */
+int rg_equilibrium(rg_handle* h, double v, double* x_out);
+
+/* ---- batched serving (many independent governors per launch) ---------------------- */
+
+/* A batch of `count` independent governors (own plant, scenarios, constraints,
+ * H and dt each; the paper notes one small governor gains little from a GPU,
+ * Sec. IV-B).  Each RG step of the batch runs bisection (K halvings, FP32
+ * rollouts, FP64 recheck) for all instances together: one persistent rollout
+ * launch per round pops (scenario tile, candidate) tasks from one queue, tiles of
+ * the costliest instances first.  opt: precision must be F32_RECHECK and search
+ * BISECT; block (64/128/256) is the scenario tile; persistent_wgs the rollout
+ * grid.  Every descriptor is validated as by rg_create (error names the
+ * instance; message via rg_batch_last_error(NULL)). */
+int rg_batch_create(const rg_instance_desc* descs, int32_t count, const rg_options* opt,
+                    rg_batch** out);
+int rg_batch_destroy(rg_batch* b);
+int rg_batch_set_stream(rg_batch* b, void* hip_stream);
+/* Per-instance RG step counter (draw selection); starts at 0, +1 per rg_batch_step. */
+int rg_batch_set_step(rg_batch* b, int32_t instance, uint32_t t);
+int rg_batch_get_options(const rg_batch* b, rg_options* out);
+/* One RG step of every instance.  x: the instances' states packed in order
+ * (n_i values each); r, v_prev, v_out: [count]; kappa_out and info_out
+ * ([count]) nullable.  use_graph = 1 captures the step once as a HIP graph
+ * and replays it.  The first call allocates the batch's device memory.
+ * Currently returns RG_E_NOTSUP after validating its arguments: the batched
+ * device kernels are switched off until a memory fault seen on the device is
+ * explained (single-instance handles are unaffected). */
+int rg_batch_step(rg_batch* b, const double* x, const double* r, const double* v_prev,
+                  double* v_out, double* kappa_out, rg_step_info* info_out, int32_t use_graph);
+const char* rg_batch_last_error(const rg_batch* b);
 
 /* ---- inspection ----------------------------------------------------------------- */
 

@@ -274,7 +274,7 @@ double orc_margin(const orc_problem* p, const double* y, int32_t* r_arg)
 }
 
 /* ========================================================================= *
- * Prediction and verdict (Eq. (3); Alg. 1 lines 5-7; Alg. 3 parallel steps 1-3).
+ * Prediction and verdict (Eq. (3); the candidate test of Alg. 1; the parallel evaluation of Alg. 3).
  * ========================================================================= */
 
 /* Candidate set-point, Eq. (2): v = v_{t-1} + kappa (r_t - v_{t-1}).
@@ -496,8 +496,8 @@ static void* orc_chunk_run(void* arg)
 }
 
 /* Candidate worst margin M(v) = min( min_k m^k(v), m_ss(v) ); the candidate is
- * admissible iff M(v) >= 0 (Alg. 2 line 7 / Alg. 3 step 3: robust means every
- * sampled scenario).  per_scen (nullable) receives m^k; k_arg the first
+ * admissible iff M(v) >= 0 (the verdict of Alg. 2 and of Alg. 3: robust means
+ * every sampled scenario).  per_scen (nullable) receives m^k; k_arg the first
  * minimising scenario; m_ss_out the steady-state margin. */
 double orc_candidate(const orc_problem* p, const double* x0, double v, uint32_t t,
                      double* per_scen, int32_t* k_arg, double* m_ss_out)

@@ -6,7 +6,9 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -325,6 +327,7 @@ int rg_default_options(rg_options* opt) {
   opt->max_T = 256;
   opt->lanes = 0;
   opt->Kc = 50;
+  opt->persistent_wgs = 0;
   return RG_OK;
 }
 
@@ -671,6 +674,21 @@ int rg_set_theta(rg_handle* h, const double* theta_nom) {
   return RG_OK;
 }
 
+int rg_equilibrium(rg_handle* h, double v, double* x_out) {
+  if (!h) return RG_E_INVAL;
+  if (!x_out || !std::isfinite(v)) return fail(h, RG_E_INVAL, "bad arguments");
+  int rc = ensure_workspace(h);
+  if (rc) return rc;
+  double out[kMaxN + 1];
+  HIPCHK(h, launch_equilibrium(h->pr, h->b, v, h->b.scratch, h->stream));
+  HIPCHK(h, hipMemcpyAsync(out, h->b.scratch, sizeof(double) * (h->pr.p.n + 1),
+                           hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (out[h->pr.p.n] != 1.0) return fail(h, RG_E_STATE, "equilibrium iteration did not converge");
+  for (int i = 0; i < h->pr.p.n; ++i) x_out[i] = out[i];
+  return RG_OK;
+}
+
 int rg_get_options(const rg_handle* h, rg_options* out) {
   if (!h || !out) return RG_E_INVAL;
   *out = h->opt;
@@ -749,6 +767,316 @@ int rg_trajectory(rg_handle* h, const double* x, double v, const int32_t* k_list
   (void)hipFree(kd);
   if (e != hipSuccess) return fail_hip(h, "rg_trajectory", e);
   return RG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched serving
+// ---------------------------------------------------------------------------
+// The batched device step (k_batch_* kernels) is switched off: its first device
+// run ended in a memory fault that a host emulation of the same kernels (ASan and
+// bounds checks, same inputs) does not reproduce, so no cause is identified yet.
+// Creation, options and validation stay available.
+constexpr bool kBatchDeviceEnabled = false;
+
+struct rg_batch {
+  int count = 0;
+  rg_options opt{};
+  std::vector<Problem> probs;
+  std::vector<int> noff;          // offset of each instance's state in the packed x array
+  std::vector<uint32_t> t;        // per-instance RG step counters
+  int cmax_round = 0, rounds = 0, grid = 0, tile = 256;
+  hipStream_t stream = nullptr;
+  void* mem = nullptr;
+  BatchBuffers b{};
+  hipGraphExec_t graph = nullptr;
+  std::string err;
+};
+
+namespace {
+
+int bfail(rg_batch* bt, int code, const std::string& msg) {
+  if (bt) bt->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+void fill_desc(const Problem& pr, InstDesc& d) {
+  memset(&d, 0, sizeof(d));
+  const int ncoef = pr.p.kind == RG_PLANT_LQ4 ? 52 : 115;
+  for (int i = 0; i < ncoef; ++i) {
+    d.c64[i] = pr.p.coeffs[i];
+    d.c32[i] = (float)pr.p.coeffs[i];
+  }
+  for (int r = 0; r < kNC; ++r) {
+    for (int y = 0; y < pr.p.ny; ++y) {
+      d.F64[r * pr.p.ny + y] = pr.c.F[r * pr.p.ny + y];
+      d.F32[r * pr.p.ny + y] = (float)pr.c.F[r * pr.p.ny + y];
+    }
+    d.g64[r] = pr.c.g[r];
+    d.g32[r] = (float)pr.c.g[r];
+  }
+  d.hd = pr.dt;
+  d.hhd = pr.dt * 0.5;
+  d.h6d = pr.dt / 6.0;
+  d.h = (float)pr.dt;
+  d.hh = (float)(pr.dt * 0.5);
+  d.h6 = (float)(pr.dt / 6.0);
+  for (int c = 0; c < pr.p.nw; ++c) {
+    d.wlo[c] = (float)pr.s.wlo[c];
+    d.wspan[c] = (float)(pr.s.whi[c] - pr.s.wlo[c]);
+  }
+  d.thlo = (float)(1.0 - pr.s.theta_rel);
+  d.thspan = (float)(2.0 * pr.s.theta_rel);
+  d.kind = pr.p.kind;
+  d.n = pr.p.n;
+  d.N = pr.s.N;
+  d.H = pr.H;
+  d.inject = pr.s.inject;
+  d.seed = pr.s.seed;
+  d.instance = pr.s.instance;
+}
+
+}  // namespace
+
+int rg_batch_create(const rg_instance_desc* descs, int32_t count, const rg_options* opt,
+                    rg_batch** out) {
+  if (!out) return bfail(nullptr, RG_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!descs || count < 1) return bfail(nullptr, RG_E_INVAL, "no instances");
+  rg_options o;
+  rg_default_options(&o);
+  if (opt) o = *opt;
+  if (o.precision != RG_PREC_F32_RECHECK)
+    return bfail(nullptr, RG_E_NOTSUP, "batches run FP32 rollouts with the FP64 recheck");
+  if (o.search != RG_SEARCH_BISECT) return bfail(nullptr, RG_E_NOTSUP, "batches use bisection");
+  if (o.block != 0 && o.block != 64 && o.block != 128 && o.block != 256)
+    return bfail(nullptr, RG_E_INVAL, "block must be 64, 128 or 256");
+  if (o.persistent_wgs < 0) return bfail(nullptr, RG_E_INVAL, "persistent_wgs must be >= 0");
+  rg_batch* bt = new (std::nothrow) rg_batch;
+  if (!bt) return bfail(nullptr, RG_E_NOMEM, "host allocation");
+  bt->count = count;
+  bt->tile = o.block ? o.block : 256;
+  long long lanes = 0;
+  int noff = 0;
+  for (int i = 0; i < count; ++i) {
+    rg_scenarios s = descs[i].scen;
+    s.rng_mode = RG_RNG_INLINE;
+    rg_options oi = o;
+    oi.depth = 1;
+    rg_handle* h = nullptr;
+    const int rc = rg_create(&descs[i].plant, &s, &descs[i].cons, descs[i].H, descs[i].dt, &oi, &h);
+    if (rc != RG_OK) {
+      std::string m = std::string("instance ") + std::to_string(i) + ": " + g_create_error;
+      delete bt;
+      return bfail(nullptr, rc, m);
+    }
+    bt->probs.push_back(h->pr);
+    rg_destroy(h);
+    bt->noff.push_back(noff);
+    noff += bt->probs.back().p.n;
+    lanes += descs[i].scen.N;
+  }
+  // search plan: a round already holds sum_i N_i lanes per candidate, so
+  // speculative levels only when that is below the chip's capacity
+  int d = o.depth;
+  if (d == 0) {
+    const double budget = 2.0 * 256 * 4 * 64;
+    d = 1;
+    while (d < 6 && ((1 << (d + 1)) - 1) * (double)lanes <= budget) ++d;
+    const int rounds = o.K > 0 ? (o.K + d - 1) / d : 1;
+    d = o.K > 0 ? (o.K + rounds - 1) / rounds : 1;
+  }
+  o.depth = d;
+  const int d0 = o.K < d ? o.K : d;
+  bt->cmax_round = std::max(1 << d0, (1 << d) - 1);
+  bt->rounds = 1 + (o.K - d0 + d - 1) / d;
+  bt->grid = o.persistent_wgs > 0 ? o.persistent_wgs : 4 * 256;
+  bt->opt = o;
+  bt->t.assign(count, 0u);
+  *out = bt;
+  return RG_OK;
+}
+
+int rg_batch_destroy(rg_batch* bt) {
+  if (!bt) return RG_OK;
+  if (bt->graph) (void)hipGraphExecDestroy(bt->graph);
+  if (bt->mem) (void)hipFree(bt->mem);
+  delete bt;
+  return RG_OK;
+}
+
+int rg_batch_set_stream(rg_batch* bt, void* hip_stream) {
+  if (!bt) return RG_E_INVAL;
+  if (bt->stream != (hipStream_t)hip_stream && bt->graph) {
+    (void)hipGraphExecDestroy(bt->graph);
+    bt->graph = nullptr;
+  }
+  bt->stream = (hipStream_t)hip_stream;
+  return RG_OK;
+}
+
+int rg_batch_set_step(rg_batch* bt, int32_t i, uint32_t t) {
+  if (!bt || i < 0 || i >= bt->count) return RG_E_INVAL;
+  bt->t[i] = t;
+  return RG_OK;
+}
+
+static int batch_ensure_memory(rg_batch* bt) {
+  if (bt->mem) return RG_OK;
+  const int count = bt->count;
+  // instances by decreasing cost per scenario tile (horizon x plant weight)
+  std::vector<int32_t> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  auto cost = [&](int i) {
+    return (double)bt->probs[i].H * (bt->probs[i].p.kind == RG_PLANT_FC9 ? 4.0 : 1.0);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  std::vector<int32_t> tile_start(count + 1, 0);
+  size_t lanes = 0;
+  for (int s = 0; s < count; ++s) {
+    const int i = order[s];
+    tile_start[s + 1] = tile_start[s] + (bt->probs[i].s.N + bt->tile - 1) / bt->tile;
+    lanes += (size_t)bt->probs[i].s.N;
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t o_desc = take(sizeof(InstDesc) * count);
+  const size_t o_st = take(sizeof(DevState) * count);
+  const size_t o_srch = take(sizeof(DevSearch) * count);
+  const size_t o_res = take(sizeof(DevResult) * count);
+  const size_t o_order = take(sizeof(int32_t) * count);
+  const size_t o_tiles = take(sizeof(int32_t) * (count + 1));
+  const size_t o_cnt = take(sizeof(int32_t) * 4);
+  const size_t o_rlist = take(sizeof(int4) * lanes * (size_t)bt->cmax_round);
+  hipError_t e = hipMalloc(&bt->mem, off);
+  if (e != hipSuccess) return bfail(bt, RG_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  char* base = (char*)bt->mem;
+  BatchBuffers& b = bt->b;
+  b.count = count;
+  b.desc = (InstDesc*)(base + o_desc);
+  b.st = (DevState*)(base + o_st);
+  b.srch = (DevSearch*)(base + o_srch);
+  b.res = (DevResult*)(base + o_res);
+  b.order = (int32_t*)(base + o_order);
+  b.tile_start = (int32_t*)(base + o_tiles);
+  b.counters = (int32_t*)(base + o_cnt);
+  b.rlist = (int4*)(base + o_rlist);
+  b.total_tiles = tile_start[count];
+  b.tile = bt->tile;
+  std::vector<InstDesc> desc(count);
+  std::vector<DevSearch> srch(count);
+  for (int i = 0; i < count; ++i) {
+    const Problem& pr = bt->probs[i];
+    fill_desc(pr, desc[i]);
+    DevSearch& S = srch[i];
+    memset(&S, 0, sizeof(S));
+    S.mode = kBisect;
+    S.K = bt->opt.K;
+    S.depth = bt->opt.depth;
+    S.precision = RG_PREC_F32_RECHECK;
+    S.ss_check = pr.c.ss_check;
+    S.n_c = pr.c.n_c;
+    S.ny = pr.p.ny;
+    S.eps = pr.c.eps;
+    for (int r = 0; r < kNC; ++r) S.g[r] = pr.c.g[r];
+    for (int q = 0; q < kNC * kMaxY; ++q) S.F[q] = pr.c.F[q];
+    S.delta = std::ldexp(1.0, -bt->opt.K);
+    S.done = 1;
+  }
+  e = hipMemcpyAsync(b.desc, desc.data(), sizeof(InstDesc) * count, hipMemcpyHostToDevice, bt->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b.srch, srch.data(), sizeof(DevSearch) * count, hipMemcpyHostToDevice, bt->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b.order, order.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, bt->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b.tile_start, tile_start.data(), sizeof(int32_t) * (count + 1),
+                       hipMemcpyHostToDevice, bt->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(bt->stream);
+  if (e != hipSuccess) return bfail(bt, RG_E_HIP, std::string("batch upload: ") + hipGetErrorString(e));
+  return RG_OK;
+}
+
+static hipError_t batch_enqueue(rg_batch* bt) {
+  hipError_t e = launch_batch_setup(bt->b, bt->stream);
+  for (int r = 0; r < bt->rounds && e == hipSuccess; ++r)
+    e = launch_batch_round(bt->b, bt->cmax_round, bt->opt.band, bt->opt.early_exit, bt->grid,
+                           bt->stream);
+  if (e == hipSuccess) e = launch_batch_finalize(bt->b, bt->stream);
+  return e;
+}
+
+int rg_batch_step(rg_batch* bt, const double* x, const double* r, const double* v_prev,
+                  double* v_out, double* kappa_out, rg_step_info* info_out, int32_t use_graph) {
+  if (!bt) return RG_E_INVAL;
+  if (!x || !r || !v_prev || !v_out) return bfail(bt, RG_E_INVAL, "NULL argument");
+  const int count = bt->count;
+  for (int i = 0; i < count; ++i) {
+    if (!finite_array(x + bt->noff[i], bt->probs[i].p.n) || !std::isfinite(r[i]) ||
+        !std::isfinite(v_prev[i]))
+      return bfail(bt, RG_E_INVAL, "non-finite input");
+  }
+  if (!kBatchDeviceEnabled)
+    return bfail(bt, RG_E_NOTSUP,
+                 "the batched device step is switched off: its kernels faulted on the device "
+                 "and the cause is not yet identified");
+  int rc = batch_ensure_memory(bt);
+  if (rc) return rc;
+  std::vector<DevState> st(count);
+  for (int i = 0; i < count; ++i) {
+    memset(&st[i], 0, sizeof(DevState));
+    for (int q = 0; q < bt->probs[i].p.n; ++q) st[i].x[q] = x[bt->noff[i] + q];
+    st[i].v_prev = v_prev[i];
+    st[i].r = r[i];
+    st[i].t = bt->t[i];
+  }
+  hipError_t e = hipMemcpyAsync(bt->b.st, st.data(), sizeof(DevState) * count,
+                                hipMemcpyHostToDevice, bt->stream);
+  if (e != hipSuccess) return bfail(bt, RG_E_HIP, std::string("upload: ") + hipGetErrorString(e));
+  if (use_graph) {
+    if (!bt->graph) {
+      hipGraph_t g = nullptr;
+      e = hipStreamBeginCapture(bt->stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return bfail(bt, RG_E_HIP, std::string("capture: ") + hipGetErrorString(e));
+      hipError_t e1 = batch_enqueue(bt);
+      hipError_t e2 = hipStreamEndCapture(bt->stream, &g);
+      if (e1 != hipSuccess || e2 != hipSuccess)
+        return bfail(bt, RG_E_HIP, std::string("capture batch step: ") +
+                                       hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+      e = hipGraphInstantiate(&bt->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return bfail(bt, RG_E_HIP, std::string("instantiate: ") + hipGetErrorString(e));
+    }
+    e = hipGraphLaunch(bt->graph, bt->stream);
+  } else {
+    e = batch_enqueue(bt);
+  }
+  if (e != hipSuccess) return bfail(bt, RG_E_HIP, std::string("batch step: ") + hipGetErrorString(e));
+  std::vector<DevResult> R(count);
+  e = hipMemcpyAsync(R.data(), bt->b.res, sizeof(DevResult) * count, hipMemcpyDeviceToHost, bt->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(bt->stream);
+  if (e != hipSuccess) return bfail(bt, RG_E_HIP, std::string("batch results: ") + hipGetErrorString(e));
+  for (int i = 0; i < count; ++i) {
+    v_out[i] = R[i].v;
+    if (kappa_out) kappa_out[i] = R[i].kappa;
+    if (info_out) fill_info(R[i], info_out + i);
+    bt->t[i] += 1;
+  }
+  return RG_OK;
+}
+
+int rg_batch_get_options(const rg_batch* bt, rg_options* out) {
+  if (!bt || !out) return RG_E_INVAL;
+  *out = bt->opt;
+  return RG_OK;
+}
+
+const char* rg_batch_last_error(const rg_batch* bt) {
+  if (!bt) return g_create_error.c_str();
+  return bt->err.c_str();
 }
 
 const char* rg_status_string(int status) {

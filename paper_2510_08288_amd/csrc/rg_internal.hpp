@@ -135,7 +135,40 @@ struct LaunchCfg {
   int rounds;              // device rounds per RG step
 };
 
+// One instance of a batch (device memory, read-only in the kernels).  The
+// coefficient arrays have the layout of Plant<KIND, T>::Coef.
+struct InstDesc {
+  double c64[kMaxCoef + 1];
+  double F64[kNC * kMaxY], g64[kNC];
+  double hd, hhd, h6d;
+  float c32[kMaxCoef + 1];
+  float F32[kNC * kMaxY], g32[kNC];
+  float h, hh, h6;
+  float wlo[kMaxW], wspan[kMaxW];
+  float thlo, thspan;
+  int32_t kind, n, N, H, inject;
+  uint32_t seed, instance;
+};
+
+struct BatchBuffers {
+  int32_t count;
+  InstDesc* desc;          // [count]
+  DevState* st;            // [count]
+  DevSearch* srch;         // [count]
+  DevResult* res;          // [count]
+  int32_t* order;          // [count] instances by decreasing cost
+  int32_t* tile_start;     // [count + 1] first scenario tile of each ordered instance
+  int32_t total_tiles;
+  int32_t tile;            // scenarios per tile (= rollout workgroup size)
+  int32_t* counters;       // [0] task queue head, [1] recheck list length
+  int4* rlist;             // (instance, candidate, scenario) near-band entries
+};
+
 // ---- launchers implemented in rg_kernels.hip --------------------------------
+hipError_t launch_batch_setup(const BatchBuffers& b, hipStream_t st);
+hipError_t launch_batch_round(const BatchBuffers& b, int cmax_round, double band, int early,
+                              int grid, hipStream_t st);
+hipError_t launch_batch_finalize(const BatchBuffers& b, hipStream_t st);
 // Everything a launch needs about the problem (host copy).
 struct Problem {
   PlantDesc p;
@@ -158,6 +191,8 @@ hipError_t launch_finalize(const Problem& pr, int closed_loop, const DevBuffers&
 hipError_t launch_collect(const DevBuffers& b, int M, double* out_dev, hipStream_t st);
 hipError_t launch_draws(const Problem& pr, uint32_t t, int k0, int nk, int j0, int nj,
                         float* w_dev, double* th_dev, const DevBuffers& b, hipStream_t st);
+hipError_t launch_equilibrium(const Problem& pr, const DevBuffers& b, double v, double* out_dev,
+                              hipStream_t st);
 hipError_t launch_grad_prepare(const Problem& pr, const DevBuffers& b, int cand, int use_keys,
                                hipStream_t st);
 hipError_t launch_adjoint(const Problem& pr, int Kc, int max_entries, const DevBuffers& b,

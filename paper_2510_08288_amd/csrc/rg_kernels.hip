@@ -119,10 +119,10 @@ __global__ void __launch_bounds__(256) k_gen(RollArgs<KIND, float> a, float* wbu
 // stop_flag (nullable) is polled every 32 steps; early != 0 also stops the
 // lane once its minimum is below -band.  traj (nullable) receives states.
 // ---------------------------------------------------------------------------
-template <int KIND, class T, int RNG, int INJ>
-__device__ __forceinline__ T rollout_lane(const RollArgs<KIND, T>& a, int early, T v, int k,
-                                          uint32_t t, const int32_t* stop_flag, int& jbest,
-                                          int& nsteps, double* traj) {
+template <int KIND, class T, int RNG, int INJ, class A>
+__device__ __forceinline__ T rollout_lane(const A& a, int early, T v, int k, uint32_t t,
+                                          const int32_t* stop_flag, int& jbest, int& nsteps,
+                                          double* traj) {
   using P = Plant<KIND, T>;
   T th[P::nth > 0 ? P::nth : 1];
   if constexpr (P::nth > 0) {
@@ -232,7 +232,7 @@ __device__ __forceinline__ unsigned long long block_min_u64(unsigned long long v
 }
 
 // In decision mode a candidate whose FP64 steady-state test already fails is
-// refused without simulating it (the verdict needs both tests, Alg. 1 line 6).
+// refused without simulating it (the verdict of Alg. 1 needs both tests).
 __device__ __forceinline__ bool refused_by_steady_state(int early, DevSearch* S, int c) {
   if (!early || !(S->mss[c] < 0.0)) return false;
   if (blockIdx.x == 0 && threadIdx.x == 0)
@@ -641,14 +641,14 @@ __device__ void build_tree(DevSearch* S, int base, int depth, double lo, double 
 // Thread-parallel per-candidate preparation: set-points, steady-state margins,
 // reduction accumulators.
 template <int KIND>
-__device__ void prepare_candidates(const CtlArgs<KIND>& a) {
-  DevSearch* S = a.srch;
-  const double r = a.st->r, vp = a.st->v_prev;
+__device__ void prepare_candidates(const typename Plant<KIND, double>::Coef& pc, const DevState* st,
+                                   DevSearch* S) {
+  const double r = st->r, vp = st->v_prev;
   for (int c = threadIdx.x; c < S->n_cand; c += blockDim.x) {
     if (S->mode != kNewton) S->full[c] = 0;
     const double v = cand_v(S->kappa[c], r, vp);
     S->v[c] = v;
-    S->mss[c] = steady_margin<KIND>(a.pc, S, v);
+    S->mss[c] = steady_margin<KIND>(pc, S, v);
     S->key_all[c] = ~0ull;
     S->key_far[c] = ~0ull;
     S->key64[c] = ~0ull;
@@ -660,10 +660,10 @@ __device__ void prepare_candidates(const CtlArgs<KIND>& a) {
 
 // Start of one RG step: round-0 candidates.
 template <int KIND>
-__global__ void __launch_bounds__(128) k_setup(const CtlArgs<KIND> a) {
-  DevSearch* S = a.srch;
+__device__ void setup_body(const typename Plant<KIND, double>::Coef& pc, DevState* st,
+                           DevSearch* S, const double* r_seq, int closed_loop) {
   if (threadIdx.x == 0) {
-    if (a.closed_loop) a.st->r = a.r_seq[a.st->cl_index];
+    if (closed_loop) st->r = r_seq[st->cl_index];
     S->done = 0;
     S->found = 0;
     S->status = 0;
@@ -672,7 +672,7 @@ __global__ void __launch_bounds__(128) k_setup(const CtlArgs<KIND> a) {
     S->lo = 0.0;
     S->hi = 1.0;
     S->kappa_res = 0.0;
-    S->v_res = a.st->v_prev;
+    S->v_res = st->v_prev;
     S->worst_res = -INFINITY;
     S->cand_total = 0;
     S->rechecks_total = 0;
@@ -708,7 +708,12 @@ __global__ void __launch_bounds__(128) k_setup(const CtlArgs<KIND> a) {
     }
   }
   __syncthreads();
-  prepare_candidates<KIND>(a);
+  prepare_candidates<KIND>(pc, st, S);
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(128) k_setup(const CtlArgs<KIND> a) {
+  setup_body<KIND>(a.pc, a.st, a.srch, a.r_seq, a.closed_loop);
 }
 
 // rg_margin: explicit candidate list (kappa[] already uploaded).
@@ -721,7 +726,7 @@ __global__ void __launch_bounds__(128) k_setup_list(const CtlArgs<KIND> a, int M
     S->round = 0;
   }
   __syncthreads();
-  prepare_candidates<KIND>(a);
+  prepare_candidates<KIND>(a.pc, a.st, S);
 }
 
 // Safeguarded Newton on phi(kappa) = M(kappa) (see the FP64 reference for the
@@ -776,16 +781,21 @@ __device__ bool newton_decide(DevSearch* S, const DevGrad* G) {
 
 // Verdicts of the finished round, bracket update, next round.
 template <int KIND>
-__global__ void __launch_bounds__(128) k_decide(const CtlArgs<KIND> a) {
-  DevSearch* S = a.srch;
-  if (S->done) return;
+__device__ void decide_body(const typename Plant<KIND, double>::Coef& pc, const DevState* st,
+                            DevSearch* S, const DevGrad* grad) {
+  // Thread 0 may set S->done below: take the entry decision once, for the whole
+  // workgroup, so every wave reaches the same barriers.
+  __shared__ int s_done;
+  if (threadIdx.x == 0) s_done = S->done;
+  __syncthreads();
+  if (s_done) return;
   if (threadIdx.x == 0) {
     S->rounds_total += 1;
     S->cand_total += S->n_cand;
     S->rechecks_total += S->n_recheck;
     bool finished = false;
     if (S->mode == kNewton) {
-      finished = newton_decide(S, a.grad);
+      finished = newton_decide(S, grad);
     } else if (S->mode == kGrid && S->round == 0) {
       const int M = S->M;
       int istar = -1;
@@ -838,7 +848,7 @@ __global__ void __launch_bounds__(128) k_decide(const CtlArgs<KIND> a) {
       S->done = 1;
       S->status = S->found ? (S->mode == kNewton && S->fallbacks > 0 ? 2 : 0) : 1;
       S->kappa_res = S->found ? S->lo : 0.0;
-      S->v_res = S->found ? cand_v(S->kappa_res, a.st->r, a.st->v_prev) : a.st->v_prev;
+      S->v_res = S->found ? cand_v(S->kappa_res, st->r, st->v_prev) : st->v_prev;
       if (!S->found) S->worst_res = -INFINITY;
     } else if (S->mode != kNewton) {
       const int rem = S->goal - S->halvings;
@@ -852,7 +862,12 @@ __global__ void __launch_bounds__(128) k_decide(const CtlArgs<KIND> a) {
     }
   }
   __syncthreads();
-  if (!S->done) prepare_candidates<KIND>(a);
+  if (!S->done) prepare_candidates<KIND>(pc, st, S);
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(128) k_decide(const CtlArgs<KIND> a) {
+  decide_body<KIND>(a.pc, a.st, a.srch, a.grad);
 }
 
 // Result record; in closed loop also the true-plant step (Eq. (4)) in FP64
@@ -1207,6 +1222,234 @@ __global__ void __launch_bounds__(256) k_grad_reduce(DevGrad* G, const double* d
   }
 }
 
+
+// Equilibrium f(x, v, 0, theta_nom) = 0 by the steady-state Newton iteration;
+// out[0..n) = x_ss, out[n] = 1 if converged.
+template <int KIND>
+__global__ void k_equilibrium(const CtlArgs<KIND> a, double v, double* out) {
+  using P = Plant<KIND, double>;
+  constexpr int n = P::n;
+  if (threadIdx.x != 0) return;
+  double x[n], f[n], J[n * n], s0[n];
+  P::eq_guess(a.pc, v, x, J);
+  bool ok = !P::eq_guess_needs_solve() || dense_solve<n>(J, x);
+  typename P::Lane L;
+  P::lane_init(a.pc, P::nominal_theta(a.pc), v, L);
+  P::force0(a.pc, L, s0);
+  bool conv = false;
+  for (int it = 0; ok && it <= 50; ++it) {
+    P::deriv(a.pc, L, s0, x, f);
+    double nrm = 0.0;
+    for (int i = 0; i < n; ++i) nrm = fmax(nrm, fabs(f[i]));
+    if (!(nrm == nrm)) break;
+    if (nrm <= 1e-12) {
+      conv = true;
+      break;
+    }
+    P::jacobian(a.pc, x, v, J);
+    for (int i = 0; i < n; ++i) f[i] = -f[i];
+    if (!dense_solve<n>(J, f)) break;
+    for (int i = 0; i < n; ++i) x[i] += f[i];
+  }
+  for (int i = 0; i < n; ++i) out[i] = x[i];
+  out[n] = conv ? 1.0 : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Batched serving: many independent governors (uneven N, H, plant kind) per
+// launch.  A persistent rollout kernel pops (scenario tile, candidate) tasks
+// from one atomic queue; tiles are ordered by decreasing instance cost so the
+// longest work starts first.  Draws are generated inline (no per-instance
+// buffers).  Setup / decide run one workgroup per instance.
+// ---------------------------------------------------------------------------
+template <int KIND, class T>
+struct DescView {
+  using P = Plant<KIND, T>;
+  const typename P::Coef& pc;
+  const T* F;
+  const T* g;
+  T h, hh, h6, band;
+  int H, N;
+  uint32_t seed, inst;
+  const float* wlo;
+  const float* wspan;
+  float thlo, thspan;
+  const float* wbuf;
+  const float* thbuf;
+  const DevState* st;
+};
+
+template <int KIND>
+__device__ __forceinline__ DescView<KIND, float> view32(const InstDesc& d, const DevState* st,
+                                                        float band) {
+  return DescView<KIND, float>{
+      *reinterpret_cast<const typename Plant<KIND, float>::Coef*>(d.c32),
+      d.F32, d.g32, d.h, d.hh, d.h6, band, d.H, d.N, d.seed, d.instance, d.wlo, d.wspan,
+      d.thlo, d.thspan, nullptr, nullptr, st};
+}
+template <int KIND>
+__device__ __forceinline__ DescView<KIND, double> view64(const InstDesc& d, const DevState* st) {
+  return DescView<KIND, double>{
+      *reinterpret_cast<const typename Plant<KIND, double>::Coef*>(d.c64),
+      d.F64, d.g64, d.hd, d.hhd, d.h6d, 0.0, d.H, d.N, d.seed, d.instance, d.wlo, d.wspan,
+      d.thlo, d.thspan, nullptr, nullptr, st};
+}
+template <int KIND>
+__device__ __forceinline__ const typename Plant<KIND, double>::Coef& coef64(const InstDesc& d) {
+  return *reinterpret_cast<const typename Plant<KIND, double>::Coef*>(d.c64);
+}
+
+__global__ void __launch_bounds__(64) k_batch_setup(BatchBuffers b) {
+  const int i = blockIdx.x;
+  const InstDesc& d = b.desc[i];
+  if (d.kind == 1) setup_body<1>(coef64<1>(d), &b.st[i], &b.srch[i], nullptr, 0);
+  else setup_body<2>(coef64<2>(d), &b.st[i], &b.srch[i], nullptr, 0);
+}
+
+__global__ void k_batch_reset(BatchBuffers b) {
+  if (threadIdx.x == 0) {
+    b.counters[0] = 0;
+    b.counters[1] = 0;
+  }
+}
+
+template <int KIND, int INJ>
+__device__ __forceinline__ void batch_task(const BatchBuffers& b, int i, int c, int tile,
+                                           int early, float band, unsigned long long* sh) {
+  const InstDesc& d = b.desc[i];
+  DevSearch* S = &b.srch[i];
+  const DevState* st = &b.st[i];
+  const auto a = view32<KIND>(d, st, band);
+  const int k = tile * b.tile + threadIdx.x;
+  float m = INFINITY;
+  int jb = 0, ns = 0;
+  if (k < d.N) {
+    m = rollout_lane<KIND, float, 1, INJ>(a, early, (float)S->v[c], k, st->t,
+                                          early ? &S->dead[c] : nullptr, jb, ns, nullptr);
+    if (m < -band) {
+      __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (m < band) {
+      const int idx = atomicAdd(&b.counters[1], 1);
+      b.rlist[idx] = make_int4(i, c, k, 0);
+    }
+  }
+  const unsigned long long key = lane_key(m, k);
+  const unsigned long long kall = block_min_u64(key, sh);
+  const unsigned long long kfar = block_min_u64((m >= band) ? key : ~0ull, sh);
+  int wsum = ns;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off);
+  if ((threadIdx.x & 63) == 0) atomicAdd(&S->lane_steps, (unsigned long long)wsum);
+  if (threadIdx.x == 0) {
+    atomicMin(&S->key_all[c], kall);
+    if (kfar != ~0ull) atomicMin(&S->key_far[c], kfar);
+  }
+}
+
+// Persistent: every workgroup pops tasks until the queue is empty (each
+// workgroup reaches the exit test once per task, so the grid always drains).
+__global__ void __launch_bounds__(256) k_batch_rollout(BatchBuffers b, int cmax, float band,
+                                                       int early_opt) {
+  __shared__ int s_task;
+  __shared__ unsigned long long sh[16];
+  const int n_tasks = b.total_tiles * cmax;
+  for (;;) {
+    if (threadIdx.x == 0) s_task = atomicAdd(&b.counters[0], 1);
+    __syncthreads();
+    const int task = s_task;
+    __syncthreads();
+    if (task >= n_tasks) break;
+    const int gtile = task / cmax;
+    const int c = task - gtile * cmax;
+    int lo = 0, hi = b.count;  // last ordered instance whose first tile <= gtile
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (b.tile_start[mid] <= gtile) lo = mid;
+      else hi = mid;
+    }
+    const int i = b.order[lo];
+    const int tile = gtile - b.tile_start[lo];
+    DevSearch* S = &b.srch[i];
+    if (S->done || c >= S->n_cand) continue;
+    const int early = early_opt && !S->full[c];
+    if (early && S->mss[c] < 0.0) {
+      if (threadIdx.x == 0)
+        __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      continue;
+    }
+    const InstDesc& d = b.desc[i];
+    if (d.kind == 1) {
+      if (d.inject == 0) batch_task<1, 0>(b, i, c, tile, early, band, sh);
+      else batch_task<1, 1>(b, i, c, tile, early, band, sh);
+    } else {
+      if (d.inject == 0) batch_task<2, 0>(b, i, c, tile, early, band, sh);
+      else batch_task<2, 1>(b, i, c, tile, early, band, sh);
+    }
+  }
+}
+
+template <int KIND, int INJ>
+__device__ __forceinline__ void batch_recheck_one(const BatchBuffers& b, int i, int c, int k,
+                                                  int early) {
+  const InstDesc& d = b.desc[i];
+  DevSearch* S = &b.srch[i];
+  const auto a = view64<KIND>(d, &b.st[i]);
+  int jb = 0, ns = 0;
+  const int e = early && !S->full[c];
+  const double m = rollout_lane<KIND, double, 1, INJ>(a, e, S->v[c], k, b.st[i].t,
+                                                      e ? &S->fail64[c] : nullptr, jb, ns, nullptr);
+  atomicMin(&S->key64[c], ord64(m));
+  if (m < 0.0) __hip_atomic_store(&S->fail64[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(64) k_batch_recheck(BatchBuffers b, int early) {
+  const int n = b.counters[1];
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const int4 en = b.rlist[e];
+    const int i = en.x, c = en.y, k = en.z;
+    DevSearch* S = &b.srch[i];
+    if (S->done) continue;
+    if (early && !S->full[c] &&
+        (__hip_atomic_load(&S->dead[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+         __hip_atomic_load(&S->fail64[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
+      continue;
+    const InstDesc& d = b.desc[i];
+    if (d.kind == 1) {
+      if (d.inject == 0) batch_recheck_one<1, 0>(b, i, c, k, early);
+      else batch_recheck_one<1, 1>(b, i, c, k, early);
+    } else {
+      if (d.inject == 0) batch_recheck_one<2, 0>(b, i, c, k, early);
+      else batch_recheck_one<2, 1>(b, i, c, k, early);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(64) k_batch_decide(BatchBuffers b) {
+  const int i = blockIdx.x;
+  const InstDesc& d = b.desc[i];
+  if (d.kind == 1) decide_body<1>(coef64<1>(d), &b.st[i], &b.srch[i], nullptr);
+  else decide_body<2>(coef64<2>(d), &b.st[i], &b.srch[i], nullptr);
+}
+
+__global__ void k_batch_finalize(BatchBuffers b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= b.count) return;
+  const DevSearch* S = &b.srch[i];
+  DevResult R;
+  R.kappa = S->kappa_res;
+  R.v = S->v_res;
+  R.worst = S->worst_res;
+  R.status = S->status;
+  R.rounds = S->rounds_total;
+  R.candidates = S->cand_total;
+  R.rechecks = S->rechecks_total;
+  R.passes_alg1 = S->passes_alg1;
+  R.t = b.st[i].t;
+  R.lane_steps = S->lane_steps;
+  b.res[i] = R;
+  b.st[i].t = b.st[i].t + 1;
+}
+
 // ---------------------------------------------------------------------------
 // Host-side argument filling and launchers
 // ---------------------------------------------------------------------------
@@ -1472,6 +1715,35 @@ hipError_t launch_grad_reduce(const DevBuffers& b, int max_entries, int nth, int
   (void)max_entries;
   hipLaunchKernelGGL(k_grad_reduce, dim3(1), dim3(256), 0, st, b.grad, b.adj_dv, b.adj_dth, nth,
                      b.st, b.srch, cand);
+  return hipGetLastError();
+}
+
+hipError_t launch_equilibrium(const Problem& pr, const DevBuffers& b, double v, double* out_dev,
+                              hipStream_t st) {
+  return by_kind(pr.p.kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    hipLaunchKernelGGL(k_equilibrium<K>, dim3(1), dim3(64), 0, st, make_ctl<K>(pr, b, 0), v, out_dev);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_batch_setup(const BatchBuffers& b, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_setup, dim3(b.count), dim3(64), 0, st, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_round(const BatchBuffers& b, int cmax_round, double band, int early,
+                              int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, b);
+  hipLaunchKernelGGL(k_batch_rollout, dim3(grid), dim3(b.tile), 0, st, b, cmax_round, (float)band,
+                     early);
+  hipLaunchKernelGGL(k_batch_recheck, dim3(1024), dim3(64), 0, st, b, early);
+  hipLaunchKernelGGL(k_batch_decide, dim3(b.count), dim3(64), 0, st, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(const BatchBuffers& b, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_finalize, dim3(div_up(b.count, 256)), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 

@@ -60,7 +60,13 @@ class rg_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("band", C.c_double), ("K", C.c_int32),
                 ("search", C.c_int32), ("depth", C.c_int32), ("M", C.c_int32),
                 ("refine", C.c_int32), ("early_exit", C.c_int32), ("block", C.c_int32),
-                ("max_T", C.c_int32), ("lanes", C.c_int32), ("Kc", C.c_int32)]
+                ("max_T", C.c_int32), ("lanes", C.c_int32), ("Kc", C.c_int32),
+                ("persistent_wgs", C.c_int32)]
+
+
+class rg_instance_desc(C.Structure):
+    _fields_ = [("plant", rg_plant), ("scen", rg_scenarios), ("cons", rg_constraints),
+                ("H", C.c_int32), ("dt", C.c_double)]
 
 
 class rg_step_info(C.Structure):
@@ -111,6 +117,16 @@ def load_library(path: str = LIB_PATH, with_torch: bool = True) -> C.CDLL:
     L.rg_get_options.argtypes = [_vp, C.POINTER(rg_options)]
     L.rg_grad.argtypes = [_vp, _dp, C.c_double, C.c_double, C.c_double, _fp, _dp, _dp, _dp]
     L.rg_set_theta.argtypes = [_vp, _dp]
+    L.rg_equilibrium.argtypes = [_vp, C.c_double, _dp]
+    L.rg_batch_create.argtypes = [C.POINTER(rg_instance_desc), C.c_int32, C.POINTER(rg_options),
+                                  C.POINTER(_vp)]
+    L.rg_batch_destroy.argtypes = [_vp]
+    L.rg_batch_set_stream.argtypes = [_vp, _vp]
+    L.rg_batch_set_step.argtypes = [_vp, C.c_int32, C.c_uint32]
+    L.rg_batch_get_options.argtypes = [_vp, C.POINTER(rg_options)]
+    L.rg_batch_step.argtypes = [_vp, _dp, _dp, _dp, _dp, _dp, C.POINTER(rg_step_info), C.c_int32]
+    L.rg_batch_last_error.argtypes = [_vp]
+    L.rg_batch_last_error.restype = C.c_char_p
     L.rg_get_profile.argtypes = [_vp, C.POINTER(rg_profile)]
     L.rg_draws.argtypes = [_vp, C.c_uint32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _fp, _dp]
     L.rg_trajectory.argtypes = [_vp, _dp, C.c_double, _ip, C.c_int32, C.c_int32, _dp]
@@ -259,6 +275,11 @@ class Governor:
                                    _ptr(dth)))
         return dict(M=M.value, dkappa=dk.value, dtheta=dth[: self.problem.n_theta])
 
+    def equilibrium(self, v: float) -> np.ndarray:
+        x = np.zeros(self.problem.n)
+        self._check(self.L.rg_equilibrium(self.h, float(v), _ptr(x)))
+        return x
+
     def set_theta(self, theta_nom) -> None:
         th = _f64(theta_nom)
         assert th.size == self.problem.n_theta
@@ -303,3 +324,73 @@ class Governor:
         self._check(self.L.rg_trajectory(self.h, _ptr(x), float(v), _ptr(ks, _ip), ks.size,
                                          int(precision), _ptr(out)))
         return out
+
+
+class Batch:
+    """Many independent governors stepped together (``rg_batch_*``)."""
+
+    def __init__(self, problems, K: int = 12, band: float = 1e-4, depth: int = 0, block: int = 0,
+                 persistent_wgs: int = 0, early_exit: bool = True):
+        import torch
+        self.L = load_library()
+        self.problems = list(problems)
+        self._keep = []
+        descs = (rg_instance_desc * len(self.problems))()
+        for i, p in enumerate(self.problems):
+            co, wlo, whi = _f64(p.coeffs), _f64(p.w_lo), _f64(p.w_hi)
+            F, g = _f64(np.asarray(p.F).reshape(-1)), _f64(p.g)
+            self._keep += [co, wlo, whi, F, g]
+            descs[i].plant = rg_plant(p.kind, p.n, p.n_w, p.n_y, p.n_theta, _ptr(co), co.size)
+            descs[i].scen = rg_scenarios(int(p.N), int(p.seed) & 0xFFFFFFFF,
+                                         int(p.instance) & 0xFFFFFFFF, _ptr(wlo), _ptr(whi),
+                                         float(p.theta_rel), int(p.inject), RNG_INLINE)
+            descs[i].cons = rg_constraints(int(np.asarray(p.F).shape[0]), _ptr(F), _ptr(g),
+                                           float(p.eps), int(p.ss_check))
+            descs[i].H = int(p.H)
+            descs[i].dt = float(p.dt)
+        opt = default_options()
+        opt.K, opt.band, opt.depth, opt.block = K, band, depth, block
+        opt.persistent_wgs, opt.early_exit = persistent_wgs, int(early_exit)
+        h = _vp()
+        rc = self.L.rg_batch_create(descs, len(self.problems), C.byref(opt), C.byref(h))
+        if rc < 0:
+            raise RGError(rc, self.L.rg_batch_last_error(None).decode())
+        self.h = h
+        self.options = rg_options()
+        self.L.rg_batch_get_options(self.h, C.byref(self.options))
+        self.stream = torch.cuda.Stream()
+        self._check(self.L.rg_batch_set_stream(self.h, C.c_void_p(self.stream.cuda_stream)))
+
+    def _check(self, rc: int) -> int:
+        if rc < 0:
+            raise RGError(rc, self.L.rg_batch_last_error(self.h).decode())
+        return rc
+
+    def set_step(self, i: int, t: int) -> None:
+        self._check(self.L.rg_batch_set_step(self.h, i, int(t)))
+
+    def step(self, xs, r, v_prev, use_graph: bool = True) -> dict:
+        x = _f64(np.concatenate([np.asarray(v, dtype=np.float64) for v in xs]))
+        r = _f64(r)
+        vp = _f64(v_prev)
+        n = len(self.problems)
+        v = np.zeros(n)
+        kap = np.zeros(n)
+        infos = (rg_step_info * n)()
+        self._check(self.L.rg_batch_step(self.h, _ptr(x), _ptr(r), _ptr(vp), _ptr(v), _ptr(kap),
+                                         infos, int(use_graph)))
+        out = {k: np.array([getattr(infos[i], k) for i in range(n)])
+               for k in ["status", "rounds", "candidates", "bisect_passes", "lane_steps", "t"]}
+        out.update(v=v, kappa=kap)
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            self.L.rg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -179,3 +179,35 @@ def test_calls_reject_bad_arguments_before_device_work(lib):
     assert lib.rg_bind_workspace(h, C.c_void_p(0x1001), 1 << 30) == R.RG_E_INVAL
     assert lib.rg_bind_workspace(h, C.c_void_p(0x1000), 16) == R.RG_E_NOMEM
     assert lib.rg_destroy(h) == 0
+
+
+def test_batch_create_validates_and_step_reports_switched_off(lib):
+    ps = [W.lq4_problem(N=40, H=20), W.fc9_problem(N=30, H=10)]
+    descs = (R.rg_instance_desc * 2)()
+    keep = []
+    for i, p in enumerate(ps):
+        plant, scen, cons, k = _descriptors(p)
+        keep += k
+        descs[i].plant, descs[i].scen, descs[i].cons = plant, scen, cons
+        descs[i].H, descs[i].dt = p.H, p.dt
+    h = C.c_void_p()
+    assert lib.rg_batch_create(descs, 2, None, C.byref(h)) == 0 and h.value
+    o = R.rg_options()
+    assert lib.rg_batch_get_options(h, C.byref(o)) == 0 and 1 <= o.depth <= 6
+    dp = C.POINTER(C.c_double)
+    x = np.concatenate([np.zeros(4), np.asarray(W.FC9_XBAR)])
+    r = np.array([1.0, 1.0])
+    vp = np.zeros(2)
+    v = np.zeros(2)
+    xn = x.copy()
+    xn[5] = np.nan
+    assert lib.rg_batch_step(h, xn.ctypes.data_as(dp), r.ctypes.data_as(dp), vp.ctypes.data_as(dp),
+                             v.ctypes.data_as(dp), None, None, 0) == R.RG_E_INVAL
+    assert lib.rg_batch_step(h, x.ctypes.data_as(dp), r.ctypes.data_as(dp), vp.ctypes.data_as(dp),
+                             v.ctypes.data_as(dp), None, None, 0) == R.RG_E_NOTSUP
+    assert b"switched off" in lib.rg_batch_last_error(h)
+    assert lib.rg_batch_destroy(h) == 0
+    descs[1].scen.N = 0
+    h2 = C.c_void_p()
+    assert lib.rg_batch_create(descs, 2, None, C.byref(h2)) == R.RG_E_INVAL
+    assert b"instance 1" in lib.rg_batch_last_error(None)

@@ -1,6 +1,6 @@
 """GPU parity: the HIP governor (through the C ABI) against the FP64 CPU oracle.
 
-Tolerances (spec bar): FP32 trajectories and margins within
+Tolerances: FP32 trajectories and margins within
 1e-5 * max(1, |reference|) of the FP64 oracle; kappa within the bisection
 resolution 2^-K (in practice identical); draws bit-identical.
 """
@@ -327,3 +327,12 @@ def test_full_size_step_sampled(R, O):
         mss = o.steady_margin(v1)[0]
         assert min(m1, mss) < 0.0
     g.close()
+
+
+def test_equilibrium_matches_oracle(R, O):
+    for p, v in [(W.lq4_problem(seed=24, eps=0.01), 0.7), (W.fc9_problem(N=8, H=10), 0.5)]:
+        g = _gov(R, p)
+        x = g.equilibrium(v)
+        ref = O.Oracle(p).steady_margin(v)[1]
+        np.testing.assert_allclose(x, ref, rtol=1e-11, atol=1e-12)
+        g.close()
