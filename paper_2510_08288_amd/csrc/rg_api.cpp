@@ -92,7 +92,7 @@ Layout layout_of(const rg_handle* h) {
   L.res = take(sizeof(DevResult) * T);
   L.r_seq = take(sizeof(double) * T);
   L.x_hist = take(sizeof(double) * (T + 1) * kMaxN);
-  L.wbuf = take(pr.s.rng_mode == RG_RNG_STREAM ? sizeof(float) * (size_t)pr.H * pr.p.nw * N : 0);
+  L.wbuf = take(pr.s.rng_mode == RG_RNG_STREAM ? sizeof(float) * (size_t)(pr.H + kQuadGroup) * pr.p.nw * N : 0);
   L.thbuf = take(pr.s.rng_mode == RG_RNG_STREAM ? sizeof(float) * (size_t)pr.p.nth * N : 0);
   L.rlist = take(sizeof(int2) * (size_t)kCMax * N);
   L.per_m = take(sizeof(float) * (size_t)kCMax * N);

@@ -287,9 +287,10 @@ __global__ void __launch_bounds__(256) k_rollout(const RollArgs<KIND, T> a) {
 // state component x_q.  Every derivative evaluation forms the contributions of
 // x_q to the four rows in lane-relative order (slot s <-> row q XOR s), so two
 // DPP butterflies (partner q^2, then q^1) leave row q's sum in lane q with no
-// selects.  The margin rows use D = F C the same way, then a quad minimum.
-// All control decisions are quad-uniform (every lane of a quad holds the same
-// margin), which the DPP exchanges require.
+// selects.  The margin rows use D = F C the same way: lane q keeps the running
+// minimum of row q, and the quad minimum is formed once per group of steps
+// (for the exit test) and at the end.  All control decisions are quad-uniform,
+// which the DPP exchanges require.
 // ---------------------------------------------------------------------------
 struct QuadCoef {
   float a[4][4];  // a[q][s] = A[q^s][q]
@@ -312,24 +313,31 @@ struct QuadLane {
   float a0, a1, a2, a3, g0, g1, g2, g3;
 };
 
-// Row q of f(x) = s + A x + G (x.*x), reduced over the quad.
+// Row q of f(x) = s + A x + G (x.*x), summed over the quad.  Lane q forms
+// x_q's contribution to row q^s as c_s = (A[q^s][q] + G[q^s][q] x_q) x_q (slot
+// s); two DPP butterflies (partner q^2, then q^1) leave row q's sum in lane q.
 __device__ __forceinline__ float quad_deriv(const QuadLane& L, float s, float x) {
-  const float q = x * x;
-  float c0 = __builtin_fmaf(L.g0, q, __builtin_fmaf(L.a0, x, s));
-  float c1 = __builtin_fmaf(L.g1, q, L.a1 * x);
-  float c2 = __builtin_fmaf(L.g2, q, L.a2 * x);
-  float c3 = __builtin_fmaf(L.g3, q, L.a3 * x);
-  c0 = c0 + dpp<kSwap2>(c2);
+  const float c2 = __builtin_fmaf(L.g2, x, L.a2) * x;
+  const float c3 = __builtin_fmaf(L.g3, x, L.a3) * x;
+  float c0 = __builtin_fmaf(__builtin_fmaf(L.g0, x, L.a0), x, s);
+  float c1 = __builtin_fmaf(L.g1, x, L.a1) * x;
   c1 = c1 + dpp<kSwap2>(c3);
+  c0 = c0 + dpp<kSwap2>(c2);
   return c0 + dpp<kSwap1>(c1);
 }
 
 __device__ __forceinline__ float min2(float a, float b) { return b < a ? b : a; }
 
+// Minimum over the four lanes of a quad (every lane gets it).
+__device__ __forceinline__ float quad_min(float m) {
+  m = min2(m, dpp<kSwap1>(m));
+  return min2(m, dpp<kSwap2>(m));
+}
+
 template <int RNG, int INJ, int RECORD>
 __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, float> a,
                                                          const QuadCoef qc) {
-  constexpr int U = 4;  // steps per group: one prefetch, one exit test per group
+  constexpr int U = kQuadGroup;  // steps per group: one prefetch, one exit test per group
   DevSearch* S = a.srch;
   const int c = blockIdx.y;
   if (S->done || c >= S->n_cand) return;  // uniform over the workgroup
@@ -351,15 +359,20 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
     const float h = a.h, hh = a.hh, h6 = a.h6;
     const int H = a.H;
     float x = (float)a.st->x[q];
-    auto margin = [&](float xv) {
+    // lane q: margin of constraint row q (g_q - (F C x)_q); padding rows are +inf
+    auto row_margin = [&](float xv) {
+      const float c2 = d2 * xv, c3 = d3 * xv;
       float c0 = __builtin_fmaf(d0, xv, grow);
-      float c1 = d1 * xv, c2 = d2 * xv, c3 = d3 * xv;
-      c0 = c0 + dpp<kSwap2>(c2);
+      float c1 = d1 * xv;
       c1 = c1 + dpp<kSwap2>(c3);
-      float m = c0 + dpp<kSwap1>(c1);
-      m = min2(m, dpp<kSwap1>(m));
-      return min2(m, dpp<kSwap2>(m));
+      c0 = c0 + dpp<kSwap2>(c2);
+      return c0 + dpp<kSwap1>(c1);
     };
+    // Without a recorded arg-min step each lane keeps the running minimum of
+    // its own row; the quad minimum is taken once per group (exit test) and
+    // at the end, which gives the same minimum over rows and steps.
+    float bq = row_margin(x);
+    if (RECORD) best = quad_min(bq);
     auto step = [&](float w0, float w1, int jnext) {
       const float s = INJ == 0 ? __builtin_fmaf(e1, w1, __builtin_fmaf(e0, w0, bv)) : bv;
       const float k1 = quad_deriv(L, s, x);
@@ -374,34 +387,42 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
       const float k4 = quad_deriv(L, s, xs);
       x = __builtin_fmaf(h6, acc + k4, x);
       if (INJ == 1) x = x + (e0 * w0 + e1 * w1);
-      const float m = margin(x);
+      const float mr = row_margin(x);
       if (RECORD) {
+        const float m = quad_min(mr);
         if (m < best) {
           best = m;
           jb = jnext;
         }
       } else {
-        best = min2(best, m);
+        bq = fminf(bq, mr);
       }
     };
-    // draws of steps j..j+U-1 (indices clamped into the horizon)
-    const size_t N2 = 2 * (size_t)a.N;
+    // Draws of steps j..j+U-1.  Streamed: raw buffer loads with the row's byte
+    // offset in a scalar register and the lane's offset in a vector register
+    // (no per-lane address arithmetic); the buffer holds U spare rows past H and
+    // its byte size fits the 32-bit offsets (checked by the launcher).
+    const uint32_t row_bytes = 8u * (uint32_t)a.N;  // one step: n_w = 2 floats x N
+    const uint32_t vo0 = 4u * (uint32_t)k, vo1 = vo0 + 4u * (uint32_t)a.N;
+    const __amdgpu_buffer_rsrc_t wres = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)a.wbuf, (short)0, (int)(row_bytes * (uint32_t)(H + U)), 0x00020000);
+    uint32_t so = 0;  // byte offset of the next group's first row
     auto load_group = [&](int j, float* w) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int jj = (j + u) < H ? (j + u) : (H - 1);
         if (RNG == 0) {
-          const float* p = a.wbuf + (size_t)jj * N2 + k;
-          w[2 * u] = p[0];
-          w[2 * u + 1] = p[a.N];
+          const uint32_t sr = so + (uint32_t)u * row_bytes;
+          w[2 * u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(wres, vo0, sr, 0));
+          w[2 * u + 1] =
+              __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(wres, vo1, sr, 0));
         } else {
-          const Words r = philox10((uint32_t)k, (uint32_t)jj, t, 0u, a.seed, a.inst);
+          const Words r = philox10((uint32_t)k, (uint32_t)(j + u), t, 0u, a.seed, a.inst);
           w[2 * u] = box_draw(r.v[0], a.wlo[0], a.wspan[0]);
           w[2 * u + 1] = box_draw(r.v[1], a.wlo[1], a.wspan[1]);
         }
       }
+      if (RNG == 0) so += (uint32_t)U * row_bytes;
     };
-    best = margin(x);
     float wcur[2 * U], wnext[2 * U];
     load_group(0, wcur);
     const int full = H / U;
@@ -413,7 +434,8 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
 #pragma unroll
       for (int u = 0; u < 2 * U; ++u) wcur[u] = wnext[u];
       if (early) {
-        if (best < -a.band) {
+        const float bg = RECORD ? best : quad_min(bq);
+        if (bg < -a.band) {
           ++g;
           break;
         }
@@ -429,6 +451,7 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
       for (int u = 0; u < H - full * U; ++u) step(wcur[2 * u], wcur[2 * u + 1], full * U + u + 1);
       ns = H;
     }
+    if (!RECORD) best = quad_min(bq);
     // non-finite state in any lane of the quad -> -inf
     float bad = x - x;
     bad = bad + dpp<kSwap1>(bad);
@@ -1576,9 +1599,15 @@ static QuadCoef make_quad_coef(const Problem& pr) {
   return qc;
 }
 
+// The quad kernel addresses the streamed draws with 32-bit byte offsets.
+static bool quad_draws_addressable(const Problem& pr) {
+  const double bytes = 8.0 * (double)pr.s.N * (double)(pr.H + kQuadGroup);
+  return pr.s.rng_mode != 0 || bytes < 4294967296.0;  // rng_mode 1: inline draws
+}
+
 hipError_t launch_rollout(const Problem& pr, double band, int precision, int early_exit, int record,
                           const LaunchCfg& cfg, const DevBuffers& b, hipStream_t st) {
-  if (cfg.lanes == 4 && precision == 0 && pr.p.kind == 1) {
+  if (cfg.lanes == 4 && precision == 0 && pr.p.kind == 1 && quad_draws_addressable(pr)) {
     const dim3 grid(div_up((size_t)pr.s.N * 4, (size_t)cfg.block), cfg.cmax_round);
     const QuadCoef qc = make_quad_coef(pr);
     auto a = make_args<1, float>(pr, band, early_exit, record, b);
