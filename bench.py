@@ -39,6 +39,11 @@ FLOP_PER_STEP_LQ4 = 375      # algorithmic FLOP of one LQ4 scenario-step (FMA = 
 BYTES_PER_STEP_LQ4 = 8       # streamed draws read per scenario-step (2 x fp32)
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (needs packed FP32)
 PEAK_FP32_NONPACKED_TFLOPS = 78.6
+# HBM bytes per rollout launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
+# this bench (4 updates), each scaled by the counter's reading for a 256 MiB device
+# copy; valid only for the kernel source they were taken on (SHA-1 below).
+HBM_TRAFFIC = {"kernels_sha1": "7dd9bfa4a9ccbf38f76cc95fdd171289a3306130",
+               "bytes_per_launch": 28848945}
 
 
 def cpu_baseline(wl, r_seq, seconds):
@@ -71,6 +76,16 @@ def cpu_baseline(wl, r_seq, seconds):
                 rg_updates_per_s=steps / el,
                 sample=f"first {steps} RG updates of the same closed loop (N={p.N}, H={p.H}), "
                        f"FP64 bisection, {threads} threads over scenarios, {el:.1f} s"), kappas
+
+
+def measured_traffic():
+    """roofline.traffic: the counter-based HBM bytes per rollout launch, or None
+    once the kernel source differs from the one the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_2510_08288_amd", "csrc", "rg_kernels.hip")
+    with open(path, "rb") as f:
+        sha = hashlib.sha1(f.read()).hexdigest()
+    return HBM_TRAFFIC["bytes_per_launch"] if sha == HBM_TRAFFIC["kernels_sha1"] else None
 
 
 def run_form(args):
@@ -115,10 +130,14 @@ def main():
     ap.add_argument("--depth", type=int, default=0)
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
     ap.add_argument("--lanes", type=int, default=0)
-    ap.add_argument("--mode-steps", type=int, default=25,
-                    help="closed-loop steps timed for the Newton and FP64 search forms")
+    ap.add_argument("--mode-steps", type=int, default=0,
+                    help="closed-loop steps timed for the Newton and FP64 search forms "
+                         "(0: the same steps as the headline form)")
     ap.add_argument("--form", choices=["fp32_adjoint_newton", "fp64_sequential_bisection"],
                     default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only copy one device buffer of BYTES into another three times (the "
+                         "reference kernel for scaling HBM counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the scenario axis would "
@@ -134,6 +153,14 @@ def main():
     torch.cuda.set_device(0)
     if args.form is not None:
         return run_form(args)
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_calibration, "copies": 3}))
+        return
     T = max(args.steps, args.warmup)
     wl = W.workload_lq4_closed_loop(T=T)
     p = wl["problem"]
@@ -175,9 +202,9 @@ def main():
     # The same closed loop under the other two search forms the metric names:
     # FP32 rollouts + adjoint-driven Newton, and plain sequential FP64 bisection
     # (one candidate per device round, Alg. 1 as written).  Each runs in a child
-    # process; fewer steps, as the FP64 form is slow.
+    # process over the same updates.
     modes = {}
-    Km = min(args.steps, args.mode_steps)
+    Km = min(args.steps, args.mode_steps) if args.mode_steps > 0 else args.steps
     for label in ["fp32_adjoint_newton", "fp64_sequential_bisection"]:
         child = subprocess.run([sys.executable, os.path.abspath(__file__), "--form", label,
                                 "--steps", str(Km)], capture_output=True, text=True)
@@ -231,7 +258,8 @@ def main():
                          "bisect_passes": int(np.sum(out["bisect_passes"])),
                          "infeasible_steps": int(np.sum(out["status"] != 0))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": measured_traffic(),
                      "kernel": ("k_rollout_lq4_quad (one scenario per 4 lanes)" if g.options.lanes == 4
                                 else "k_rollout<LQ4, float>"),
                      "launches": prof["rollout_launches"],

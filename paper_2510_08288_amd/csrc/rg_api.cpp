@@ -73,7 +73,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Workspace layout: offsets of each buffer inside one allocation.
 struct Layout {
   size_t st, srch, res, r_seq, x_hist, wbuf, thbuf, rlist, per_m, per_j, scratch;
-  size_t grad, adj_k, adj_w, adj_m, adj_dv, adj_dth, adj_ckpt, adj_seg, total;
+  size_t grad, adj_k, adj_w, adj_m, adj_dv, adj_dth, adj_ckpt, adj_seg;
+  size_t seg_m, seg_j, seg_r, seg_x, seg_a, seg_cv, seg_ct, seg_scr, total;
 };
 
 Layout layout_of(const rg_handle* h) {
@@ -107,6 +108,15 @@ Layout layout_of(const rg_handle* h) {
   L.adj_dth = take(sizeof(double) * kMaxTh * N);
   L.adj_ckpt = take(sizeof(float) * ((size_t)pr.H / Kc + 1) * n * N);
   L.adj_seg = take(sizeof(float) * Kc * n * N);
+  const size_t S = (size_t)pr.H / Kc + 1;
+  L.seg_m = take(sizeof(float) * S);
+  L.seg_j = take(sizeof(int32_t) * S);
+  L.seg_r = take(sizeof(int32_t) * S);
+  L.seg_x = take(sizeof(float) * S * n);
+  L.seg_a = take(sizeof(float) * S * n * n);
+  L.seg_cv = take(sizeof(double) * S * n);
+  L.seg_ct = take(sizeof(double) * S * n * kMaxTh);
+  L.seg_scr = take(sizeof(float) * Kc * n * S * n);
   L.total = off;
   return L;
 }
@@ -189,6 +199,14 @@ int ensure_workspace(rg_handle* h) {
   b.adj_dth = (double*)(base + L.adj_dth);
   b.adj_ckpt = (float*)(base + L.adj_ckpt);
   b.adj_seg = (float*)(base + L.adj_seg);
+  b.seg_m = (float*)(base + L.seg_m);
+  b.seg_j = (int32_t*)(base + L.seg_j);
+  b.seg_r = (int32_t*)(base + L.seg_r);
+  b.seg_x = (float*)(base + L.seg_x);
+  b.seg_a = (float*)(base + L.seg_a);
+  b.seg_cv = (double*)(base + L.seg_cv);
+  b.seg_ct = (double*)(base + L.seg_ct);
+  b.seg_scr = (float*)(base + L.seg_scr);
   // Search configuration.
   DevSearch* S = new (std::nothrow) DevSearch;
   if (!S) return fail(h, RG_E_NOMEM, "host allocation");
@@ -278,16 +296,17 @@ hipError_t enqueue_step(rg_handle* h, int closed_loop) {
       if ((e = next_event(h, &e0)) != hipSuccess || (e = next_event(h, &e1)) != hipSuccess) return e;
       if ((e = hipEventRecord(e0, h->stream)) != hipSuccess) return e;
     }
-    if ((e = launch_rollout(h->pr, band, prec, h->opt.early_exit, 0, h->cfg, h->b, h->stream)) !=
-        hipSuccess)
+    // the Newton iterate keeps checkpoints for its derivative
+    if ((e = launch_rollout(h->pr, band, prec, h->opt.early_exit, 0, h->cfg, h->b, h->stream,
+                            newton ? -1 : -2, h->opt.Kc)) != hipSuccess)
       return e;
     if (h->profiling && (e = hipEventRecord(e1, h->stream)) != hipSuccess) return e;
     if (prec == RG_PREC_F32_RECHECK &&
         (e = launch_recheck(h->pr, h->opt.early_exit, h->cfg, h->b, h->stream)) != hipSuccess)
       return e;
-    if (newton) {  // derivative of the Newton iterate's worst margin (adjoint)
+    if (newton) {  // derivative of the Newton iterate's worst margin (segment adjoint)
       if ((e = launch_grad_prepare(h->pr, h->b, -1, 1, h->stream)) != hipSuccess) return e;
-      if ((e = launch_adjoint(h->pr, h->opt.Kc, 1, h->b, -1, h->stream)) != hipSuccess) return e;
+      if ((e = launch_seg_grad(h->pr, h->opt.Kc, -1, h->b, h->stream)) != hipSuccess) return e;
       if ((e = launch_grad_reduce(h->b, 1, h->pr.p.nth, -1, h->stream)) != hipSuccess) return e;
     }
     if ((e = launch_decide(h->pr, h->b, h->stream)) != hipSuccess) return e;
@@ -632,7 +651,8 @@ int rg_grad(rg_handle* h, const double* x, double r, double v_prev, double kappa
                            hipMemcpyHostToDevice, h->stream));
   HIPCHK(h, launch_setup_list(h->pr, h->b, 1, h->stream));
   // arg-min scenario from the FP32 rollouts (keys carry the scenario index)
-  HIPCHK(h, launch_rollout(h->pr, h->opt.band, RG_PREC_F32_RECHECK, 0, 1, cfg, h->b, h->stream));
+  HIPCHK(h, launch_rollout(h->pr, h->opt.band, RG_PREC_F32_RECHECK, 0, 1, cfg, h->b, h->stream,
+                           upstream ? -2 : 0, h->opt.Kc));
   HIPCHK(h, launch_recheck(h->pr, 0, cfg, h->b, h->stream));
   int max_entries = 1;
   if (upstream) {
@@ -650,7 +670,10 @@ int rg_grad(rg_handle* h, const double* x, double r, double v_prev, double kappa
   } else {
     HIPCHK(h, launch_grad_prepare(h->pr, h->b, 0, 1, h->stream));
   }
-  HIPCHK(h, launch_adjoint(h->pr, h->opt.Kc, max_entries, h->b, 0, h->stream));
+  if (upstream)  // weighted scenarios: one sequential reverse sweep per scenario
+    HIPCHK(h, launch_adjoint(h->pr, h->opt.Kc, max_entries, h->b, 0, h->stream));
+  else  // the arg-min scenario: segment-parallel reverse sweep
+    HIPCHK(h, launch_seg_grad(h->pr, h->opt.Kc, 0, h->b, h->stream));
   HIPCHK(h, launch_grad_reduce(h->b, max_entries, h->pr.p.nth, 0, h->stream));
   DevGrad G;
   HIPCHK(h, hipMemcpyAsync(&G, h->b.grad, sizeof(G), hipMemcpyDeviceToHost, h->stream));

@@ -129,6 +129,15 @@ struct DevBuffers {
   double* adj_dth;         // [N * kMaxTh] weighted dm/dtheta_nom of each entry
   float* adj_ckpt;         // [(H / Kc + 1) * n * N] forward checkpoints (SoA by entry)
   float* adj_seg;          // [Kc * n * N] recomputed segment states
+  // segment-parallel derivative (S = H / Kc + 1 segments)
+  float* seg_m;            // [S]
+  int32_t* seg_j;          // [S]
+  int32_t* seg_r;          // [S]
+  float* seg_x;            // [S * n]
+  float* seg_a;            // [S * n * n]
+  double* seg_cv;          // [S * n]
+  double* seg_ct;          // [S * n * kMaxTh]
+  float* seg_scr;          // [Kc * n * S * n]
 };
 
 struct LaunchCfg {
@@ -184,8 +193,11 @@ struct Problem {
 hipError_t launch_gen(const Problem& pr, const DevBuffers& b, hipStream_t st);
 hipError_t launch_setup(const Problem& pr, const DevBuffers& b, int closed_loop, hipStream_t st);
 hipError_t launch_setup_list(const Problem& pr, const DevBuffers& b, int M, hipStream_t st);
+// ckpt_cand >= 0 (or -1 for the Newton iterate) keeps that candidate's
+// checkpoints every Kc steps for the segment derivative; -2 keeps none.
 hipError_t launch_rollout(const Problem& pr, double band, int precision, int early_exit, int record,
-                          const LaunchCfg& cfg, const DevBuffers& b, hipStream_t st);
+                          const LaunchCfg& cfg, const DevBuffers& b, hipStream_t st,
+                          int ckpt_cand = -2, int Kc = 0);
 hipError_t launch_recheck(const Problem& pr, int early_exit, const LaunchCfg& cfg,
                           const DevBuffers& b, hipStream_t st);
 hipError_t launch_decide(const Problem& pr, const DevBuffers& b, hipStream_t st);
@@ -200,6 +212,10 @@ hipError_t launch_grad_prepare(const Problem& pr, const DevBuffers& b, int cand,
                                hipStream_t st);
 hipError_t launch_adjoint(const Problem& pr, int Kc, int max_entries, const DevBuffers& b,
                           int cand, hipStream_t st);
+// Derivative of the worst margin of one scenario (k_star of the gradient
+// record) from the checkpoints the rollout kept: segment kernels.
+hipError_t launch_seg_grad(const Problem& pr, int Kc, int cand, const DevBuffers& b,
+                           hipStream_t st);
 hipError_t launch_grad_reduce(const DevBuffers& b, int max_entries, int nth, int cand,
                               hipStream_t st);
 hipError_t launch_trajectory(const Problem& pr, double v, const int32_t* k_list_dev, int nk,

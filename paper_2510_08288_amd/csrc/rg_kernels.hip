@@ -46,6 +46,11 @@ struct RollArgs {
   float* per_m;
   int32_t* per_j;
   int2* rlist;
+  // checkpoints of one candidate's scenarios for the segment derivative:
+  // ckpt[(s * n + i) * N + k] = state component i of scenario k at step s * Kc
+  float* ckpt;
+  int Kc;
+  int ckpt_cand;  // that candidate (-1: the Newton iterate of the round)
 };
 
 template <int KIND>
@@ -119,10 +124,10 @@ __global__ void __launch_bounds__(256) k_gen(RollArgs<KIND, float> a, float* wbu
 // stop_flag (nullable) is polled every 32 steps; early != 0 also stops the
 // lane once its minimum is below -band.  traj (nullable) receives states.
 // ---------------------------------------------------------------------------
-template <int KIND, class T, int RNG, int INJ, class A>
+template <int KIND, class T, int RNG, int INJ, class A, int CKPT = 0>
 __device__ __forceinline__ T rollout_lane(const A& a, int early, T v, int k, uint32_t t,
                                           const int32_t* stop_flag, int& jbest, int& nsteps,
-                                          double* traj) {
+                                          double* traj, bool ck = false) {
   using P = Plant<KIND, T>;
   T th[P::nth > 0 ? P::nth : 1];
   if constexpr (P::nth > 0) {
@@ -148,6 +153,13 @@ __device__ __forceinline__ T rollout_lane(const A& a, int early, T v, int k, uin
   jbest = 0;
   if (traj) {
     for (int i = 0; i < P::n; ++i) traj[i] = (double)x[i];
+  }
+  int ck_left = 0, ck_seg = 0;  // steps to the next checkpoint, its index
+  if constexpr (CKPT) {
+    if (ck) {
+      for (int i = 0; i < P::n; ++i) a.ckpt[(size_t)i * a.N + k] = (float)x[i];
+      ck_left = a.Kc;
+    }
   }
   float wc[P::nw], wn[P::nw];
   auto load = [&](int j, float* w) {
@@ -187,6 +199,14 @@ __device__ __forceinline__ T rollout_lane(const A& a, int early, T v, int k, uin
     }
     if (traj) {
       for (int i = 0; i < P::n; ++i) traj[(size_t)(j + 1) * P::n + i] = (double)x[i];
+    }
+    if constexpr (CKPT) {
+      if (ck && --ck_left == 0) {
+        ck_left = a.Kc;
+        ++ck_seg;
+        for (int i = 0; i < P::n; ++i)
+          a.ckpt[((size_t)ck_seg * P::n + i) * a.N + k] = (float)x[i];
+      }
     }
     if (early) {
       if (best < -a.band) {
@@ -242,11 +262,12 @@ __device__ __forceinline__ bool refused_by_steady_state(int early, DevSearch* S,
 
 // Main rollout kernel: blockIdx.y = candidate of the round, blockIdx.x * block
 // + threadIdx.x = scenario.
-template <int KIND, class T, int RNG, int INJ>
+template <int KIND, class T, int RNG, int INJ, int CKPT>
 __global__ void __launch_bounds__(256) k_rollout(const RollArgs<KIND, T> a) {
   DevSearch* S = a.srch;
   const int c = blockIdx.y;
   if (S->done || c >= S->n_cand) return;  // uniform over the workgroup
+  const bool ck = CKPT && c == (a.ckpt_cand >= 0 ? a.ckpt_cand : S->nk_idx);
   const int early = a.early && !S->full[c];
   if (refused_by_steady_state(early, S, c)) return;
   __shared__ unsigned long long sh[16];
@@ -255,8 +276,8 @@ __global__ void __launch_bounds__(256) k_rollout(const RollArgs<KIND, T> a) {
   T m = t_inf<T>();
   int jb = 0, ns = 0;
   if (k < a.N) {
-    m = rollout_lane<KIND, T, RNG, INJ>(a, early, (T)S->v[c], k, t,
-                                        early ? &S->dead[c] : nullptr, jb, ns, nullptr);
+    m = rollout_lane<KIND, T, RNG, INJ, RollArgs<KIND, T>, CKPT>(
+        a, early, (T)S->v[c], k, t, early ? &S->dead[c] : nullptr, jb, ns, nullptr, ck);
     if (a.record) {
       a.per_m[(size_t)c * a.N + k] = (float)m;
       a.per_j[(size_t)c * a.N + k] = jb;
@@ -334,13 +355,14 @@ __device__ __forceinline__ float quad_min(float m) {
   return min2(m, dpp<kSwap2>(m));
 }
 
-template <int RNG, int INJ, int RECORD>
+template <int RNG, int INJ, int RECORD, int CKPT>
 __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, float> a,
                                                          const QuadCoef qc) {
   constexpr int U = kQuadGroup;  // steps per group: one prefetch, one exit test per group
   DevSearch* S = a.srch;
   const int c = blockIdx.y;
   if (S->done || c >= S->n_cand) return;  // uniform over the workgroup
+  const bool ck = CKPT && c == (a.ckpt_cand >= 0 ? a.ckpt_cand : S->nk_idx);
   const int early = a.early && !S->full[c];
   if (refused_by_steady_state(early, S, c)) return;
   __shared__ unsigned long long sh[16];
@@ -373,6 +395,11 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
     // at the end, which gives the same minimum over rows and steps.
     float bq = row_margin(x);
     if (RECORD) best = quad_min(bq);
+    int ck_left = 0, ck_seg = 0;  // steps to the next checkpoint, its index
+    if (CKPT && ck) {
+      a.ckpt[(size_t)q * a.N + k] = x;
+      ck_left = a.Kc;
+    }
     auto step = [&](float w0, float w1, int jnext) {
       const float s = INJ == 0 ? __builtin_fmaf(e1, w1, __builtin_fmaf(e0, w0, bv)) : bv;
       const float k1 = quad_deriv(L, s, x);
@@ -387,6 +414,11 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
       const float k4 = quad_deriv(L, s, xs);
       x = __builtin_fmaf(h6, acc + k4, x);
       if (INJ == 1) x = x + (e0 * w0 + e1 * w1);
+      if (CKPT && ck && --ck_left == 0) {
+        ck_left = a.Kc;
+        ++ck_seg;
+        a.ckpt[((size_t)ck_seg * 4 + q) * a.N + k] = x;
+      }
       const float mr = row_margin(x);
       if (RECORD) {
         const float m = quad_min(mr);
@@ -1109,6 +1141,241 @@ __global__ void __launch_bounds__(64) k_adjoint(const RollArgs<KIND, float> a, c
   }
 }
 
+// ---------------------------------------------------------------------------
+// Segment-parallel derivative of one scenario's worst margin.
+//
+// The rollout keeps the state of every scenario of one candidate at steps
+// s * Kc.  For the chosen scenario k*:
+//   k_seg_min      one lane per segment: recompute the segment, its margin
+//                  minimum, first minimising step and row, and that state;
+//   k_seg_vjp      one lane per (segment s, state component o), segments up to
+//                  the first minimising step j*: recompute the segment, then
+//                  run the RK4 reverse sweep from lambda = e_o at its end.  The
+//                  lane leaves row o of the segment's state transfer matrix and
+//                  the derivative of component o at the segment end with
+//                  respect to v and theta over that segment;
+//   k_seg_combine  one thread: lambda = dm/dx at j*, then for the segments
+//                  from the last to the first, add lambda . (v, theta columns)
+//                  and apply the transposed transfer matrix.
+// The result equals the reverse sweep over all j* steps (chain rule over the
+// segments); the sequential part is one short loop per segment instead of
+// one RK4 step per time step.
+// ---------------------------------------------------------------------------
+struct SegArgs {
+  int Kc, S;          // checkpoint interval; segments covering steps 0..H
+  int cand;           // candidate (-1: the Newton iterate)
+  int lanes;          // stride of the state scratch (= S * n)
+  float* seg_m;       // [S] segment minimum (NaN: non-finite trajectory)
+  int32_t* seg_j;     // [S] its first minimising step
+  int32_t* seg_r;     // [S] its constraint row
+  float* seg_x;       // [S * n] state at that step
+  float* seg_a;       // [(s * n + o) * n + i] row o of the segment's transfer matrix
+  double* seg_cv;     // [s * n + o] d x_o(segment end) / d v over the segment
+  double* seg_ct;     // [(s * n + o) * kMaxTh + c] same for theta^k_c
+  float* scratch;     // [(jj * n + i) * lanes + lane] states of a lane's segment
+  float* out_m;       // entry 0 outputs, as the sequential adjoint writes them
+  double* out_dv;
+  double* out_dth;
+  DevGrad* grad;
+};
+
+// Per-lane scenario model shared by the segment kernels.
+template <int KIND, int RNG, int INJ>
+struct SegLane {
+  using P = Plant<KIND, float>;
+  const RollArgs<KIND, float>& a;
+  int k;
+  uint32_t t;
+  typename P::Lane L;
+  float fac[P::nth > 0 ? P::nth : 1];
+  __device__ SegLane(const RollArgs<KIND, float>& a_, int k_, float v) : a(a_), k(k_) {
+    t = a.st->t;
+    float th[P::nth > 0 ? P::nth : 1];
+    if constexpr (P::nth > 0) {
+      if (RNG == 0) {
+        for (int c = 0; c < P::nth; ++c) fac[c] = a.thbuf[(size_t)c * a.N + k];
+      } else {
+        draw_theta_factor<P::nth>(a.seed, a.inst, t, (uint32_t)k, a.thlo, a.thspan, fac);
+      }
+      for (int c = 0; c < P::nth; ++c) th[c] = a.pc.thnom[c] * fac[c];
+    } else {
+      fac[0] = 1.f;
+    }
+    P::lane_init(a.pc, th, v, L);
+  }
+  __device__ void draws(int j, float* w) const {
+    if (RNG == 0) {
+      for (int c = 0; c < P::nw; ++c) w[c] = a.wbuf[((size_t)j * P::nw + c) * a.N + k];
+    } else {
+      draw_w<P::nw>(a.seed, a.inst, t, 0u, (uint32_t)k, (uint32_t)j, a.wlo, a.wspan, w);
+    }
+  }
+  __device__ void forcing(const float* w, float* s) const {
+    if (INJ == 0) P::force(a.pc, L, w, s);
+    else P::force0(a.pc, L, s);
+  }
+  __device__ void step(float* x, int j) const {
+    float w[P::nw], s[P::n];
+    draws(j, w);
+    forcing(w, s);
+    rk4_step<KIND, float>(a.pc, L, s, a.h, a.hh, a.h6, x);
+    if (INJ == 1) P::post(a.pc, w, x);
+  }
+  __device__ float margin(const float* x, int& r) const {
+    float y[P::ny];
+    P::output(a.pc, L, x, y);
+    return margin_rows_arg<P::ny>(a.F, a.g, y, r);
+  }
+};
+
+// Which candidate and scenario the segment kernels work on; false when there
+// is nothing to do (search finished, or the steady-state term is active).
+__device__ __forceinline__ bool seg_target(const DevSearch* S, const SegArgs& g, int& cand,
+                                           int& ks) {
+  if (g.cand < 0 && S->done) return false;
+  cand = g.cand >= 0 ? g.cand : S->nk_idx;
+  ks = g.grad->k_star;
+  return ks >= 0 && g.grad->n_entries > 0;
+}
+
+// First minimiser over the segment minima; false if any segment is non-finite.
+__device__ __forceinline__ bool seg_argmin(const SegArgs& g, float& best, int& sb) {
+  best = INFINITY;
+  sb = 0;
+  for (int s = 0; s < g.S; ++s) {
+    const float m = g.seg_m[s];
+    if (m != m) return false;
+    if (m < best) {
+      best = m;
+      sb = s;
+    }
+  }
+  return true;
+}
+
+template <int KIND, int RNG, int INJ>
+__global__ void __launch_bounds__(64) k_seg_min(const RollArgs<KIND, float> a, const SegArgs g,
+                                                const float* ckpt) {
+  using P = Plant<KIND, float>;
+  constexpr int n = P::n;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.S) return;
+  int cand, ks;
+  if (!seg_target(a.srch, g, cand, ks)) return;
+  const SegLane<KIND, RNG, INJ> M(a, ks, (float)a.srch->v[cand]);
+  float x[n], xb[n];
+  for (int i = 0; i < n; ++i) x[i] = ckpt[((size_t)s * n + i) * a.N + ks];
+  const int j0 = s * g.Kc, j1 = (j0 + g.Kc < a.H) ? j0 + g.Kc : a.H;
+  float best = INFINITY;
+  int jb = j0, rb = 0;
+  if (s == 0) {  // the initial state belongs to the first segment
+    best = M.margin(x, rb);
+    jb = 0;
+  }
+  for (int i = 0; i < n; ++i) xb[i] = x[i];
+  for (int j = j0; j < j1; ++j) {
+    M.step(x, j);
+    int r = 0;
+    const float m = M.margin(x, r);
+    if (m < best || m != m) {
+      best = m;
+      jb = j + 1;
+      rb = r;
+      for (int i = 0; i < n; ++i) xb[i] = x[i];
+    }
+  }
+  bool finite = true;
+  for (int i = 0; i < n; ++i) finite = finite && (x[i] - x[i] == 0.f);
+  g.seg_m[s] = finite ? best : NAN;
+  g.seg_j[s] = jb;
+  g.seg_r[s] = rb;
+  for (int i = 0; i < n; ++i) g.seg_x[(size_t)s * n + i] = xb[i];
+}
+
+template <int KIND, int RNG, int INJ>
+__global__ void __launch_bounds__(64) k_seg_vjp(const RollArgs<KIND, float> a, const SegArgs g,
+                                                const float* ckpt) {
+  using P = Plant<KIND, float>;
+  constexpr int n = P::n;
+  const int lane = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lane >= g.S * n) return;
+  int cand, ks;
+  if (!seg_target(a.srch, g, cand, ks)) return;
+  float best;
+  int sb;
+  if (!seg_argmin(g, best, sb)) return;
+  const int js = g.seg_j[sb];
+  const int s = lane / n, o = lane - s * n;
+  const int j0 = s * g.Kc;
+  if (j0 >= js) return;  // segment after the minimising step
+  const int j1 = (j0 + g.Kc < js) ? j0 + g.Kc : js;
+  const SegLane<KIND, RNG, INJ> M(a, ks, (float)a.srch->v[cand]);
+  float x[n];
+  for (int i = 0; i < n; ++i) x[i] = ckpt[((size_t)s * n + i) * a.N + ks];
+  const size_t L = (size_t)g.lanes;
+  for (int j = j0; j < j1; ++j) {
+    for (int i = 0; i < n; ++i) g.scratch[((size_t)(j - j0) * n + i) * L + lane] = x[i];
+    M.step(x, j);
+  }
+  float lam[n];
+  for (int i = 0; i < n; ++i) lam[i] = (i == o) ? 1.f : 0.f;
+  double vb = 0.0;
+  double tb[P::nth > 0 ? P::nth : 1];
+  for (int c = 0; c < (P::nth > 0 ? P::nth : 1); ++c) tb[c] = 0.0;
+  for (int j = j1 - 1; j >= j0; --j) {
+    for (int i = 0; i < n; ++i) x[i] = g.scratch[((size_t)(j - j0) * n + i) * L + lane];
+    float w[P::nw], sf[n];
+    M.draws(j, w);
+    M.forcing(w, sf);
+    rk4_vjp<KIND, float>(a.pc, M.L, sf, a.h, a.hh, a.h6, x, lam, vb, tb);
+  }
+  for (int i = 0; i < n; ++i) g.seg_a[((size_t)s * n + o) * n + i] = lam[i];
+  g.seg_cv[(size_t)s * n + o] = vb;
+  for (int c = 0; c < P::nth; ++c) g.seg_ct[((size_t)s * n + o) * kMaxTh + c] = tb[c];
+}
+
+template <int KIND, int RNG, int INJ>
+__global__ void k_seg_combine(const RollArgs<KIND, float> a, const SegArgs g) {
+  using P = Plant<KIND, float>;
+  constexpr int n = P::n;
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int cand, ks;
+  if (!seg_target(a.srch, g, cand, ks)) return;
+  float best;
+  int sb;
+  double dv = 0.0, dth[P::nth > 0 ? P::nth : 1];
+  for (int c = 0; c < (P::nth > 0 ? P::nth : 1); ++c) dth[c] = 0.0;
+  int js = 0, rs = 0;
+  if (!seg_argmin(g, best, sb)) {
+    best = -INFINITY;
+  } else {
+    js = g.seg_j[sb];
+    rs = g.seg_r[sb];
+    float xs[n], gx[n];
+    for (int i = 0; i < n; ++i) xs[i] = g.seg_x[(size_t)sb * n + i];
+    P::out_grad(a.pc, a.F + rs * P::ny, xs, gx);
+    double lam[n], nl[n];
+    for (int i = 0; i < n; ++i) lam[i] = (double)gx[i];
+    for (int s = (js + g.Kc - 1) / g.Kc - 1; js > 0 && s >= 0; --s) {
+      for (int i = 0; i < n; ++i) nl[i] = 0.0;
+      for (int o = 0; o < n; ++o) {
+        const double lo = lam[o];
+        dv += lo * g.seg_cv[(size_t)s * n + o];
+        for (int c = 0; c < P::nth; ++c) dth[c] += lo * g.seg_ct[((size_t)s * n + o) * kMaxTh + c];
+        for (int i = 0; i < n; ++i) nl[i] += lo * (double)g.seg_a[((size_t)s * n + o) * n + i];
+      }
+      for (int i = 0; i < n; ++i) lam[i] = nl[i];
+    }
+  }
+  // theta^k = theta_nom * factor_k
+  const SegLane<KIND, RNG, INJ> M(a, ks, (float)a.srch->v[cand]);
+  g.out_m[0] = best;
+  g.out_dv[0] = dv;
+  for (int c = 0; c < P::nth; ++c) g.out_dth[c] = dth[c] * (double)M.fac[c];
+  g.grad->j_star = js;
+  g.grad->r_star = rs;
+}
+
 // Steady-state margin gradient by the adjoint of the equilibrium condition:
 // f(x_ss, v) = 0, m = g_r - eps|g_r| - F_r h(x_ss):  solve J^T mu = dm/dx, then
 // dm/dv = -mu . df/dv and dm/dtheta_nom = -mu . df/dtheta (FP64).
@@ -1237,10 +1504,7 @@ __global__ void __launch_bounds__(256) k_grad_reduce(DevGrad* G, const double* d
     }
     __syncthreads();
   }
-  if (tid == 0) {
-    const double kap = S->kappa[cand];
-    // v = r exactly at kappa = 1; dv/dkappa = r - v_prev on both sides
-    (void)kap;
+  if (tid == 0) {  // v = r exactly at kappa = 1; dv/dkappa = r - v_prev on both sides
     G->dM_dkappa = G->dM_dv * (st->r - st->v_prev);
   }
 }
@@ -1606,20 +1870,28 @@ static bool quad_draws_addressable(const Problem& pr) {
 }
 
 hipError_t launch_rollout(const Problem& pr, double band, int precision, int early_exit, int record,
-                          const LaunchCfg& cfg, const DevBuffers& b, hipStream_t st) {
+                          const LaunchCfg& cfg, const DevBuffers& b, hipStream_t st, int ckpt_cand,
+                          int Kc) {
+  const bool ckpt = ckpt_cand >= -1 && precision == 0;
   if (cfg.lanes == 4 && precision == 0 && pr.p.kind == 1 && quad_draws_addressable(pr)) {
     const dim3 grid(div_up((size_t)pr.s.N * 4, (size_t)cfg.block), cfg.cmax_round);
     const QuadCoef qc = make_quad_coef(pr);
     auto a = make_args<1, float>(pr, band, early_exit, record, b);
+    a.ckpt = b.adj_ckpt;
+    a.Kc = Kc;
+    a.ckpt_cand = ckpt_cand;
     return by_bit(pr.s.rng_mode, [&](auto rc) {
       constexpr int R = decltype(rc)::value;
       return by_bit(pr.s.inject, [&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        if (record)
-          hipLaunchKernelGGL((k_rollout_lq4_quad<R, I, 1>), grid, dim3(cfg.block), 0, st, a, qc);
-        else
-          hipLaunchKernelGGL((k_rollout_lq4_quad<R, I, 0>), grid, dim3(cfg.block), 0, st, a, qc);
-        return hipGetLastError();
+        return by_bit(record, [&](auto dc) {
+          constexpr int D = decltype(dc)::value;
+          if (ckpt)
+            hipLaunchKernelGGL((k_rollout_lq4_quad<R, I, D, 1>), grid, dim3(cfg.block), 0, st, a, qc);
+          else
+            hipLaunchKernelGGL((k_rollout_lq4_quad<R, I, D, 0>), grid, dim3(cfg.block), 0, st, a, qc);
+          return hipGetLastError();
+        });
       });
     });
   }
@@ -1632,10 +1904,16 @@ hipError_t launch_rollout(const Problem& pr, double band, int precision, int ear
         constexpr int I = decltype(ic)::value;
         if (precision == 0) {
           auto a = make_args<K, float>(pr, band, early_exit, record, b);
-          hipLaunchKernelGGL((k_rollout<K, float, R, I>), grid, dim3(cfg.block), 0, st, a);
+          a.ckpt = b.adj_ckpt;
+          a.Kc = Kc;
+          a.ckpt_cand = ckpt_cand;
+          if (ckpt)
+            hipLaunchKernelGGL((k_rollout<K, float, R, I, 1>), grid, dim3(cfg.block), 0, st, a);
+          else
+            hipLaunchKernelGGL((k_rollout<K, float, R, I, 0>), grid, dim3(cfg.block), 0, st, a);
         } else {
           auto a = make_args<K, double>(pr, 0.0, early_exit, record, b);
-          hipLaunchKernelGGL((k_rollout<K, double, R, I>), grid, dim3(cfg.block), 0, st, a);
+          hipLaunchKernelGGL((k_rollout<K, double, R, I, 0>), grid, dim3(cfg.block), 0, st, a);
         }
         return hipGetLastError();
       });
@@ -1733,6 +2011,43 @@ hipError_t launch_adjoint(const Problem& pr, int Kc, int max_entries, const DevB
         auto a = make_args<K, float>(pr, 0.0, 0, 0, b);
         hipLaunchKernelGGL((k_adjoint<K, R, I>), dim3(div_up(max_entries, 64)), dim3(64), 0, st, a,
                            g);
+        return hipGetLastError();
+      });
+    });
+  });
+}
+
+hipError_t launch_seg_grad(const Problem& pr, int Kc, int cand, const DevBuffers& b,
+                           hipStream_t st) {
+  SegArgs g;
+  g.Kc = Kc;
+  g.S = pr.H / Kc + 1;
+  g.cand = cand;
+  g.lanes = g.S * pr.p.n;
+  g.seg_m = b.seg_m;
+  g.seg_j = b.seg_j;
+  g.seg_r = b.seg_r;
+  g.seg_x = b.seg_x;
+  g.seg_a = b.seg_a;
+  g.seg_cv = b.seg_cv;
+  g.seg_ct = b.seg_ct;
+  g.scratch = b.seg_scr;
+  g.out_m = b.adj_m;
+  g.out_dv = b.adj_dv;
+  g.out_dth = b.adj_dth;
+  g.grad = b.grad;
+  return by_kind(pr.p.kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    return by_bit(pr.s.rng_mode, [&](auto rc) {
+      constexpr int R = decltype(rc)::value;
+      return by_bit(pr.s.inject, [&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        auto a = make_args<K, float>(pr, 0.0, 0, 0, b);
+        hipLaunchKernelGGL((k_seg_min<K, R, I>), dim3(div_up(g.S, 64)), dim3(64), 0, st, a, g,
+                           (const float*)b.adj_ckpt);
+        hipLaunchKernelGGL((k_seg_vjp<K, R, I>), dim3(div_up(g.lanes, 64)), dim3(64), 0, st, a, g,
+                           (const float*)b.adj_ckpt);
+        hipLaunchKernelGGL((k_seg_combine<K, R, I>), dim3(1), dim3(64), 0, st, a, g);
         return hipGetLastError();
       });
     });
