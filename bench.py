@@ -101,7 +101,8 @@ def run_form(args):
     p = wl["problem"]
     r_seq = wl["r_seq"]
     kw = (dict(precision=rg.PREC_F32_RECHECK, search=rg.SEARCH_NEWTON)
-          if args.form == "fp32_adjoint_newton" else dict(precision=rg.PREC_F64, depth=1))
+          if args.form == "fp32_adjoint_newton"
+          else dict(precision=rg.PREC_F64, depth=1, predict=False))
     gm = rg.Governor(p, band=wl["band"], K=wl["K"], max_T=max(256, T), **kw)
     x0 = np.asarray(wl["x0"], dtype=np.float64)
     gm.set_step(0)
@@ -117,7 +118,9 @@ def run_form(args):
                       "value": float(np.sum(om["bisect_passes"])) * p.N * p.H / el,
                       "rounds_per_step": float(np.mean(om["rounds"])),
                       "fallback_steps": int(np.sum(om["status"] == 2)),
-                      "kappa": [float(k) for k in om["kappa"]]}))
+                      "kappa": [float(k) for k in om["kappa"]],
+                      "x": [[float(c) for c in row] for row in om["x"]],
+                      "v": [float(v) for v in om["v"]]}))
 
 
 def main():
@@ -213,9 +216,18 @@ def main():
             raise SystemExit(f"search form {label} failed (exit {child.returncode})")
         om = json.loads(child.stdout.strip().splitlines()[-1])
         kap = np.asarray(om.pop("kappa"))
-        om["max_abs_kappa_diff_vs_default"] = float(np.max(np.abs(kap - out["kappa"][:Km])))
-        om["kappa_within_2^-12"] = bool(np.all(np.abs(kap - out["kappa"][:Km])
-                                               <= 2.0 ** -wl["K"] + 1e-15))
+        xs = np.asarray(om.pop("x"))
+        vs = np.asarray(om.pop("v"))
+        # accuracy at equal inputs: the headline bisection re-run at every state
+        # of this form's own closed loop (its trajectory may leave the headline's
+        # once a kappa differs within the 2^-K resolution)
+        kb = np.zeros(Km)
+        for s in range(Km):
+            g.set_step(s)
+            kb[s] = g.step(xs[s], r_seq[s], wl["v_prev"] if s == 0 else vs[s - 1])["kappa"]
+        om["max_abs_kappa_diff_vs_bisection_same_state"] = float(np.max(np.abs(kap - kb)))
+        om["kappa_within_2^-12"] = bool(np.all(np.abs(kap - kb) <= 2.0 ** -wl["K"] + 1e-15))
+        om["same_closed_loop_as_headline"] = bool(np.array_equal(kap, out["kappa"][:Km]))
         modes[label] = om
 
     K = args.steps
@@ -241,7 +253,9 @@ def main():
         "config": {"workload": wl["name"], "plant": "LQ4", "N": p.N, "H": p.H, "dt": p.dt,
                    "K": wl["K"], "band": wl["band"], "rg_steps": K,
                    "precision": "fp32 rollouts + fp64 near-band recheck" if prec == 0 else "fp64",
-                   "search": f"bisection, {g.options.depth} levels per device round",
+                   "search": (f"bisection: first device round = kappa 1 probe + the midpoints on "
+                              f"the path to the previous update's kappa, then "
+                              f"{g.options.depth} levels per round"),
                    "lanes_per_scenario": g.options.lanes,
                    "launch": "one captured HIP graph per RG update, replayed"},
         "rg_updates_per_s": K / elapsed,

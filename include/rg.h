@@ -80,10 +80,10 @@ enum rg_search {
     RG_SEARCH_NEWTON = 2  /* safeguarded Newton on the worst margin M(kappa), derivative from
                              the adjoint of the arg-min rollout (or the steady-state term):
                              each device round tests the iterate kappa_N, kappa_N -/+ 2^-K and
-                             the bracket midpoint; a step outside the bracket or with a
-                             non-negative slope falls back to the midpoint (status
-                             RG_S_FALLBACK); stops at a bracket of 2^-K (at most K+2 rounds).
-                             FP32 precision only. */
+                             the bracket midpoint; a step at or past a bracket end moves
+                             2^-K inside that end, a non-negative or non-finite slope falls
+                             back to the midpoint (status RG_S_FALLBACK); stops at a bracket
+                             of 2^-K (at most K+2 rounds).  FP32 precision only. */
 };
 
 /* ---- descriptors -------------------------------------------------------------- */
@@ -136,6 +136,12 @@ typedef struct rg_options {
                               quad, state split across lanes), 0 = auto */
     int32_t Kc;            /* adjoint checkpoint interval in RK4 steps (default 50) */
     int32_t persistent_wgs;/* batches: workgroups of the persistent rollout kernel (0 = auto) */
+    int32_t predict;       /* bisection: 1 (default) makes the first device round of a step
+                              evaluate the kappa = 1 probe plus every midpoint on the bisection
+                              path to the previous step's kappa (the probe alone when that was
+                              1); later rounds use the speculative tree.  Only which
+                              candidates are evaluated early changes: the result is that of
+                              sequential bisection either way.  0: tree from round 0. */
 } rg_options;
 
 typedef struct rg_step_info {

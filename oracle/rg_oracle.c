@@ -1041,6 +1041,11 @@ orc_result orc_newton(const orc_problem* p, const double* x0, double r, double v
         double kn;
         int newton_ok = isfinite(phi) && isfinite(dphi) && dphi < 0.0;
         kn = newton_ok ? kc - phi / dphi : 0.5 * (lo + hi);
+        /* A step at or past a bracket end is moved just inside that end: the
+         * root lies next to it (hi - lo > delta keeps lo + delta and hi - delta
+         * strictly inside). */
+        if (newton_ok && kn <= lo) kn = lo + delta;
+        else if (newton_ok && kn >= hi) kn = hi - delta;
         if (!(kn > lo && kn < hi)) {
             kn = 0.5 * (lo + hi);
             newton_ok = 0;

@@ -162,6 +162,10 @@ void plan(rg_handle* h) {
     const int r0 = 1 << d0;
     c.cmax_round = r0 > tree ? r0 : tree;
     c.rounds = 1 + (h->opt.K - d0 + d - 1) / d;
+    if (h->opt.predict) {  // round 0: probe + the predicted path (K midpoints), or the probe alone
+      if (1 + h->opt.K > c.cmax_round) c.cmax_round = 1 + h->opt.K;
+      c.rounds = 1 + (h->opt.K + d - 1) / d;
+    }
   }
   h->cfg = c;
 }
@@ -214,6 +218,8 @@ int ensure_workspace(rg_handle* h) {
   S->mode = h->opt.search == RG_SEARCH_GRID ? kGrid
             : h->opt.search == RG_SEARCH_NEWTON ? kNewton : kBisect;
   S->delta = std::ldexp(1.0, -h->opt.K);
+  S->predict = h->opt.search == RG_SEARCH_BISECT ? h->opt.predict : 0;
+  S->pred = std::nan("");
   S->K = h->opt.K;
   S->depth = h->opt.depth;
   S->M = h->opt.M;
@@ -347,6 +353,7 @@ int rg_default_options(rg_options* opt) {
   opt->lanes = 0;
   opt->Kc = 50;
   opt->persistent_wgs = 0;
+  opt->predict = 1;
   return RG_OK;
 }
 
@@ -413,6 +420,7 @@ int rg_create(const rg_plant* plant, const rg_scenarios* scen, const rg_constrai
   if (o.max_T < 1 || o.max_T > 65536) return fail(nullptr, RG_E_INVAL, "max_T must be in [1, 65536]");
   if (o.lanes != 0 && o.lanes != 1 && o.lanes != 4) return fail(nullptr, RG_E_INVAL, "lanes must be 0, 1 or 4");
   if (o.Kc < 1 || o.Kc > 4096) return fail(nullptr, RG_E_INVAL, "Kc must be in [1, 4096]");
+  if (o.predict != 0 && o.predict != 1) return fail(nullptr, RG_E_INVAL, "predict must be 0 or 1");
 
   rg_handle* h = new (std::nothrow) rg_handle;
   if (!h) return fail(nullptr, RG_E_NOMEM, "host allocation");
@@ -1008,6 +1016,8 @@ static int batch_ensure_memory(rg_batch* bt) {
     for (int r = 0; r < kNC; ++r) S.g[r] = pr.c.g[r];
     for (int q = 0; q < kNC * kMaxY; ++q) S.F[q] = pr.c.F[q];
     S.delta = std::ldexp(1.0, -bt->opt.K);
+    S.predict = 0;
+    S.pred = std::nan("");
     S.done = 1;
   }
   e = hipMemcpyAsync(b.desc, desc.data(), sizeof(InstDesc) * count, hipMemcpyHostToDevice, bt->stream);

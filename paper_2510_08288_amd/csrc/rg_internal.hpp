@@ -64,6 +64,9 @@ struct DevSearch {
   int32_t nk_idx;                     // candidate carrying the Newton iterate this round
   int32_t fallbacks;                  // rounds that used the midpoint instead of a Newton step
   double delta;                       // 2^-K
+  // Bisection: round 0 speculates along the path to the previous step's kappa
+  int32_t predict;                    // 1: enabled
+  double pred;                        // previous step's kappa (NaN: none yet)
 };
 
 // Result record of one RG step.

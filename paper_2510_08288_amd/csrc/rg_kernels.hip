@@ -526,12 +526,15 @@ __global__ void __launch_bounds__(64) k_recheck(const RollArgs<KIND, double> a) 
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int2 e = a.rlist[i];
     const int c = e.x, k = e.y;
-    if (a.early && !S->full[c] &&
+    // The verdict needs one failing lane only, also for a candidate whose FP32
+    // rollout ran in full (the Newton iterate): its rechecks stop at the first
+    // FP64 violation too.
+    if (a.early &&
         (__hip_atomic_load(&S->dead[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
          __hip_atomic_load(&S->fail64[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
       continue;
     int jb = 0, ns = 0;
-    const int early = a.early && !S->full[c];
+    const int early = a.early;
     const double m = rollout_lane<KIND, double, RNG, INJ>(a, early, S->v[c], k, t,
                                                           early ? &S->fail64[c] : nullptr, jb,
                                                           ns, nullptr);
@@ -756,10 +759,31 @@ __device__ void setup_body(const typename Plant<KIND, double>::Coef& pc, DevStat
       S->kappa[0] = 1.0;
       S->probe = 1;
       S->goal = S->K;
-      const int d0 = S->K < S->depth ? S->K : S->depth;
-      if (d0 > 0) build_tree(S, 1, d0, 0.0, 1.0);
-      else S->tree_depth = 0;
-      S->n_cand = 1 + ((1 << d0) - 1);
+      const double pr = S->pred;
+      if (S->predict && pr == pr && S->K > 0) {
+        // Speculate along the previous step's result: the kappa = 1 probe alone
+        // when it was 1, else every midpoint on the bisection path towards it.
+        // The decision still takes each level's verdict from its own midpoint,
+        // so the result is that of sequential bisection whatever the guess.
+        S->tree_depth = 0;
+        if (pr >= 1.0) {
+          S->n_cand = 1;
+        } else {
+          double lo = 0.0, hi = 1.0;
+          for (int l = 0; l < S->K; ++l) {
+            const double m = midpoint(lo, hi);
+            S->kappa[1 + l] = m;
+            if (pr >= m) lo = m;
+            else hi = m;
+          }
+          S->n_cand = 1 + S->K;
+        }
+      } else {
+        const int d0 = S->K < S->depth ? S->K : S->depth;
+        if (d0 > 0) build_tree(S, 1, d0, 0.0, 1.0);
+        else S->tree_depth = 0;
+        S->n_cand = 1 + ((1 << d0) - 1);
+      }
     }
   }
   __syncthreads();
@@ -784,11 +808,11 @@ __global__ void __launch_bounds__(128) k_setup_list(const CtlArgs<KIND> a, int M
   prepare_candidates<KIND>(a.pc, a.st, S);
 }
 
-// Safeguarded Newton on phi(kappa) = M(kappa) (see the FP64 reference for the
-// same rule): every verdict tightens [lo, hi]; the next iterate is
-// kappa_c - phi/phi' from this round's iterate (adjoint derivative), or the
-// midpoint when that step is not strictly inside the bracket or the slope is
-// not negative; candidates kappa_N -/+ delta and the midpoint go with it.
+// Safeguarded Newton on phi(kappa) = M(kappa): every verdict tightens
+// [lo, hi]; the next iterate is kappa_c - phi/phi' from this round's iterate
+// (adjoint derivative), moved to lo + delta or hi - delta when it lands at or
+// past that end, and the midpoint when the slope is not negative or not
+// finite; candidates kappa_N -/+ delta and the midpoint go with it.
 // Returns true when hi - lo <= delta (or the round cap K + 2 is reached).
 __device__ bool newton_decide(DevSearch* S, const DevGrad* G) {
   const double delta = S->delta;
@@ -816,6 +840,9 @@ __device__ bool newton_decide(DevSearch* S, const DevGrad* G) {
   const double phi = G->M, dphi = G->dM_dkappa;
   bool ok = (phi == phi) && (dphi == dphi) && isfinite(phi) && isfinite(dphi) && dphi < 0.0;
   double kn = ok ? kap_c - phi / dphi : 0.5 * (S->lo + S->hi);
+  // a step at or past a bracket end moves just inside that end (the root is next to it)
+  if (ok && kn <= S->lo) kn = S->lo + delta;
+  else if (ok && kn >= S->hi) kn = S->hi - delta;
   if (!(kn > S->lo && kn < S->hi)) {
     kn = 0.5 * (S->lo + S->hi);
     ok = false;
@@ -881,21 +908,30 @@ __device__ void decide_body(const typename Plant<KIND, double>::Coef& pc, const 
         }
       }
       if (!finished) {
-        int node = 0;
-        for (int l = 0; l < S->tree_depth; ++l) {
-          const int c = S->tree_base + node;
+        // Sequential bisection over this round's candidates: each level takes
+        // the verdict of the candidate equal to the current midpoint (dyadic
+        // midpoints are exact, so equality identifies the node), until a
+        // midpoint was not evaluated this round.
+        while (S->halvings < S->goal) {
+          const double m = midpoint(S->lo, S->hi);
+          int c = -1;
+          for (int i = S->probe; i < S->n_cand; ++i) {
+            if (S->kappa[i] == m) {
+              c = i;
+              break;
+            }
+          }
+          if (c < 0) break;
           S->passes_alg1 += 1;
           if (cand_feasible(S, c)) {
-            S->lo = S->kappa[c];
+            S->lo = m;
             S->found = 1;
             S->worst_res = cand_worst(S, c);
-            node = 2 * node + 2;
           } else {
-            S->hi = S->kappa[c];
-            node = 2 * node + 1;
+            S->hi = m;
           }
+          S->halvings += 1;
         }
-        S->halvings += S->tree_depth;
         if (S->halvings >= S->goal) finished = true;
       }
     }
@@ -903,6 +939,7 @@ __device__ void decide_body(const typename Plant<KIND, double>::Coef& pc, const 
       S->done = 1;
       S->status = S->found ? (S->mode == kNewton && S->fallbacks > 0 ? 2 : 0) : 1;
       S->kappa_res = S->found ? S->lo : 0.0;
+      S->pred = S->kappa_res;
       S->v_res = S->found ? cand_v(S->kappa_res, st->r, st->v_prev) : st->v_prev;
       if (!S->found) S->worst_res = -INFINITY;
     } else if (S->mode != kNewton) {

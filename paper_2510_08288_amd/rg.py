@@ -61,7 +61,7 @@ class rg_options(C.Structure):
                 ("search", C.c_int32), ("depth", C.c_int32), ("M", C.c_int32),
                 ("refine", C.c_int32), ("early_exit", C.c_int32), ("block", C.c_int32),
                 ("max_T", C.c_int32), ("lanes", C.c_int32), ("Kc", C.c_int32),
-                ("persistent_wgs", C.c_int32)]
+                ("persistent_wgs", C.c_int32), ("predict", C.c_int32)]
 
 
 class rg_instance_desc(C.Structure):
@@ -165,7 +165,7 @@ class Governor:
                  K: int = 12, search: int = SEARCH_BISECT, depth: int = 0, M: int = 64,
                  refine: int = 6, early_exit: bool = True, block: int = 0, max_T: int = 256,
                  rng_mode: int = RNG_STREAM, lanes: int = 0, Kc: int = 50,
-                 torch_workspace: bool = True):
+                 predict: bool = True, torch_workspace: bool = True):
         import torch
         self.L = load_library()
         self.problem = problem
@@ -186,6 +186,7 @@ class Governor:
         opt.depth, opt.M, opt.refine = depth, M, refine
         opt.early_exit, opt.block, opt.max_T, opt.lanes = int(early_exit), block, max_T, lanes
         opt.Kc = Kc
+        opt.predict = int(predict)
         h = _vp()
         rc = self.L.rg_create(C.byref(plant), C.byref(scen), C.byref(cons), int(p.H), float(p.dt),
                               C.byref(opt), C.byref(h))

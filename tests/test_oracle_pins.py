@@ -626,3 +626,20 @@ def test_newton_fc9_bracket(oracle_mod):
     assert abs(n["kappa"] - b["kappa"]) <= 2.0 ** -12
     assert o.candidate(x0, o.candidate_v(n["kappa"], 2.0, 0.5), 0)[0] >= 0
     assert o.candidate(x0, o.candidate_v(n["kappa"] + 2.0 ** -12, 2.0, 0.5), 0)[0] < 0
+
+
+@pytest.mark.parametrize("vp,r", [(0.7954, 1.377), (-0.8452, -1.15)])
+def test_newton_refused_everywhere_ends_in_two_rounds(oracle_mod, vp, r):
+    # From the equilibrium of v_prev (admissible now) a wide disturbance box
+    # refuses every candidate: both searches return kappa = 0 (status 1).
+    # Newton's step lands below the admissible end, moves to lo + 2^-K, is
+    # refused there and closes the bracket in the second round (bisection
+    # needs all K + 1 evaluations).
+    p = W.lq4_problem(seed=24, N=32, H=300, dt=0.005, eps=0.01, w_half=0.3)
+    o = oracle_mod.Oracle(p, nthreads=4)
+    x0 = o.steady_margin(vp)[1]
+    b = o.bisect(x0, r, vp, 0, 12)
+    assert b["status"] == 1 and b["kappa"] == 0.0 and b["passes"] == 13
+    n = o.newton(x0, r, vp, 0, 12)
+    assert n["status"] == 1 and n["kappa"] == 0.0
+    assert n["rounds"] == 2 and n["fallbacks"] == 0
