@@ -42,8 +42,8 @@ PEAK_FP32_NONPACKED_TFLOPS = 78.6
 # HBM bytes per rollout launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
 # this bench (4 updates), each scaled by the counter's reading for a 256 MiB device
 # copy; valid only for the kernel source they were taken on (SHA-1 below).
-HBM_TRAFFIC = {"kernels_sha1": "7dd9bfa4a9ccbf38f76cc95fdd171289a3306130",
-               "bytes_per_launch": 28848945}
+HBM_TRAFFIC = {"kernels_sha1": "9498e6c9a5c5582ab0be2c6a6c4eb96a5816bc0b",
+               "bytes_per_launch": 14029784}
 
 
 def cpu_baseline(wl, r_seq, seconds):

@@ -516,6 +516,147 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
   }
 }
 
+// FP64 re-simulation of the near-band list, LQ4 with one entry per quad of
+// lanes (the layout of the FP32 quad rollout, in double precision: a 64-bit
+// DPP exchange is two 32-bit ones).  Same verdict as the one-lane recheck.
+struct QuadCoef64 {
+  double a[4][4], g[4][4], d[4][4];
+  double b[4];
+  double e[4][2];
+  double grow[4];
+};
+
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ __forceinline__ double min2d(double a, double b) { return b < a ? b : a; }
+
+__device__ __forceinline__ double quad_min64(double m) {
+  m = min2d(m, dpp64<kSwap1>(m));
+  return min2d(m, dpp64<kSwap2>(m));
+}
+
+template <int RNG, int INJ>
+__global__ void __launch_bounds__(256) k_recheck_lq4_quad(const RollArgs<1, double> a,
+                                                         const QuadCoef64 qc) {
+  constexpr int U = kQuadGroup;
+  DevSearch* S = a.srch;
+  if (S->done) return;
+  const int n = S->n_recheck;
+  const uint32_t t = a.st->t;
+  const int q = threadIdx.x & 3;
+  const double A0 = qc.a[q][0], A1 = qc.a[q][1], A2 = qc.a[q][2], A3 = qc.a[q][3];
+  const double G0 = qc.g[q][0], G1 = qc.g[q][1], G2 = qc.g[q][2], G3 = qc.g[q][3];
+  const double d0 = qc.d[q][0], d1 = qc.d[q][1], d2 = qc.d[q][2], d3 = qc.d[q][3];
+  const double e0 = qc.e[q][0], e1 = qc.e[q][1], grow = qc.grow[q], bq = qc.b[q];
+  const double h = a.h, hh = a.hh, h6 = a.h6;
+  const int H = a.H;
+  const uint32_t row_bytes = 8u * (uint32_t)a.N;
+  const __amdgpu_buffer_rsrc_t wres = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)a.wbuf, (short)0, (int)(row_bytes * (uint32_t)(H + U)), 0x00020000);
+  const int stride = (int)((gridDim.x * blockDim.x) >> 2);
+  // every lane of a quad holds the same entry, so all exits are quad-uniform
+  for (int i = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 2); i < n; i += stride) {
+    const int2 en = a.rlist[i];
+    const int c = en.x, k = en.y;
+    if (a.early &&
+        (__hip_atomic_load(&S->dead[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+         __hip_atomic_load(&S->fail64[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
+      continue;
+    const double bv = bq * S->v[c];
+    double x = a.st->x[q];
+    auto deriv = [&](double s, double xv) {
+      const double c2 = __builtin_fma(G2, xv, A2) * xv;
+      const double c3 = __builtin_fma(G3, xv, A3) * xv;
+      double c0 = __builtin_fma(__builtin_fma(G0, xv, A0), xv, s);
+      double c1 = __builtin_fma(G1, xv, A1) * xv;
+      c1 = c1 + dpp64<kSwap2>(c3);
+      c0 = c0 + dpp64<kSwap2>(c2);
+      return c0 + dpp64<kSwap1>(c1);
+    };
+    auto row_margin = [&](double xv) {
+      const double c2 = d2 * xv, c3 = d3 * xv;
+      double c0 = __builtin_fma(d0, xv, grow);
+      double c1 = d1 * xv;
+      c1 = c1 + dpp64<kSwap2>(c3);
+      c0 = c0 + dpp64<kSwap2>(c2);
+      return c0 + dpp64<kSwap1>(c1);
+    };
+    double bm = row_margin(x);  // lane q: running minimum of row q
+    const uint32_t vo0 = 4u * (uint32_t)k, vo1 = vo0 + 4u * (uint32_t)a.N;
+    uint32_t so = 0;
+    auto load_group = [&](int j, float* w) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (RNG == 0) {
+          const uint32_t sr = so + (uint32_t)u * row_bytes;
+          w[2 * u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(wres, vo0, sr, 0));
+          w[2 * u + 1] =
+              __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(wres, vo1, sr, 0));
+        } else {
+          const Words r = philox10((uint32_t)k, (uint32_t)(j + u), t, 0u, a.seed, a.inst);
+          w[2 * u] = box_draw(r.v[0], a.wlo[0], a.wspan[0]);
+          w[2 * u + 1] = box_draw(r.v[1], a.wlo[1], a.wspan[1]);
+        }
+      }
+      if (RNG == 0) so += (uint32_t)U * row_bytes;
+    };
+    auto step = [&](float w0f, float w1f) {
+      const double w0 = (double)w0f, w1 = (double)w1f;
+      const double s = INJ == 0 ? __builtin_fma(e1, w1, __builtin_fma(e0, w0, bv)) : bv;
+      const double k1 = deriv(s, x);
+      double acc = k1;
+      double xs = __builtin_fma(hh, k1, x);
+      const double k2 = deriv(s, xs);
+      acc = __builtin_fma(2.0, k2, acc);
+      xs = __builtin_fma(hh, k2, x);
+      const double k3 = deriv(s, xs);
+      acc = __builtin_fma(2.0, k3, acc);
+      xs = __builtin_fma(h, k3, x);
+      const double k4 = deriv(s, xs);
+      x = __builtin_fma(h6, acc + k4, x);
+      if (INJ == 1) x = x + (e0 * w0 + e1 * w1);
+      bm = fmin(bm, row_margin(x));
+    };
+    float wcur[2 * U], wnext[2 * U];
+    load_group(0, wcur);
+    const int full = H / U;
+    int g = 0;
+    for (; g < full; ++g) {
+      load_group((g + 1) * U, wnext);
+#pragma unroll
+      for (int u = 0; u < U; ++u) step(wcur[2 * u], wcur[2 * u + 1]);
+#pragma unroll
+      for (int u = 0; u < 2 * U; ++u) wcur[u] = wnext[u];
+      if (a.early) {
+        if (quad_min64(bm) < 0.0) {
+          ++g;
+          break;
+        }
+        if ((g & 7) == 7 &&
+            __hip_atomic_load(&S->fail64[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+          break;
+      }
+    }
+    if (g == full)
+      for (int u = 0; u < H - full * U; ++u) step(wcur[2 * u], wcur[2 * u + 1]);
+    double m = quad_min64(bm);
+    double bad = x - x;
+    bad = bad + dpp64<kSwap1>(bad);
+    bad = bad + dpp64<kSwap2>(bad);
+    if (!(bad == 0.0) || m != m) m = -INFINITY;
+    if (q == 0) {
+      atomicMin(&S->key64[c], ord64(m));
+      if (m < 0.0) __hip_atomic_store(&S->fail64[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 // FP64 re-simulation of the near-band list.
 template <int KIND, int RNG, int INJ>
 __global__ void __launch_bounds__(64) k_recheck(const RollArgs<KIND, double> a) {
@@ -1958,9 +2099,53 @@ hipError_t launch_rollout(const Problem& pr, double band, int precision, int ear
   });
 }
 
+// The FP64 counterpart of make_quad_coef (same slot layout).
+static QuadCoef64 make_quad_coef64(const Problem& pr) {
+  QuadCoef64 qc;
+  memset(&qc, 0, sizeof(qc));
+  const double* A = pr.p.coeffs;
+  const double* B = pr.p.coeffs + 16;
+  const double* G = pr.p.coeffs + 20;
+  const double* E = pr.p.coeffs + 36;
+  const double* Cm = pr.p.coeffs + 44;
+  double D[4][4];
+  for (int r = 0; r < 4; ++r)
+    for (int i = 0; i < 4; ++i) {
+      double acc = 0.0;
+      for (int y = 0; y < 2; ++y) acc += pr.c.F[r * 2 + y] * Cm[y * 4 + i];
+      D[r][i] = acc;
+    }
+  for (int q = 0; q < 4; ++q) {
+    for (int s = 0; s < 4; ++s) {
+      const int row = q ^ s;
+      qc.a[q][s] = A[row * 4 + q];
+      qc.g[q][s] = G[row * 4 + q];
+      qc.d[q][s] = -D[row][q];
+    }
+    qc.b[q] = B[q];
+    qc.e[q][0] = E[q * 2 + 0];
+    qc.e[q][1] = E[q * 2 + 1];
+    qc.grow[q] = pr.c.g[q];
+  }
+  return qc;
+}
+
 hipError_t launch_recheck(const Problem& pr, int early_exit, const LaunchCfg& cfg,
                           const DevBuffers& b, hipStream_t st) {
   const size_t cap = (size_t)cfg.cmax_round * pr.s.N;
+  if (cfg.lanes == 4 && pr.p.kind == 1 && quad_draws_addressable(pr)) {
+    const int qblocks = div_up((cap < 16384 ? cap : 16384) * 4, 256);
+    const QuadCoef64 qc = make_quad_coef64(pr);
+    auto a = make_args<1, double>(pr, 0.0, early_exit, 0, b);
+    return by_bit(pr.s.rng_mode, [&](auto rc) {
+      constexpr int R = decltype(rc)::value;
+      return by_bit(pr.s.inject, [&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        hipLaunchKernelGGL((k_recheck_lq4_quad<R, I>), dim3(qblocks), dim3(256), 0, st, a, qc);
+        return hipGetLastError();
+      });
+    });
+  }
   const int blocks = div_up(cap < 65536 ? cap : 65536, 64);
   return by_kind(pr.p.kind, [&](auto kc) {
     constexpr int K = decltype(kc)::value;
