@@ -36,6 +36,7 @@ if ROOT not in sys.path:
 
 METRIC = "scenario-steps/s + RG updates/s at κ tol 2^-12 (FP32+adjoint vs FP64 bisect)"
 FLOP_PER_STEP_LQ4 = 375      # algorithmic FLOP of one LQ4 scenario-step (FMA = 2)
+FLOP_PER_STEP_FC9 = 1055     # same for FC9, plus 36 tanh, 24 sqrt and 1 division
 BYTES_PER_STEP_LQ4 = 8       # streamed draws read per scenario-step (2 x fp32)
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (needs packed FP32)
 PEAK_FP32_NONPACKED_TFLOPS = 78.6
@@ -88,6 +89,44 @@ def measured_traffic():
     return HBM_TRAFFIC["bytes_per_launch"] if sha == HBM_TRAFFIC["kernels_sha1"] else None
 
 
+def fc9_grid_measurement(args, updates: int = 3):
+    """Secondary measurement: RG updates of the 9-state grid workload (64-point
+    grid + 6 refinements, N = 65536, H = 1000), each a separate update at its own
+    draws (t = 0, 1, ...) from the equilibrium of v_prev."""
+    import numpy as np
+    import torch
+
+    from paper_2510_08288_amd import rg, workloads as W
+
+    wl = W.workload_fc9_grid()
+    p = wl["problem"]
+    g = rg.Governor(p, search=rg.SEARCH_GRID, M=wl["M"], refine=wl["refine"], band=wl["band"])
+    x0 = g.equilibrium(wl["v_prev"])
+    g.set_step(0)
+    g.step(x0, wl["r"], wl["v_prev"])  # warm-up (kernel loading, draws)
+    g.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for t in range(updates):
+        g.set_step(t)
+        res.append(g.step(x0, wl["r"], wl["v_prev"]))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = g.profile()
+    g.close()
+    nominal = sum(r["bisect_passes"] for r in res) * p.N * p.H
+    executed = sum(r["lane_steps"] for r in res)
+    return {"workload": wl["name"], "updates": updates, "ms_per_update": el / updates * 1e3,
+            "kappa": [r["kappa"] for r in res], "rounds_per_update": float(np.mean([r["rounds"] for r in res])),
+            "value": nominal / el, "executed_scenario_steps_per_s": executed / el,
+            "rollout_ms_per_update": prof["rollout_ms"] / updates,
+            "rollout_tflops": (prof["lane_steps"] * FLOP_PER_STEP_FC9 / (prof["rollout_ms"] * 1e-3) / 1e12
+                               if prof["rollout_ms"] > 0 else 0.0),
+            "flop_per_scenario_step": FLOP_PER_STEP_FC9,
+            "unit": "scenario-steps/s"}
+
+
 def run_form(args):
     """One alternative search form on the first `--steps` updates of the same
     closed loop, replayed from captured HIP graphs; prints one JSON line."""
@@ -138,6 +177,8 @@ def main():
                          "(0: the same steps as the headline form)")
     ap.add_argument("--form", choices=["fp32_adjoint_newton", "fp64_sequential_bisection"],
                     default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--no-fc9", action="store_true",
+                    help="skip the secondary 9-state grid-search measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy one device buffer of BYTES into another three times (the "
                          "reference kernel for scaling HBM counters) and exit")
@@ -230,6 +271,8 @@ def main():
         om["same_closed_loop_as_headline"] = bool(np.array_equal(kap, out["kappa"][:Km]))
         modes[label] = om
 
+    fc9 = {} if args.no_fc9 else fc9_grid_measurement(args)
+
     K = args.steps
     nominal = int(np.sum(out["bisect_passes"])) * p.N * p.H
     executed = int(np.sum(out["lane_steps"]))
@@ -266,6 +309,7 @@ def main():
         "search_modes": dict(modes, fp32_speculative_bisection={
             "rg_updates_per_s": K / elapsed, "ms_per_step": elapsed / K * 1e3, "steps": K,
             "rounds_per_step": float(np.mean(out["rounds"]))}),
+        "fc9_grid": fc9,
         "search_stats": {"rounds": int(np.sum(out["rounds"])),
                          "candidates": int(np.sum(out["candidates"])),
                          "rechecks": int(np.sum(out["rechecks"])),

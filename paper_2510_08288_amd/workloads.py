@@ -200,3 +200,21 @@ def batch_instances(count: int = 1024, seed: int = 99, n_min: int = 256, n_max: 
             v_prev = 0.0
         out.append(BatchInstance(problem=p, x0=x0, v_prev=v_prev, r=r))
     return out
+
+
+def workload_fc9_grid() -> dict:
+    """FC9, N=65536 scenarios (parameters +-10 % on 20 coefficients, additive
+    disturbance +-0.02), H=1000, dt=0.002, 3 output constraints; 64-point kappa
+    grid evaluated in parallel, then 6 bisection refinements, FP32 rollouts with
+    FP64 near-boundary recheck.  Starts at the equilibrium of v_prev = 0.5 with
+    the set-point request r = 2.0 (the supply ratio dips mid-transient)."""
+    p = fc9_problem(N=65536, H=1000, dt=0.002)
+    return dict(name="fc9_grid_n65536_h1000", problem=p, v_prev=0.5, r=2.0, M=64, refine=6,
+                band=1e-4)
+
+
+def workload_fc9_adjoint() -> dict:
+    """FC9, N=16384, H=1000, dt=0.002: worst-margin derivative by the reverse
+    sweep with checkpoints every 50 steps, and the Newton search to 2^-12."""
+    p = fc9_problem(N=16384, H=1000, dt=0.002)
+    return dict(name="fc9_adjoint_n16384_h1000", problem=p, v_prev=0.5, r=2.0, Kc=50, K=12)

@@ -336,3 +336,38 @@ def test_equilibrium_matches_oracle(R, O):
         ref = O.Oracle(p).steady_margin(v)[1]
         np.testing.assert_allclose(x, ref, rtol=1e-11, atol=1e-12)
         g.close()
+
+
+@pytest.mark.parametrize("rng_mode", [0, 1])
+@pytest.mark.parametrize("inject", [W.INJECT_ODE, W.INJECT_POST])
+def test_fp64_recheck_decides_with_wide_band(R, O, rng_mode, inject):
+    # band 0.5: nearly every lane is re-simulated in FP64, so the recheck (one
+    # entry per quad of lanes for lanes = 4, one lane per entry for lanes = 1)
+    # gives the verdicts; kappa must be the FP64 oracle's
+    p = W.lq4_problem(seed=24, N=300, H=250, dt=0.005, eps=0.01, inject=inject)
+    o = O.Oracle(p, nthreads=8)
+    cases = [(np.zeros(4), 1.9, 0.0), (np.array([0.1, -0.1, 0.2, 0.0]), -1.5, 0.3)]
+    for lanes in [4, 1]:
+        g = _gov(R, p, lanes=lanes, band=0.5, rng_mode=rng_mode)
+        for t, (x0, r, vp) in enumerate(cases):
+            g.set_step(t)
+            res = g.step(x0, r, vp)
+            ref = o.bisect(x0, r, vp, t, 12)
+            assert res["kappa"] == ref["kappa"], (lanes, t, res["kappa"], ref["kappa"])
+            assert res["rechecks"] > 0
+        g.close()
+
+
+def test_prediction_keeps_sequential_bisection_result(R, O):
+    # the first round speculates along the previous update's kappa: the closed
+    # loop must give the same kappa with and without it, equal to the oracle's
+    p = W.lq4_problem(seed=24, N=256, H=300, dt=0.005, eps=0.01)
+    r_seq = W.reference_sequence(5, 24, switch_every=4, lo=-2.5, hi=2.5)
+    a = _gov(R, p, predict=True).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    b = _gov(R, p, predict=False).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    assert np.array_equal(a["kappa"], b["kappa"]) and np.array_equal(a["x"], b["x"])
+    o = O.Oracle(p, nthreads=8)
+    v_prev = 0.0
+    for s in range(len(r_seq)):
+        assert a["kappa"][s] == o.bisect(a["x"][s], r_seq[s], v_prev, s, 12)["kappa"]
+        v_prev = a["v"][s]
