@@ -90,9 +90,17 @@ __device__ __forceinline__ T t_inf() {
   return (T)INFINITY;
 }
 
-__device__ __forceinline__ float t_tanh(float z) { return tanhf(z); }
+// FP32 rollouts: tanh from the hardware base-2 exponential and reciprocal,
+// tanh(z) = sign(z) (1 - 2 / (1 + e^{2|z|})), branch-free, absolute error a few
+// 2^-24 (relative error grows only where |tanh z| is itself below 1e-6); square
+// root from the hardware instruction (1 ulp).  FP64 paths use the library.
+__device__ __forceinline__ float t_tanh(float z) {
+  const float e = __builtin_amdgcn_exp2f(fabsf(z) * 2.8853900817779268f);  // 2 log2(e) |z|
+  const float r = __builtin_amdgcn_rcpf(e + 1.0f);
+  return __builtin_copysignf(__builtin_fmaf(-2.0f, r, 1.0f), z);
+}
 __device__ __forceinline__ double t_tanh(double z) { return tanh(z); }
-__device__ __forceinline__ float t_sqrt(float z) { return __builtin_sqrtf(z); }
+__device__ __forceinline__ float t_sqrt(float z) { return __builtin_amdgcn_sqrtf(z); }
 __device__ __forceinline__ double t_sqrt(double z) { return sqrt(z); }
 __device__ __forceinline__ float t_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double t_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
