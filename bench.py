@@ -177,6 +177,10 @@ def main():
                          "(0: the same steps as the headline form)")
     ap.add_argument("--form", choices=["fp32_adjoint_newton", "fp64_sequential_bisection"],
                     default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default schedule instead of the autotuned one")
+    ap.add_argument("--tune-steps", type=int, default=50,
+                    help="closed-loop updates the autotuner times each schedule on")
     ap.add_argument("--no-fc9", action="store_true",
                     help="skip the secondary 9-state grid-search measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -213,6 +217,13 @@ def main():
     g = rg.Governor(p, precision=prec, band=wl["band"], K=wl["K"], depth=args.depth,
                     lanes=args.lanes, max_T=max(256, T))
     x0 = np.asarray(wl["x0"], dtype=np.float64)
+
+    # launch schedule (lanes per scenario, workgroup, search depth, first-round
+    # prediction) from the autotuner, timed on the workload's first updates
+    tuned = None
+    if not args.no_autotune and args.tune_steps > 0:
+        g.set_step(0)
+        tuned = g.autotune(x0, wl["v_prev"], r_seq[: min(args.tune_steps, len(r_seq))])
 
     # warmup: the first W updates of the workload (untimed)
     if args.warmup > 0:
@@ -298,8 +309,13 @@ def main():
                    "precision": "fp32 rollouts + fp64 near-band recheck" if prec == 0 else "fp64",
                    "search": (f"bisection: first device round = kappa 1 probe + the midpoints on "
                               f"the path to the previous update's kappa, then "
-                              f"{g.options.depth} levels per round"),
+                              f"{g.options.depth} levels per round" if g.options.predict else
+                              f"bisection, {g.options.depth} levels per device round"),
                    "lanes_per_scenario": g.options.lanes,
+                   "workgroup": g.options.block if g.options.block else 256,
+                   "first_round_prediction": bool(g.options.predict),
+                   "schedule": ("autotuned on the first %d updates" % min(args.tune_steps, T)
+                                if tuned else "library default"),
                    "launch": "one captured HIP graph per RG update, replayed"},
         "rg_updates_per_s": K / elapsed,
         "executed_scenario_steps_per_s": executed / elapsed,
@@ -317,7 +333,7 @@ def main():
                          "infeasible_steps": int(np.sum(out["status"] != 0))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": measured_traffic(),
+                     "traffic": measured_traffic() if g.options.lanes == 4 else None,
                      "kernel": ("k_rollout_lq4_quad (one scenario per 4 lanes)" if g.options.lanes == 4
                                 else "k_rollout<LQ4, float>"),
                      "launches": prof["rollout_launches"],

@@ -243,6 +243,21 @@ int rg_closed_loop(rg_handle* h, const double* x0, double v0, const double* r_se
 /* The options in force, with auto fields (depth, lanes) resolved. */
 int rg_get_options(const rg_handle* h, rg_options* out);
 
+/* Autotuner of the launch schedule.  Runs the closed loop of T RG updates from
+ * (x0, v0) under r_seq (as rg_closed_loop, graph replay, starting at the
+ * handle's step counter, which is restored afterwards) once per candidate
+ * schedule and times it: lanes per scenario (1 or 4, LQ4 FP32 only), rollout
+ * workgroup (128 or 256 threads), device search depth (2..5; 1..3 for the grid
+ * refinement) and first-round prediction (on/off, bisection only).  Schedules
+ * change only which candidates run when, so every one must give the same kappa
+ * sequence; a mismatch returns RG_E_STATE.  best_out (nullable) receives the
+ * fastest schedule's options, best_ms_out (nullable) its time per update; with
+ * apply = 1 the handle keeps that schedule, else its own.  The first-round
+ * prediction state is reset.  Host-blocking; allocates nothing beyond the
+ * workspace. */
+int rg_autotune(rg_handle* h, const double* x0, double v0, const double* r_seq, int32_t T,
+                int32_t apply, rg_options* best_out, double* best_ms_out);
+
 /* Profiling: with enable = 1, every rollout launch is bracketed by HIP events
  * on the handle's stream and the totals accumulate until reset (enable = 1
  * again resets).  rg_get_profile copies the totals. */

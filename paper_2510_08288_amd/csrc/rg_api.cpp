@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <chrono>
 #include <new>
 #include <numeric>
 #include <string>
@@ -717,6 +718,109 @@ int rg_equilibrium(rg_handle* h, double v, double* x_out) {
   HIPCHK(h, hipStreamSynchronize(h->stream));
   if (out[h->pr.p.n] != 1.0) return fail(h, RG_E_STATE, "equilibrium iteration did not converge");
   for (int i = 0; i < h->pr.p.n; ++i) x_out[i] = out[i];
+  return RG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Switch the launch schedule (lanes, block, depth, prediction) of a handle:
+// re-plan, drop the captured step graph, update the device search record.
+int apply_schedule(rg_handle* h, const rg_options& o) {
+  h->opt.lanes = o.lanes;
+  h->opt.block = o.block;
+  h->opt.depth = o.depth;
+  h->opt.predict = o.predict;
+  plan(h);
+  if (h->step_graph) {
+    (void)hipGraphExecDestroy(h->step_graph);
+    h->step_graph = nullptr;
+  }
+  if (h->ws_ready) {
+    const int32_t depth = h->opt.depth;
+    const int32_t predict = h->opt.search == RG_SEARCH_BISECT ? h->opt.predict : 0;
+    const double none = std::nan("");
+    HIPCHK(h, hipMemcpyAsync((char*)h->b.srch + offsetof(DevSearch, depth), &depth, sizeof(depth),
+                             hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync((char*)h->b.srch + offsetof(DevSearch, predict), &predict,
+                             sizeof(predict), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync((char*)h->b.srch + offsetof(DevSearch, pred), &none, sizeof(none),
+                             hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+  }
+  return RG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rg_autotune(rg_handle* h, const double* x0, double v0, const double* r_seq, int32_t T,
+                int32_t apply, rg_options* best_out, double* best_ms_out) {
+  if (!h) return RG_E_INVAL;
+  if (!x0 || !r_seq || T < 1) return fail(h, RG_E_INVAL, "bad arguments");
+  if (h->profiling) return fail(h, RG_E_STATE, "autotune with profiling enabled");
+  int rc = ensure_workspace(h);
+  if (rc) return rc;
+  const rg_options own = h->opt;
+  const uint32_t t0 = h->t;
+  const bool quad_ok = h->pr.p.kind == RG_PLANT_LQ4 && h->opt.precision == RG_PREC_F32_RECHECK;
+  std::vector<rg_options> cands;
+  for (int lanes : {4, 1}) {
+    if (lanes == 4 && !quad_ok) continue;
+    for (int block : {256, 128}) {
+      const bool grid = h->opt.search == RG_SEARCH_GRID;
+      const int dlo = grid ? 1 : 2, dhi = grid ? 3 : 5;
+      for (int depth = dlo; depth <= dhi; ++depth) {
+        for (int predict : {1, 0}) {
+          if (predict && h->opt.search != RG_SEARCH_BISECT) continue;
+          if (h->opt.search == RG_SEARCH_NEWTON && depth != dlo) continue;  // depth unused
+          rg_options o = own;
+          o.lanes = lanes;
+          o.block = block;
+          o.depth = depth;
+          o.predict = predict;
+          cands.push_back(o);
+        }
+      }
+    }
+  }
+  std::vector<double> v(T), kap(T), ref;
+  double best_ms = INFINITY;
+  rg_options best = own;
+  for (const rg_options& o : cands) {
+    if ((rc = apply_schedule(h, o))) break;
+    double ms = INFINITY;
+    for (int rep = 0; rep < 2 && rc == RG_OK; ++rep) {  // the first run captures the graph
+      if ((rc = apply_schedule(h, o))) break;  // fresh prediction state for each run
+      h->t = t0;
+      const auto c0 = std::chrono::steady_clock::now();
+      rc = rg_closed_loop(h, x0, v0, r_seq, T, v.data(), kap.data(), nullptr, nullptr, 1);
+      const auto c1 = std::chrono::steady_clock::now();
+      ms = std::chrono::duration<double, std::milli>(c1 - c0).count() / T;
+    }
+    if (rc) break;
+    if (ref.empty()) {
+      ref = kap;
+    } else if (ref != kap) {
+      rc = fail(h, RG_E_STATE, "schedules disagree on kappa (lanes " + std::to_string(o.lanes) +
+                                   ", block " + std::to_string(o.block) + ", depth " +
+                                   std::to_string(o.depth) + ")");
+      break;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = h->opt;  // as planned (depth and lanes resolved)
+    }
+  }
+  h->t = t0;
+  h->gen_t = -1;  // the streamed draws no longer match the step counter
+  const int rc2 = apply_schedule(h, (rc == RG_OK && apply) ? best : own);
+  if (rc) return rc;
+  if (rc2) return rc2;
+  if (best_out) *best_out = best;
+  if (best_ms_out) *best_ms_out = best_ms;
   return RG_OK;
 }
 

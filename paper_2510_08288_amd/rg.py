@@ -115,6 +115,8 @@ def load_library(path: str = LIB_PATH, with_torch: bool = True) -> C.CDLL:
                                  C.POINTER(rg_step_info), C.c_int32]
     L.rg_set_profiling.argtypes = [_vp, C.c_int32]
     L.rg_get_options.argtypes = [_vp, C.POINTER(rg_options)]
+    L.rg_autotune.argtypes = [_vp, _dp, C.c_double, _dp, C.c_int32, C.c_int32,
+                              C.POINTER(rg_options), C.POINTER(C.c_double)]
     L.rg_grad.argtypes = [_vp, _dp, C.c_double, C.c_double, C.c_double, _fp, _dp, _dp, _dp]
     L.rg_set_theta.argtypes = [_vp, _dp]
     L.rg_equilibrium.argtypes = [_vp, C.c_double, _dp]
@@ -275,6 +277,20 @@ class Governor:
                                    None if up is None else _ptr(up, _fp), C.byref(M), C.byref(dk),
                                    _ptr(dth)))
         return dict(M=M.value, dkappa=dk.value, dtheta=dth[: self.problem.n_theta])
+
+    def autotune(self, x0, v0: float, r_seq, apply: bool = True) -> dict:
+        """Time the closed loop over r_seq under each launch schedule (rg_autotune);
+        with apply the handle keeps the fastest.  Returns that schedule."""
+        x0 = _f64(x0)
+        r = _f64(r_seq)
+        best = rg_options()
+        ms = C.c_double()
+        self._check(self.L.rg_autotune(self.h, _ptr(x0), float(v0), _ptr(r), r.size, int(apply),
+                                       C.byref(best), C.byref(ms)))
+        self.options = rg_options()
+        self.L.rg_get_options(self.h, C.byref(self.options))
+        return dict(lanes=best.lanes, block=best.block, depth=best.depth, predict=best.predict,
+                    ms_per_update=ms.value)
 
     def equilibrium(self, v: float) -> np.ndarray:
         x = np.zeros(self.problem.n)

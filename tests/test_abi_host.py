@@ -34,7 +34,7 @@ def test_header_declares_the_boundary():
                      "rg_workspace_size", "rg_bind_workspace", "rg_set_stream", "rg_set_step",
                      "rg_get_step", "rg_draws", "rg_trajectory", "rg_status_string",
                      "rg_last_error", "rg_default_options", "rg_grad", "rg_set_theta",
-                     "rg_get_options", "rg_set_profiling", "rg_get_profile"]:
+                     "rg_get_options", "rg_set_profiling", "rg_get_profile", "rg_autotune"]:
         assert required in names
 
 
@@ -177,6 +177,11 @@ def test_calls_reject_bad_arguments_before_device_work(lib):
     tr = np.zeros(100)
     assert lib.rg_trajectory(h, x.ctypes.data_as(dp), 0.5, ks.ctypes.data_as(C.POINTER(C.c_int32)),
                              2, 0, tr.ctypes.data_as(dp)) == R.RG_E_INVAL
+    assert lib.rg_autotune(h, None, 0.0, r.ctypes.data_as(dp), 3, 1, None, None) == R.RG_E_INVAL
+    assert lib.rg_autotune(h, x.ctypes.data_as(dp), 0.0, r.ctypes.data_as(dp), 0, 1, None,
+                           None) == R.RG_E_INVAL
+    assert lib.rg_autotune(None, x.ctypes.data_as(dp), 0.0, r.ctypes.data_as(dp), 3, 1, None,
+                           None) == R.RG_E_INVAL
     assert lib.rg_bind_workspace(h, C.c_void_p(0x1001), 1 << 30) == R.RG_E_INVAL
     assert lib.rg_bind_workspace(h, C.c_void_p(0x1000), 16) == R.RG_E_NOMEM
     assert lib.rg_destroy(h) == 0

@@ -371,3 +371,18 @@ def test_prediction_keeps_sequential_bisection_result(R, O):
     for s in range(len(r_seq)):
         assert a["kappa"][s] == o.bisect(a["x"][s], r_seq[s], v_prev, s, 12)["kappa"]
         v_prev = a["v"][s]
+
+
+def test_autotune_keeps_results_and_picks_a_schedule(R, O):
+    p = W.lq4_problem(seed=24, N=512, H=300, dt=0.005, eps=0.01)
+    r_seq = W.reference_sequence(5, 16, switch_every=4, lo=-2.5, hi=2.5)
+    ref = _gov(R, p).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    g = _gov(R, p)
+    best = g.autotune(np.zeros(4), 0.0, r_seq[:8])
+    assert best["lanes"] in (1, 4) and best["block"] in (128, 256) and 2 <= best["depth"] <= 5
+    assert best["ms_per_update"] > 0
+    assert g.options.lanes == best["lanes"] and g.options.depth == best["depth"]
+    assert g.get_step() == 0
+    out = g.closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    assert np.array_equal(out["kappa"], ref["kappa"]) and np.array_equal(out["x"], ref["x"])
+    g.close()
