@@ -42,9 +42,11 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (needs packed FP32)
 PEAK_FP32_NONPACKED_TFLOPS = 78.6
 # HBM bytes per rollout launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
 # this bench (4 updates), each scaled by the counter's reading for a 256 MiB device
-# copy; valid only for the kernel source they were taken on (SHA-1 below).
-HBM_TRAFFIC = {"kernels_sha1": "9498e6c9a5c5582ab0be2c6a6c4eb96a5816bc0b",
-               "bytes_per_launch": 14029784}
+# copy; valid only for the kernel sources they were taken on (SHA-1 of the device
+# sources below, concatenated in this order).
+KERNEL_SOURCES = ("rg_kernels.hip", "rg_device.hpp", "rg_internal.hpp")
+HBM_TRAFFIC = {"kernels_sha1": "8c1d66109b107b5a958b1b2360aa3f71b57e6dfd",
+               "bytes_per_launch": 14037258}
 
 
 def cpu_baseline(wl, r_seq, seconds):
@@ -83,9 +85,11 @@ def measured_traffic():
     """roofline.traffic: the counter-based HBM bytes per rollout launch, or None
     once the kernel source differs from the one the counters were taken on."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2510_08288_amd", "csrc", "rg_kernels.hip")
-    with open(path, "rb") as f:
-        sha = hashlib.sha1(f.read()).hexdigest()
+    h = hashlib.sha1()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2510_08288_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    sha = h.hexdigest()
     return HBM_TRAFFIC["bytes_per_launch"] if sha == HBM_TRAFFIC["kernels_sha1"] else None
 
 
@@ -172,6 +176,7 @@ def main():
     ap.add_argument("--depth", type=int, default=0)
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0, help="rollout workgroup (0: library choice)")
     ap.add_argument("--mode-steps", type=int, default=0,
                     help="closed-loop steps timed for the Newton and FP64 search forms "
                          "(0: the same steps as the headline form)")
@@ -209,13 +214,13 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": args.copy_calibration, "copies": 3}))
         return
-    T = max(args.steps, args.warmup)
+    T = max(args.steps, args.warmup, 0 if args.no_autotune else args.tune_steps)
     wl = W.workload_lq4_closed_loop(T=T)
     p = wl["problem"]
     r_seq = wl["r_seq"]
     prec = rg.PREC_F32_RECHECK if args.precision == "f32" else rg.PREC_F64
     g = rg.Governor(p, precision=prec, band=wl["band"], K=wl["K"], depth=args.depth,
-                    lanes=args.lanes, max_T=max(256, T))
+                    lanes=args.lanes, block=args.block, max_T=max(256, T))
     x0 = np.asarray(wl["x0"], dtype=np.float64)
 
     # launch schedule (lanes per scenario, workgroup, search depth, first-round
