@@ -186,6 +186,7 @@ def main():
                     help="keep the library's default schedule instead of the autotuned one")
     ap.add_argument("--tune-steps", type=int, default=50,
                     help="closed-loop updates the autotuner times each schedule on")
+    ap.add_argument("--autotune-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-fc9", action="store_true",
                     help="skip the secondary 9-state grid-search measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -214,21 +215,34 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": args.copy_calibration, "copies": 3}))
         return
-    T = max(args.steps, args.warmup, 0 if args.no_autotune else args.tune_steps)
+    T = max(args.steps, args.warmup, args.tune_steps if args.autotune_only else 0)
     wl = W.workload_lq4_closed_loop(T=T)
     p = wl["problem"]
     r_seq = wl["r_seq"]
     prec = rg.PREC_F32_RECHECK if args.precision == "f32" else rg.PREC_F64
-    g = rg.Governor(p, precision=prec, band=wl["band"], K=wl["K"], depth=args.depth,
-                    lanes=args.lanes, block=args.block, max_T=max(256, T))
     x0 = np.asarray(wl["x0"], dtype=np.float64)
+    if args.autotune_only:
+        ga = rg.Governor(p, precision=prec, band=wl["band"], K=wl["K"], max_T=max(256, T))
+        ga.set_step(0)
+        print(json.dumps(ga.autotune(x0, wl["v_prev"], r_seq[: args.tune_steps])))
+        ga.close()
+        return
 
     # launch schedule (lanes per scenario, workgroup, search depth, first-round
-    # prediction) from the autotuner, timed on the workload's first updates
+    # prediction) from the autotuner, timed on the workload's first updates in a
+    # child process of its own (its trial launches stay out of this process)
     tuned = None
+    sched = dict(depth=args.depth, lanes=args.lanes, block=args.block)
     if not args.no_autotune and args.tune_steps > 0:
-        g.set_step(0)
-        tuned = g.autotune(x0, wl["v_prev"], r_seq[: min(args.tune_steps, len(r_seq))])
+        child = subprocess.run([sys.executable, os.path.abspath(__file__), "--autotune-only",
+                                "--tune-steps", str(args.tune_steps)], capture_output=True, text=True)
+        if child.returncode != 0:
+            sys.stderr.write(child.stdout + child.stderr)
+            raise SystemExit(f"autotuner failed (exit {child.returncode})")
+        tuned = json.loads(child.stdout.strip().splitlines()[-1])
+        sched = dict(depth=tuned["depth"], lanes=tuned["lanes"], block=tuned["block"],
+                     predict=bool(tuned["predict"]))
+    g = rg.Governor(p, precision=prec, band=wl["band"], K=wl["K"], max_T=max(256, T), **sched)
 
     # warmup: the first W updates of the workload (untimed)
     if args.warmup > 0:
@@ -319,8 +333,8 @@ def main():
                    "lanes_per_scenario": g.options.lanes,
                    "workgroup": g.options.block if g.options.block else 256,
                    "first_round_prediction": bool(g.options.predict),
-                   "schedule": ("autotuned on the first %d updates" % min(args.tune_steps, T)
-                                if tuned else "library default"),
+                   "schedule": ("autotuned on the first %d updates" % args.tune_steps
+                                if tuned else "library default or command line"),
                    "launch": "one captured HIP graph per RG update, replayed"},
         "rg_updates_per_s": K / elapsed,
         "executed_scenario_steps_per_s": executed / elapsed,
