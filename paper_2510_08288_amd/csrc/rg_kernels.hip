@@ -124,10 +124,16 @@ __global__ void __launch_bounds__(256) k_gen(RollArgs<KIND, float> a, float* wbu
 // stop_flag (nullable) is polled every 32 steps; early != 0 also stops the
 // lane once its minimum is below -band.  traj (nullable) receives states.
 // ---------------------------------------------------------------------------
-template <int KIND, class T, int RNG, int INJ, class A, int CKPT = 0>
+// With WAVE set the whole wave evaluates one candidate and stop_flag is that
+// candidate's dead flag: one violation anywhere ends the candidate, so the
+// wave stops as soon as any of its lanes sees one, and raises the flag at once
+// for the other waves (which read it every 8 steps).  Without WAVE, lanes
+// stop on their own and stop_flag is only read.
+template <int KIND, class T, int RNG, int INJ, class A, int CKPT = 0, bool WAVE = false>
 __device__ __forceinline__ T rollout_lane(const A& a, int early, T v, int k, uint32_t t,
-                                          const int32_t* stop_flag, int& jbest, int& nsteps,
-                                          double* traj, bool ck = false) {
+                                          int32_t* stop_flag, int& jbest, int& nsteps,
+                                          double* traj, bool ck = false,
+                                          bool* stopped = nullptr) {
   using P = Plant<KIND, T>;
   T th[P::nth > 0 ? P::nth : 1];
   if constexpr (P::nth > 0) {
@@ -172,8 +178,11 @@ __device__ __forceinline__ T rollout_lane(const A& a, int early, T v, int k, uin
   };
   if (a.H > 0) load(0, wc);
   int j = 0;
+  int stop_seen = 0;  // dead flag read at the start of an 8-step block, tested at its end
   for (; j < a.H; ++j) {
     if (j + 1 < a.H) load(j + 1, wn);
+    if (WAVE && early && (j & 7) == 0)
+      stop_seen = __hip_atomic_load(stop_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     T s[P::n];
     if (INJ == 0) {
       T wt[P::nw];
@@ -209,14 +218,29 @@ __device__ __forceinline__ T rollout_lane(const A& a, int early, T v, int k, uin
       }
     }
     if (early) {
-      if (best < -a.band) {
-        ++j;
-        break;
-      }
-      if ((j & 31) == 31 && stop_flag &&
-          __hip_atomic_load(stop_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        ++j;
-        break;
+      if constexpr (WAVE) {
+        const bool viol = best < -a.band;
+        if (__builtin_amdgcn_ballot_w64(viol) != 0) {
+          if (viol) __hip_atomic_store(stop_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          *stopped = true;
+          ++j;
+          break;
+        }
+        if ((j & 7) == 7 && stop_seen) {
+          *stopped = true;
+          ++j;
+          break;
+        }
+      } else {
+        if (best < -a.band) {
+          ++j;
+          break;
+        }
+        if ((j & 31) == 31 && stop_flag &&
+            __hip_atomic_load(stop_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          ++j;
+          break;
+        }
       }
     }
 #pragma unroll
@@ -276,15 +300,16 @@ __global__ void __launch_bounds__(256) k_rollout(const RollArgs<KIND, T> a) {
   T m = t_inf<T>();
   int jb = 0, ns = 0;
   if (k < a.N) {
-    m = rollout_lane<KIND, T, RNG, INJ, RollArgs<KIND, T>, CKPT>(
-        a, early, (T)S->v[c], k, t, early ? &S->dead[c] : nullptr, jb, ns, nullptr, ck);
+    bool stopped = false;  // the candidate died while this wave ran (no recheck needed)
+    m = rollout_lane<KIND, T, RNG, INJ, RollArgs<KIND, T>, CKPT, true>(
+        a, early, (T)S->v[c], k, t, &S->dead[c], jb, ns, nullptr, ck, &stopped);
     if (a.record) {
       a.per_m[(size_t)c * a.N + k] = (float)m;
       a.per_j[(size_t)c * a.N + k] = jb;
     }
     if (m < -a.band) {
       __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else if (m < a.band) {
+    } else if (m < a.band && !stopped) {
       const int idx = atomicAdd(&S->n_recheck, 1);
       a.rlist[idx] = make_int2(c, k);
     }
@@ -371,6 +396,7 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
   const uint32_t t = a.st->t;
   float best = INFINITY;
   int jb = 0, ns = 0;
+  bool stopped = false;  // the candidate died while this wave ran (no recheck needed)
   if (k < a.N) {  // whole quads are active or inactive together
     QuadLane L;
     L.a0 = qc.a[q][0]; L.a1 = qc.a[q][1]; L.a2 = qc.a[q][2]; L.a3 = qc.a[q][3];
@@ -459,27 +485,36 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
     load_group(0, wcur);
     const int full = H / U;
     int g = 0;
+    // One violation anywhere ends the candidate: the wave stops as soon as any
+    // of its quads sees one and raises the dead flag at once; the flag is read
+    // at the start of every group and tested at its end.
     for (; g < full; ++g) {
       load_group((g + 1) * U, wnext);
+      const int dead_seen =
+          early ? __hip_atomic_load(&S->dead[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
 #pragma unroll
       for (int u = 0; u < U; ++u) step(wcur[2 * u], wcur[2 * u + 1], g * U + u + 1);
 #pragma unroll
       for (int u = 0; u < 2 * U; ++u) wcur[u] = wnext[u];
       if (early) {
         const float bg = RECORD ? best : quad_min(bq);
-        if (bg < -a.band) {
+        const bool viol = bg < -a.band;
+        if (__builtin_amdgcn_ballot_w64(viol) != 0) {
+          if (viol && q == 0)
+            __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          stopped = true;
           ++g;
           break;
         }
-        if ((g & 7) == 7 &&
-            __hip_atomic_load(&S->dead[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        if (dead_seen) {
+          stopped = true;
           ++g;
           break;
         }
       }
     }
     ns = g * U;
-    if (g == full) {  // ragged tail of the horizon
+    if (g == full && !stopped) {  // ragged tail of the horizon
       for (int u = 0; u < H - full * U; ++u) step(wcur[2 * u], wcur[2 * u + 1], full * U + u + 1);
       ns = H;
     }
@@ -498,7 +533,7 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
     }
     if (best < -a.band) {
       __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else if (best < a.band) {
+    } else if (best < a.band && !stopped) {
       const int idx = atomicAdd(&S->n_recheck, 1);
       a.rlist[idx] = make_int2(c, k);
     }
