@@ -293,10 +293,14 @@ hipError_t enqueue_step(rg_handle* h, int closed_loop) {
   hipError_t e;
   const int prec = h->opt.precision;
   const double band = prec == RG_PREC_F32_RECHECK ? h->opt.band : 0.0;
-  if (h->pr.s.rng_mode == RG_RNG_STREAM && (e = launch_gen(h->pr, h->b, h->stream)) != hipSuccess)
-    return e;
-  if ((e = launch_setup(h->pr, h->b, closed_loop, h->stream)) != hipSuccess) return e;
+  // draws and round-0 setup share a launch in stream mode
+  e = h->pr.s.rng_mode == RG_RNG_STREAM ? launch_gen_setup(h->pr, h->b, closed_loop, h->stream)
+                                         : launch_setup(h->pr, h->b, closed_loop, h->stream);
+  if (e != hipSuccess) return e;
   const bool newton = h->opt.search == RG_SEARCH_NEWTON;
+  // with FP32 rollouts the recheck launch ends with the decision (the Newton
+  // decision needs the derivative first)
+  const bool fused_decide = prec == RG_PREC_F32_RECHECK && !newton;
   for (int r = 0; r < h->cfg.rounds; ++r) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->profiling) {
@@ -309,14 +313,15 @@ hipError_t enqueue_step(rg_handle* h, int closed_loop) {
       return e;
     if (h->profiling && (e = hipEventRecord(e1, h->stream)) != hipSuccess) return e;
     if (prec == RG_PREC_F32_RECHECK &&
-        (e = launch_recheck(h->pr, h->opt.early_exit, h->cfg, h->b, h->stream)) != hipSuccess)
+        (e = launch_recheck(h->pr, h->opt.early_exit, h->cfg, h->b, h->stream, fused_decide)) !=
+            hipSuccess)
       return e;
     if (newton) {  // derivative of the Newton iterate's worst margin (segment adjoint)
       if ((e = launch_grad_prepare(h->pr, h->b, -1, 1, h->stream)) != hipSuccess) return e;
       if ((e = launch_seg_grad(h->pr, h->opt.Kc, -1, h->b, h->stream)) != hipSuccess) return e;
       if ((e = launch_grad_reduce(h->b, 1, h->pr.p.nth, -1, h->stream)) != hipSuccess) return e;
     }
-    if ((e = launch_decide(h->pr, h->b, h->stream)) != hipSuccess) return e;
+    if (!fused_decide && (e = launch_decide(h->pr, h->b, h->stream)) != hipSuccess) return e;
   }
   return launch_finalize(h->pr, closed_loop, h->b, h->stream);
 }

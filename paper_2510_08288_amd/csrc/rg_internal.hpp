@@ -67,6 +67,9 @@ struct DevSearch {
   // Bisection: round 0 speculates along the path to the previous step's kappa
   int32_t predict;                    // 1: enabled
   double pred;                        // previous step's kappa (NaN: none yet)
+  // Workgroups of the current recheck launch that have finished; the last one
+  // takes the round's decision and resets the count.
+  uint32_t blocks_done;
 };
 
 // Result record of one RG step.
@@ -194,6 +197,8 @@ struct Problem {
 };
 
 hipError_t launch_gen(const Problem& pr, const DevBuffers& b, hipStream_t st);
+// Draws plus the round-0 setup in one launch (workgroup 0 runs the setup).
+hipError_t launch_gen_setup(const Problem& pr, const DevBuffers& b, int closed_loop, hipStream_t st);
 hipError_t launch_setup(const Problem& pr, const DevBuffers& b, int closed_loop, hipStream_t st);
 hipError_t launch_setup_list(const Problem& pr, const DevBuffers& b, int M, hipStream_t st);
 // ckpt_cand >= 0 (or -1 for the Newton iterate) keeps that candidate's
@@ -201,8 +206,10 @@ hipError_t launch_setup_list(const Problem& pr, const DevBuffers& b, int M, hipS
 hipError_t launch_rollout(const Problem& pr, double band, int precision, int early_exit, int record,
                           const LaunchCfg& cfg, const DevBuffers& b, hipStream_t st,
                           int ckpt_cand = -2, int Kc = 0);
+// decide != 0: the last workgroup to finish also takes the round's decision
+// (the work of launch_decide), so no separate decision launch follows.
 hipError_t launch_recheck(const Problem& pr, int early_exit, const LaunchCfg& cfg,
-                          const DevBuffers& b, hipStream_t st);
+                          const DevBuffers& b, hipStream_t st, int decide = 0);
 hipError_t launch_decide(const Problem& pr, const DevBuffers& b, hipStream_t st);
 hipError_t launch_finalize(const Problem& pr, int closed_loop, const DevBuffers& b,
                            hipStream_t st);

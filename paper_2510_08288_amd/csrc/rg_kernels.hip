@@ -98,10 +98,10 @@ __device__ __forceinline__ void draw_theta_factor(uint32_t seed, uint32_t inst, 
 // Streamed draws: w[(j * nw + c) * N + k] (consecutive scenarios contiguous, so
 // a wave's loads of one step coalesce), theta factors f[c * N + k].
 template <int KIND>
-__global__ void __launch_bounds__(256) k_gen(RollArgs<KIND, float> a, float* wbuf, float* thbuf) {
+__device__ __forceinline__ void gen_body(const RollArgs<KIND, float>& a, float* wbuf, float* thbuf,
+                                         size_t gid) {
   using P = Plant<KIND, float>;
   const uint32_t t = a.st->t;
-  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t nwork = (size_t)a.H * a.N;
   if (gid < nwork) {
     const int j = (int)(gid / a.N);
@@ -118,6 +118,18 @@ __global__ void __launch_bounds__(256) k_gen(RollArgs<KIND, float> a, float* wbu
     for (int c = 0; c < P::nth; ++c) thbuf[(size_t)c * a.N + k] = f[c];
   }
 }
+
+template <int KIND>
+__global__ void __launch_bounds__(256) k_gen(RollArgs<KIND, float> a, float* wbuf, float* thbuf) {
+  gen_body<KIND>(a, wbuf, thbuf, (size_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Forward declarations: the recheck kernels end with the round's decision.
+template <int KIND>
+__device__ void decide_body(const typename Plant<KIND, double>::Coef& pc, const DevState* st,
+                            DevSearch* S, const DevGrad* grad);
+template <int KIND>
+__device__ void last_block_decides(const CtlArgs<KIND>& ctl);
 
 // ---------------------------------------------------------------------------
 // One scenario rollout with the fused running-minimum margin.
@@ -578,7 +590,8 @@ __device__ __forceinline__ double quad_min64(double m) {
 
 template <int RNG, int INJ>
 __global__ void __launch_bounds__(256) k_recheck_lq4_quad(const RollArgs<1, double> a,
-                                                         const QuadCoef64 qc) {
+                                                         const QuadCoef64 qc,
+                                                         const CtlArgs<1> ctl, int decide) {
   constexpr int U = kQuadGroup;
   DevSearch* S = a.srch;
   if (S->done) return;
@@ -690,11 +703,13 @@ __global__ void __launch_bounds__(256) k_recheck_lq4_quad(const RollArgs<1, doub
       if (m < 0.0) __hip_atomic_store(&S->fail64[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
+  if (decide) last_block_decides<1>(ctl);
 }
 
 // FP64 re-simulation of the near-band list.
 template <int KIND, int RNG, int INJ>
-__global__ void __launch_bounds__(64) k_recheck(const RollArgs<KIND, double> a) {
+__global__ void __launch_bounds__(64) k_recheck(const RollArgs<KIND, double> a,
+                                                const CtlArgs<KIND> ctl, int decide) {
   DevSearch* S = a.srch;
   if (S->done) return;
   const int n = S->n_recheck;
@@ -717,6 +732,7 @@ __global__ void __launch_bounds__(64) k_recheck(const RollArgs<KIND, double> a) 
     atomicMin(&S->key64[c], ord64(m));
     if (m < 0.0) __hip_atomic_store(&S->fail64[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  if (decide) last_block_decides<KIND>(ctl);
 }
 
 // ---------------------------------------------------------------------------
@@ -1136,6 +1152,39 @@ __device__ void decide_body(const typename Plant<KIND, double>::Coef& pc, const 
 template <int KIND>
 __global__ void __launch_bounds__(128) k_decide(const CtlArgs<KIND> a) {
   decide_body<KIND>(a.pc, a.st, a.srch, a.grad);
+}
+
+// End of a recheck launch: the last workgroup to finish takes the round's
+// decision.  Each workgroup publishes its verdict updates (device-scope
+// fence) before it counts itself; the last one fences again before reading
+// them, resets the count for the next launch and runs the decision.  No
+// workgroup waits for another.
+template <int KIND>
+__device__ void last_block_decides(const CtlArgs<KIND>& ctl) {
+  __shared__ int s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t prev = atomicAdd(&ctl.srch->blocks_done, 1u);
+    s_last = (prev == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  if (threadIdx.x == 0) ctl.srch->blocks_done = 0u;
+  decide_body<KIND>(ctl.pc, ctl.st, ctl.srch, ctl.grad);
+}
+
+// Draws and the round-0 setup in one launch: workgroup 0 runs the setup (it
+// needs no draws), the others generate the draws.
+template <int KIND>
+__global__ void __launch_bounds__(256) k_gen_setup(RollArgs<KIND, float> a, float* wbuf,
+                                                   float* thbuf, const CtlArgs<KIND> ctl) {
+  if (blockIdx.x == 0) {
+    setup_body<KIND>(ctl.pc, ctl.st, ctl.srch, ctl.r_seq, ctl.closed_loop);
+    return;
+  }
+  gen_body<KIND>(a, wbuf, thbuf, (size_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x);
 }
 
 // Result record; in closed loop also the true-plant step (Eq. (4)) in FP64
@@ -2030,6 +2079,18 @@ hipError_t launch_gen(const Problem& pr, const DevBuffers& b, hipStream_t st) {
   });
 }
 
+hipError_t launch_gen_setup(const Problem& pr, const DevBuffers& b, int closed_loop,
+                            hipStream_t st) {
+  return by_kind(pr.p.kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    auto a = make_args<K, float>(pr, 0.0, 0, 0, b);
+    const size_t work = (size_t)pr.H * pr.s.N + (Plant<K, float>::nth > 0 ? pr.s.N : 0);
+    hipLaunchKernelGGL(k_gen_setup<K>, dim3(1 + div_up(work, 256)), dim3(256), 0, st, a, b.wbuf,
+                       b.thbuf, make_ctl<K>(pr, b, closed_loop));
+    return hipGetLastError();
+  });
+}
+
 hipError_t launch_setup(const Problem& pr, const DevBuffers& b, int closed_loop, hipStream_t st) {
   return by_kind(pr.p.kind, [&](auto kc) {
     constexpr int K = decltype(kc)::value;
@@ -2166,7 +2227,7 @@ static QuadCoef64 make_quad_coef64(const Problem& pr) {
 }
 
 hipError_t launch_recheck(const Problem& pr, int early_exit, const LaunchCfg& cfg,
-                          const DevBuffers& b, hipStream_t st) {
+                          const DevBuffers& b, hipStream_t st, int decide) {
   const size_t cap = (size_t)cfg.cmax_round * pr.s.N;
   if (cfg.lanes == 4 && pr.p.kind == 1 && quad_draws_addressable(pr)) {
     const int qblocks = div_up((cap < 16384 ? cap : 16384) * 4, 256);
@@ -2176,7 +2237,8 @@ hipError_t launch_recheck(const Problem& pr, int early_exit, const LaunchCfg& cf
       constexpr int R = decltype(rc)::value;
       return by_bit(pr.s.inject, [&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        hipLaunchKernelGGL((k_recheck_lq4_quad<R, I>), dim3(qblocks), dim3(256), 0, st, a, qc);
+        hipLaunchKernelGGL((k_recheck_lq4_quad<R, I>), dim3(qblocks), dim3(256), 0, st, a, qc,
+                           make_ctl<1>(pr, b, 0), decide);
         return hipGetLastError();
       });
     });
@@ -2189,7 +2251,8 @@ hipError_t launch_recheck(const Problem& pr, int early_exit, const LaunchCfg& cf
       return by_bit(pr.s.inject, [&](auto ic) {
         constexpr int I = decltype(ic)::value;
         auto a = make_args<K, double>(pr, 0.0, early_exit, 0, b);
-        hipLaunchKernelGGL((k_recheck<K, R, I>), dim3(blocks), dim3(64), 0, st, a);
+        hipLaunchKernelGGL((k_recheck<K, R, I>), dim3(blocks), dim3(64), 0, st, a,
+                           make_ctl<K>(pr, b, 0), decide);
         return hipGetLastError();
       });
     });
