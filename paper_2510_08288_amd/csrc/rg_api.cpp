@@ -33,8 +33,8 @@ struct rg_handle {
   uint32_t t = 0;
   long long gen_t = -1;  // RG step whose draws are in the streamed buffer
   std::string err;
-  // one captured closed-loop RG step, replayed per step
-  hipGraphExec_t step_graph = nullptr;
+  // one captured closed-loop RG step per draw-buffer parity, replayed per step
+  hipGraphExec_t step_graph[2] = {nullptr, nullptr};
   // profiling
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -63,6 +63,13 @@ int fail_hip(rg_handle* h, const char* what, hipError_t e) {
     if (e_ != hipSuccess) return fail_hip(h, #call, e_); \
   } while (0)
 
+void drop_graphs(rg_handle* h) {
+  for (hipGraphExec_t& g : h->step_graph) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+}
+
 bool finite_array(const double* a, int n) {
   for (int i = 0; i < n; ++i)
     if (!std::isfinite(a[i])) return false;
@@ -73,7 +80,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace layout: offsets of each buffer inside one allocation.
 struct Layout {
-  size_t st, srch, res, r_seq, x_hist, wbuf, thbuf, rlist, per_m, per_j, scratch;
+  size_t st, srch, res, r_seq, x_hist, wbuf, thbuf, wbuf2, thbuf2, rlist, per_m, per_j, scratch;
   size_t grad, adj_k, adj_w, adj_m, adj_dv, adj_dth, adj_ckpt, adj_seg;
   size_t seg_m, seg_j, seg_r, seg_x, seg_a, seg_cv, seg_ct, seg_scr, total;
 };
@@ -94,8 +101,13 @@ Layout layout_of(const rg_handle* h) {
   L.res = take(sizeof(DevResult) * T);
   L.r_seq = take(sizeof(double) * T);
   L.x_hist = take(sizeof(double) * (T + 1) * kMaxN);
-  L.wbuf = take(pr.s.rng_mode == RG_RNG_STREAM ? sizeof(float) * (size_t)(pr.H + kQuadGroup) * pr.p.nw * N : 0);
-  L.thbuf = take(pr.s.rng_mode == RG_RNG_STREAM ? sizeof(float) * (size_t)pr.p.nth * N : 0);
+  const size_t wbytes =
+      pr.s.rng_mode == RG_RNG_STREAM ? sizeof(float) * (size_t)(pr.H + kQuadGroup) * pr.p.nw * N : 0;
+  const size_t thbytes = pr.s.rng_mode == RG_RNG_STREAM ? sizeof(float) * (size_t)pr.p.nth * N : 0;
+  L.wbuf = take(wbytes);
+  L.thbuf = take(thbytes);
+  L.wbuf2 = take(wbytes);
+  L.thbuf2 = take(thbytes);
   L.rlist = take(sizeof(int2) * (size_t)kCMax * N);
   L.per_m = take(sizeof(float) * (size_t)kCMax * N);
   L.per_j = take(sizeof(int32_t) * (size_t)kCMax * N);
@@ -191,6 +203,8 @@ int ensure_workspace(rg_handle* h) {
   b.x_hist = (double*)(base + L.x_hist);
   b.wbuf = (float*)(base + L.wbuf);
   b.thbuf = (float*)(base + L.thbuf);
+  b.wbuf2 = (float*)(base + L.wbuf2);
+  b.thbuf2 = (float*)(base + L.thbuf2);
   b.rlist = (int2*)(base + L.rlist);
   b.per_m = (float*)(base + L.per_m);
   b.per_j = (int32_t*)(base + L.per_j);
@@ -289,14 +303,31 @@ hipError_t harvest_events(rg_handle* h) {
 }
 
 // Enqueue one RG step: draws, round-0 setup, the rounds, the result record.
-hipError_t enqueue_step(rg_handle* h, int closed_loop) {
+// In closed loop (parity = t & 1) the draws and the round-0 setup of step t
+// were made by step t - 1 or the chunk's prologue: the step reads draw pair
+// `parity`, its first round generates the draws of step t + 1 into the other
+// pair, and its result launch prepares round 0 of step t + 1.
+hipError_t enqueue_step(rg_handle* h, int closed_loop, int parity) {
   hipError_t e;
   const int prec = h->opt.precision;
   const double band = prec == RG_PREC_F32_RECHECK ? h->opt.band : 0.0;
-  // draws and round-0 setup share a launch in stream mode
-  e = h->pr.s.rng_mode == RG_RNG_STREAM ? launch_gen_setup(h->pr, h->b, closed_loop, h->stream)
-                                         : launch_setup(h->pr, h->b, closed_loop, h->stream);
-  if (e != hipSuccess) return e;
+  const bool streamed = h->pr.s.rng_mode == RG_RNG_STREAM;
+  DevBuffers b = h->b;
+  float *gen_w = nullptr, *gen_th = nullptr;
+  if (closed_loop) {
+    if (streamed) {
+      if (parity) {
+        b.wbuf = h->b.wbuf2;
+        b.thbuf = h->b.thbuf2;
+      }
+      gen_w = parity ? h->b.wbuf : h->b.wbuf2;
+      gen_th = parity ? h->b.thbuf : h->b.thbuf2;
+    }
+  } else {
+    // draws and round-0 setup share a launch in stream mode
+    e = streamed ? launch_gen_setup(h->pr, b, 0, h->stream) : launch_setup(h->pr, b, 0, h->stream);
+    if (e != hipSuccess) return e;
+  }
   const bool newton = h->opt.search == RG_SEARCH_NEWTON;
   // with FP32 rollouts the recheck launch ends with the decision (the Newton
   // decision needs the derivative first)
@@ -308,22 +339,23 @@ hipError_t enqueue_step(rg_handle* h, int closed_loop) {
       if ((e = hipEventRecord(e0, h->stream)) != hipSuccess) return e;
     }
     // the Newton iterate keeps checkpoints for its derivative
-    if ((e = launch_rollout(h->pr, band, prec, h->opt.early_exit, 0, h->cfg, h->b, h->stream,
-                            newton ? -1 : -2, h->opt.Kc)) != hipSuccess)
+    if ((e = launch_rollout(h->pr, band, prec, h->opt.early_exit, 0, h->cfg, b, h->stream,
+                            newton ? -1 : -2, h->opt.Kc, r == 0 ? gen_w : nullptr,
+                            r == 0 ? gen_th : nullptr)) != hipSuccess)
       return e;
     if (h->profiling && (e = hipEventRecord(e1, h->stream)) != hipSuccess) return e;
     if (prec == RG_PREC_F32_RECHECK &&
-        (e = launch_recheck(h->pr, h->opt.early_exit, h->cfg, h->b, h->stream, fused_decide)) !=
+        (e = launch_recheck(h->pr, h->opt.early_exit, h->cfg, b, h->stream, fused_decide)) !=
             hipSuccess)
       return e;
     if (newton) {  // derivative of the Newton iterate's worst margin (segment adjoint)
-      if ((e = launch_grad_prepare(h->pr, h->b, -1, 1, h->stream)) != hipSuccess) return e;
-      if ((e = launch_seg_grad(h->pr, h->opt.Kc, -1, h->b, h->stream)) != hipSuccess) return e;
-      if ((e = launch_grad_reduce(h->b, 1, h->pr.p.nth, -1, h->stream)) != hipSuccess) return e;
+      if ((e = launch_grad_prepare(h->pr, b, -1, 1, h->stream)) != hipSuccess) return e;
+      if ((e = launch_seg_grad(h->pr, h->opt.Kc, -1, b, h->stream)) != hipSuccess) return e;
+      if ((e = launch_grad_reduce(b, 1, h->pr.p.nth, -1, h->stream)) != hipSuccess) return e;
     }
-    if (!fused_decide && (e = launch_decide(h->pr, h->b, h->stream)) != hipSuccess) return e;
+    if (!fused_decide && (e = launch_decide(h->pr, b, h->stream)) != hipSuccess) return e;
   }
-  return launch_finalize(h->pr, closed_loop, h->b, h->stream);
+  return launch_finalize(h->pr, closed_loop, b, h->stream, closed_loop);
 }
 
 void fill_info(const DevResult& R, rg_step_info* info) {
@@ -455,7 +487,7 @@ int rg_create(const rg_plant* plant, const rg_scenarios* scen, const rg_constrai
 
 int rg_destroy(rg_handle* h) {
   if (!h) return RG_OK;
-  if (h->step_graph) (void)hipGraphExecDestroy(h->step_graph);
+  drop_graphs(h);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   if (h->ws_owned && h->ws) (void)hipFree(h->ws);
   delete h;
@@ -481,10 +513,7 @@ int rg_bind_workspace(rg_handle* h, void* device_ptr, size_t bytes) {
 
 int rg_set_stream(rg_handle* h, void* hip_stream) {
   if (!h) return RG_E_INVAL;
-  if (h->stream != (hipStream_t)hip_stream && h->step_graph) {
-    (void)hipGraphExecDestroy(h->step_graph);
-    h->step_graph = nullptr;
-  }
+  if (h->stream != (hipStream_t)hip_stream) drop_graphs(h);
   h->stream = (hipStream_t)hip_stream;
   return RG_OK;
 }
@@ -510,7 +539,7 @@ int rg_step(rg_handle* h, const double* x, double r, double v_prev, double* v_ou
   int rc = ensure_workspace(h);
   if (rc) return rc;
   if ((rc = upload_state(h, x, r, v_prev))) return rc;
-  hipError_t e = enqueue_step(h, 0);
+  hipError_t e = enqueue_step(h, 0, 0);
   if (e != hipSuccess) return fail_hip(h, "enqueue RG step", e);
   h->gen_t = (long long)h->t;
   DevResult R;
@@ -582,10 +611,11 @@ int rg_closed_loop(rg_handle* h, const double* x0, double v0, const double* r_se
   if ((rc = upload_state(h, x0, r_seq[0], v0))) return rc;
   if (x_out)
     for (int i = 0; i < n; ++i) x_out[i] = x0[i];
-  if (graph && !h->step_graph) {
+  for (int p = 0; graph && p < 2; ++p) {
+    if (h->step_graph[p]) continue;
     hipGraph_t g = nullptr;
     HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = enqueue_step(h, 1);
+    hipError_t e = enqueue_step(h, 1, p);
     hipError_t e2 = hipStreamEndCapture(h->stream, &g);
     if (e != hipSuccess) return fail_hip(h, "capture closed-loop step", e);
     if (e2 != hipSuccess) return fail_hip(h, "hipStreamEndCapture", e2);
@@ -593,21 +623,35 @@ int rg_closed_loop(rg_handle* h, const double* x0, double v0, const double* r_se
     e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail_hip(h, "hipGraphInstantiate", e);
-    h->step_graph = ge;
+    h->step_graph[p] = ge;
   }
   std::vector<DevResult> R;
   std::vector<double> xs;
   int32_t done = 0;
   while (done < T) {
     const int chunk = (T - done) < h->opt.max_T ? (T - done) : h->opt.max_T;
-    const int32_t zero = 0;
+    const int32_t cl[2] = {0, chunk};  // cl_index, cl_len
+    static_assert(offsetof(DevState, cl_len) == offsetof(DevState, cl_index) + sizeof(int32_t),
+                  "cl_index and cl_len are adjacent");
     HIPCHK(h, hipMemcpyAsync(h->b.r_seq, r_seq + done, sizeof(double) * chunk,
                              hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync((char*)h->b.st + offsetof(DevState, cl_index), &zero, sizeof(zero),
+    HIPCHK(h, hipMemcpyAsync((char*)h->b.st + offsetof(DevState, cl_index), cl, sizeof(cl),
                              hipMemcpyHostToDevice, h->stream));
+    // prologue of the chunk: draws (pair t & 1) and round 0 of its first step
+    const int p0 = (int)(h->t & 1u);
+    if (h->pr.s.rng_mode == RG_RNG_STREAM) {
+      DevBuffers b0 = h->b;
+      if (p0) {
+        b0.wbuf = h->b.wbuf2;
+        b0.thbuf = h->b.thbuf2;
+      }
+      HIPCHK(h, launch_gen(h->pr, b0, h->stream));
+    }
+    HIPCHK(h, launch_setup(h->pr, h->b, 1, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     for (int s = 0; s < chunk; ++s) {
-      hipError_t e = graph ? hipGraphLaunch(h->step_graph, h->stream) : enqueue_step(h, 1);
+      const int p = (int)((h->t + (uint32_t)s) & 1u);
+      hipError_t e = graph ? hipGraphLaunch(h->step_graph[p], h->stream) : enqueue_step(h, 1, p);
       if (e != hipSuccess) return fail_hip(h, "enqueue closed-loop step", e);
     }
     R.resize(chunk);
@@ -632,7 +676,7 @@ int rg_closed_loop(rg_handle* h, const double* x0, double v0, const double* r_se
     done += chunk;
     h->t += (uint32_t)chunk;
   }
-  h->gen_t = (long long)h->t - 1;
+  h->gen_t = -1;  // the single-step draw pair no longer holds a known step
   return RG_OK;
 }
 
@@ -704,10 +748,7 @@ int rg_set_theta(rg_handle* h, const double* theta_nom) {
   if (h->pr.p.nth == 0) return fail(h, RG_E_NOTSUP, "this plant has no uncertain coefficients");
   if (!theta_nom || !finite_array(theta_nom, h->pr.p.nth)) return fail(h, RG_E_INVAL, "bad theta");
   for (int c = 0; c < h->pr.p.nth; ++c) h->pr.p.coeffs[90 + c] = theta_nom[c];
-  if (h->step_graph) {  // kernel arguments changed
-    (void)hipGraphExecDestroy(h->step_graph);
-    h->step_graph = nullptr;
-  }
+  drop_graphs(h);  // kernel arguments changed
   return RG_OK;
 }
 
@@ -738,10 +779,7 @@ int apply_schedule(rg_handle* h, const rg_options& o) {
   h->opt.depth = o.depth;
   h->opt.predict = o.predict;
   plan(h);
-  if (h->step_graph) {
-    (void)hipGraphExecDestroy(h->step_graph);
-    h->step_graph = nullptr;
-  }
+  drop_graphs(h);
   if (h->ws_ready) {
     const int32_t depth = h->opt.depth;
     const int32_t predict = h->opt.search == RG_SEARCH_BISECT ? h->opt.predict : 0;

@@ -28,6 +28,7 @@ struct DevState {
   double r;             // r_t
   uint32_t t;           // RG step counter (selects the draws)
   int32_t cl_index;     // closed loop: index of the current step in the chunk
+  int32_t cl_len;       // closed loop: steps in the chunk
 };
 
 // Search state of one RG step.  Candidate c of the current round has set-point
@@ -121,6 +122,10 @@ struct DevBuffers {
   double* x_hist;          // [(max_T + 1) * n]
   float* wbuf;             // [H][nw][N] streamed draws
   float* thbuf;            // [nth][N] per-scenario coefficient factors
+  // second pair for the closed loop: step t reads pair t & 1 while its first
+  // round generates the draws of step t + 1 into the other pair
+  float* wbuf2;
+  float* thbuf2;
   int2* rlist;             // [cmax_round * N] recheck list (candidate, scenario)
   float* per_m;            // [cmax_round * N] per-scenario margins (rg_margin)
   int32_t* per_j;          // [cmax_round * N]
@@ -203,16 +208,21 @@ hipError_t launch_setup(const Problem& pr, const DevBuffers& b, int closed_loop,
 hipError_t launch_setup_list(const Problem& pr, const DevBuffers& b, int M, hipStream_t st);
 // ckpt_cand >= 0 (or -1 for the Newton iterate) keeps that candidate's
 // checkpoints every Kc steps for the segment derivative; -2 keeps none.
+// gen_w (non-null, streamed draws): the launch also generates the draws of
+// step t + 1 into gen_w / gen_th with workgroups of its own.
 hipError_t launch_rollout(const Problem& pr, double band, int precision, int early_exit, int record,
                           const LaunchCfg& cfg, const DevBuffers& b, hipStream_t st,
-                          int ckpt_cand = -2, int Kc = 0);
+                          int ckpt_cand = -2, int Kc = 0, float* gen_w = nullptr,
+                          float* gen_th = nullptr);
 // decide != 0: the last workgroup to finish also takes the round's decision
 // (the work of launch_decide), so no separate decision launch follows.
 hipError_t launch_recheck(const Problem& pr, int early_exit, const LaunchCfg& cfg,
                           const DevBuffers& b, hipStream_t st, int decide = 0);
 hipError_t launch_decide(const Problem& pr, const DevBuffers& b, hipStream_t st);
+// setup_next (closed loop): the same launch prepares round 0 of the next step
+// of the chunk, if there is one.
 hipError_t launch_finalize(const Problem& pr, int closed_loop, const DevBuffers& b,
-                           hipStream_t st);
+                           hipStream_t st, int setup_next = 0);
 hipError_t launch_collect(const DevBuffers& b, int M, double* out_dev, hipStream_t st);
 hipError_t launch_draws(const Problem& pr, uint32_t t, int k0, int nk, int j0, int nj,
                         float* w_dev, double* th_dev, const DevBuffers& b, hipStream_t st);

@@ -51,6 +51,11 @@ struct RollArgs {
   float* ckpt;
   int Kc;
   int ckpt_cand;  // that candidate (-1: the Newton iterate of the round)
+  // gen_row0 > 0: rows blockIdx.y >= gen_row0 of the launch generate the
+  // draws of step t + 1 into gen_w / gen_th instead of simulating
+  int gen_row0;
+  float* gen_w;
+  float* gen_th;
 };
 
 template <int KIND>
@@ -97,11 +102,10 @@ __device__ __forceinline__ void draw_theta_factor(uint32_t seed, uint32_t inst, 
 
 // Streamed draws: w[(j * nw + c) * N + k] (consecutive scenarios contiguous, so
 // a wave's loads of one step coalesce), theta factors f[c * N + k].
-template <int KIND>
-__device__ __forceinline__ void gen_body(const RollArgs<KIND, float>& a, float* wbuf, float* thbuf,
-                                         size_t gid) {
+template <int KIND, class A>
+__device__ __forceinline__ void gen_body(const A& a, float* wbuf, float* thbuf, size_t gid,
+                                         uint32_t t) {
   using P = Plant<KIND, float>;
-  const uint32_t t = a.st->t;
   const size_t nwork = (size_t)a.H * a.N;
   if (gid < nwork) {
     const int j = (int)(gid / a.N);
@@ -121,7 +125,22 @@ __device__ __forceinline__ void gen_body(const RollArgs<KIND, float>& a, float* 
 
 template <int KIND>
 __global__ void __launch_bounds__(256) k_gen(RollArgs<KIND, float> a, float* wbuf, float* thbuf) {
-  gen_body<KIND>(a, wbuf, thbuf, (size_t)blockIdx.x * blockDim.x + threadIdx.x);
+  gen_body<KIND>(a, wbuf, thbuf, (size_t)blockIdx.x * blockDim.x + threadIdx.x, a.st->t);
+}
+
+// Draw rows of a rollout launch: the draws of step t + 1 (grid-stride over
+// the rows' threads).  Returns true in those rows.
+template <int KIND, class A>
+__device__ __forceinline__ bool gen_rows(const A& a) {
+  if (a.gen_row0 <= 0 || (int)blockIdx.y < a.gen_row0) return false;
+  const size_t nth = (size_t)(gridDim.y - a.gen_row0) * gridDim.x * blockDim.x;
+  const size_t work = (size_t)a.H * a.N + (Plant<KIND, float>::nth > 0 ? (size_t)a.N : 0);
+  const uint32_t t1 = a.st->t + 1u;
+  for (size_t i = ((size_t)(blockIdx.y - a.gen_row0) * gridDim.x + blockIdx.x) * blockDim.x +
+                  threadIdx.x;
+       i < work; i += nth)
+    gen_body<KIND>(a, a.gen_w, a.gen_th, i, t1);
+  return true;
 }
 
 // Forward declarations: the recheck kernels end with the round's decision.
@@ -300,6 +319,7 @@ __device__ __forceinline__ bool refused_by_steady_state(int early, DevSearch* S,
 // + threadIdx.x = scenario.
 template <int KIND, class T, int RNG, int INJ, int CKPT>
 __global__ void __launch_bounds__(256) k_rollout(const RollArgs<KIND, T> a) {
+  if (gen_rows<KIND>(a)) return;
   DevSearch* S = a.srch;
   const int c = blockIdx.y;
   if (S->done || c >= S->n_cand) return;  // uniform over the workgroup
@@ -396,6 +416,7 @@ template <int RNG, int INJ, int RECORD, int CKPT>
 __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, float> a,
                                                          const QuadCoef qc) {
   constexpr int U = kQuadGroup;  // steps per group: one prefetch, one exit test per group
+  if (gen_rows<1>(a)) return;
   DevSearch* S = a.srch;
   const int c = blockIdx.y;
   if (S->done || c >= S->n_cand) return;  // uniform over the workgroup
@@ -493,21 +514,22 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
       }
       if (RNG == 0) so += (uint32_t)U * row_bytes;
     };
-    float wcur[2 * U], wnext[2 * U];
-    load_group(0, wcur);
+    // Two draw buffers in turn: a group of U steps runs on one while the next
+    // group's draws stream into the other.
+    float wa[2 * U], wb[2 * U];
+    load_group(0, wa);
     const int full = H / U;
     int g = 0;
     // One violation anywhere ends the candidate: the wave stops as soon as any
     // of its quads sees one and raises the dead flag at once; the flag is read
-    // at the start of every group and tested at its end.
-    for (; g < full; ++g) {
-      load_group((g + 1) * U, wnext);
+    // at the start of every group and tested at its end.  Returns true to stop.
+    auto run_group = [&](const float* wc, float* wn) -> bool {
+      load_group((g + 1) * U, wn);
       const int dead_seen =
           early ? __hip_atomic_load(&S->dead[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
 #pragma unroll
-      for (int u = 0; u < U; ++u) step(wcur[2 * u], wcur[2 * u + 1], g * U + u + 1);
-#pragma unroll
-      for (int u = 0; u < 2 * U; ++u) wcur[u] = wnext[u];
+      for (int u = 0; u < U; ++u) step(wc[2 * u], wc[2 * u + 1], g * U + u + 1);
+      ++g;
       if (early) {
         const float bg = RECORD ? best : quad_min(bq);
         const bool viol = bg < -a.band;
@@ -515,19 +537,33 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
           if (viol && q == 0)
             __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           stopped = true;
-          ++g;
-          break;
+          return true;
         }
         if (dead_seen) {
           stopped = true;
-          ++g;
-          break;
+          return true;
         }
       }
+      return false;
+    };
+    bool tail_in_b = false;  // which buffer holds the draws after the last full group
+    while (g < full) {
+      if (run_group(wa, wb)) break;
+      if (g == full) {
+        tail_in_b = true;
+        break;
+      }
+      if (run_group(wb, wa)) break;
     }
     ns = g * U;
     if (g == full && !stopped) {  // ragged tail of the horizon
-      for (int u = 0; u < H - full * U; ++u) step(wcur[2 * u], wcur[2 * u + 1], full * U + u + 1);
+      if (tail_in_b) {
+#pragma unroll
+        for (int u = 0; u < 2 * U; ++u) wa[u] = wb[u];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (u < H - full * U) step(wa[2 * u], wa[2 * u + 1], full * U + u + 1);
       ns = H;
     }
     if (!RECORD) best = quad_min(bq);
@@ -1184,16 +1220,16 @@ __global__ void __launch_bounds__(256) k_gen_setup(RollArgs<KIND, float> a, floa
     setup_body<KIND>(ctl.pc, ctl.st, ctl.srch, ctl.r_seq, ctl.closed_loop);
     return;
   }
-  gen_body<KIND>(a, wbuf, thbuf, (size_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x);
+  gen_body<KIND>(a, wbuf, thbuf, (size_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x, a.st->t);
 }
 
 // Result record; in closed loop also the true-plant step (Eq. (4)) in FP64
-// under the tag-2 disturbance, and the hand-over v_prev <- v_t.
+// under the tag-2 disturbance, and the hand-over v_prev <- v_t.  With
+// setup_next the launch then prepares round 0 of the chunk's next step.
 template <int KIND>
-__global__ void k_finalize(const RollArgs<KIND, double> a, DevResult* res, double* x_hist,
-                           int closed_loop) {
+__device__ void finalize_body(const RollArgs<KIND, double>& a, DevResult* res, double* x_hist,
+                              int closed_loop) {
   using P = Plant<KIND, double>;
-  if (threadIdx.x != 0) return;
   DevSearch* S = a.srch;
   DevState* st = const_cast<DevState*>(a.st);
   const int idx = closed_loop ? st->cl_index : 0;
@@ -1234,6 +1270,20 @@ __global__ void k_finalize(const RollArgs<KIND, double> a, DevResult* res, doubl
     st->cl_index = idx + 1;
   }
   st->t = st->t + 1;
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(64) k_finalize(const RollArgs<KIND, double> a, DevResult* res,
+                                                 double* x_hist, int closed_loop,
+                                                 const CtlArgs<KIND> ctl, int setup_next) {
+  __shared__ int s_next;
+  if (threadIdx.x == 0) {
+    finalize_body<KIND>(a, res, x_hist, closed_loop);
+    s_next = setup_next && a.st->cl_index < a.st->cl_len;
+  }
+  if (!setup_next) return;
+  __syncthreads();
+  if (s_next) setup_body<KIND>(ctl.pc, ctl.st, ctl.srch, ctl.r_seq, 1);
 }
 
 // rg_margin: worst margin of each listed candidate.
@@ -2145,15 +2195,31 @@ static bool quad_draws_addressable(const Problem& pr) {
 
 hipError_t launch_rollout(const Problem& pr, double band, int precision, int early_exit, int record,
                           const LaunchCfg& cfg, const DevBuffers& b, hipStream_t st, int ckpt_cand,
-                          int Kc) {
+                          int Kc, float* gen_w, float* gen_th) {
   const bool ckpt = ckpt_cand >= -1 && precision == 0;
+  const bool gen = gen_w != nullptr && pr.s.rng_mode == 0;
+  // rows of draw workgroups after the candidate rows: up to about 2^17 threads
+  auto gen_rows_for = [&](size_t row_threads) {
+    if (!gen) return 0;
+    size_t work = (size_t)pr.H * pr.s.N + (size_t)pr.s.N;
+    if (work > (size_t(1) << 17)) work = size_t(1) << 17;
+    return (int)((work + row_threads - 1) / row_threads);
+  };
+  auto set_gen = [&](auto& a) {
+    if (!gen) return;
+    a.gen_row0 = cfg.cmax_round;
+    a.gen_w = gen_w;
+    a.gen_th = gen_th;
+  };
   if (cfg.lanes == 4 && precision == 0 && pr.p.kind == 1 && quad_draws_addressable(pr)) {
-    const dim3 grid(div_up((size_t)pr.s.N * 4, (size_t)cfg.block), cfg.cmax_round);
+    const int gx = div_up((size_t)pr.s.N * 4, (size_t)cfg.block);
+    const dim3 grid(gx, cfg.cmax_round + gen_rows_for((size_t)gx * cfg.block));
     const QuadCoef qc = make_quad_coef(pr);
     auto a = make_args<1, float>(pr, band, early_exit, record, b);
     a.ckpt = b.adj_ckpt;
     a.Kc = Kc;
     a.ckpt_cand = ckpt_cand;
+    set_gen(a);
     return by_bit(pr.s.rng_mode, [&](auto rc) {
       constexpr int R = decltype(rc)::value;
       return by_bit(pr.s.inject, [&](auto ic) {
@@ -2169,7 +2235,8 @@ hipError_t launch_rollout(const Problem& pr, double band, int precision, int ear
       });
     });
   }
-  const dim3 grid(div_up((size_t)pr.s.N, (size_t)cfg.block), cfg.cmax_round);
+  const int gx = div_up((size_t)pr.s.N, (size_t)cfg.block);
+  const dim3 grid(gx, cfg.cmax_round + gen_rows_for((size_t)gx * cfg.block));
   return by_kind(pr.p.kind, [&](auto kc) {
     constexpr int K = decltype(kc)::value;
     return by_bit(pr.s.rng_mode, [&](auto rc) {
@@ -2181,12 +2248,14 @@ hipError_t launch_rollout(const Problem& pr, double band, int precision, int ear
           a.ckpt = b.adj_ckpt;
           a.Kc = Kc;
           a.ckpt_cand = ckpt_cand;
+          set_gen(a);
           if (ckpt)
             hipLaunchKernelGGL((k_rollout<K, float, R, I, 1>), grid, dim3(cfg.block), 0, st, a);
           else
             hipLaunchKernelGGL((k_rollout<K, float, R, I, 0>), grid, dim3(cfg.block), 0, st, a);
         } else {
           auto a = make_args<K, double>(pr, 0.0, early_exit, record, b);
+          set_gen(a);
           hipLaunchKernelGGL((k_rollout<K, double, R, I, 0>), grid, dim3(cfg.block), 0, st, a);
         }
         return hipGetLastError();
@@ -2268,11 +2337,12 @@ hipError_t launch_decide(const Problem& pr, const DevBuffers& b, hipStream_t st)
 }
 
 hipError_t launch_finalize(const Problem& pr, int closed_loop, const DevBuffers& b,
-                           hipStream_t st) {
+                           hipStream_t st, int setup_next) {
   return by_kind(pr.p.kind, [&](auto kc) {
     constexpr int K = decltype(kc)::value;
     auto a = make_args<K, double>(pr, 0.0, 0, 0, b);
-    hipLaunchKernelGGL(k_finalize<K>, dim3(1), dim3(64), 0, st, a, b.res, b.x_hist, closed_loop);
+    hipLaunchKernelGGL(k_finalize<K>, dim3(1), dim3(64), 0, st, a, b.res, b.x_hist, closed_loop,
+                       make_ctl<K>(pr, b, closed_loop), setup_next);
     return hipGetLastError();
   });
 }
