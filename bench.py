@@ -45,8 +45,8 @@ PEAK_FP32_NONPACKED_TFLOPS = 78.6
 # copy; valid only for the kernel sources they were taken on (SHA-1 of the device
 # sources below, concatenated in this order).
 KERNEL_SOURCES = ("rg_kernels.hip", "rg_device.hpp", "rg_internal.hpp")
-HBM_TRAFFIC = {"kernels_sha1": "8c1d66109b107b5a958b1b2360aa3f71b57e6dfd",
-               "bytes_per_launch": 14037258}
+HBM_TRAFFIC = {"kernels_sha1": "0486bdc6caca8cae7c5bec323f71d78de6a83668",
+               "bytes_per_launch": 30955904}
 
 
 def cpu_baseline(wl, r_seq, seconds):
