@@ -363,6 +363,35 @@ def test_fp64_recheck_decides_with_wide_band(R, O, rng_mode, inject):
         g.close()
 
 
+def test_probe_only_rounds_worst_margin_matches_oracle(R, O):
+    # From the second update on the previous kappa is 1, so each update's only
+    # round evaluates the kappa = 1 probe alone.  Steady-state test off: the
+    # reported worst margin is then the FP32 rollouts' minimum over scenarios
+    # and steps, compared with the FP64 oracle's at the same state.
+    p = W.lq4_problem(seed=24, N=300, H=250, dt=0.005, eps=0.01, ss_check=0)
+    r_seq = np.full(6, 0.6)
+    o = O.Oracle(p, nthreads=8)
+    g = _gov(R, p)
+    out = g.closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    g.close()
+    for s in range(1, len(r_seq)):
+        assert out["kappa"][s] == 1.0 and out["candidates"][s] == 1 and out["rounds"][s] == 1
+        ref = float(o.candidate(out["x"][s], 0.6, s)[1].min())
+        assert abs(out["worst"][s] - ref) <= TOL32 * max(1.0, abs(ref)), s
+
+
+def test_closed_loop_with_failing_probes_matches_oracle(R, O):
+    # reference switches: probe-only rounds that fail, then tree rounds
+    p = W.lq4_problem(seed=7, N=256, H=300, dt=0.005, eps=0.01)
+    r_seq = W.reference_sequence(11, 20, switch_every=5, lo=-2.5, hi=2.5)
+    a = _gov(R, p).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    o = O.Oracle(p, nthreads=8)
+    v_prev = 0.0
+    for s in range(len(r_seq)):
+        assert a["kappa"][s] == o.bisect(a["x"][s], r_seq[s], v_prev, s, 12)["kappa"], s
+        v_prev = a["v"][s]
+
+
 def test_prediction_keeps_sequential_bisection_result(R, O):
     # the first round speculates along the previous update's kappa: the closed
     # loop must give the same kappa with and without it, equal to the oracle's
