@@ -71,6 +71,14 @@ struct DevSearch {
   // Workgroups of the current recheck launch that have finished; the last one
   // takes the round's decision and resets the count.
   uint32_t blocks_done;
+  // Closed loop, probe-only round 0: candidate `spec` (>= 0) is the next
+  // step's kappa = 1 probe, simulated from x_spec, the state the next step
+  // starts in if this step's kappa is 1, under the next step's draws.
+  int32_t spec_on;                    // 1: allowed (set by the host)
+  int32_t spec;                       // that candidate this step (-1: none)
+  double r_spec;                      // the next step's reference
+  double x_spec[kMaxN];
+  double band;                        // FP32 recheck band (a speculative verdict must be outside it)
 };
 
 // Result record of one RG step.
@@ -122,10 +130,15 @@ struct DevBuffers {
   double* x_hist;          // [(max_T + 1) * n]
   float* wbuf;             // [H][nw][N] streamed draws
   float* thbuf;            // [nth][N] per-scenario coefficient factors
-  // second pair for the closed loop: step t reads pair t & 1 while its first
-  // round generates the draws of step t + 1 into the other pair
+  // further pairs for the closed loop: step t reads pair t % 3, the next
+  // step's speculative probe reads pair (t + 1) % 3, and the first round
+  // generates the draws of step t + 2 into pair (t + 2) % 3
   float* wbuf2;
   float* thbuf2;
+  float* wbuf3;             // third pair: with speculation step t also reads step t + 1's draws
+  float* thbuf3;
+  const float* wbuf_spec;   // draws of the next step (speculative probe), set per launch
+  const float* thbuf_spec;
   int2* rlist;             // [cmax_round * N] recheck list (candidate, scenario)
   float* per_m;            // [cmax_round * N] per-scenario margins (rg_margin)
   int32_t* per_j;          // [cmax_round * N]
@@ -201,7 +214,10 @@ struct Problem {
   double dt;
 };
 
-hipError_t launch_gen(const Problem& pr, const DevBuffers& b, hipStream_t st);
+// Draws of step t + t_ofs (t: the device step counter) into b.wbuf / b.thbuf.
+hipError_t launch_gen(const Problem& pr, const DevBuffers& b, hipStream_t st, uint32_t t_ofs = 0);
+// Whether launch_rollout runs the LQ4 quad kernel for this configuration.
+bool rollout_uses_quad(const Problem& pr, const LaunchCfg& cfg, int precision);
 // Draws plus the round-0 setup in one launch (workgroup 0 runs the setup).
 hipError_t launch_gen_setup(const Problem& pr, const DevBuffers& b, int closed_loop, hipStream_t st);
 hipError_t launch_setup(const Problem& pr, const DevBuffers& b, int closed_loop, hipStream_t st);

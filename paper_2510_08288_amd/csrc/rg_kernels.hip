@@ -54,8 +54,10 @@ struct RollArgs {
   // gen_row0 > 0: rows blockIdx.y >= gen_row0 of the launch generate the
   // draws of step t + 1 into gen_w / gen_th instead of simulating
   int gen_row0;
+  uint32_t gen_ofs;  // the draws generated are those of step t + gen_ofs
   float* gen_w;
   float* gen_th;
+  const float* wbuf_spec;  // draws of step t + 1 (the speculative probe, closed loop)
 };
 
 template <int KIND>
@@ -124,8 +126,9 @@ __device__ __forceinline__ void gen_body(const A& a, float* wbuf, float* thbuf, 
 }
 
 template <int KIND>
-__global__ void __launch_bounds__(256) k_gen(RollArgs<KIND, float> a, float* wbuf, float* thbuf) {
-  gen_body<KIND>(a, wbuf, thbuf, (size_t)blockIdx.x * blockDim.x + threadIdx.x, a.st->t);
+__global__ void __launch_bounds__(256) k_gen(RollArgs<KIND, float> a, float* wbuf, float* thbuf,
+                                             uint32_t t_ofs) {
+  gen_body<KIND>(a, wbuf, thbuf, (size_t)blockIdx.x * blockDim.x + threadIdx.x, a.st->t + t_ofs);
 }
 
 // Draw rows of a rollout launch: the draws of step t + 1 (grid-stride over
@@ -135,7 +138,7 @@ __device__ __forceinline__ bool gen_rows(const A& a) {
   if (a.gen_row0 <= 0 || (int)blockIdx.y < a.gen_row0) return false;
   const size_t nth = (size_t)(gridDim.y - a.gen_row0) * gridDim.x * blockDim.x;
   const size_t work = (size_t)a.H * a.N + (Plant<KIND, float>::nth > 0 ? (size_t)a.N : 0);
-  const uint32_t t1 = a.st->t + 1u;
+  const uint32_t t1 = a.st->t + a.gen_ofs;
   for (size_t i = ((size_t)(blockIdx.y - a.gen_row0) * gridDim.x + blockIdx.x) * blockDim.x +
                   threadIdx.x;
        i < work; i += nth)
@@ -149,6 +152,9 @@ __device__ void decide_body(const typename Plant<KIND, double>::Coef& pc, const 
                             DevSearch* S, const DevGrad* grad);
 template <int KIND>
 __device__ void last_block_decides(const CtlArgs<KIND>& ctl);
+template <int KIND>
+__device__ void true_plant_step(const RollArgs<KIND, double>& a, const double* x_in, double v,
+                                uint32_t t, double* x_out);
 
 // ---------------------------------------------------------------------------
 // One scenario rollout with the fused running-minimum margin.
@@ -426,7 +432,10 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
   __shared__ unsigned long long sh[16];
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = gid >> 2, q = gid & 3;
-  const uint32_t t = a.st->t;
+  // the next step's speculative probe: its own start state and draws
+  const bool spec = c == S->spec;
+  const uint32_t t = a.st->t + (spec ? 1u : 0u);
+  const float* wsrc = spec ? a.wbuf_spec : a.wbuf;
   float best = INFINITY;
   int jb = 0, ns = 0;
   bool stopped = false;  // the candidate died while this wave ran (no recheck needed)
@@ -439,7 +448,7 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
     const float bv = qc.b[q] * (float)S->v[c];
     const float h = a.h, hh = a.hh, h6 = a.h6;
     const int H = a.H;
-    float x = (float)a.st->x[q];
+    float x = (float)(spec ? S->x_spec[q] : a.st->x[q]);
     // lane q: margin of constraint row q (g_q - (F C x)_q); padding rows are +inf
     auto row_margin = [&](float xv) {
       const float c2 = d2 * xv, c3 = d3 * xv;
@@ -496,7 +505,7 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
     const uint32_t row_bytes = 8u * (uint32_t)a.N;  // one step: n_w = 2 floats x N
     const uint32_t vo0 = 4u * (uint32_t)k, vo1 = vo0 + 4u * (uint32_t)a.N;
     const __amdgpu_buffer_rsrc_t wres = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)a.wbuf, (short)0, (int)(row_bytes * (uint32_t)(H + U)), 0x00020000);
+        (void*)wsrc, (short)0, (int)(row_bytes * (uint32_t)(H + U)), 0x00020000);
     uint32_t so = 0;  // byte offset of the next group's first row
     auto load_group = [&](int j, float* w) {
 #pragma unroll
@@ -581,7 +590,7 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
     }
     if (best < -a.band) {
       __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else if (best < a.band && !stopped) {
+    } else if (best < a.band && !stopped && !spec) {  // a speculative probe is never rechecked
       const int idx = atomicAdd(&S->n_recheck, 1);
       a.rlist[idx] = make_int2(c, k);
     }
@@ -932,7 +941,7 @@ __device__ void prepare_candidates(const typename Plant<KIND, double>::Coef& pc,
   const double r = st->r, vp = st->v_prev;
   for (int c = threadIdx.x; c < S->n_cand; c += blockDim.x) {
     if (S->mode != kNewton) S->full[c] = 0;
-    const double v = cand_v(S->kappa[c], r, vp);
+    const double v = c == S->spec ? S->r_spec : cand_v(S->kappa[c], r, vp);
     S->v[c] = v;
     S->mss[c] = steady_margin<KIND>(pc, S, v);
     S->key_all[c] = ~0ull;
@@ -947,9 +956,29 @@ __device__ void prepare_candidates(const typename Plant<KIND, double>::Coef& pc,
 // Start of one RG step: round-0 candidates.
 template <int KIND>
 __device__ void setup_body(const typename Plant<KIND, double>::Coef& pc, DevState* st,
-                           DevSearch* S, const double* r_seq, int closed_loop) {
+                           DevSearch* S, const double* r_seq, int closed_loop,
+                           const RollArgs<KIND, double>* pa = nullptr) {
   if (threadIdx.x == 0) {
     if (closed_loop) st->r = r_seq[st->cl_index];
+    // Was this step's kappa = 1 probe already evaluated by the previous step
+    // (speculatively, from the state this step starts in when the previous
+    // kappa is 1)?  Its verdict counts only if the previous kappa was 1 and
+    // every scenario of the probe kept an FP32 margin of at least the band
+    // (no FP64 recheck needed); Alg. 1 then returns kappa = 1 on its first
+    // evaluation.
+    bool decided = false;
+    double spec_worst = 0.0;
+    if (closed_loop && S->spec >= 0) {
+      const int c = S->spec;
+      const double kall =
+          S->key_all[c] == ~0ull ? INFINITY : key_margin(S->key_all[c], S->precision);
+      if (S->done && S->kappa_res == 1.0 && !S->dead[c] && !S->fail64[c] && S->mss[c] >= 0.0 &&
+          kall >= S->band) {
+        decided = true;
+        spec_worst = kall < S->mss[c] ? kall : S->mss[c];
+      }
+    }
+    S->spec = -1;
     S->done = 0;
     S->found = 0;
     S->status = 0;
@@ -966,7 +995,17 @@ __device__ void setup_body(const typename Plant<KIND, double>::Coef& pc, DevStat
     S->passes_alg1 = 0;
     S->lane_steps = 0ull;
     S->fallbacks = 0;
-    if (S->mode == kNewton) {
+    if (decided) {
+      S->done = 1;
+      S->found = 1;
+      S->lo = 1.0;
+      S->kappa_res = 1.0;
+      S->pred = 1.0;
+      S->v_res = st->r;  // cand_v at kappa = 1
+      S->worst_res = spec_worst;
+      S->passes_alg1 = 1;
+      S->n_cand = 0;
+    } else if (S->mode == kNewton) {
       S->kappa[0] = 1.0;  // probe, carries the first derivative
       S->kappa[1] = 0.5;
       S->full[0] = 1;
@@ -996,6 +1035,17 @@ __device__ void setup_body(const typename Plant<KIND, double>::Coef& pc, DevStat
         S->tree_depth = 0;
         if (pr >= 1.0) {
           S->n_cand = 1;
+          // The probe alone fills few SIMDs: the round also runs the next
+          // step's probe, from the state the next step starts in if this
+          // step's kappa is 1 (the same FP64 true-plant step as the result
+          // launch), under the next step's draws.
+          if (pa && S->spec_on && closed_loop && st->cl_index + 1 < st->cl_len) {
+            true_plant_step<KIND>(*pa, st->x, st->r, st->t, S->x_spec);
+            S->r_spec = r_seq[st->cl_index + 1];
+            S->kappa[1] = -1.0;  // equals no midpoint: the walk never reads it
+            S->spec = 1;
+            S->n_cand = 2;
+          }
         } else {
           double lo = 0.0, hi = 1.0;
           for (int l = 0; l < S->K; ++l) {
@@ -1174,6 +1224,7 @@ __device__ void decide_body(const typename Plant<KIND, double>::Coef& pc, const 
       const int rem = S->goal - S->halvings;
       const int d = rem < S->depth ? rem : S->depth;
       S->probe = 0;
+      S->spec = -1;  // its slot is reused; this step's kappa is below 1 anyway
       build_tree(S, 0, d, S->lo, S->hi);
       S->n_cand = (1 << d) - 1;
       S->round += 1;
@@ -1226,6 +1277,31 @@ __global__ void __launch_bounds__(256) k_gen_setup(RollArgs<KIND, float> a, floa
 // Result record; in closed loop also the true-plant step (Eq. (4)) in FP64
 // under the tag-2 disturbance, and the hand-over v_prev <- v_t.  With
 // setup_next the launch then prepares round 0 of the chunk's next step.
+// True-plant step of the closed loop in FP64 (Eq. (4)) from x under set-point
+// v and the tag-2 disturbance of step t.
+template <int KIND>
+__device__ void true_plant_step(const RollArgs<KIND, double>& a, const double* x_in, double v,
+                                uint32_t t, double* x_out) {
+  using P = Plant<KIND, double>;
+  float w32[P::nw];
+  draw_w<P::nw>(a.seed, a.inst, t, 2u, 0u, 0u, a.wlo, a.wspan, w32);
+  double w[P::nw];
+  for (int c = 0; c < P::nw; ++c) w[c] = (double)w32[c];
+  typename P::Lane L;
+  P::lane_init(a.pc, P::nominal_theta(a.pc), v, L);
+  double x[P::n], s[P::n];
+  for (int i = 0; i < P::n; ++i) x[i] = x_in[i];
+  if (a.inject == 0) {
+    P::force(a.pc, L, w, s);
+    rk4_step<KIND, double>(a.pc, L, s, a.h, a.hh, a.h6, x);
+  } else {
+    P::force0(a.pc, L, s);
+    rk4_step<KIND, double>(a.pc, L, s, a.h, a.hh, a.h6, x);
+    P::post(a.pc, w, x);
+  }
+  for (int i = 0; i < P::n; ++i) x_out[i] = x[i];
+}
+
 template <int KIND>
 __device__ void finalize_body(const RollArgs<KIND, double>& a, DevResult* res, double* x_hist,
                               int closed_loop) {
@@ -1246,22 +1322,8 @@ __device__ void finalize_body(const RollArgs<KIND, double>& a, DevResult* res, d
   R.lane_steps = S->lane_steps;
   res[idx] = R;
   if (closed_loop) {
-    float w32[P::nw];
-    draw_w<P::nw>(a.seed, a.inst, st->t, 2u, 0u, 0u, a.wlo, a.wspan, w32);
-    double w[P::nw];
-    for (int c = 0; c < P::nw; ++c) w[c] = (double)w32[c];
-    typename P::Lane L;
-    P::lane_init(a.pc, P::nominal_theta(a.pc), R.v, L);
-    double x[P::n], s[P::n];
-    for (int i = 0; i < P::n; ++i) x[i] = st->x[i];
-    if (a.inject == 0) {
-      P::force(a.pc, L, w, s);
-      rk4_step<KIND, double>(a.pc, L, s, a.h, a.hh, a.h6, x);
-    } else {
-      P::force0(a.pc, L, s);
-      rk4_step<KIND, double>(a.pc, L, s, a.h, a.hh, a.h6, x);
-      P::post(a.pc, w, x);
-    }
+    double x[P::n];
+    true_plant_step<KIND>(a, st->x, R.v, st->t, x);
     for (int i = 0; i < P::n; ++i) {
       st->x[i] = x[i];
       x_hist[(size_t)(idx + 1) * P::n + i] = x[i];
@@ -1283,7 +1345,7 @@ __global__ void __launch_bounds__(64) k_finalize(const RollArgs<KIND, double> a,
   }
   if (!setup_next) return;
   __syncthreads();
-  if (s_next) setup_body<KIND>(ctl.pc, ctl.st, ctl.srch, ctl.r_seq, 1);
+  if (s_next) setup_body<KIND>(ctl.pc, ctl.st, ctl.srch, ctl.r_seq, 1, &a);
 }
 
 // rg_margin: worst margin of each listed candidate.
@@ -2082,6 +2144,7 @@ static RollArgs<KIND, T> make_args(const Problem& pr, double band, int early, in
   a.thspan = (float)(2.0 * pr.s.theta_rel);
   a.wbuf = b.wbuf;
   a.thbuf = b.thbuf;
+  a.wbuf_spec = b.wbuf_spec;
   a.st = b.st;
   a.srch = b.srch;
   a.per_m = b.per_m;
@@ -2119,12 +2182,13 @@ static hipError_t by_bit(int v, F&& f) {
 
 static int div_up(size_t a, size_t b) { return (int)((a + b - 1) / b); }
 
-hipError_t launch_gen(const Problem& pr, const DevBuffers& b, hipStream_t st) {
+hipError_t launch_gen(const Problem& pr, const DevBuffers& b, hipStream_t st, uint32_t t_ofs) {
   return by_kind(pr.p.kind, [&](auto kc) {
     constexpr int K = decltype(kc)::value;
     auto a = make_args<K, float>(pr, 0.0, 0, 0, b);
     const size_t work = (size_t)pr.H * pr.s.N + (Plant<K, float>::nth > 0 ? pr.s.N : 0);
-    hipLaunchKernelGGL(k_gen<K>, dim3(div_up(work, 256)), dim3(256), 0, st, a, b.wbuf, b.thbuf);
+    hipLaunchKernelGGL(k_gen<K>, dim3(div_up(work, 256)), dim3(256), 0, st, a, b.wbuf, b.thbuf,
+                       t_ofs);
     return hipGetLastError();
   });
 }
@@ -2193,6 +2257,10 @@ static bool quad_draws_addressable(const Problem& pr) {
   return pr.s.rng_mode != 0 || bytes < 4294967296.0;  // rng_mode 1: inline draws
 }
 
+bool rollout_uses_quad(const Problem& pr, const LaunchCfg& cfg, int precision) {
+  return cfg.lanes == 4 && precision == 0 && pr.p.kind == 1 && quad_draws_addressable(pr);
+}
+
 hipError_t launch_rollout(const Problem& pr, double band, int precision, int early_exit, int record,
                           const LaunchCfg& cfg, const DevBuffers& b, hipStream_t st, int ckpt_cand,
                           int Kc, float* gen_w, float* gen_th) {
@@ -2208,6 +2276,7 @@ hipError_t launch_rollout(const Problem& pr, double band, int precision, int ear
   auto set_gen = [&](auto& a) {
     if (!gen) return;
     a.gen_row0 = cfg.cmax_round;
+    a.gen_ofs = 2;
     a.gen_w = gen_w;
     a.gen_th = gen_th;
   };

@@ -61,7 +61,8 @@ class rg_options(C.Structure):
                 ("search", C.c_int32), ("depth", C.c_int32), ("M", C.c_int32),
                 ("refine", C.c_int32), ("early_exit", C.c_int32), ("block", C.c_int32),
                 ("max_T", C.c_int32), ("lanes", C.c_int32), ("Kc", C.c_int32),
-                ("persistent_wgs", C.c_int32), ("predict", C.c_int32)]
+                ("persistent_wgs", C.c_int32), ("predict", C.c_int32),
+                ("speculate", C.c_int32)]
 
 
 class rg_instance_desc(C.Structure):
@@ -167,7 +168,7 @@ class Governor:
                  K: int = 12, search: int = SEARCH_BISECT, depth: int = 0, M: int = 64,
                  refine: int = 6, early_exit: bool = True, block: int = 0, max_T: int = 256,
                  rng_mode: int = RNG_STREAM, lanes: int = 0, Kc: int = 50,
-                 predict: bool = True, torch_workspace: bool = True):
+                 predict: bool = True, speculate: bool = True, torch_workspace: bool = True):
         import torch
         self.L = load_library()
         self.problem = problem
@@ -189,6 +190,7 @@ class Governor:
         opt.early_exit, opt.block, opt.max_T, opt.lanes = int(early_exit), block, max_T, lanes
         opt.Kc = Kc
         opt.predict = int(predict)
+        opt.speculate = int(speculate)
         h = _vp()
         rc = self.L.rg_create(C.byref(plant), C.byref(scen), C.byref(cons), int(p.H), float(p.dt),
                               C.byref(opt), C.byref(h))
@@ -290,7 +292,7 @@ class Governor:
         self.options = rg_options()
         self.L.rg_get_options(self.h, C.byref(self.options))
         return dict(lanes=best.lanes, block=best.block, depth=best.depth, predict=best.predict,
-                    ms_per_update=ms.value)
+                    speculate=best.speculate, ms_per_update=ms.value)
 
     def equilibrium(self, v: float) -> np.ndarray:
         x = np.zeros(self.problem.n)
