@@ -241,7 +241,7 @@ def main():
             raise SystemExit(f"autotuner failed (exit {child.returncode})")
         tuned = json.loads(child.stdout.strip().splitlines()[-1])
         sched = dict(depth=tuned["depth"], lanes=tuned["lanes"], block=tuned["block"],
-                     predict=bool(tuned["predict"]), speculate=bool(tuned["speculate"]))
+                     predict=bool(tuned["predict"]), speculate=int(tuned["speculate"]))
     g = rg.Governor(p, precision=prec, band=wl["band"], K=wl["K"], max_T=max(256, T), **sched)
 
     # warmup: the first W updates of the workload (untimed)
@@ -333,7 +333,7 @@ def main():
                    "lanes_per_scenario": g.options.lanes,
                    "workgroup": g.options.block if g.options.block else 256,
                    "first_round_prediction": bool(g.options.predict),
-                   "next_step_speculation": bool(g.options.speculate),
+                   "speculation_depth": int(g.options.speculate),
                    "schedule": ("autotuned on the first %d updates" % args.tune_steps
                                 if tuned else "library default or command line"),
                    "launch": "one captured HIP graph per RG update, replayed"},

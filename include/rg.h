@@ -143,12 +143,13 @@ typedef struct rg_options {
                               candidates are evaluated early changes: the result is that of
                               sequential bisection either way.  0: tree from round 0. */
     int32_t speculate;     /* closed loop, bisection with prediction, FP32 LQ4 rollouts on 4 lanes
-                              per scenario, streamed draws: 1 (default) lets a round that runs the
-                              kappa = 1 probe alone also run the next step's probe, from the state
-                              the next step starts in if this step's kappa is 1.  When that holds
-                              and every scenario of the next probe keeps a margin of at least the
-                              band, the next step is decided (kappa = 1) without a round of its
-                              own.  The results are those of sequential bisection either way. */
+                              per scenario, streamed draws: s in 0..3 (default 3) lets a round
+                              that runs the kappa = 1 probe alone also run the probes of the next
+                              s steps, step t + j from the state it starts in if steps t..t+j-1
+                              all have kappa = 1.  When that holds and every scenario of step
+                              t + j's probe keeps a margin of at least the band, step t + j is
+                              decided (kappa = 1) without a round of its own.  The results are
+                              those of sequential bisection either way.  0: off. */
 } rg_options;
 
 typedef struct rg_step_info {
@@ -255,8 +256,8 @@ int rg_get_options(const rg_handle* h, rg_options* out);
  * handle's step counter, which is restored afterwards) once per candidate
  * schedule and times it: lanes per scenario (1 or 4, LQ4 FP32 only), rollout
  * workgroup (128 or 256 threads), device search depth (2..5; 1..3 for the grid
- * refinement), first-round prediction (on/off, bisection only) and next-step
- * speculation (on/off, with prediction and 4 lanes).  Schedules
+ * refinement), first-round prediction (on/off, bisection only) and the
+ * speculation depth (3, 1, 0; with prediction and 4 lanes).  Schedules
  * change only which candidates run when, so every one must give the same kappa
  * sequence; a mismatch returns RG_E_STATE.  best_out (nullable) receives the
  * fastest schedule's options, best_ms_out (nullable) its time per update; with

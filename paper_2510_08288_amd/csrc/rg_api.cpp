@@ -34,7 +34,7 @@ struct rg_handle {
   long long gen_t = -1;  // RG step whose draws are in the streamed buffer
   std::string err;
   // one captured closed-loop RG step per draw-buffer parity, replayed per step
-  hipGraphExec_t step_graph[3] = {nullptr, nullptr, nullptr};
+  hipGraphExec_t step_graph[kPairs] = {};
   // profiling
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -63,12 +63,13 @@ int fail_hip(rg_handle* h, const char* what, hipError_t e) {
     if (e_ != hipSuccess) return fail_hip(h, #call, e_); \
   } while (0)
 
-// Whether a probe-only round may also run the next step's probe (closed loop,
+// How many later steps' probes a probe-only round may also run (closed loop,
 // bisection with first-round prediction, FP32 quad rollouts on streamed draws).
 int32_t spec_allowed(const rg_handle* h) {
-  return h->opt.speculate && h->opt.search == RG_SEARCH_BISECT && h->opt.predict &&
-         h->pr.s.rng_mode == RG_RNG_STREAM &&
-         rollout_uses_quad(h->pr, h->cfg, h->opt.precision);
+  const bool ok = h->opt.search == RG_SEARCH_BISECT && h->opt.predict &&
+                  h->pr.s.rng_mode == RG_RNG_STREAM &&
+                  rollout_uses_quad(h->pr, h->cfg, h->opt.precision);
+  return ok ? h->opt.speculate : 0;
 }
 
 void drop_graphs(rg_handle* h) {
@@ -88,8 +89,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace layout: offsets of each buffer inside one allocation.
 struct Layout {
-  size_t st, srch, res, r_seq, x_hist, wbuf, thbuf, wbuf2, thbuf2, wbuf3, thbuf3, rlist, per_m, per_j,
-      scratch;
+  size_t st, srch, res, r_seq, x_hist, wpair[kPairs], thpair[kPairs], rlist, per_m, per_j, scratch;
   size_t grad, adj_k, adj_w, adj_m, adj_dv, adj_dth, adj_ckpt, adj_seg;
   size_t seg_m, seg_j, seg_r, seg_x, seg_a, seg_cv, seg_ct, seg_scr, total;
 };
@@ -113,12 +113,10 @@ Layout layout_of(const rg_handle* h) {
   const size_t wbytes =
       pr.s.rng_mode == RG_RNG_STREAM ? sizeof(float) * (size_t)(pr.H + kQuadGroup) * pr.p.nw * N : 0;
   const size_t thbytes = pr.s.rng_mode == RG_RNG_STREAM ? sizeof(float) * (size_t)pr.p.nth * N : 0;
-  L.wbuf = take(wbytes);
-  L.thbuf = take(thbytes);
-  L.wbuf2 = take(wbytes);
-  L.thbuf2 = take(thbytes);
-  L.wbuf3 = take(wbytes);
-  L.thbuf3 = take(thbytes);
+  for (int i = 0; i < kPairs; ++i) {
+    L.wpair[i] = take(wbytes);
+    L.thpair[i] = take(thbytes);
+  }
   L.rlist = take(sizeof(int2) * (size_t)kCMax * N);
   L.per_m = take(sizeof(float) * (size_t)kCMax * N);
   L.per_j = take(sizeof(int32_t) * (size_t)kCMax * N);
@@ -212,14 +210,13 @@ int ensure_workspace(rg_handle* h) {
   b.res = (DevResult*)(base + L.res);
   b.r_seq = (double*)(base + L.r_seq);
   b.x_hist = (double*)(base + L.x_hist);
-  b.wbuf = (float*)(base + L.wbuf);
-  b.thbuf = (float*)(base + L.thbuf);
-  b.wbuf2 = (float*)(base + L.wbuf2);
-  b.thbuf2 = (float*)(base + L.thbuf2);
-  b.wbuf3 = (float*)(base + L.wbuf3);
-  b.thbuf3 = (float*)(base + L.thbuf3);
-  b.wbuf_spec = nullptr;
-  b.thbuf_spec = nullptr;
+  for (int i = 0; i < kPairs; ++i) {
+    b.wpair[i] = (float*)(base + L.wpair[i]);
+    b.thpair[i] = (float*)(base + L.thpair[i]);
+  }
+  b.wbuf = b.wpair[0];  // single steps, rg_margin, rg_grad, rg_draws
+  b.thbuf = b.thpair[0];
+  for (int j = 0; j < kSpecMax; ++j) b.wbuf_spec[j] = nullptr;
   b.rlist = (int2*)(base + L.rlist);
   b.per_m = (float*)(base + L.per_m);
   b.per_j = (int32_t*)(base + L.per_j);
@@ -262,8 +259,9 @@ int ensure_workspace(rg_handle* h) {
   for (int r = 0; r < kNC; ++r) S->g[r] = h->pr.c.g[r];
   for (int i = 0; i < kNC * kMaxY; ++i) S->F[i] = h->pr.c.F[i];
   S->done = 1;
-  S->spec = -1;
-  S->spec_on = spec_allowed(h);
+  S->spec_depth = spec_allowed(h);
+  S->spec_n = 0;
+  S->spec_used = 0;
   S->band = h->opt.band;
   hipError_t e = hipMemcpyAsync(b.srch, S, sizeof(DevSearch), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -320,18 +318,18 @@ hipError_t harvest_events(rg_handle* h) {
   return hipSuccess;
 }
 
-// Draw pair i of the closed loop (i = step % 3).
+// Draw pair i of the closed loop (step s uses pair s % kPairs).
 void draw_pair(const rg_handle* h, int i, float** w, float** th) {
-  *w = i == 0 ? h->b.wbuf : i == 1 ? h->b.wbuf2 : h->b.wbuf3;
-  *th = i == 0 ? h->b.thbuf : i == 1 ? h->b.thbuf2 : h->b.thbuf3;
+  *w = h->b.wpair[i % kPairs];
+  *th = h->b.thpair[i % kPairs];
 }
 
 // Enqueue one RG step: draws, round-0 setup, the rounds, the result record.
-// In closed loop (phase = t % 3) the draws of steps t and t + 1 and the
-// round-0 setup of step t were made by earlier steps or the chunk's prologue:
-// the step reads draw pair `phase` (the next step's speculative probe reads
-// pair phase + 1), its first round generates the draws of step t + 2 into
-// pair phase + 2, and its result launch prepares round 0 of step t + 1.
+// In closed loop (phase = t % kPairs) the draws of steps t..t + kSpecMax and
+// the round-0 setup of step t were made by earlier steps or the chunk's
+// prologue: the step reads draw pair `phase` (the speculative probe of step
+// t + j reads pair phase + j), its first round generates the draws of step
+// t + kSpecMax + 1, and its result launch prepares round 0 of step t + 1.
 hipError_t enqueue_step(rg_handle* h, int closed_loop, int phase) {
   hipError_t e;
   const int prec = h->opt.precision;
@@ -341,12 +339,13 @@ hipError_t enqueue_step(rg_handle* h, int closed_loop, int phase) {
   float *gen_w = nullptr, *gen_th = nullptr;
   if (closed_loop) {
     if (streamed) {
-      float *sw, *sth;
-      draw_pair(h, phase % 3, &b.wbuf, &b.thbuf);
-      draw_pair(h, (phase + 1) % 3, &sw, &sth);
-      b.wbuf_spec = sw;
-      b.thbuf_spec = sth;
-      draw_pair(h, (phase + 2) % 3, &gen_w, &gen_th);
+      draw_pair(h, phase, &b.wbuf, &b.thbuf);
+      for (int j = 0; j < kSpecMax; ++j) {
+        float *sw, *sth;
+        draw_pair(h, phase + 1 + j, &sw, &sth);
+        b.wbuf_spec[j] = sw;
+      }
+      draw_pair(h, phase + kSpecMax + 1, &gen_w, &gen_th);
     }
   } else {
     // draws and round-0 setup share a launch in stream mode
@@ -417,7 +416,7 @@ int rg_default_options(rg_options* opt) {
   opt->Kc = 50;
   opt->persistent_wgs = 0;
   opt->predict = 1;
-  opt->speculate = 1;
+  opt->speculate = kSpecMax;
   return RG_OK;
 }
 
@@ -485,8 +484,8 @@ int rg_create(const rg_plant* plant, const rg_scenarios* scen, const rg_constrai
   if (o.lanes != 0 && o.lanes != 1 && o.lanes != 4) return fail(nullptr, RG_E_INVAL, "lanes must be 0, 1 or 4");
   if (o.Kc < 1 || o.Kc > 4096) return fail(nullptr, RG_E_INVAL, "Kc must be in [1, 4096]");
   if (o.predict != 0 && o.predict != 1) return fail(nullptr, RG_E_INVAL, "predict must be 0 or 1");
-  if (o.speculate != 0 && o.speculate != 1)
-    return fail(nullptr, RG_E_INVAL, "speculate must be 0 or 1");
+  if (o.speculate < 0 || o.speculate > kSpecMax)
+    return fail(nullptr, RG_E_INVAL, "speculate must be 0.." + std::to_string(kSpecMax));
 
   rg_handle* h = new (std::nothrow) rg_handle;
   if (!h) return fail(nullptr, RG_E_NOMEM, "host allocation");
@@ -639,7 +638,7 @@ int rg_closed_loop(rg_handle* h, const double* x0, double v0, const double* r_se
   if ((rc = upload_state(h, x0, r_seq[0], v0))) return rc;
   if (x_out)
     for (int i = 0; i < n; ++i) x_out[i] = x0[i];
-  for (int p = 0; graph && p < 3; ++p) {
+  for (int p = 0; graph && p < kPairs; ++p) {
     if (h->step_graph[p]) continue;
     hipGraph_t g = nullptr;
     HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
@@ -665,19 +664,19 @@ int rg_closed_loop(rg_handle* h, const double* x0, double v0, const double* r_se
                              hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync((char*)h->b.st + offsetof(DevState, cl_index), cl, sizeof(cl),
                              hipMemcpyHostToDevice, h->stream));
-    // prologue of the chunk: draws of its first two steps (pairs t % 3 and
-    // (t + 1) % 3) and round 0 of its first step
+    // prologue of the chunk: draws of its first kSpecMax + 1 steps and round 0
+    // of its first step
     if (h->pr.s.rng_mode == RG_RNG_STREAM) {
-      for (uint32_t d = 0; d < 2; ++d) {
+      for (uint32_t d = 0; d <= (uint32_t)kSpecMax; ++d) {
         DevBuffers bd = h->b;
-        draw_pair(h, (int)((h->t + d) % 3u), &bd.wbuf, &bd.thbuf);
+        draw_pair(h, (int)((h->t + d) % (uint32_t)kPairs), &bd.wbuf, &bd.thbuf);
         HIPCHK(h, launch_gen(h->pr, bd, h->stream, d));
       }
     }
     HIPCHK(h, launch_setup(h->pr, h->b, 1, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     for (int s = 0; s < chunk; ++s) {
-      const int p = (int)((h->t + (uint32_t)s) % 3u);
+      const int p = (int)((h->t + (uint32_t)s) % (uint32_t)kPairs);
       hipError_t e = graph ? hipGraphLaunch(h->step_graph[p], h->stream) : enqueue_step(h, 1, p);
       if (e != hipSuccess) return fail_hip(h, "enqueue closed-loop step", e);
     }
@@ -809,10 +808,10 @@ int apply_schedule(rg_handle* h, const rg_options& o) {
   plan(h);
   drop_graphs(h);
   if (h->ws_ready) {
-    const int32_t spec[2] = {spec_allowed(h), -1};  // spec_on, spec
-    static_assert(offsetof(DevSearch, spec) == offsetof(DevSearch, spec_on) + sizeof(int32_t),
-                  "spec_on and spec are adjacent");
-    HIPCHK(h, hipMemcpyAsync((char*)h->b.srch + offsetof(DevSearch, spec_on), spec, sizeof(spec),
+    const int32_t spec[3] = {spec_allowed(h), 0, 0};  // spec_depth, spec_n, spec_used
+    static_assert(offsetof(DevSearch, spec_used) == offsetof(DevSearch, spec_depth) + 8,
+                  "spec_depth, spec_n and spec_used are adjacent");
+    HIPCHK(h, hipMemcpyAsync((char*)h->b.srch + offsetof(DevSearch, spec_depth), spec, sizeof(spec),
                              hipMemcpyHostToDevice, h->stream));
     const int32_t depth = h->opt.depth;
     const int32_t predict = h->opt.search == RG_SEARCH_BISECT ? h->opt.predict : 0;
@@ -852,7 +851,7 @@ int rg_autotune(rg_handle* h, const double* x0, double v0, const double* r_seq, 
         for (int predict : {1, 0}) {
           if (predict && h->opt.search != RG_SEARCH_BISECT) continue;
           if (h->opt.search == RG_SEARCH_NEWTON && depth != dlo) continue;  // depth unused
-          for (int speculate : {1, 0}) {
+          for (int speculate : {kSpecMax, 1, 0}) {
             if (speculate && !(predict && lanes == 4)) continue;
             rg_options o = own;
             o.lanes = lanes;

@@ -22,6 +22,11 @@ enum Mode { kBisect = 0, kGrid = 1, kNewton = 2 };
 
 // Per-handle control state kept in device memory so that whole RG steps (and
 // closed loops) can be enqueued or graph-captured without host round trips.
+// Closed-loop speculation: a probe-only round may also run the kappa = 1
+// probes of up to kSpecMax later steps; draws are kept for kPairs steps.
+constexpr int kSpecMax = 3;
+constexpr int kPairs = kSpecMax + 2;
+
 struct DevState {
   double x[kMaxN];      // x_t
   double v_prev;        // v_{t-1}
@@ -71,13 +76,15 @@ struct DevSearch {
   // Workgroups of the current recheck launch that have finished; the last one
   // takes the round's decision and resets the count.
   uint32_t blocks_done;
-  // Closed loop, probe-only round 0: candidate `spec` (>= 0) is the next
-  // step's kappa = 1 probe, simulated from x_spec, the state the next step
-  // starts in if this step's kappa is 1, under the next step's draws.
-  int32_t spec_on;                    // 1: allowed (set by the host)
-  int32_t spec;                       // that candidate this step (-1: none)
-  double r_spec;                      // the next step's reference
-  double x_spec[kMaxN];
+  // Closed loop, probe-only round 0: candidates 1..spec_n are the kappa = 1
+  // probes of the next spec_n steps, candidate j simulated from x_spec[j - 1],
+  // the state step t + j starts in if steps t..t + j - 1 all have kappa = 1,
+  // under the draws of step t + j.  The following steps consume them in order.
+  int32_t spec_depth;                 // allowed speculation depth (set by the host)
+  int32_t spec_n;                     // probes of later steps run in the last live round
+  int32_t spec_used;                  // of those, consumed by the steps since
+  double r_spec[kSpecMax];            // their references
+  double x_spec[kSpecMax][kMaxN];     // their start states
   double band;                        // FP32 recheck band (a speculative verdict must be outside it)
 };
 
@@ -130,15 +137,12 @@ struct DevBuffers {
   double* x_hist;          // [(max_T + 1) * n]
   float* wbuf;             // [H][nw][N] streamed draws
   float* thbuf;            // [nth][N] per-scenario coefficient factors
-  // further pairs for the closed loop: step t reads pair t % 3, the next
-  // step's speculative probe reads pair (t + 1) % 3, and the first round
-  // generates the draws of step t + 2 into pair (t + 2) % 3
-  float* wbuf2;
-  float* thbuf2;
-  float* wbuf3;             // third pair: with speculation step t also reads step t + 1's draws
-  float* thbuf3;
-  const float* wbuf_spec;   // draws of the next step (speculative probe), set per launch
-  const float* thbuf_spec;
+  // closed loop: step t reads pair t % kPairs, the speculative probe of step
+  // t + j reads pair (t + j) % kPairs, and the first round generates the draws
+  // of step t + kSpecMax + 1
+  float* wpair[kPairs];     // closed-loop draw pairs (step s uses pair s % kPairs)
+  float* thpair[kPairs];
+  const float* wbuf_spec[kSpecMax];  // draws of steps t + 1.. (speculative probes), per launch
   int2* rlist;             // [cmax_round * N] recheck list (candidate, scenario)
   float* per_m;            // [cmax_round * N] per-scenario margins (rg_margin)
   int32_t* per_j;          // [cmax_round * N]

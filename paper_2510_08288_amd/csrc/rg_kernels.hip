@@ -57,7 +57,7 @@ struct RollArgs {
   uint32_t gen_ofs;  // the draws generated are those of step t + gen_ofs
   float* gen_w;
   float* gen_th;
-  const float* wbuf_spec;  // draws of step t + 1 (the speculative probe, closed loop)
+  const float* wbuf_spec[kSpecMax];  // draws of steps t + 1.. (speculative probes, closed loop)
 };
 
 template <int KIND>
@@ -432,10 +432,11 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
   __shared__ unsigned long long sh[16];
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = gid >> 2, q = gid & 3;
-  // the next step's speculative probe: its own start state and draws
-  const bool spec = c == S->spec;
-  const uint32_t t = a.st->t + (spec ? 1u : 0u);
-  const float* wsrc = spec ? a.wbuf_spec : a.wbuf;
+  // speculative probe of step t + sj (sj >= 1): its own start state and draws
+  const int sj = (c >= 1 && c <= S->spec_n) ? c : 0;
+  const bool spec = sj > 0;
+  const uint32_t t = a.st->t + (uint32_t)sj;
+  const float* wsrc = spec ? a.wbuf_spec[sj - 1] : a.wbuf;
   float best = INFINITY;
   int jb = 0, ns = 0;
   bool stopped = false;  // the candidate died while this wave ran (no recheck needed)
@@ -448,7 +449,7 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
     const float bv = qc.b[q] * (float)S->v[c];
     const float h = a.h, hh = a.hh, h6 = a.h6;
     const int H = a.H;
-    float x = (float)(spec ? S->x_spec[q] : a.st->x[q]);
+    float x = (float)(spec ? S->x_spec[sj - 1][q] : a.st->x[q]);
     // lane q: margin of constraint row q (g_q - (F C x)_q); padding rows are +inf
     auto row_margin = [&](float xv) {
       const float c2 = d2 * xv, c3 = d3 * xv;
@@ -941,7 +942,7 @@ __device__ void prepare_candidates(const typename Plant<KIND, double>::Coef& pc,
   const double r = st->r, vp = st->v_prev;
   for (int c = threadIdx.x; c < S->n_cand; c += blockDim.x) {
     if (S->mode != kNewton) S->full[c] = 0;
-    const double v = c == S->spec ? S->r_spec : cand_v(S->kappa[c], r, vp);
+    const double v = (c >= 1 && c <= S->spec_n) ? S->r_spec[c - 1] : cand_v(S->kappa[c], r, vp);
     S->v[c] = v;
     S->mss[c] = steady_margin<KIND>(pc, S, v);
     S->key_all[c] = ~0ull;
@@ -960,25 +961,29 @@ __device__ void setup_body(const typename Plant<KIND, double>::Coef& pc, DevStat
                            const RollArgs<KIND, double>* pa = nullptr) {
   if (threadIdx.x == 0) {
     if (closed_loop) st->r = r_seq[st->cl_index];
-    // Was this step's kappa = 1 probe already evaluated by the previous step
-    // (speculatively, from the state this step starts in when the previous
-    // kappa is 1)?  Its verdict counts only if the previous kappa was 1 and
-    // every scenario of the probe kept an FP32 margin of at least the band
-    // (no FP64 recheck needed); Alg. 1 then returns kappa = 1 on its first
-    // evaluation.
+    // Was this step's kappa = 1 probe already evaluated by an earlier round
+    // (speculatively, from the state this step starts in when the steps before
+    // it all have kappa = 1)?  Its verdict counts only if the previous kappa
+    // was 1 and every scenario of the probe kept an FP32 margin of at least
+    // the band (no FP64 recheck needed); Alg. 1 then returns kappa = 1 on its
+    // first evaluation.
     bool decided = false;
     double spec_worst = 0.0;
-    if (closed_loop && S->spec >= 0) {
-      const int c = S->spec;
+    if (closed_loop && S->spec_used < S->spec_n) {
+      const int c = 1 + S->spec_used;
       const double kall =
           S->key_all[c] == ~0ull ? INFINITY : key_margin(S->key_all[c], S->precision);
       if (S->done && S->kappa_res == 1.0 && !S->dead[c] && !S->fail64[c] && S->mss[c] >= 0.0 &&
           kall >= S->band) {
         decided = true;
         spec_worst = kall < S->mss[c] ? kall : S->mss[c];
+        S->spec_used += 1;
       }
     }
-    S->spec = -1;
+    if (!decided) {
+      S->spec_n = 0;
+      S->spec_used = 0;
+    }
     S->done = 0;
     S->found = 0;
     S->status = 0;
@@ -1039,12 +1044,19 @@ __device__ void setup_body(const typename Plant<KIND, double>::Coef& pc, DevStat
           // step's probe, from the state the next step starts in if this
           // step's kappa is 1 (the same FP64 true-plant step as the result
           // launch), under the next step's draws.
-          if (pa && S->spec_on && closed_loop && st->cl_index + 1 < st->cl_len) {
-            true_plant_step<KIND>(*pa, st->x, st->r, st->t, S->x_spec);
-            S->r_spec = r_seq[st->cl_index + 1];
-            S->kappa[1] = -1.0;  // equals no midpoint: the walk never reads it
-            S->spec = 1;
-            S->n_cand = 2;
+          int d = pa && closed_loop ? S->spec_depth : 0;
+          if (d > st->cl_len - 1 - st->cl_index) d = st->cl_len - 1 - st->cl_index;
+          for (int j = 1; j <= d; ++j) {
+            const double* xp = j == 1 ? st->x : S->x_spec[j - 2];
+            const double rp = j == 1 ? st->r : S->r_spec[j - 2];
+            true_plant_step<KIND>(*pa, xp, rp, st->t + (uint32_t)(j - 1), S->x_spec[j - 1]);
+            S->r_spec[j - 1] = r_seq[st->cl_index + j];
+            S->kappa[j] = -1.0;  // equals no midpoint: the walk never reads it
+          }
+          if (d > 0) {
+            S->spec_n = d;
+            S->spec_used = 0;
+            S->n_cand = 1 + d;
           }
         } else {
           double lo = 0.0, hi = 1.0;
@@ -1224,7 +1236,8 @@ __device__ void decide_body(const typename Plant<KIND, double>::Coef& pc, const 
       const int rem = S->goal - S->halvings;
       const int d = rem < S->depth ? rem : S->depth;
       S->probe = 0;
-      S->spec = -1;  // its slot is reused; this step's kappa is below 1 anyway
+      S->spec_n = 0;  // the slots are reused; this step's kappa is below 1 anyway
+      S->spec_used = 0;
       build_tree(S, 0, d, S->lo, S->hi);
       S->n_cand = (1 << d) - 1;
       S->round += 1;
@@ -2144,7 +2157,7 @@ static RollArgs<KIND, T> make_args(const Problem& pr, double band, int early, in
   a.thspan = (float)(2.0 * pr.s.theta_rel);
   a.wbuf = b.wbuf;
   a.thbuf = b.thbuf;
-  a.wbuf_spec = b.wbuf_spec;
+  for (int j = 0; j < kSpecMax; ++j) a.wbuf_spec[j] = b.wbuf_spec[j];
   a.st = b.st;
   a.srch = b.srch;
   a.per_m = b.per_m;
@@ -2276,7 +2289,7 @@ hipError_t launch_rollout(const Problem& pr, double band, int precision, int ear
   auto set_gen = [&](auto& a) {
     if (!gen) return;
     a.gen_row0 = cfg.cmax_round;
-    a.gen_ofs = 2;
+    a.gen_ofs = kSpecMax + 1;
     a.gen_w = gen_w;
     a.gen_th = gen_th;
   };

@@ -363,12 +363,12 @@ def test_fp64_recheck_decides_with_wide_band(R, O, rng_mode, inject):
         g.close()
 
 
-@pytest.mark.parametrize("speculate", [True, False])
+@pytest.mark.parametrize("speculate", [3, 1, 0])
 def test_probe_only_rounds_worst_margin_matches_oracle(R, O, speculate):
     # From the second update on the previous kappa is 1, so an update's only
     # round evaluates the kappa = 1 probe alone; with speculation that round
-    # also evaluates the next update's probe, which then needs no round of its
-    # own.  Steady-state test off: the reported worst margin is the FP32
+    # also evaluates the probes of the next `speculate` updates, which then
+    # need no round of their own.  Steady-state test off: the reported worst margin is the FP32
     # rollouts' minimum over scenarios and steps, compared with the FP64
     # oracle's at the same state.
     p = W.lq4_problem(seed=24, N=300, H=250, dt=0.005, eps=0.01, ss_check=0)
@@ -385,19 +385,21 @@ def test_probe_only_rounds_worst_margin_matches_oracle(R, O, speculate):
             assert out["rounds"][s] == 1 and out["candidates"][s] == 1
         ref = float(o.candidate(out["x"][s], 0.6, s)[1].min())
         assert abs(out["worst"][s] - ref) <= TOL32 * max(1.0, abs(ref)), s
-    if speculate:  # every other update is decided by the previous one's round
-        assert int(np.sum(out["rounds"][1:] == 0)) >= (len(r_seq) - 2) // 2
+    if speculate:  # of each 1 + speculate updates, all but one are decided ahead
+        decided = int(np.sum(out["rounds"][1:] == 0))
+        assert decided >= (len(r_seq) - 1) * speculate // (speculate + 1) - 1
 
 
+@pytest.mark.parametrize("speculate", [3, 1])
 @pytest.mark.parametrize("seed,r_seed", [(24, 5), (7, 11)])
-def test_speculation_keeps_closed_loop_identical(R, O, seed, r_seed):
-    # next-step speculation changes only which rollouts run in which launch:
-    # kappa, v, the plant states and the worst margins are identical with and
-    # without it, and kappa is the oracle's
+def test_speculation_keeps_closed_loop_identical(R, O, seed, r_seed, speculate):
+    # speculation changes only which rollouts run in which launch: kappa, v,
+    # the plant states and the worst margins are identical with and without
+    # it, and kappa is the oracle's
     p = W.lq4_problem(seed=seed, N=256, H=300, dt=0.005, eps=0.01)
     r_seq = W.reference_sequence(r_seed, 30, switch_every=6, lo=-0.8, hi=0.8)
-    a = _gov(R, p, speculate=True).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
-    b = _gov(R, p, speculate=False).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    a = _gov(R, p, speculate=speculate).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    b = _gov(R, p, speculate=0).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
     for key in ("kappa", "v", "x", "worst"):
         assert np.array_equal(a[key], b[key]), key
     assert int(np.sum(a["rounds"] == 0)) > 0  # some updates decided ahead
