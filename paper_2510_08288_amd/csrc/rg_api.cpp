@@ -259,6 +259,7 @@ int ensure_workspace(rg_handle* h) {
   for (int r = 0; r < kNC; ++r) S->g[r] = h->pr.c.g[r];
   for (int i = 0; i < kNC * kMaxY; ++i) S->F[i] = h->pr.c.F[i];
   S->done = 1;
+  for (int i = 0; i < kMssCache; ++i) S->mss_v[i] = std::nan("");  // empty cache
   S->spec_depth = spec_allowed(h);
   S->spec_n = 0;
   S->spec_used = 0;
@@ -775,6 +776,13 @@ int rg_set_theta(rg_handle* h, const double* theta_nom) {
   if (!theta_nom || !finite_array(theta_nom, h->pr.p.nth)) return fail(h, RG_E_INVAL, "bad theta");
   for (int c = 0; c < h->pr.p.nth; ++c) h->pr.p.coeffs[90 + c] = theta_nom[c];
   drop_graphs(h);  // kernel arguments changed
+  if (h->ws_ready) {  // cached steady-state margins belong to the old coefficients
+    double none[kMssCache];
+    for (double& x : none) x = std::nan("");
+    HIPCHK(h, hipMemcpyAsync((char*)h->b.srch + offsetof(DevSearch, mss_v), none, sizeof(none),
+                             hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+  }
   return RG_OK;
 }
 
@@ -1188,6 +1196,7 @@ static int batch_ensure_memory(rg_batch* bt) {
     fill_desc(pr, desc[i]);
     DevSearch& S = srch[i];
     memset(&S, 0, sizeof(S));
+    for (int e = 0; e < kMssCache; ++e) S.mss_v[e] = std::nan("");
     S.mode = kBisect;
     S.K = bt->opt.K;
     S.depth = bt->opt.depth;

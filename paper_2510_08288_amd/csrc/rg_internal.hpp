@@ -25,6 +25,7 @@ enum Mode { kBisect = 0, kGrid = 1, kNewton = 2 };
 // Closed-loop speculation: a probe-only round may also run the kappa = 1
 // probes of up to kSpecMax later steps; draws are kept for kPairs steps.
 constexpr int kSpecMax = 3;
+constexpr int kMssCache = 64;
 constexpr int kPairs = kSpecMax + 2;
 
 struct DevState {
@@ -86,6 +87,12 @@ struct DevSearch {
   double r_spec[kSpecMax];            // their references
   double x_spec[kSpecMax][kMaxN];     // their start states
   double band;                        // FP32 recheck band (a speculative verdict must be outside it)
+  // Steady-state margins of recent set-points (a pure function of v for fixed
+  // plant coefficients; NaN keys are empty entries, cleared when the nominal
+  // coefficients change)
+  double mss_v[kMssCache];
+  double mss_m[kMssCache];
+  int32_t mss_next;
 };
 
 // Result record of one RG step.

@@ -106,7 +106,7 @@ __device__ __forceinline__ void draw_theta_factor(uint32_t seed, uint32_t inst, 
 // a wave's loads of one step coalesce), theta factors f[c * N + k].
 template <int KIND, class A>
 __device__ __forceinline__ void gen_body(const A& a, float* wbuf, float* thbuf, size_t gid,
-                                         uint32_t t) {
+                                         uint32_t t, bool streaming = false) {
   using P = Plant<KIND, float>;
   const size_t nwork = (size_t)a.H * a.N;
   if (gid < nwork) {
@@ -115,13 +115,21 @@ __device__ __forceinline__ void gen_body(const A& a, float* wbuf, float* thbuf, 
     float w[P::nw];
     draw_w<P::nw>(a.seed, a.inst, t, 0u, (uint32_t)k, (uint32_t)j, a.wlo, a.wspan, w);
 #pragma unroll
-    for (int c = 0; c < P::nw; ++c) wbuf[((size_t)j * P::nw + c) * a.N + k] = w[c];
+    for (int c = 0; c < P::nw; ++c) {
+      float* dst = &wbuf[((size_t)j * P::nw + c) * a.N + k];
+      if (streaming) __builtin_nontemporal_store(w[c], dst);
+      else *dst = w[c];
+    }
   } else if (P::nth > 0 && gid < nwork + (size_t)a.N) {
     const int k = (int)(gid - nwork);
     float f[P::nth > 0 ? P::nth : 1];
     draw_theta_factor<P::nth>(a.seed, a.inst, t, (uint32_t)k, a.thlo, a.thspan, f);
 #pragma unroll
-    for (int c = 0; c < P::nth; ++c) thbuf[(size_t)c * a.N + k] = f[c];
+    for (int c = 0; c < P::nth; ++c) {
+      float* dst = &thbuf[(size_t)c * a.N + k];
+      if (streaming) __builtin_nontemporal_store(f[c], dst);
+      else *dst = f[c];
+    }
   }
 }
 
@@ -139,10 +147,12 @@ __device__ __forceinline__ bool gen_rows(const A& a) {
   const size_t nth = (size_t)(gridDim.y - a.gen_row0) * gridDim.x * blockDim.x;
   const size_t work = (size_t)a.H * a.N + (Plant<KIND, float>::nth > 0 ? (size_t)a.N : 0);
   const uint32_t t1 = a.st->t + a.gen_ofs;
+  // streaming stores: these draws are read steps later, and lines left dirty in
+  // L2 would have to be written back by the device-scope fences in between
   for (size_t i = ((size_t)(blockIdx.y - a.gen_row0) * gridDim.x + blockIdx.x) * blockDim.x +
                   threadIdx.x;
        i < work; i += nth)
-    gen_body<KIND>(a, a.gen_w, a.gen_th, i, t1);
+    gen_body<KIND>(a, a.gen_w, a.gen_th, i, t1, true);
   return true;
 }
 
@@ -936,22 +946,56 @@ __device__ void build_tree(DevSearch* S, int base, int depth, double lo, double 
 
 // Thread-parallel per-candidate preparation: set-points, steady-state margins,
 // reduction accumulators.
+// Steady-state margins come from a small cache of recent set-points when
+// possible (the same v recurs from one RG step to the next while the governor
+// holds v or has reached r).
 template <int KIND>
 __device__ void prepare_candidates(const typename Plant<KIND, double>::Coef& pc, const DevState* st,
                                    DevSearch* S) {
   const double r = st->r, vp = st->v_prev;
-  for (int c = threadIdx.x; c < S->n_cand; c += blockDim.x) {
+  __shared__ double s_cv[kMssCache], s_cm[kMssCache];
+  __shared__ int s_miss[kCMax];
+  for (int i = threadIdx.x; i < kMssCache; i += blockDim.x) {
+    s_cv[i] = S->mss_v[i];
+    s_cm[i] = S->mss_m[i];
+  }
+  __syncthreads();
+  const int n = S->n_cand;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
     if (S->mode != kNewton) S->full[c] = 0;
     const double v = (c >= 1 && c <= S->spec_n) ? S->r_spec[c - 1] : cand_v(S->kappa[c], r, vp);
     S->v[c] = v;
-    S->mss[c] = steady_margin<KIND>(pc, S, v);
+    int hit = -1;
+    for (int i = 0; i < kMssCache; ++i) {
+      if (s_cv[i] == v) {
+        hit = i;
+        break;
+      }
+    }
+    S->mss[c] = hit >= 0 ? s_cm[hit] : steady_margin<KIND>(pc, S, v);
+    if (c < kCMax) s_miss[c] = hit < 0;
     S->key_all[c] = ~0ull;
     S->key_far[c] = ~0ull;
     S->key64[c] = ~0ull;
     S->dead[c] = 0;
     S->fail64[c] = 0;
   }
-  if (threadIdx.x == 0) S->n_recheck = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    S->n_recheck = 0;
+    int next = S->mss_next;
+    for (int c = 0; c < n && c < kCMax; ++c) {
+      if (!s_miss[c]) continue;
+      const double v = S->v[c];
+      bool dup = false;  // the same set-point twice in one round
+      for (int e = 0; e < c; ++e) dup = dup || (s_miss[e] && S->v[e] == v);
+      if (dup) continue;
+      S->mss_v[next] = v;
+      S->mss_m[next] = S->mss[c];
+      next = (next + 1) % kMssCache;
+    }
+    S->mss_next = next;
+  }
 }
 
 // Start of one RG step: round-0 candidates.
@@ -1156,11 +1200,26 @@ template <int KIND>
 __device__ void decide_body(const typename Plant<KIND, double>::Coef& pc, const DevState* st,
                             DevSearch* S, const DevGrad* grad) {
   // Thread 0 may set S->done below: take the entry decision once, for the whole
-  // workgroup, so every wave reaches the same barriers.
-  __shared__ int s_done;
-  if (threadIdx.x == 0) s_done = S->done;
+  // workgroup, so every wave reaches the same barriers.  The verdicts and worst
+  // margins of the round's candidates are staged in LDS by all threads first,
+  // so the sequential walk below reads no global memory in its loop.
+  __shared__ int s_done, s_n;
+  __shared__ double s_kappa[kCMax], s_worst[kCMax];
+  __shared__ unsigned char s_ok[kCMax];
+  if (threadIdx.x == 0) {
+    s_done = S->done;
+    s_n = S->n_cand < kCMax ? S->n_cand : kCMax;
+  }
   __syncthreads();
   if (s_done) return;
+  if (S->mode != kNewton) {
+    for (int c = threadIdx.x; c < s_n; c += blockDim.x) {
+      s_kappa[c] = S->kappa[c];
+      s_ok[c] = cand_feasible(S, c) ? 1 : 0;
+      s_worst[c] = cand_worst(S, c);
+    }
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     S->rounds_total += 1;
     S->cand_total += S->n_cand;
@@ -1172,28 +1231,31 @@ __device__ void decide_body(const typename Plant<KIND, double>::Coef& pc, const 
       const int M = S->M;
       int istar = -1;
       for (int i = 0; i < M; ++i)
-        if (cand_feasible(S, i)) istar = i;
+        if (s_ok[i]) istar = i;
       S->passes_alg1 += M;
       if (istar < 0) {
         finished = true;
       } else {
         S->found = 1;
-        S->worst_res = cand_worst(S, istar);
-        S->lo = S->kappa[istar];
+        S->worst_res = s_worst[istar];
+        S->lo = s_kappa[istar];
         if (istar == M - 1) {
           finished = true;
         } else {
-          S->hi = S->kappa[istar + 1];
+          S->hi = s_kappa[istar + 1];
           if (S->goal <= 0) finished = true;
         }
       }
     } else {
-      if (S->probe) {
-        S->passes_alg1 += 1;
-        if (cand_feasible(S, 0)) {
-          S->found = 1;
-          S->lo = 1.0;
-          S->worst_res = cand_worst(S, 0);
+      double lo = S->lo, hi = S->hi, worst = S->worst_res;
+      int halvings = S->halvings, passes = S->passes_alg1, found = S->found;
+      const int probe = S->probe, goal = S->goal, n = s_n;
+      if (probe) {
+        passes += 1;
+        if (s_ok[0]) {
+          found = 1;
+          lo = 1.0;
+          worst = s_worst[0];
           finished = true;
         }
       }
@@ -1202,28 +1264,34 @@ __device__ void decide_body(const typename Plant<KIND, double>::Coef& pc, const 
         // the verdict of the candidate equal to the current midpoint (dyadic
         // midpoints are exact, so equality identifies the node), until a
         // midpoint was not evaluated this round.
-        while (S->halvings < S->goal) {
-          const double m = midpoint(S->lo, S->hi);
+        while (halvings < goal) {
+          const double m = midpoint(lo, hi);
           int c = -1;
-          for (int i = S->probe; i < S->n_cand; ++i) {
-            if (S->kappa[i] == m) {
+          for (int i = probe; i < n; ++i) {
+            if (s_kappa[i] == m) {
               c = i;
               break;
             }
           }
           if (c < 0) break;
-          S->passes_alg1 += 1;
-          if (cand_feasible(S, c)) {
-            S->lo = m;
-            S->found = 1;
-            S->worst_res = cand_worst(S, c);
+          passes += 1;
+          if (s_ok[c]) {
+            lo = m;
+            found = 1;
+            worst = s_worst[c];
           } else {
-            S->hi = m;
+            hi = m;
           }
-          S->halvings += 1;
+          halvings += 1;
         }
-        if (S->halvings >= S->goal) finished = true;
+        if (halvings >= goal) finished = true;
       }
+      S->lo = lo;
+      S->hi = hi;
+      S->worst_res = worst;
+      S->halvings = halvings;
+      S->passes_alg1 = passes;
+      S->found = found;
     }
     if (finished) {
       S->done = 1;
@@ -1245,8 +1313,10 @@ __device__ void decide_body(const typename Plant<KIND, double>::Coef& pc, const 
       S->round += 1;
     }
   }
+  __shared__ int s_more;
+  if (threadIdx.x == 0) s_more = !S->done;
   __syncthreads();
-  if (!S->done) prepare_candidates<KIND>(pc, st, S);
+  if (s_more) prepare_candidates<KIND>(pc, st, S);  // uniform: it has barriers
 }
 
 template <int KIND>
@@ -2380,8 +2450,11 @@ static QuadCoef64 make_quad_coef64(const Problem& pr) {
 hipError_t launch_recheck(const Problem& pr, int early_exit, const LaunchCfg& cfg,
                           const DevBuffers& b, hipStream_t st, int decide) {
   const size_t cap = (size_t)cfg.cmax_round * pr.s.N;
+  // Few workgroups: each of them counts itself on one device-scope counter at
+  // the end (the last one decides), and near-band entries are rare; a
+  // grid-stride loop takes any excess.
   if (cfg.lanes == 4 && pr.p.kind == 1 && quad_draws_addressable(pr)) {
-    const int qblocks = div_up((cap < 16384 ? cap : 16384) * 4, 256);
+    const int qblocks = div_up((cap < 4096 ? cap : 4096) * 4, 256);
     const QuadCoef64 qc = make_quad_coef64(pr);
     auto a = make_args<1, double>(pr, 0.0, early_exit, 0, b);
     return by_bit(pr.s.rng_mode, [&](auto rc) {
@@ -2394,7 +2467,7 @@ hipError_t launch_recheck(const Problem& pr, int early_exit, const LaunchCfg& cf
       });
     });
   }
-  const int blocks = div_up(cap < 65536 ? cap : 65536, 64);
+  const int blocks = div_up(cap < 16384 ? cap : 16384, 64);
   return by_kind(pr.p.kind, [&](auto kc) {
     constexpr int K = decltype(kc)::value;
     return by_bit(pr.s.rng_mode, [&](auto rc) {

@@ -156,3 +156,28 @@ def test_adjoint_full_size(R, oracle_mod):
     kn = gn.step(x0, r, vp)["kappa"]
     gn.close()
     assert abs(kn - kb) <= 2.0 ** -12
+
+
+def test_set_theta_refreshes_cached_steady_state(R, oracle_mod):
+    O = oracle_mod
+    # eps 0.45: the steady-state margin is the binding term.  The library keeps
+    # the steady-state margins of recent set-points; new nominal coefficients
+    # must replace them (both before and after the change the margins are the
+    # FP64 oracle's for the coefficients in force).
+    p = W.fc9_problem(N=128, H=300, dt=0.002).replace(eps=0.45)
+    o = O.Oracle(p, nthreads=8)
+    x0 = o.steady_margin(0.5)[1]
+    co = p.coeffs.copy()
+    co[90:110] *= 1.04
+    o2 = O.Oracle(p.replace(coeffs=co), nthreads=8)
+    g = R.Governor(p)
+    kap = [1.0, 0.5]
+    for ref_o, new in ((o, False), (o2, True), (o2, True)):
+        if new:
+            g.set_theta(co[90:110])
+        g.set_step(0)
+        m = g.margin(x0, 1.2, 0.5, kap)["margins"]
+        for i, k in enumerate(kap):
+            ref = ref_o.candidate(x0, ref_o.candidate_v(k, 1.2, 0.5), 0)[0]
+            assert abs(m[i] - ref) <= 1e-9 * max(1.0, abs(ref)), (new, k, m[i], ref)
+    g.close()
