@@ -336,7 +336,7 @@ def main():
                    "speculation_depth": int(g.options.speculate),
                    "schedule": ("autotuned on the first %d updates" % args.tune_steps
                                 if tuned else "library default or command line"),
-                   "launch": "one captured HIP graph per RG update, replayed"},
+                   "launch": "captured HIP graphs of five RG updates each, replayed"},
         "rg_updates_per_s": K / elapsed,
         "executed_scenario_steps_per_s": executed / elapsed,
         "eager_profiled": {"ms_per_step": elapsed_eager / K * 1e3,

@@ -33,8 +33,11 @@ struct rg_handle {
   uint32_t t = 0;
   long long gen_t = -1;  // RG step whose draws are in the streamed buffer
   std::string err;
-  // one captured closed-loop RG step per draw-buffer parity, replayed per step
+  // one captured closed-loop RG step per draw-buffer phase, replayed per step,
+  // and kPairs consecutive steps from each phase (one graph launch for kPairs
+  // updates: fewer gaps between graph launches)
   hipGraphExec_t step_graph[kPairs] = {};
+  hipGraphExec_t cycle_graph[kPairs] = {};
   // profiling
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -74,6 +77,10 @@ int32_t spec_allowed(const rg_handle* h) {
 
 void drop_graphs(rg_handle* h) {
   for (hipGraphExec_t& g : h->step_graph) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+  for (hipGraphExec_t& g : h->cycle_graph) {
     if (g) (void)hipGraphExecDestroy(g);
     g = nullptr;
   }
@@ -639,20 +646,20 @@ int rg_closed_loop(rg_handle* h, const double* x0, double v0, const double* r_se
   if ((rc = upload_state(h, x0, r_seq[0], v0))) return rc;
   if (x_out)
     for (int i = 0; i < n; ++i) x_out[i] = x0[i];
-  for (int p = 0; graph && p < kPairs; ++p) {
-    if (h->step_graph[p]) continue;
+  // steps p, p + 1, .., p + len - 1 (draw-buffer phases mod kPairs) as one graph
+  auto capture = [&](int p, int len, hipGraphExec_t* out) -> int {
     hipGraph_t g = nullptr;
     HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = enqueue_step(h, 1, p);
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < len && e == hipSuccess; ++i) e = enqueue_step(h, 1, (p + i) % kPairs);
     hipError_t e2 = hipStreamEndCapture(h->stream, &g);
     if (e != hipSuccess) return fail_hip(h, "capture closed-loop step", e);
     if (e2 != hipSuccess) return fail_hip(h, "hipStreamEndCapture", e2);
-    hipGraphExec_t ge = nullptr;
-    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail_hip(h, "hipGraphInstantiate", e);
-    h->step_graph[p] = ge;
-  }
+    return RG_OK;
+  };
   std::vector<DevResult> R;
   std::vector<double> xs;
   int32_t done = 0;
@@ -676,10 +683,19 @@ int rg_closed_loop(rg_handle* h, const double* x0, double v0, const double* r_se
     }
     HIPCHK(h, launch_setup(h->pr, h->b, 1, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    for (int s = 0; s < chunk; ++s) {
+    for (int s = 0; s < chunk;) {
       const int p = (int)((h->t + (uint32_t)s) % (uint32_t)kPairs);
-      hipError_t e = graph ? hipGraphLaunch(h->step_graph[p], h->stream) : enqueue_step(h, 1, p);
+      const int len = graph && chunk - s >= kPairs ? kPairs : 1;
+      hipError_t e = hipSuccess;
+      if (graph) {
+        hipGraphExec_t* ge = len == kPairs ? &h->cycle_graph[p] : &h->step_graph[p];
+        if (!*ge && (rc = capture(p, len, ge))) return rc;
+        e = hipGraphLaunch(*ge, h->stream);
+      } else {
+        e = enqueue_step(h, 1, p);
+      }
       if (e != hipSuccess) return fail_hip(h, "enqueue closed-loop step", e);
+      s += len;
     }
     R.resize(chunk);
     xs.resize((size_t)(chunk + 1) * n);
