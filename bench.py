@@ -177,6 +177,8 @@ def main():
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--block", type=int, default=0, help="rollout workgroup (0: library choice)")
+    ap.add_argument("--speculate", type=int, default=-1,
+                    help="speculation depth with --no-autotune (-1: library default)")
     ap.add_argument("--mode-steps", type=int, default=0,
                     help="closed-loop steps timed for the Newton and FP64 search forms "
                          "(0: the same steps as the headline form)")
@@ -233,6 +235,8 @@ def main():
     # child process of its own (its trial launches stay out of this process)
     tuned = None
     sched = dict(depth=args.depth, lanes=args.lanes, block=args.block)
+    if args.speculate >= 0:
+        sched["speculate"] = args.speculate
     if not args.no_autotune and args.tune_steps > 0:
         child = subprocess.run([sys.executable, os.path.abspath(__file__), "--autotune-only",
                                 "--tune-steps", str(args.tune_steps)], capture_output=True, text=True)
@@ -336,7 +340,7 @@ def main():
                    "speculation_depth": int(g.options.speculate),
                    "schedule": ("autotuned on the first %d updates" % args.tune_steps
                                 if tuned else "library default or command line"),
-                   "launch": "captured HIP graphs of five RG updates each, replayed"},
+                   "launch": "captured HIP graphs of nine RG updates each, replayed"},
         "rg_updates_per_s": K / elapsed,
         "executed_scenario_steps_per_s": executed / elapsed,
         "eager_profiled": {"ms_per_step": elapsed_eager / K * 1e3,

@@ -143,7 +143,7 @@ typedef struct rg_options {
                               candidates are evaluated early changes: the result is that of
                               sequential bisection either way.  0: tree from round 0. */
     int32_t speculate;     /* closed loop, bisection with prediction, FP32 LQ4 rollouts on 4 lanes
-                              per scenario, streamed draws: s in 0..3 (default 3) lets a round
+                              per scenario, streamed draws: s in 0..7 (default 7) lets a round
                               that runs the kappa = 1 probe alone also run the probes of the next
                               s steps, step t + j from the state it starts in if steps t..t+j-1
                               all have kappa = 1.  When that holds and every scenario of step

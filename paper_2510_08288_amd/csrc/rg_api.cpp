@@ -197,6 +197,9 @@ void plan(rg_handle* h) {
     }
   }
   h->cfg = c;
+  // a probe-only round 0 holds the probe and the probes of the next steps
+  const int sp = spec_allowed(h);
+  if (1 + sp > h->cfg.cmax_round) h->cfg.cmax_round = 1 + sp;
 }
 
 int ensure_workspace(rg_handle* h) {
@@ -875,7 +878,7 @@ int rg_autotune(rg_handle* h, const double* x0, double v0, const double* r_seq, 
         for (int predict : {1, 0}) {
           if (predict && h->opt.search != RG_SEARCH_BISECT) continue;
           if (h->opt.search == RG_SEARCH_NEWTON && depth != dlo) continue;  // depth unused
-          for (int speculate : {kSpecMax, 1, 0}) {
+          for (int speculate : {kSpecMax, 3, 1, 0}) {
             if (speculate && !(predict && lanes == 4)) continue;
             rg_options o = own;
             o.lanes = lanes;

@@ -24,7 +24,7 @@ enum Mode { kBisect = 0, kGrid = 1, kNewton = 2 };
 // closed loops) can be enqueued or graph-captured without host round trips.
 // Closed-loop speculation: a probe-only round may also run the kappa = 1
 // probes of up to kSpecMax later steps; draws are kept for kPairs steps.
-constexpr int kSpecMax = 3;
+constexpr int kSpecMax = 7;
 constexpr int kMssCache = 64;
 constexpr int kPairs = kSpecMax + 2;
 

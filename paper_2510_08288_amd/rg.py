@@ -168,7 +168,7 @@ class Governor:
                  K: int = 12, search: int = SEARCH_BISECT, depth: int = 0, M: int = 64,
                  refine: int = 6, early_exit: bool = True, block: int = 0, max_T: int = 256,
                  rng_mode: int = RNG_STREAM, lanes: int = 0, Kc: int = 50,
-                 predict: bool = True, speculate: int = 3, torch_workspace: bool = True):
+                 predict: bool = True, speculate: int = 7, torch_workspace: bool = True):
         import torch
         self.L = load_library()
         self.problem = problem

@@ -53,7 +53,7 @@ def test_default_options(lib):
     assert lib.rg_default_options(C.byref(o)) == 0
     assert o.K == 12 and o.band == 1e-4 and o.precision == 0 and o.early_exit == 1
     assert o.predict == 1
-    assert o.speculate == 3
+    assert o.speculate == 7
     assert lib.rg_default_options(None) == R.RG_E_INVAL
 
 
@@ -124,7 +124,7 @@ def test_create_rejects_bad_horizon_and_options(lib):
                                ("block", 100, R.RG_E_INVAL), ("block", 512, R.RG_E_INVAL),
                                ("precision", 4, R.RG_E_INVAL), ("search", 3, R.RG_E_INVAL),
                                ("Kc", 0, R.RG_E_INVAL), ("lanes", 2, R.RG_E_INVAL), ("predict", 2, R.RG_E_INVAL),
-                               ("speculate", 4, R.RG_E_INVAL),
+                               ("speculate", 8, R.RG_E_INVAL),
                                ("band", float("inf"), R.RG_E_INVAL), ("max_T", 0, R.RG_E_INVAL)]:
         o = R.rg_options()
         lib.rg_default_options(C.byref(o))

@@ -363,7 +363,7 @@ def test_fp64_recheck_decides_with_wide_band(R, O, rng_mode, inject):
         g.close()
 
 
-@pytest.mark.parametrize("speculate", [3, 1, 0])
+@pytest.mark.parametrize("speculate", [7, 3, 1, 0])
 def test_probe_only_rounds_worst_margin_matches_oracle(R, O, speculate):
     # From the second update on the previous kappa is 1, so an update's only
     # round evaluates the kappa = 1 probe alone; with speculation that round
@@ -390,7 +390,7 @@ def test_probe_only_rounds_worst_margin_matches_oracle(R, O, speculate):
         assert decided >= (len(r_seq) - 1) * speculate // (speculate + 1) - 1
 
 
-@pytest.mark.parametrize("speculate", [3, 1])
+@pytest.mark.parametrize("speculate", [7, 3, 1])
 @pytest.mark.parametrize("seed,r_seed", [(24, 5), (7, 11)])
 def test_speculation_keeps_closed_loop_identical(R, O, seed, r_seed, speculate):
     # speculation changes only which rollouts run in which launch: kappa, v,
