@@ -422,6 +422,28 @@ def test_closed_loop_with_failing_probes_matches_oracle(R, O):
         v_prev = a["v"][s]
 
 
+def test_speculation_across_chunks_and_graph_cycles(R, O):
+    # Chunks of 4 updates cut speculation chains (no probe of a step past the
+    # chunk) and are shorter than one graph cycle; chunks of 256 replay cycle
+    # graphs for the first updates and single-update graphs for the rest.
+    # Either way the results are those without speculation, and kappa is the
+    # oracle's.
+    p = W.lq4_problem(seed=24, N=256, H=300, dt=0.005, eps=0.01)
+    r_seq = W.reference_sequence(5, 23, switch_every=8, lo=-0.8, hi=0.8)
+    ref = _gov(R, p, speculate=0).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    for max_T in (4, 256):
+        out = _gov(R, p, speculate=7, max_T=max_T).closed_loop(np.zeros(4), 0.0, r_seq,
+                                                                use_graph=True)
+        for key in ("kappa", "v", "x", "worst"):
+            assert np.array_equal(out[key], ref[key]), (max_T, key)
+        assert int(np.sum(out["rounds"] == 0)) > 0, max_T  # some updates decided ahead
+    o = O.Oracle(p, nthreads=8)
+    v_prev = 0.0
+    for s in range(len(r_seq)):
+        assert ref["kappa"][s] == o.bisect(ref["x"][s], r_seq[s], v_prev, s, 12)["kappa"], s
+        v_prev = ref["v"][s]
+
+
 def test_prediction_keeps_sequential_bisection_result(R, O):
     # the first round speculates along the previous update's kappa: the closed
     # loop must give the same kappa with and without it, equal to the oracle's
