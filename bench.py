@@ -340,7 +340,7 @@ def main():
                    "speculation_depth": int(g.options.speculate),
                    "schedule": ("autotuned on the first %d updates" % args.tune_steps
                                 if tuned else "library default or command line"),
-                   "launch": "captured HIP graphs of nine RG updates each, replayed"},
+                   "launch": "captured HIP graphs of four generic search rounds, replayed until every update is recorded"},
         "rg_updates_per_s": K / elapsed,
         "executed_scenario_steps_per_s": executed / elapsed,
         "eager_profiled": {"ms_per_step": elapsed_eager / K * 1e3,

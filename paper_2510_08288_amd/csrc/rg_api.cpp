@@ -33,11 +33,8 @@ struct rg_handle {
   uint32_t t = 0;
   long long gen_t = -1;  // RG step whose draws are in the streamed buffer
   std::string err;
-  // one captured closed-loop RG step per draw-buffer phase, replayed per step,
-  // and kPairs consecutive steps from each phase (one graph launch for kPairs
-  // updates: fewer gaps between graph launches)
-  hipGraphExec_t step_graph[kPairs] = {};
-  hipGraphExec_t cycle_graph[kPairs] = {};
+  // captured generic closed-loop rounds: kGraphRounds of them, and one
+  hipGraphExec_t round_graph[2] = {};
   // profiling
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -76,11 +73,7 @@ int32_t spec_allowed(const rg_handle* h) {
 }
 
 void drop_graphs(rg_handle* h) {
-  for (hipGraphExec_t& g : h->step_graph) {
-    if (g) (void)hipGraphExecDestroy(g);
-    g = nullptr;
-  }
-  for (hipGraphExec_t& g : h->cycle_graph) {
+  for (hipGraphExec_t& g : h->round_graph) {
     if (g) (void)hipGraphExecDestroy(g);
     g = nullptr;
   }
@@ -393,6 +386,48 @@ hipError_t enqueue_step(rg_handle* h, int closed_loop, int phase) {
   return launch_finalize(h->pr, closed_loop, b, h->stream, closed_loop);
 }
 
+// Enqueue one generic round of the closed loop: whatever round the current
+// step's search is at.  The kernels take the step from the device state and
+// select its draw buffers themselves (pair t % kPairs; the speculative probe of
+// step t + j reads pair (t + j) % kPairs); the first round of each step also
+// generates the draws of step t + kSpecMax + 1.  The result launch records the
+// step only once its search has ended, applies the true-plant step and
+// prepares round 0 of the next step, so a step costs the rounds it needs and a
+// step decided ahead costs one round of launches that return at once.
+hipError_t enqueue_round(rg_handle* h) {
+  hipError_t e;
+  const int prec = h->opt.precision;
+  const double band = prec == RG_PREC_F32_RECHECK ? h->opt.band : 0.0;
+  const bool streamed = h->pr.s.rng_mode == RG_RNG_STREAM;
+  DevBuffers b = h->b;
+  b.ring = 1;
+  // any non-null target switches the draw workgroups on; the kernel picks the buffer
+  float* gen_w = streamed ? b.wpair[0] : nullptr;
+  float* gen_th = streamed ? b.thpair[0] : nullptr;
+  const bool newton = h->opt.search == RG_SEARCH_NEWTON;
+  const bool fused_decide = prec == RG_PREC_F32_RECHECK && !newton;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->profiling) {
+    if ((e = next_event(h, &e0)) != hipSuccess || (e = next_event(h, &e1)) != hipSuccess) return e;
+    if ((e = hipEventRecord(e0, h->stream)) != hipSuccess) return e;
+  }
+  if ((e = launch_rollout(h->pr, band, prec, h->opt.early_exit, 0, h->cfg, b, h->stream,
+                          newton ? -1 : -2, h->opt.Kc, gen_w, gen_th)) != hipSuccess)
+    return e;
+  if (h->profiling && (e = hipEventRecord(e1, h->stream)) != hipSuccess) return e;
+  if (prec == RG_PREC_F32_RECHECK &&
+      (e = launch_recheck(h->pr, h->opt.early_exit, h->cfg, b, h->stream, fused_decide)) !=
+          hipSuccess)
+    return e;
+  if (newton) {
+    if ((e = launch_grad_prepare(h->pr, b, -1, 1, h->stream)) != hipSuccess) return e;
+    if ((e = launch_seg_grad(h->pr, h->opt.Kc, -1, b, h->stream)) != hipSuccess) return e;
+    if ((e = launch_grad_reduce(b, 1, h->pr.p.nth, -1, h->stream)) != hipSuccess) return e;
+  }
+  if (!fused_decide && (e = launch_decide(h->pr, b, h->stream)) != hipSuccess) return e;
+  return launch_finalize(h->pr, 1, b, h->stream, 1, 1);
+}
+
 void fill_info(const DevResult& R, rg_step_info* info) {
   if (!info) return;
   info->kappa = R.kappa;
@@ -649,20 +684,23 @@ int rg_closed_loop(rg_handle* h, const double* x0, double v0, const double* r_se
   if ((rc = upload_state(h, x0, r_seq[0], v0))) return rc;
   if (x_out)
     for (int i = 0; i < n; ++i) x_out[i] = x0[i];
-  // steps p, p + 1, .., p + len - 1 (draw-buffer phases mod kPairs) as one graph
-  auto capture = [&](int p, int len, hipGraphExec_t* out) -> int {
+  // generic rounds captured as graphs: kGraphRounds rounds, and one round
+  constexpr int kGraphRounds = 4;
+  auto capture = [&](int len, hipGraphExec_t* out) -> int {
     hipGraph_t g = nullptr;
     HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int i = 0; i < len && e == hipSuccess; ++i) e = enqueue_step(h, 1, (p + i) % kPairs);
+    for (int i = 0; i < len && e == hipSuccess; ++i) e = enqueue_round(h);
     hipError_t e2 = hipStreamEndCapture(h->stream, &g);
-    if (e != hipSuccess) return fail_hip(h, "capture closed-loop step", e);
+    if (e != hipSuccess) return fail_hip(h, "capture closed-loop rounds", e);
     if (e2 != hipSuccess) return fail_hip(h, "hipStreamEndCapture", e2);
     e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail_hip(h, "hipGraphInstantiate", e);
     return RG_OK;
   };
+  if (graph && !h->round_graph[0] && (rc = capture(kGraphRounds, &h->round_graph[0]))) return rc;
+  if (graph && !h->round_graph[1] && (rc = capture(1, &h->round_graph[1]))) return rc;
   std::vector<DevResult> R;
   std::vector<double> xs;
   int32_t done = 0;
@@ -686,19 +724,32 @@ int rg_closed_loop(rg_handle* h, const double* x0, double v0, const double* r_se
     }
     HIPCHK(h, launch_setup(h->pr, h->b, 1, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    for (int s = 0; s < chunk;) {
-      const int p = (int)((h->t + (uint32_t)s) % (uint32_t)kPairs);
-      const int len = graph && chunk - s >= kPairs ? kPairs : 1;
-      hipError_t e = hipSuccess;
-      if (graph) {
-        hipGraphExec_t* ge = len == kPairs ? &h->cycle_graph[p] : &h->step_graph[p];
-        if (!*ge && (rc = capture(p, len, ge))) return rc;
-        e = hipGraphLaunch(*ge, h->stream);
-      } else {
-        e = enqueue_step(h, 1, p);
+    // Every step takes at least one round: enqueue one round per step not yet
+    // recorded, then read how many are recorded, until all are.  A step needs
+    // at most cfg.rounds rounds, which bounds the loop.
+    int32_t recorded = 0;
+    long long issued = 0;
+    const long long max_rounds = (long long)chunk * (h->cfg.rounds + 1) + kGraphRounds;
+    while (recorded < chunk) {
+      int need = chunk - recorded;
+      if (issued + need > max_rounds)
+        return fail(h, RG_E_STATE, "closed loop: steps not recorded after the maximum rounds");
+      issued += need;
+      while (need > 0) {
+        hipError_t e = hipSuccess;
+        if (graph) {
+          const bool big = need >= kGraphRounds;
+          e = hipGraphLaunch(h->round_graph[big ? 0 : 1], h->stream);
+          need -= big ? kGraphRounds : 1;
+        } else {
+          e = enqueue_round(h);
+          need -= 1;
+        }
+        if (e != hipSuccess) return fail_hip(h, "enqueue closed-loop round", e);
       }
-      if (e != hipSuccess) return fail_hip(h, "enqueue closed-loop step", e);
-      s += len;
+      HIPCHK(h, hipMemcpyAsync(&recorded, (char*)h->b.st + offsetof(DevState, cl_index),
+                               sizeof(recorded), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, hipStreamSynchronize(h->stream));
     }
     R.resize(chunk);
     xs.resize((size_t)(chunk + 1) * n);

@@ -150,6 +150,7 @@ struct DevBuffers {
   float* wpair[kPairs];     // closed-loop draw pairs (step s uses pair s % kPairs)
   float* thpair[kPairs];
   const float* wbuf_spec[kSpecMax];  // draws of steps t + 1.. (speculative probes), per launch
+  int32_t ring;            // 1: kernels select pair t % kPairs themselves (generic closed-loop rounds)
   int2* rlist;             // [cmax_round * N] recheck list (candidate, scenario)
   float* per_m;            // [cmax_round * N] per-scenario margins (rg_margin)
   int32_t* per_j;          // [cmax_round * N]
@@ -248,8 +249,9 @@ hipError_t launch_recheck(const Problem& pr, int early_exit, const LaunchCfg& cf
 hipError_t launch_decide(const Problem& pr, const DevBuffers& b, hipStream_t st);
 // setup_next (closed loop): the same launch prepares round 0 of the next step
 // of the chunk, if there is one.
+// when_done: only once the step's search has ended (generic closed-loop rounds).
 hipError_t launch_finalize(const Problem& pr, int closed_loop, const DevBuffers& b,
-                           hipStream_t st, int setup_next = 0);
+                           hipStream_t st, int setup_next = 0, int when_done = 0);
 hipError_t launch_collect(const DevBuffers& b, int M, double* out_dev, hipStream_t st);
 hipError_t launch_draws(const Problem& pr, uint32_t t, int k0, int nk, int j0, int nj,
                         float* w_dev, double* th_dev, const DevBuffers& b, hipStream_t st);

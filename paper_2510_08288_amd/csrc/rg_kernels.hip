@@ -58,7 +58,23 @@ struct RollArgs {
   float* gen_w;
   float* gen_th;
   const float* wbuf_spec[kSpecMax];  // draws of steps t + 1.. (speculative probes, closed loop)
+  // ring != 0 (closed loop): the draws of step s are in wring[s % kPairs],
+  // selected from the step counter on the device (wbuf, wbuf_spec, gen_w and
+  // gen_th are then unused)
+  int ring;
+  float* wring[kPairs];
+  float* thring[kPairs];
 };
+
+// Draws of step t (streamed mode).
+template <class A>
+__device__ __forceinline__ const float* step_w(const A& a, uint32_t t) {
+  return a.ring ? a.wring[t % kPairs] : a.wbuf;
+}
+template <class A>
+__device__ __forceinline__ const float* step_th(const A& a, uint32_t t) {
+  return a.ring ? a.thring[t % kPairs] : a.thbuf;
+}
 
 template <int KIND>
 struct CtlArgs {
@@ -144,15 +160,22 @@ __global__ void __launch_bounds__(256) k_gen(RollArgs<KIND, float> a, float* wbu
 template <int KIND, class A>
 __device__ __forceinline__ bool gen_rows(const A& a) {
   if (a.gen_row0 <= 0 || (int)blockIdx.y < a.gen_row0) return false;
+  const uint32_t t1 = a.st->t + a.gen_ofs;
+  float* gw = a.gen_w;
+  float* gth = a.gen_th;
+  if (a.ring) {  // once per step (its first round), while the chunk has steps left
+    if (a.srch->round != 0 || a.st->cl_index >= a.st->cl_len) return true;
+    gw = a.wring[t1 % kPairs];
+    gth = a.thring[t1 % kPairs];
+  }
   const size_t nth = (size_t)(gridDim.y - a.gen_row0) * gridDim.x * blockDim.x;
   const size_t work = (size_t)a.H * a.N + (Plant<KIND, float>::nth > 0 ? (size_t)a.N : 0);
-  const uint32_t t1 = a.st->t + a.gen_ofs;
   // streaming stores: these draws are read steps later, and lines left dirty in
   // L2 would have to be written back by the device-scope fences in between
   for (size_t i = ((size_t)(blockIdx.y - a.gen_row0) * gridDim.x + blockIdx.x) * blockDim.x +
                   threadIdx.x;
        i < work; i += nth)
-    gen_body<KIND>(a, a.gen_w, a.gen_th, i, t1, true);
+    gen_body<KIND>(a, gw, gth, i, t1, true);
   return true;
 }
 
@@ -186,8 +209,9 @@ __device__ __forceinline__ T rollout_lane(const A& a, int early, T v, int k, uin
   if constexpr (P::nth > 0) {
     float f[P::nth];
     if (RNG == 0) {
+      const float* tb = step_th(a, t);
 #pragma unroll
-      for (int c = 0; c < P::nth; ++c) f[c] = a.thbuf[(size_t)c * a.N + k];
+      for (int c = 0; c < P::nth; ++c) f[c] = tb[(size_t)c * a.N + k];
     } else {
       draw_theta_factor<P::nth>(a.seed, a.inst, t, (uint32_t)k, a.thlo, a.thspan, f);
     }
@@ -215,10 +239,11 @@ __device__ __forceinline__ T rollout_lane(const A& a, int early, T v, int k, uin
     }
   }
   float wc[P::nw], wn[P::nw];
+  const float* wb = RNG == 0 ? step_w(a, t) : nullptr;
   auto load = [&](int j, float* w) {
     if (RNG == 0) {
 #pragma unroll
-      for (int c = 0; c < P::nw; ++c) w[c] = a.wbuf[((size_t)j * P::nw + c) * a.N + k];
+      for (int c = 0; c < P::nw; ++c) w[c] = wb[((size_t)j * P::nw + c) * a.N + k];
     } else {
       draw_w<P::nw>(a.seed, a.inst, t, 0u, (uint32_t)k, (uint32_t)j, a.wlo, a.wspan, w);
     }
@@ -446,7 +471,7 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
   const int sj = (c >= 1 && c <= S->spec_n) ? c : 0;
   const bool spec = sj > 0;
   const uint32_t t = a.st->t + (uint32_t)sj;
-  const float* wsrc = spec ? a.wbuf_spec[sj - 1] : a.wbuf;
+  const float* wsrc = a.ring ? a.wring[t % kPairs] : (spec ? a.wbuf_spec[sj - 1] : a.wbuf);
   float best = INFINITY;
   int jb = 0, ns = 0;
   bool stopped = false;  // the candidate died while this wave ran (no recheck needed)
@@ -662,7 +687,7 @@ __global__ void __launch_bounds__(256) k_recheck_lq4_quad(const RollArgs<1, doub
   const int H = a.H;
   const uint32_t row_bytes = 8u * (uint32_t)a.N;
   const __amdgpu_buffer_rsrc_t wres = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)a.wbuf, (short)0, (int)(row_bytes * (uint32_t)(H + U)), 0x00020000);
+      (void*)step_w(a, t), (short)0, (int)(row_bytes * (uint32_t)(H + U)), 0x00020000);
   const int stride = (int)((gridDim.x * blockDim.x) >> 2);
   // every lane of a quad holds the same entry, so all exits are quad-uniform
   for (int i = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 2); i < n; i += stride) {
@@ -1420,11 +1445,15 @@ __device__ void finalize_body(const RollArgs<KIND, double>& a, DevResult* res, d
 template <int KIND>
 __global__ void __launch_bounds__(64) k_finalize(const RollArgs<KIND, double> a, DevResult* res,
                                                  double* x_hist, int closed_loop,
-                                                 const CtlArgs<KIND> ctl, int setup_next) {
+                                                 const CtlArgs<KIND> ctl, int setup_next,
+                                                 int when_done) {
+  // when_done: a launch of a generic closed-loop round, which records the
+  // result only once the step's search has ended (and never past the chunk)
   __shared__ int s_next;
   if (threadIdx.x == 0) {
-    finalize_body<KIND>(a, res, x_hist, closed_loop);
-    s_next = setup_next && a.st->cl_index < a.st->cl_len;
+    const bool skip = when_done && (!a.srch->done || a.st->cl_index >= a.st->cl_len);
+    if (!skip) finalize_body<KIND>(a, res, x_hist, closed_loop);
+    s_next = !skip && setup_next && a.st->cl_index < a.st->cl_len;
   }
   if (!setup_next) return;
   __syncthreads();
@@ -1510,7 +1539,8 @@ __global__ void __launch_bounds__(64) k_adjoint(const RollArgs<KIND, float> a, c
   float th[P::nth > 0 ? P::nth : 1], fac[P::nth > 0 ? P::nth : 1];
   if constexpr (P::nth > 0) {
     if (RNG == 0) {
-      for (int c = 0; c < P::nth; ++c) fac[c] = a.thbuf[(size_t)c * a.N + k];
+      const float* tb = step_th(a, t);
+      for (int c = 0; c < P::nth; ++c) fac[c] = tb[(size_t)c * a.N + k];
     } else {
       draw_theta_factor<P::nth>(a.seed, a.inst, t, (uint32_t)k, a.thlo, a.thspan, fac);
     }
@@ -1518,9 +1548,10 @@ __global__ void __launch_bounds__(64) k_adjoint(const RollArgs<KIND, float> a, c
   }
   typename P::Lane Ln;
   P::lane_init(a.pc, th, v, Ln);
+  const float* wb = RNG == 0 ? step_w(a, t) : nullptr;
   auto load_w = [&](int j, float* w) {
     if (RNG == 0) {
-      for (int c = 0; c < P::nw; ++c) w[c] = a.wbuf[((size_t)j * P::nw + c) * a.N + k];
+      for (int c = 0; c < P::nw; ++c) w[c] = wb[((size_t)j * P::nw + c) * a.N + k];
     } else {
       draw_w<P::nw>(a.seed, a.inst, t, 0u, (uint32_t)k, (uint32_t)j, a.wlo, a.wspan, w);
     }
@@ -1650,7 +1681,8 @@ struct SegLane {
     float th[P::nth > 0 ? P::nth : 1];
     if constexpr (P::nth > 0) {
       if (RNG == 0) {
-        for (int c = 0; c < P::nth; ++c) fac[c] = a.thbuf[(size_t)c * a.N + k];
+        const float* tb = step_th(a, t);
+        for (int c = 0; c < P::nth; ++c) fac[c] = tb[(size_t)c * a.N + k];
       } else {
         draw_theta_factor<P::nth>(a.seed, a.inst, t, (uint32_t)k, a.thlo, a.thspan, fac);
       }
@@ -1662,7 +1694,8 @@ struct SegLane {
   }
   __device__ void draws(int j, float* w) const {
     if (RNG == 0) {
-      for (int c = 0; c < P::nw; ++c) w[c] = a.wbuf[((size_t)j * P::nw + c) * a.N + k];
+      const float* wb = step_w(a, t);
+      for (int c = 0; c < P::nw; ++c) w[c] = wb[((size_t)j * P::nw + c) * a.N + k];
     } else {
       draw_w<P::nw>(a.seed, a.inst, t, 0u, (uint32_t)k, (uint32_t)j, a.wlo, a.wspan, w);
     }
@@ -2021,6 +2054,9 @@ struct DescView {
   const float* wbuf;
   const float* thbuf;
   const DevState* st;
+  int ring = 0;  // batches draw inline: no closed-loop draw ring
+  float* const* wring = nullptr;
+  float* const* thring = nullptr;
 };
 
 template <int KIND>
@@ -2228,6 +2264,11 @@ static RollArgs<KIND, T> make_args(const Problem& pr, double band, int early, in
   a.wbuf = b.wbuf;
   a.thbuf = b.thbuf;
   for (int j = 0; j < kSpecMax; ++j) a.wbuf_spec[j] = b.wbuf_spec[j];
+  a.ring = b.ring;
+  for (int j = 0; j < kPairs; ++j) {
+    a.wring[j] = b.wpair[j];
+    a.thring[j] = b.thpair[j];
+  }
   a.st = b.st;
   a.srch = b.srch;
   a.per_m = b.per_m;
@@ -2492,12 +2533,12 @@ hipError_t launch_decide(const Problem& pr, const DevBuffers& b, hipStream_t st)
 }
 
 hipError_t launch_finalize(const Problem& pr, int closed_loop, const DevBuffers& b,
-                           hipStream_t st, int setup_next) {
+                           hipStream_t st, int setup_next, int when_done) {
   return by_kind(pr.p.kind, [&](auto kc) {
     constexpr int K = decltype(kc)::value;
     auto a = make_args<K, double>(pr, 0.0, 0, 0, b);
     hipLaunchKernelGGL(k_finalize<K>, dim3(1), dim3(64), 0, st, a, b.res, b.x_hist, closed_loop,
-                       make_ctl<K>(pr, b, closed_loop), setup_next);
+                       make_ctl<K>(pr, b, closed_loop), setup_next, when_done);
     return hipGetLastError();
   });
 }
