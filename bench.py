@@ -45,8 +45,8 @@ PEAK_FP32_NONPACKED_TFLOPS = 78.6
 # copy; valid only for the kernel sources they were taken on (SHA-1 of the device
 # sources below, concatenated in this order).
 KERNEL_SOURCES = ("rg_kernels.hip", "rg_device.hpp", "rg_internal.hpp")
-HBM_TRAFFIC = {"kernels_sha1": "b25c9158b7a3f16f2f4568039cfdfdfc9507705d",
-               "bytes_per_launch": 29548888}
+HBM_TRAFFIC = {"kernels_sha1": "be6d637d995ecd4d08c5197608e1c49d15ae907e",
+               "bytes_per_launch": 103681816}
 
 
 def cpu_baseline(wl, r_seq, seconds):
@@ -249,9 +249,11 @@ def main():
     g = rg.Governor(p, precision=prec, band=wl["band"], K=wl["K"], max_T=max(256, T), **sched)
 
     # warmup: the first W updates of the workload (untimed)
+    warm_launches = 0  # rollout launches of the warm-up (one per round, at least one per update)
     if args.warmup > 0:
         g.set_step(0)
-        g.closed_loop(x0, wl["v_prev"], r_seq[: args.warmup], use_graph=False)
+        ow = g.closed_loop(x0, wl["v_prev"], r_seq[: args.warmup], use_graph=False)
+        warm_launches = int(np.sum(np.maximum(1, np.asarray(ow["rounds"]))))
 
     # the workload's first K updates launched eagerly, with a HIP event pair
     # around every rollout launch (the roofline figure); untimed
@@ -265,8 +267,8 @@ def main():
     prof = g.profile()
     g.set_profiling(False)
 
-    # timed region: the same K updates, each replayed from the captured HIP
-    # graph of one RG step (captured beforehand), from the initial state
+    # timed region: the same K updates replayed from the captured HIP graphs of
+    # generic search rounds (captured beforehand), from the initial state
     g.set_step(0)
     g.closed_loop(x0, wl["v_prev"], r_seq[:1], use_graph=True)
     g.set_step(0)
@@ -361,6 +363,7 @@ def main():
                      "kernel": ("k_rollout_lq4_quad (one scenario per 4 lanes)" if g.options.lanes == 4
                                 else "k_rollout<LQ4, float>"),
                      "launches": prof["rollout_launches"],
+                     "launches_before": warm_launches,
                      "avg_launch_ms": prof["rollout_ms"] / max(1, prof["rollout_launches"]),
                      "flop_per_scenario_step": FLOP_PER_STEP_LQ4,
                      "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
