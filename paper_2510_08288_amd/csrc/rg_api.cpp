@@ -219,7 +219,6 @@ int ensure_workspace(rg_handle* h) {
   }
   b.wbuf = b.wpair[0];  // single steps, rg_margin, rg_grad, rg_draws
   b.thbuf = b.thpair[0];
-  for (int j = 0; j < kSpecMax; ++j) b.wbuf_spec[j] = nullptr;
   b.rlist = (int2*)(base + L.rlist);
   b.per_m = (float*)(base + L.per_m);
   b.per_j = (int32_t*)(base + L.per_j);
@@ -328,34 +327,17 @@ void draw_pair(const rg_handle* h, int i, float** w, float** th) {
   *th = h->b.thpair[i % kPairs];
 }
 
-// Enqueue one RG step: draws, round-0 setup, the rounds, the result record.
-// In closed loop (phase = t % kPairs) the draws of steps t..t + kSpecMax and
-// the round-0 setup of step t were made by earlier steps or the chunk's
-// prologue: the step reads draw pair `phase` (the speculative probe of step
-// t + j reads pair phase + j), its first round generates the draws of step
-// t + kSpecMax + 1, and its result launch prepares round 0 of step t + 1.
-hipError_t enqueue_step(rg_handle* h, int closed_loop, int phase) {
+// Enqueue one RG step of rg_step: draws and round-0 setup, the planned rounds,
+// the result record.
+hipError_t enqueue_step(rg_handle* h) {
   hipError_t e;
   const int prec = h->opt.precision;
   const double band = prec == RG_PREC_F32_RECHECK ? h->opt.band : 0.0;
   const bool streamed = h->pr.s.rng_mode == RG_RNG_STREAM;
   DevBuffers b = h->b;
-  float *gen_w = nullptr, *gen_th = nullptr;
-  if (closed_loop) {
-    if (streamed) {
-      draw_pair(h, phase, &b.wbuf, &b.thbuf);
-      for (int j = 0; j < kSpecMax; ++j) {
-        float *sw, *sth;
-        draw_pair(h, phase + 1 + j, &sw, &sth);
-        b.wbuf_spec[j] = sw;
-      }
-      draw_pair(h, phase + kSpecMax + 1, &gen_w, &gen_th);
-    }
-  } else {
-    // draws and round-0 setup share a launch in stream mode
-    e = streamed ? launch_gen_setup(h->pr, b, 0, h->stream) : launch_setup(h->pr, b, 0, h->stream);
-    if (e != hipSuccess) return e;
-  }
+  // draws and round-0 setup share a launch in stream mode
+  e = streamed ? launch_gen_setup(h->pr, b, 0, h->stream) : launch_setup(h->pr, b, 0, h->stream);
+  if (e != hipSuccess) return e;
   const bool newton = h->opt.search == RG_SEARCH_NEWTON;
   // with FP32 rollouts the recheck launch ends with the decision (the Newton
   // decision needs the derivative first)
@@ -368,8 +350,7 @@ hipError_t enqueue_step(rg_handle* h, int closed_loop, int phase) {
     }
     // the Newton iterate keeps checkpoints for its derivative
     if ((e = launch_rollout(h->pr, band, prec, h->opt.early_exit, 0, h->cfg, b, h->stream,
-                            newton ? -1 : -2, h->opt.Kc, r == 0 ? gen_w : nullptr,
-                            r == 0 ? gen_th : nullptr)) != hipSuccess)
+                            newton ? -1 : -2, h->opt.Kc)) != hipSuccess)
       return e;
     if (h->profiling && (e = hipEventRecord(e1, h->stream)) != hipSuccess) return e;
     if (prec == RG_PREC_F32_RECHECK &&
@@ -383,7 +364,7 @@ hipError_t enqueue_step(rg_handle* h, int closed_loop, int phase) {
     }
     if (!fused_decide && (e = launch_decide(h->pr, b, h->stream)) != hipSuccess) return e;
   }
-  return launch_finalize(h->pr, closed_loop, b, h->stream, closed_loop);
+  return launch_finalize(h->pr, 0, b, h->stream);
 }
 
 // Enqueue one generic round of the closed loop: whatever round the current
@@ -612,7 +593,7 @@ int rg_step(rg_handle* h, const double* x, double r, double v_prev, double* v_ou
   int rc = ensure_workspace(h);
   if (rc) return rc;
   if ((rc = upload_state(h, x, r, v_prev))) return rc;
-  hipError_t e = enqueue_step(h, 0, 0);
+  hipError_t e = enqueue_step(h);
   if (e != hipSuccess) return fail_hip(h, "enqueue RG step", e);
   h->gen_t = (long long)h->t;
   DevResult R;

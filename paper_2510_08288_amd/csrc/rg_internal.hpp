@@ -144,12 +144,11 @@ struct DevBuffers {
   double* x_hist;          // [(max_T + 1) * n]
   float* wbuf;             // [H][nw][N] streamed draws
   float* thbuf;            // [nth][N] per-scenario coefficient factors
-  // closed loop: step t reads pair t % kPairs, the speculative probe of step
-  // t + j reads pair (t + j) % kPairs, and the first round generates the draws
-  // of step t + kSpecMax + 1
+  // closed loop: step s reads pair s % kPairs (the speculative probe of step
+  // t + j reads pair (t + j) % kPairs), and the first round of step t
+  // generates the draws of step t + kSpecMax + 1
   float* wpair[kPairs];     // closed-loop draw pairs (step s uses pair s % kPairs)
   float* thpair[kPairs];
-  const float* wbuf_spec[kSpecMax];  // draws of steps t + 1.. (speculative probes), per launch
   int32_t ring;            // 1: kernels select pair t % kPairs themselves (generic closed-loop rounds)
   int2* rlist;             // [cmax_round * N] recheck list (candidate, scenario)
   float* per_m;            // [cmax_round * N] per-scenario margins (rg_margin)
@@ -236,8 +235,9 @@ hipError_t launch_setup(const Problem& pr, const DevBuffers& b, int closed_loop,
 hipError_t launch_setup_list(const Problem& pr, const DevBuffers& b, int M, hipStream_t st);
 // ckpt_cand >= 0 (or -1 for the Newton iterate) keeps that candidate's
 // checkpoints every Kc steps for the segment derivative; -2 keeps none.
-// gen_w (non-null, streamed draws): the launch also generates the draws of
-// step t + 1 into gen_w / gen_th with workgroups of its own.
+// gen_w (non-null, streamed draws, closed loop): the launch also has
+// workgroups of its own that generate, in a step's first round, the draws of
+// step t + kSpecMax + 1 into the buffer pair the step counter selects.
 hipError_t launch_rollout(const Problem& pr, double band, int precision, int early_exit, int record,
                           const LaunchCfg& cfg, const DevBuffers& b, hipStream_t st,
                           int ckpt_cand = -2, int Kc = 0, float* gen_w = nullptr,

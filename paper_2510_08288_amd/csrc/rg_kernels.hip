@@ -57,10 +57,9 @@ struct RollArgs {
   uint32_t gen_ofs;  // the draws generated are those of step t + gen_ofs
   float* gen_w;
   float* gen_th;
-  const float* wbuf_spec[kSpecMax];  // draws of steps t + 1.. (speculative probes, closed loop)
   // ring != 0 (closed loop): the draws of step s are in wring[s % kPairs],
-  // selected from the step counter on the device (wbuf, wbuf_spec, gen_w and
-  // gen_th are then unused)
+  // selected from the step counter on the device (wbuf, gen_w and gen_th are
+  // then unused; gen_w != nullptr only switches the draw workgroups on)
   int ring;
   float* wring[kPairs];
   float* thring[kPairs];
@@ -471,7 +470,7 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
   const int sj = (c >= 1 && c <= S->spec_n) ? c : 0;
   const bool spec = sj > 0;
   const uint32_t t = a.st->t + (uint32_t)sj;
-  const float* wsrc = a.ring ? a.wring[t % kPairs] : (spec ? a.wbuf_spec[sj - 1] : a.wbuf);
+  const float* wsrc = step_w(a, t);  // speculative probes exist only in the closed loop (ring)
   float best = INFINITY;
   int jb = 0, ns = 0;
   bool stopped = false;  // the candidate died while this wave ran (no recheck needed)
@@ -2263,7 +2262,6 @@ static RollArgs<KIND, T> make_args(const Problem& pr, double band, int early, in
   a.thspan = (float)(2.0 * pr.s.theta_rel);
   a.wbuf = b.wbuf;
   a.thbuf = b.thbuf;
-  for (int j = 0; j < kSpecMax; ++j) a.wbuf_spec[j] = b.wbuf_spec[j];
   a.ring = b.ring;
   for (int j = 0; j < kPairs; ++j) {
     a.wring[j] = b.wpair[j];
