@@ -237,13 +237,18 @@ int rg_step(rg_handle* h, const double* x, double r, double v_prev, double* v_ou
 int rg_margin(rg_handle* h, const double* x, double r, double v_prev, const double* kappa,
               int32_t M, double* margins, float* per_scenario, int32_t* per_scenario_j);
 
-/* T closed-loop steps on the device with no host round trip (Fig. 1): at step
- * s the governor picks v_s from (x_s, v_{s-1}, r_seq[s]), then the true plant
- * advances x_{s+1} = RK4(x_s, v_s) under the tag-2 disturbance.  x0: [n];
- * r_seq: [T]; v_out, kappa_out: [T]; x_out: [(T+1) x n]; info_out: [T];
- * outputs nullable except v_out.  Advances t by T.  use_graph = 1 captures one
- * RG step as a HIP graph (once per handle and stream) and replays it T times;
- * profiling forces plain launches. */
+/* T closed-loop steps on the device (Fig. 1): at step s the governor picks
+ * v_s from (x_s, v_{s-1}, r_seq[s]), then the true plant advances
+ * x_{s+1} = RK4(x_s, v_s) under the tag-2 disturbance.  x0: [n]; r_seq: [T];
+ * v_out, kappa_out: [T]; x_out: [(T+1) x n]; info_out: [T]; outputs nullable
+ * except v_out.  Advances t by T.  The device runs generic search rounds (the
+ * current step's next round; a step's result is recorded, and the next step
+ * prepared, once its search has ended); the host enqueues one round per step
+ * not yet recorded and reads the device's count of recorded steps, a few
+ * times per chunk of max_T steps.  use_graph = 1 replays the rounds from HIP
+ * graphs captured once per handle and stream; profiling forces plain launches.
+ * RG_E_STATE if steps stay unrecorded after the planned number of rounds per
+ * step. */
 int rg_closed_loop(rg_handle* h, const double* x0, double v0, const double* r_seq, int32_t T,
                    double* v_out, double* kappa_out, double* x_out, rg_step_info* info_out,
                    int32_t use_graph);
@@ -253,11 +258,12 @@ int rg_get_options(const rg_handle* h, rg_options* out);
 
 /* Autotuner of the launch schedule.  Runs the closed loop of T RG updates from
  * (x0, v0) under r_seq (as rg_closed_loop, graph replay, starting at the
- * handle's step counter, which is restored afterwards) once per candidate
- * schedule and times it: lanes per scenario (1 or 4, LQ4 FP32 only), rollout
+ * handle's step counter, which is restored afterwards) for every candidate
+ * schedule (three runs: the first captures the graphs, the faster of the other
+ * two counts): lanes per scenario (1 or 4, LQ4 FP32 only), rollout
  * workgroup (128 or 256 threads), device search depth (2..5; 1..3 for the grid
  * refinement), first-round prediction (on/off, bisection only) and the
- * speculation depth (3, 1, 0; with prediction and 4 lanes).  Schedules
+ * speculation depth (7, 3, 1, 0; with prediction and 4 lanes).  Schedules
  * change only which candidates run when, so every one must give the same kappa
  * sequence; a mismatch returns RG_E_STATE.  best_out (nullable) receives the
  * fastest schedule's options, best_ms_out (nullable) its time per update; with
