@@ -422,6 +422,34 @@ def test_closed_loop_with_failing_probes_matches_oracle(R, O):
         v_prev = a["v"][s]
 
 
+@pytest.mark.parametrize("mode", ["f64_bisect", "grid", "newton"])
+def test_closed_loop_search_forms_graph_equals_eager(R, O, mode):
+    # Every search form runs the closed loop as generic rounds (a step takes
+    # as many as its search needs).  Graph replay and plain launches give
+    # identical results, and the bisection and grid forms give the oracle's
+    # kappa at every state of the loop.
+    p = W.lq4_problem(seed=24, N=192, H=200, dt=0.005, eps=0.01)
+    r_seq = W.reference_sequence(3, 10, switch_every=3, lo=-2.0, hi=2.0)
+    kw = {"f64_bisect": dict(precision=R.PREC_F64, predict=False),
+          "grid": dict(search=R.SEARCH_GRID, M=17, refine=4),
+          "newton": dict(search=R.SEARCH_NEWTON)}[mode]
+    a = _gov(R, p, **kw).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    b = _gov(R, p, **kw).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=False)
+    for key in ("kappa", "v", "x"):
+        assert np.array_equal(a[key], b[key]), (mode, key)
+    if mode == "newton":
+        return
+    o = O.Oracle(p, nthreads=8)
+    v_prev = 0.0
+    for s in range(len(r_seq)):
+        if mode == "grid":
+            ref = o.grid(a["x"][s], r_seq[s], v_prev, s, 17, 4)
+        else:
+            ref = o.bisect(a["x"][s], r_seq[s], v_prev, s, 12)
+        assert a["kappa"][s] == ref["kappa"], (mode, s, a["kappa"][s], ref["kappa"])
+        v_prev = a["v"][s]
+
+
 def test_speculation_across_chunks_and_graph_cycles(R, O):
     # Chunks of 4 updates cut speculation chains (no probe of a step past the
     # chunk) and are shorter than one graph cycle; chunks of 256 replay cycle
