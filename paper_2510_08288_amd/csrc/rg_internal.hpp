@@ -15,7 +15,7 @@ constexpr int kNC = 4;       // constraint rows evaluated per step (unused rows 
 constexpr int kMaxTh = 20;   // uncertain coefficients
 // Steps per prefetch group of the LQ4 quad rollout; the streamed draw buffer
 // holds this many spare rows past the horizon so whole groups load unclamped.
-constexpr int kQuadGroup = 8;
+constexpr int kQuadGroup = 16;
 constexpr int kMaxCoef = 115;
 
 enum Mode { kBisect = 0, kGrid = 1, kNewton = 2 };
