@@ -452,9 +452,9 @@ def test_closed_loop_search_forms_graph_equals_eager(R, O, mode):
 
 def test_speculation_across_chunks_and_graph_cycles(R, O):
     # Chunks of 4 updates cut speculation chains (no probe of a step past the
-    # chunk) and take single-round graphs; chunks of 256 replay four-round
-    # graphs first and single-round graphs for the last rounds.  Either way
-    # the results are those without speculation, and kappa is the oracle's.
+    # chunk); every chunk replays four-round graphs while at least four steps
+    # are unrecorded and single-round graphs for the rest.  Either way the
+    # results are those without speculation, and kappa is the oracle's.
     p = W.lq4_problem(seed=24, N=256, H=300, dt=0.005, eps=0.01)
     r_seq = W.reference_sequence(5, 23, switch_every=8, lo=-0.8, hi=0.8)
     ref = _gov(R, p, speculate=0).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
