@@ -546,77 +546,98 @@ double orc_candidate(const orc_problem* p, const double* x0, double v, uint32_t 
  * Kappa searches.
  * ========================================================================= */
 
-/* Alg. 1 (bisection) applied to the robust verdict M(v) >= 0 over all
- * scenarios.  N_kappa = K + 1 candidate evaluations at most: kappa = 1 first
- * (stop if admissible), then K halvings of [kappa_lo, kappa_hi]; the result is
- * the last admissible candidate (0 if none).  Reading of the iteration count:
- * K counts the halvings after the kappa = 1 probe, so the bracket closes to
- * 2^-K.  Alg. 2 computes the same value under feasibility monotone in kappa
- * (the min over scenarios commutes with the dyadic floor); orc_alg2 is its
- * literal per-scenario form. */
+/* Alg. 1 (bisection) on the robust verdict M(v) >= 0 over all scenarios.
+ * Definition used here: the search first asks whether kappa = 1 is admissible
+ * and returns it if so.  Otherwise it holds a bracket [lo, hi] with hi refused
+ * and lo the largest admissible candidate found so far (0, not evaluated, at
+ * the start) and halves it K times at its midpoint, keeping that property; the
+ * result is lo.  At most K + 1 candidate evaluations, and the bracket closes to
+ * 2^-K (reading of the iteration count: K counts the halvings after the
+ * kappa = 1 probe).  Alg. 2 computes the same value when feasibility is
+ * monotone in kappa (the minimum over scenarios commutes with the dyadic
+ * floor); orc_alg2 is the per-scenario form.  trace_* (nullable) receive the
+ * evaluated candidates and their worst margins in order. */
 orc_result orc_bisect(const orc_problem* p, const double* x0, double r, double v_prev,
                       uint32_t t, int32_t K, double* trace_kappa, double* trace_margin)
 {
     orc_result res = {0.0, v_prev, -INFINITY, 0, 1};
-    double lo = 0.0, hi = 1.0, kappa = 1.0, kopt = 0.0;
-    int found = 0;
-    double worst_at_opt = -INFINITY;
-    for (int32_t i = 1; i <= K + 1; ++i) {
-        double v = orc_candidate_v(kappa, r, v_prev);
-        double M = orc_candidate(p, x0, v, t, NULL, NULL, NULL);
-        if (trace_kappa) trace_kappa[i - 1] = kappa;
-        if (trace_margin) trace_margin[i - 1] = M;
-        res.passes = i;
-        if (M >= 0.0) {
-            kopt = kappa;
-            found = 1;
-            worst_at_opt = M;
-            if (kappa == 1.0) break;
-            lo = kappa;
-        } else {
-            hi = kappa;
-        }
-        kappa = (lo + hi) / 2.0;
+    double M = orc_candidate(p, x0, orc_candidate_v(1.0, r, v_prev), t, NULL, NULL, NULL);
+    if (trace_kappa) trace_kappa[0] = 1.0;
+    if (trace_margin) trace_margin[0] = M;
+    res.passes = 1;
+    if (M >= 0.0) {
+        res.kappa = 1.0;
+        res.v = r;
+        res.worst = M;
+        res.status = 0;
+        return res;
     }
-    res.kappa = kopt;
-    res.v = found ? orc_candidate_v(kopt, r, v_prev) : v_prev;
-    res.worst = worst_at_opt;
-    res.status = found ? 0 : 1;
+    double lo = 0.0, hi = 1.0;
+    for (int32_t h = 0; h < K; ++h) {
+        const double mid = (lo + hi) / 2.0;
+        M = orc_candidate(p, x0, orc_candidate_v(mid, r, v_prev), t, NULL, NULL, NULL);
+        if (trace_kappa) trace_kappa[res.passes] = mid;
+        if (trace_margin) trace_margin[res.passes] = M;
+        res.passes += 1;
+        if (M >= 0.0) {
+            lo = mid;
+            res.worst = M;
+            res.status = 0;
+        } else {
+            hi = mid;
+        }
+    }
+    res.kappa = res.status == 0 ? lo : 0.0;
+    res.v = res.status == 0 ? orc_candidate_v(lo, r, v_prev) : v_prev;
     return res;
 }
 
-/* Alg. 2 literally: for each scenario k run Alg. 1 with the verdict of
- * scenario k alone (and the steady-state test), then take the minimum over k. */
+/* Verdict of one scenario alone (Alg. 2 runs Alg. 1 once per scenario): its
+ * rollout margin and the steady-state margin both non-negative. */
+static int orc_scenario_admits(const orc_problem* p, const double* x0, double v, uint32_t t,
+                               uint32_t k)
+{
+    const double mk = orc_rollout(p, x0, v, t, k, NULL, NULL, NULL);
+    const double ms = orc_steady_margin(p, v, NULL, NULL);
+    return mk >= 0.0 && ms >= 0.0;
+}
+
+/* Alg. 2: the bisection defined at orc_bisect applied to each scenario's own
+ * verdict, then the smallest of the per-scenario results.  A scenario with no
+ * admissible candidate contributes 0 and makes the status 1 (kappa = 0,
+ * v = v_prev) when the minimum is 0. */
 orc_result orc_alg2(const orc_problem* p, const double* x0, double r, double v_prev,
                     uint32_t t, int32_t K)
 {
     orc_result res = {1.0, r, -INFINITY, 0, 0};
-    double kopt = 1.0;
-    int any_infeasible = 0;
+    double kmin = 1.0;
+    int any_none = 0;
     for (int32_t k = 0; k < p->N; ++k) {
-        double lo = 0.0, hi = 1.0, kappa = 1.0, kk = 0.0;
-        int found = 0;
-        for (int32_t i = 1; i <= K + 1; ++i) {
-            double v = orc_candidate_v(kappa, r, v_prev);
-            double mk = orc_rollout(p, x0, v, t, (uint32_t)k, NULL, NULL, NULL);
-            double ms = orc_steady_margin(p, v, NULL, NULL);
-            res.passes++;
-            if (mk >= 0.0 && ms >= 0.0) {
-                kk = kappa;
-                found = 1;
-                if (kappa == 1.0) break;
-                lo = kappa;
-            } else {
-                hi = kappa;
+        double kk;
+        res.passes += 1;
+        if (orc_scenario_admits(p, x0, orc_candidate_v(1.0, r, v_prev), t, (uint32_t)k)) {
+            kk = 1.0;
+        } else {
+            double lo = 0.0, hi = 1.0;
+            int found = 0;
+            for (int32_t h = 0; h < K; ++h) {
+                const double mid = (lo + hi) / 2.0;
+                res.passes += 1;
+                if (orc_scenario_admits(p, x0, orc_candidate_v(mid, r, v_prev), t, (uint32_t)k)) {
+                    lo = mid;
+                    found = 1;
+                } else {
+                    hi = mid;
+                }
             }
-            kappa = (lo + hi) / 2.0;
+            if (!found) any_none = 1;
+            kk = lo;
         }
-        if (!found) any_infeasible = 1;
-        if (kk < kopt) kopt = kk;
+        if (kk < kmin) kmin = kk;
     }
-    res.kappa = kopt;
-    res.status = (kopt == 0.0 && any_infeasible) ? 1 : 0;
-    res.v = res.status ? v_prev : orc_candidate_v(kopt, r, v_prev);
+    res.kappa = kmin;
+    res.status = (kmin == 0.0 && any_none) ? 1 : 0;
+    res.v = res.status ? v_prev : orc_candidate_v(kmin, r, v_prev);
     return res;
 }
 

@@ -14,13 +14,17 @@
  * Parity status:
  *   pinned   : Philox (published known-answer vectors), LQ4 rollout (RK4
  *              matrix-polynomial closed form), LQ4 steady state (fixed point of
- *              the closed form), bisection / Alg. 2 / Alg. 3 search (exact
- *              linear ratio test, brute-force grids, invariants), closed loop
- *              (recursive feasibility), tangent gradients (central FD, linear
- *              closed form).
- *   parity unpinned: FC9 trajectories and margins have no closed form; they are
- *              checked only through invariants (positivity, equilibrium
- *              residual and convergence, FD gradients, search invariants).
+ *              the closed form), FC9 right-hand side and outputs (values worked
+ *              out by hand at x = xbar and at chosen states, flow telescoping,
+ *              single coupling entries, the closed check valve), FC9 steady
+ *              state (closed-form equilibrium with W = 0 and a_1..a_6 = 0),
+ *              RK4 order on both plants (against an independent solver),
+ *              bisection / Alg. 2 / Alg. 3 search (exact linear ratio test,
+ *              brute-force grids, invariants), closed loop (recursive
+ *              feasibility), tangent gradients (central FD, linear closed form).
+ *   not pinned by a closed form: FC9 trajectories under disturbance and
+ *              coefficient spread (checked through the pinned right-hand side,
+ *              RK4 order, equilibrium convergence and FD gradients).
  */
 #ifndef RG_ORACLE_H
 #define RG_ORACLE_H
