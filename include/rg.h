@@ -219,6 +219,15 @@ int rg_set_stream(rg_handle* h, void* hip_stream);
 int rg_set_step(rg_handle* h, uint32_t t);
 int rg_get_step(const rg_handle* h, uint32_t* t);
 
+/* Forget what earlier RG steps left in the handle's device search state: the
+ * previous kappa that first-round prediction follows, the speculative probes
+ * of later steps, and the cache of steady-state margins by set-point.  No
+ * result depends on this state (it only decides which candidates run early,
+ * and a cached margin equals a recomputed one); after the call the next step
+ * runs exactly as the first step of a new handle would.  t is unchanged.
+ * Blocking.  RG_OK also before any device memory exists (nothing to reset). */
+int rg_reset(rg_handle* h);
+
 /* ---- the governor --------------------------------------------------------------- */
 
 /* One RG update (Alg. 1-3 inputs x_t, v_{t-1}, r_t; output kappa_opt, v_t).

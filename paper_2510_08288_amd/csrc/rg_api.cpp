@@ -409,6 +409,8 @@ hipError_t enqueue_round(rg_handle* h) {
   return launch_finalize(h->pr, 1, b, h->stream, 1, 1);
 }
 
+int reset_search_schedule(rg_handle* h);
+
 void fill_info(const DevResult& R, rg_step_info* info) {
   if (!info) return;
   info->kappa = R.kappa;
@@ -581,6 +583,22 @@ int rg_set_step(rg_handle* h, uint32_t t) {
 int rg_get_step(const rg_handle* h, uint32_t* t) {
   if (!h || !t) return RG_E_INVAL;
   *t = h->t;
+  return RG_OK;
+}
+
+int rg_reset(rg_handle* h) {
+  if (!h) return RG_E_INVAL;
+  if (!h->ws_ready) return RG_OK;
+  // prediction and speculation fields first (also used by the autotuner)
+  if (int rc = reset_search_schedule(h)) return rc;
+  double none[kMssCache];
+  for (double& x : none) x = std::nan("");
+  const int32_t next = 0;
+  HIPCHK(h, hipMemcpyAsync((char*)h->b.srch + offsetof(DevSearch, mss_v), none, sizeof(none),
+                           hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync((char*)h->b.srch + offsetof(DevSearch, mss_next), &next, sizeof(next),
+                           hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
   return RG_OK;
 }
 

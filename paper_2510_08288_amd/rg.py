@@ -109,6 +109,7 @@ def load_library(path: str = LIB_PATH, with_torch: bool = True) -> C.CDLL:
     L.rg_bind_workspace.argtypes = [_vp, _vp, C.c_size_t]
     L.rg_set_stream.argtypes = [_vp, _vp]
     L.rg_set_step.argtypes = [_vp, C.c_uint32]
+    L.rg_reset.argtypes = [_vp]
     L.rg_get_step.argtypes = [_vp, C.POINTER(C.c_uint32)]
     L.rg_step.argtypes = [_vp, _dp, C.c_double, C.c_double, _dp, _dp, C.POINTER(rg_step_info)]
     L.rg_margin.argtypes = [_vp, _dp, C.c_double, C.c_double, _dp, C.c_int32, _dp, _fp, _ip]
@@ -224,6 +225,10 @@ class Governor:
 
     def set_step(self, t: int) -> None:
         self._check(self.L.rg_set_step(self.h, int(t)))
+
+    def reset(self) -> None:
+        """Clear the search state earlier steps left (rg_reset)."""
+        self._check(self.L.rg_reset(self.h))
 
     def get_step(self) -> int:
         t = C.c_uint32()
