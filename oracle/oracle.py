@@ -90,6 +90,11 @@ def lib() -> C.CDLL:
         L.orc_grid.argtypes = [P, dp, C.c_double, C.c_double, C.c_uint32, C.c_int32, C.c_int32,
                                C.POINTER(C.c_uint8)]
         L.orc_grid.restype = _Result
+        L.orc_candidate_q.argtypes = [P, dp, C.c_double, C.c_uint32, C.c_int32, dp, ip]
+        L.orc_candidate_q.restype = C.c_double
+        L.orc_bisect_q.argtypes = [P, dp, C.c_double, C.c_double, C.c_uint32, C.c_int32,
+                                   C.c_int32]
+        L.orc_bisect_q.restype = _Result
         L.orc_plant_step.argtypes = [P, dp, C.c_double, C.c_uint32, dp]
         L.orc_closed_loop.argtypes = [P, dp, C.c_double, dp, C.c_int32, C.c_uint32, C.c_int32,
                                       C.c_int32, C.c_int32, C.c_int32, dp, dp, dp]
@@ -250,6 +255,20 @@ class Oracle:
         if want_P:
             out["P"] = P[:, : self.p.N]
         return out
+
+    def candidate_q(self, x0, v, t, q):
+        """(M_q, per-scenario margins, number of violating scenarios)."""
+        x0 = _f64(x0)
+        per = np.zeros(max(self.p.N, 1))
+        nv = C.c_int32(0)
+        M = self.L.orc_candidate_q(self.ref, _dp(x0), float(v), t, int(q), _dp(per), C.byref(nv))
+        return M, per[: self.p.N], nv.value
+
+    def bisect_q(self, x0, r, v_prev, t, K, q):
+        x0 = _f64(x0)
+        res = self.L.orc_bisect_q(self.ref, _dp(x0), float(r), float(v_prev), t, K, int(q))
+        return dict(kappa=res.kappa, v=res.v, worst=res.worst, passes=res.passes,
+                    status=res.status)
 
     # -- sensitivities -----------------------------------------------------------
     def rollout_tangent(self, x0, v, t, k):

@@ -699,6 +699,76 @@ orc_result orc_grid(const orc_problem* p, const double* x0, double r, double v_p
 }
 
 /* ========================================================================= *
+ * Chance-constrained verdict (scenario approach with discarded scenarios).
+ * Sec. II-C builds the robust governor on N sampled disturbance sequences and
+ * states its guarantee probabilistically; the scenario method it draws on also
+ * allows a candidate whose predictions leave Y in a few of the samples.  Reading
+ * used here: a candidate is admissible when the steady-state test passes and at
+ * most q of the N scenario rollouts violate (m^k < 0).  Its worst margin is
+ * M_q(v) = min(m_(q+1), m_ss), with m_(q+1) the (q+1)-th smallest scenario
+ * margin (order statistic, +inf when q >= N), so that admissible <=> M_q >= 0
+ * and q = 0 is the robust verdict.
+ * ========================================================================= */
+
+static int orc_cmp_double(const void* a, const void* b)
+{
+    const double x = *(const double*)a, y = *(const double*)b;
+    return (x > y) - (x < y);
+}
+
+/* M_q(v); n_viol (nullable) receives the number of scenarios with m^k < 0. */
+double orc_candidate_q(const orc_problem* p, const double* x0, double v, uint32_t t, int32_t q,
+                       double* per_scen, int32_t* n_viol)
+{
+    const int32_t N = p->N;
+    double* m = (double*)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+    double mss = 0.0;
+    orc_candidate(p, x0, v, t, m, NULL, &mss);
+    int32_t viol = 0;
+    for (int32_t k = 0; k < N; ++k) {
+        if (per_scen) per_scen[k] = m[k];
+        if (m[k] < 0.0) viol++;
+    }
+    qsort(m, (size_t)N, sizeof(double), orc_cmp_double);
+    const double mq = (q < N) ? m[q] : INFINITY;
+    free(m);
+    if (n_viol) *n_viol = viol;
+    return mq < mss ? mq : mss;
+}
+
+/* Alg. 1 (as defined at orc_bisect) on the chance-constrained verdict M_q >= 0. */
+orc_result orc_bisect_q(const orc_problem* p, const double* x0, double r, double v_prev,
+                        uint32_t t, int32_t K, int32_t q)
+{
+    orc_result res = {0.0, v_prev, -INFINITY, 0, 1};
+    double M = orc_candidate_q(p, x0, orc_candidate_v(1.0, r, v_prev), t, q, NULL, NULL);
+    res.passes = 1;
+    if (M >= 0.0) {
+        res.kappa = 1.0;
+        res.v = r;
+        res.worst = M;
+        res.status = 0;
+        return res;
+    }
+    double lo = 0.0, hi = 1.0;
+    for (int32_t h = 0; h < K; ++h) {
+        const double mid = (lo + hi) / 2.0;
+        M = orc_candidate_q(p, x0, orc_candidate_v(mid, r, v_prev), t, q, NULL, NULL);
+        res.passes += 1;
+        if (M >= 0.0) {
+            lo = mid;
+            res.worst = M;
+            res.status = 0;
+        } else {
+            hi = mid;
+        }
+    }
+    res.kappa = res.status == 0 ? lo : 0.0;
+    res.v = res.status == 0 ? orc_candidate_v(lo, r, v_prev) : v_prev;
+    return res;
+}
+
+/* ========================================================================= *
  * Closed loop (Fig. 1): the RG picks v_t from (x_t, v_{t-1}, r_t), the plant
  * advances one step under v_t and the true disturbance (Eq. (4)).
  * ========================================================================= */

@@ -111,6 +111,12 @@ orc_result orc_alg2(const orc_problem* p, const double* x0, double r, double v_p
 orc_result orc_grid(const orc_problem* p, const double* x0, double r, double v_prev,
                     uint32_t t, int32_t M, int32_t refine, uint8_t* Pmat);
 
+/* ---- chance-constrained verdict (at most q violating scenarios) --------- */
+double orc_candidate_q(const orc_problem* p, const double* x0, double v, uint32_t t, int32_t q,
+                       double* per_scen, int32_t* n_viol);
+orc_result orc_bisect_q(const orc_problem* p, const double* x0, double r, double v_prev,
+                        uint32_t t, int32_t K, int32_t q);
+
 /* ---- closed loop ------------------------------------------------------- */
 void orc_plant_step(const orc_problem* p, const double* x, double v, uint32_t t, double* xn);
 int32_t orc_closed_loop(const orc_problem* p, const double* x0, double v0, const double* r_seq,

@@ -437,17 +437,22 @@ def test_closed_loop_search_forms_graph_equals_eager(R, O, mode):
     b = _gov(R, p, **kw).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=False)
     for key in ("kappa", "v", "x"):
         assert np.array_equal(a[key], b[key]), (mode, key)
-    if mode == "newton":
-        return
     o = O.Oracle(p, nthreads=8)
     v_prev = 0.0
+    searched = 0
     for s in range(len(r_seq)):
         if mode == "grid":
             ref = o.grid(a["x"][s], r_seq[s], v_prev, s, 17, 4)
         else:
             ref = o.bisect(a["x"][s], r_seq[s], v_prev, s, 12)
-        assert a["kappa"][s] == ref["kappa"], (mode, s, a["kappa"][s], ref["kappa"])
+        if mode == "newton":
+            # Newton's result is the admissible end of a bracket of width <= 2^-12
+            assert abs(a["kappa"][s] - ref["kappa"]) <= 2.0 ** -12, (s, a["kappa"][s], ref["kappa"])
+        else:
+            assert a["kappa"][s] == ref["kappa"], (mode, s, a["kappa"][s], ref["kappa"])
+        searched += ref["passes"] > 1
         v_prev = a["v"][s]
+    assert searched > 0  # the reference switches force searches below kappa = 1
 
 
 def test_speculation_across_chunks_and_graph_cycles(R, O):
