@@ -260,6 +260,11 @@ def run_extras(args):
     print(json.dumps(out))
 
 
+def progress(msg):
+    """One progress line on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def child(args, *extra):
     proc = subprocess.run([sys.executable, os.path.abspath(__file__), *extra], capture_output=True,
                           text=True)
@@ -345,6 +350,7 @@ def main():
         sched["speculate"] = args.speculate
     if not args.no_autotune and args.tune_steps > 0:
         tuned = child(args, "--autotune-only", "--tune-steps", str(args.tune_steps))
+        progress(f"autotuned schedule {tuned}")
         sched = dict(depth=tuned["depth"], lanes=tuned["lanes"], block=tuned["block"],
                      predict=bool(tuned["predict"]), speculate=int(tuned["speculate"]))
     g = rg.Governor(p, band=wl["band"], K=wl["K"], max_T=256, **sched)
@@ -374,6 +380,7 @@ def main():
         outs.append(_loop(g, x0, v0, r_seq, True))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    progress(f"{args.steps} timed closed loops: {elapsed:.3f} s")
     out = outs[0]
     same = all(np.array_equal(o["v"], out["v"]) and np.array_equal(o["x"], out["x"]) for o in outs)
     graph_same = bool(np.array_equal(out_e["v"], out["v"]))
@@ -386,6 +393,7 @@ def main():
             kap = np.asarray(om.pop("kappa"))
             om["same_closed_loop_as_headline"] = bool(np.array_equal(kap, out["kappa"]))
             modes[label] = om
+            progress(f"search form {label}: {om['ms_per_update']:.3f} ms per update")
         extras = child(args, "--extras-only", "--extra-updates", str(args.extra_updates))
 
     K = args.steps
@@ -466,6 +474,7 @@ def main():
                      "achieved_hbm_gbs": prof["lane_steps"] * BYTES_PER_STEP_LQ4 / kern_s / 1e9
                      if kern_s > 0 else 0.0},
     }
+    progress("other workloads done")
     if not args.no_cpu_baseline:
         base, kappas = cpu_baseline(wl, args.cpu_seconds, args.cpu_single_seconds)
         n = len(kappas)

@@ -150,6 +150,14 @@ typedef struct rg_options {
                               t + j's probe keeps a margin of at least the band, step t + j is
                               decided (kappa = 1) without a round of its own.  The results are
                               those of sequential bisection either way.  0: off. */
+    int32_t chance_q;      /* chance-constrained verdict (scenario approach with discarded
+                              samples, Sec. II-C): a candidate is admissible when the
+                              steady-state test passes and at most chance_q of the N scenario
+                              rollouts leave Y; its worst margin is then the (chance_q + 1)-th
+                              smallest scenario margin (or m_ss if smaller).  0 (default): the
+                              robust verdict, every scenario.  > 0: one lane per scenario,
+                              bisection or grid search (Newton: RG_E_NOTSUP), per-scenario
+                              margin keys in the workspace (8 B x 128 x N). */
 } rg_options;
 
 typedef struct rg_step_info {
@@ -301,7 +309,8 @@ int rg_get_profile(const rg_handle* h, rg_profile* out);
  * v = v_prev + kappa (r - v_prev)); dtheta_out (nullable, [n_theta]) =
  * d/d(nominal coefficients) through theta^k = theta_nom * factor_k.  The margin
  * is not differentiable where the minimiser changes; the derivative returned
- * there is that of the first minimiser.  t is not advanced. */
+ * there is that of the first minimiser.  t is not advanced.  RG_E_NOTSUP for a
+ * handle with the chance-constrained verdict (chance_q > 0). */
 int rg_grad(rg_handle* h, const double* x, double r, double v_prev, double kappa,
             const float* upstream, double* margin_out, double* dkappa_out, double* dtheta_out);
 

@@ -35,6 +35,9 @@ struct rg_handle {
   std::string err;
   // captured generic closed-loop rounds: kGraphRounds of them, and one
   hipGraphExec_t round_graph[2] = {};
+  // host copy of a fresh search record (uploaded by ensure_workspace and by
+  // every allocation-free step); allocated with the handle
+  DevSearch* srch_tmpl = nullptr;
   // profiling
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -89,7 +92,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace layout: offsets of each buffer inside one allocation.
 struct Layout {
-  size_t st, srch, res, r_seq, x_hist, wpair[kPairs], thpair[kPairs], rlist, per_m, per_j, scratch;
+  size_t st, srch, res, r_seq, x_hist, wpair[kPairs], thpair[kPairs], rlist, per_m, per_j, per_key;
+  size_t scratch;
   size_t grad, adj_k, adj_w, adj_m, adj_dv, adj_dth, adj_ckpt, adj_seg;
   size_t seg_m, seg_j, seg_r, seg_x, seg_a, seg_cv, seg_ct, seg_scr, total;
 };
@@ -120,6 +124,7 @@ Layout layout_of(const rg_handle* h) {
   L.rlist = take(sizeof(int2) * (size_t)kCMax * N);
   L.per_m = take(sizeof(float) * (size_t)kCMax * N);
   L.per_j = take(sizeof(int32_t) * (size_t)kCMax * N);
+  L.per_key = take(h->opt.chance_q > 0 ? sizeof(unsigned long long) * (size_t)kCMax * N : 0);
   L.scratch = take(sizeof(double) * kCMax * 4);
   const size_t n = (size_t)pr.p.n, Kc = (size_t)h->opt.Kc;
   L.grad = take(sizeof(DevGrad));
@@ -144,7 +149,9 @@ Layout layout_of(const rg_handle* h) {
 }
 
 int lanes_for(const rg_handle* h) {
-  const bool quad_ok = h->pr.p.kind == RG_PLANT_LQ4 && h->opt.precision == RG_PREC_F32_RECHECK;
+  // the quad kernel stops a wave at its first violation: robust verdict only
+  const bool quad_ok = h->pr.p.kind == RG_PLANT_LQ4 && h->opt.precision == RG_PREC_F32_RECHECK &&
+                       h->opt.chance_q == 0;
   if (h->opt.lanes == 4) return quad_ok ? 4 : 1;
   if (h->opt.lanes == 1) return 1;
   return quad_ok ? 4 : 1;
@@ -195,6 +202,35 @@ void plan(rg_handle* h) {
   if (1 + sp > h->cfg.cmax_round) h->cfg.cmax_round = 1 + sp;
 }
 
+// Search record of a fresh handle: configuration, no step in progress, no
+// prediction, empty steady-state cache.
+void fill_search(const rg_handle* h, DevSearch* S, int32_t spec_depth) {
+  memset(S, 0, sizeof(DevSearch));
+  S->mode = h->opt.search == RG_SEARCH_GRID ? kGrid
+            : h->opt.search == RG_SEARCH_NEWTON ? kNewton : kBisect;
+  S->delta = std::ldexp(1.0, -h->opt.K);
+  S->predict = h->opt.search == RG_SEARCH_BISECT ? h->opt.predict : 0;
+  S->pred = std::nan("");
+  S->K = h->opt.K;
+  S->depth = h->opt.depth;
+  S->M = h->opt.M;
+  S->refine = h->opt.refine;
+  S->precision = h->opt.precision;
+  S->ss_check = h->pr.c.ss_check;
+  S->n_c = h->pr.c.n_c;
+  S->ny = h->pr.p.ny;
+  S->eps = h->pr.c.eps;
+  for (int r = 0; r < kNC; ++r) S->g[r] = h->pr.c.g[r];
+  for (int i = 0; i < kNC * kMaxY; ++i) S->F[i] = h->pr.c.F[i];
+  S->done = 1;
+  for (int i = 0; i < kMssCache; ++i) S->mss_v[i] = std::nan("");  // empty cache
+  S->spec_depth = spec_depth;
+  S->spec_n = 0;
+  S->spec_used = 0;
+  S->band = h->opt.band;
+  S->q = h->opt.chance_q;
+}
+
 int ensure_workspace(rg_handle* h) {
   if (h->ws_ready) return RG_OK;
   const Layout L = layout_of(h);
@@ -222,6 +258,7 @@ int ensure_workspace(rg_handle* h) {
   b.rlist = (int2*)(base + L.rlist);
   b.per_m = (float*)(base + L.per_m);
   b.per_j = (int32_t*)(base + L.per_j);
+  b.per_key = h->opt.chance_q > 0 ? (unsigned long long*)(base + L.per_key) : nullptr;
   b.scratch = (double*)(base + L.scratch);
   b.scratch_bytes = sizeof(double) * kCMax * 4;
   b.grad = (DevGrad*)(base + L.grad);
@@ -241,34 +278,10 @@ int ensure_workspace(rg_handle* h) {
   b.seg_ct = (double*)(base + L.seg_ct);
   b.seg_scr = (float*)(base + L.seg_scr);
   // Search configuration.
-  DevSearch* S = new (std::nothrow) DevSearch;
-  if (!S) return fail(h, RG_E_NOMEM, "host allocation");
-  memset(S, 0, sizeof(DevSearch));
-  S->mode = h->opt.search == RG_SEARCH_GRID ? kGrid
-            : h->opt.search == RG_SEARCH_NEWTON ? kNewton : kBisect;
-  S->delta = std::ldexp(1.0, -h->opt.K);
-  S->predict = h->opt.search == RG_SEARCH_BISECT ? h->opt.predict : 0;
-  S->pred = std::nan("");
-  S->K = h->opt.K;
-  S->depth = h->opt.depth;
-  S->M = h->opt.M;
-  S->refine = h->opt.refine;
-  S->precision = h->opt.precision;
-  S->ss_check = h->pr.c.ss_check;
-  S->n_c = h->pr.c.n_c;
-  S->ny = h->pr.p.ny;
-  S->eps = h->pr.c.eps;
-  for (int r = 0; r < kNC; ++r) S->g[r] = h->pr.c.g[r];
-  for (int i = 0; i < kNC * kMaxY; ++i) S->F[i] = h->pr.c.F[i];
-  S->done = 1;
-  for (int i = 0; i < kMssCache; ++i) S->mss_v[i] = std::nan("");  // empty cache
-  S->spec_depth = spec_allowed(h);
-  S->spec_n = 0;
-  S->spec_used = 0;
-  S->band = h->opt.band;
-  hipError_t e = hipMemcpyAsync(b.srch, S, sizeof(DevSearch), hipMemcpyHostToDevice, h->stream);
+  fill_search(h, h->srch_tmpl, spec_allowed(h));
+  hipError_t e =
+      hipMemcpyAsync(b.srch, h->srch_tmpl, sizeof(DevSearch), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  delete S;
   if (e != hipSuccess) return fail_hip(h, "upload search configuration", e);
   h->ws_ready = true;
   return RG_OK;
@@ -329,42 +342,47 @@ void draw_pair(const rg_handle* h, int i, float** w, float** th) {
 
 // Enqueue one RG step of rg_step: draws and round-0 setup, the planned rounds,
 // the result record.
-hipError_t enqueue_step(rg_handle* h) {
+// pr and b default to the handle's own problem and workspace; the
+// allocation-free step passes its inline-draw problem and static scratch (and
+// profiling off, which would create events).
+hipError_t enqueue_step(rg_handle* h, const Problem& pr, const DevBuffers& b, bool profile) {
   hipError_t e;
   const int prec = h->opt.precision;
   const double band = prec == RG_PREC_F32_RECHECK ? h->opt.band : 0.0;
-  const bool streamed = h->pr.s.rng_mode == RG_RNG_STREAM;
-  DevBuffers b = h->b;
+  const bool streamed = pr.s.rng_mode == RG_RNG_STREAM;
   // draws and round-0 setup share a launch in stream mode
-  e = streamed ? launch_gen_setup(h->pr, b, 0, h->stream) : launch_setup(h->pr, b, 0, h->stream);
+  e = streamed ? launch_gen_setup(pr, b, 0, h->stream) : launch_setup(pr, b, 0, h->stream);
   if (e != hipSuccess) return e;
   const bool newton = h->opt.search == RG_SEARCH_NEWTON;
   // with FP32 rollouts the recheck launch ends with the decision (the Newton
   // decision needs the derivative first)
-  const bool fused_decide = prec == RG_PREC_F32_RECHECK && !newton;
+  const bool chance = h->opt.chance_q > 0;
+  const bool fused_decide = prec == RG_PREC_F32_RECHECK && !newton && !chance;
   for (int r = 0; r < h->cfg.rounds; ++r) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (h->profiling) {
+    if (profile) {
       if ((e = next_event(h, &e0)) != hipSuccess || (e = next_event(h, &e1)) != hipSuccess) return e;
       if ((e = hipEventRecord(e0, h->stream)) != hipSuccess) return e;
     }
     // the Newton iterate keeps checkpoints for its derivative
-    if ((e = launch_rollout(h->pr, band, prec, h->opt.early_exit, 0, h->cfg, b, h->stream,
+    if ((e = launch_rollout(pr, band, prec, h->opt.early_exit, 0, h->cfg, b, h->stream,
                             newton ? -1 : -2, h->opt.Kc)) != hipSuccess)
       return e;
-    if (h->profiling && (e = hipEventRecord(e1, h->stream)) != hipSuccess) return e;
+    if (profile && (e = hipEventRecord(e1, h->stream)) != hipSuccess) return e;
     if (prec == RG_PREC_F32_RECHECK &&
-        (e = launch_recheck(h->pr, h->opt.early_exit, h->cfg, b, h->stream, fused_decide)) !=
+        (e = launch_recheck(pr, h->opt.early_exit, h->cfg, b, h->stream, fused_decide)) !=
             hipSuccess)
       return e;
     if (newton) {  // derivative of the Newton iterate's worst margin (segment adjoint)
-      if ((e = launch_grad_prepare(h->pr, b, -1, 1, h->stream)) != hipSuccess) return e;
-      if ((e = launch_seg_grad(h->pr, h->opt.Kc, -1, b, h->stream)) != hipSuccess) return e;
-      if ((e = launch_grad_reduce(b, 1, h->pr.p.nth, -1, h->stream)) != hipSuccess) return e;
+      if ((e = launch_grad_prepare(pr, b, -1, 1, h->stream)) != hipSuccess) return e;
+      if ((e = launch_seg_grad(pr, h->opt.Kc, -1, b, h->stream)) != hipSuccess) return e;
+      if ((e = launch_grad_reduce(b, 1, pr.p.nth, -1, h->stream)) != hipSuccess) return e;
     }
-    if (!fused_decide && (e = launch_decide(h->pr, b, h->stream)) != hipSuccess) return e;
+    if (chance && (e = launch_select_q(b, pr.s.N, h->cfg.cmax_round, 0, h->stream)) != hipSuccess)
+      return e;
+    if (!fused_decide && (e = launch_decide(pr, b, h->stream)) != hipSuccess) return e;
   }
-  return launch_finalize(h->pr, 0, b, h->stream);
+  return launch_finalize(pr, 0, b, h->stream);
 }
 
 // Enqueue one generic round of the closed loop: whatever round the current
@@ -386,7 +404,8 @@ hipError_t enqueue_round(rg_handle* h) {
   float* gen_w = streamed ? b.wpair[0] : nullptr;
   float* gen_th = streamed ? b.thpair[0] : nullptr;
   const bool newton = h->opt.search == RG_SEARCH_NEWTON;
-  const bool fused_decide = prec == RG_PREC_F32_RECHECK && !newton;
+  const bool chance = h->opt.chance_q > 0;
+  const bool fused_decide = prec == RG_PREC_F32_RECHECK && !newton && !chance;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (h->profiling) {
     if ((e = next_event(h, &e0)) != hipSuccess || (e = next_event(h, &e1)) != hipSuccess) return e;
@@ -405,6 +424,8 @@ hipError_t enqueue_round(rg_handle* h) {
     if ((e = launch_seg_grad(h->pr, h->opt.Kc, -1, b, h->stream)) != hipSuccess) return e;
     if ((e = launch_grad_reduce(b, 1, h->pr.p.nth, -1, h->stream)) != hipSuccess) return e;
   }
+  if (chance && (e = launch_select_q(b, h->pr.s.N, h->cfg.cmax_round, 0, h->stream)) != hipSuccess)
+    return e;
   if (!fused_decide && (e = launch_decide(h->pr, b, h->stream)) != hipSuccess) return e;
   return launch_finalize(h->pr, 1, b, h->stream, 1, 1);
 }
@@ -446,6 +467,7 @@ int rg_default_options(rg_options* opt) {
   opt->persistent_wgs = 0;
   opt->predict = 1;
   opt->speculate = kSpecMax;
+  opt->chance_q = 0;
   return RG_OK;
 }
 
@@ -515,9 +537,17 @@ int rg_create(const rg_plant* plant, const rg_scenarios* scen, const rg_constrai
   if (o.predict != 0 && o.predict != 1) return fail(nullptr, RG_E_INVAL, "predict must be 0 or 1");
   if (o.speculate < 0 || o.speculate > kSpecMax)
     return fail(nullptr, RG_E_INVAL, "speculate must be 0.." + std::to_string(kSpecMax));
+  if (o.chance_q < 0) return fail(nullptr, RG_E_INVAL, "chance_q must be >= 0");
+  if (o.chance_q > 0 && o.search == RG_SEARCH_NEWTON)
+    return fail(nullptr, RG_E_NOTSUP, "the chance-constrained verdict has no Newton search");
 
   rg_handle* h = new (std::nothrow) rg_handle;
   if (!h) return fail(nullptr, RG_E_NOMEM, "host allocation");
+  h->srch_tmpl = new (std::nothrow) DevSearch;
+  if (!h->srch_tmpl) {
+    delete h;
+    return fail(nullptr, RG_E_NOMEM, "host allocation");
+  }
   memset(&h->pr, 0, sizeof(h->pr));
   PlantDesc& p = h->pr.p;
   p.kind = plant->kind; p.n = n; p.nw = nw; p.ny = ny; p.nth = nth;
@@ -546,6 +576,7 @@ int rg_destroy(rg_handle* h) {
   drop_graphs(h);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   if (h->ws_owned && h->ws) (void)hipFree(h->ws);
+  delete h->srch_tmpl;
   delete h;
   return RG_OK;
 }
@@ -611,7 +642,7 @@ int rg_step(rg_handle* h, const double* x, double r, double v_prev, double* v_ou
   int rc = ensure_workspace(h);
   if (rc) return rc;
   if ((rc = upload_state(h, x, r, v_prev))) return rc;
-  hipError_t e = enqueue_step(h);
+  hipError_t e = enqueue_step(h, h->pr, h->b, h->profiling);
   if (e != hipSuccess) return fail_hip(h, "enqueue RG step", e);
   h->gen_t = (long long)h->t;
   DevResult R;
@@ -654,6 +685,7 @@ int rg_margin(rg_handle* h, const double* x, double r, double v_prev, const doub
     cfg.cmax_round = m;
     HIPCHK(h, launch_rollout(h->pr, band, prec, 0, 1, cfg, h->b, h->stream));
     if (prec == RG_PREC_F32_RECHECK) HIPCHK(h, launch_recheck(h->pr, 0, cfg, h->b, h->stream));
+    if (h->opt.chance_q > 0) HIPCHK(h, launch_select_q(h->b, (int)N, m, 1, h->stream));
     HIPCHK(h, launch_collect(h->b, m, h->b.scratch, h->stream));
     HIPCHK(h, hipMemcpyAsync(out.data(), h->b.scratch, sizeof(double) * m, hipMemcpyDeviceToHost,
                              h->stream));
@@ -783,6 +815,8 @@ int rg_grad(rg_handle* h, const double* x, double r, double v_prev, double kappa
   if (!finite_array(x, h->pr.p.n) || !std::isfinite(r) || !std::isfinite(v_prev))
     return fail(h, RG_E_INVAL, "non-finite input");
   if (!(kappa >= 0.0 && kappa <= 1.0)) return fail(h, RG_E_INVAL, "kappa outside [0, 1]");
+  if (h->opt.chance_q > 0)
+    return fail(h, RG_E_NOTSUP, "rg_grad differentiates the robust worst margin (chance_q = 0)");
   const int N = h->pr.s.N;
   std::vector<int32_t> ks;
   std::vector<float> ws;
@@ -922,7 +956,8 @@ int rg_autotune(rg_handle* h, const double* x0, double v0, const double* r_seq, 
   if (rc) return rc;
   const rg_options own = h->opt;
   const uint32_t t0 = h->t;
-  const bool quad_ok = h->pr.p.kind == RG_PLANT_LQ4 && h->opt.precision == RG_PREC_F32_RECHECK;
+  const bool quad_ok = h->pr.p.kind == RG_PLANT_LQ4 && h->opt.precision == RG_PREC_F32_RECHECK &&
+                       h->opt.chance_q == 0;
   std::vector<rg_options> cands;
   for (int lanes : {4, 1}) {
     if (lanes == 4 && !quad_ok) continue;
@@ -1146,6 +1181,7 @@ int rg_batch_create(const rg_instance_desc* descs, int32_t count, const rg_optio
   if (o.precision != RG_PREC_F32_RECHECK)
     return bfail(nullptr, RG_E_NOTSUP, "batches run FP32 rollouts with the FP64 recheck");
   if (o.search != RG_SEARCH_BISECT) return bfail(nullptr, RG_E_NOTSUP, "batches use bisection");
+  if (o.chance_q != 0) return bfail(nullptr, RG_E_NOTSUP, "batches use the robust verdict");
   if (o.block != 0 && o.block != 64 && o.block != 128 && o.block != 256)
     return bfail(nullptr, RG_E_INVAL, "block must be 64, 128 or 256");
   if (o.persistent_wgs < 0) return bfail(nullptr, RG_E_INVAL, "persistent_wgs must be >= 0");

@@ -93,6 +93,15 @@ struct DevSearch {
   double mss_v[kMssCache];
   double mss_m[kMssCache];
   int32_t mss_next;
+  // Chance-constrained verdict (q > 0): a candidate is admissible when at most
+  // q scenarios violate.  nviol counts the certain violations of the rollouts
+  // (FP32 margin below -band, FP64 margin below 0), nviol64 the FP64-rechecked
+  // ones; dead / fail64 are raised once the count exceeds q.  keyq is the
+  // (q + 1)-th smallest per-scenario margin key of the candidate (~0: none).
+  int32_t q;
+  int32_t nviol[kCMax];
+  int32_t nviol64[kCMax];
+  unsigned long long keyq[kCMax];
 };
 
 // Result record of one RG step.
@@ -153,6 +162,10 @@ struct DevBuffers {
   int2* rlist;             // [cmax_round * N] recheck list (candidate, scenario)
   float* per_m;            // [cmax_round * N] per-scenario margins (rg_margin)
   int32_t* per_j;          // [cmax_round * N]
+  // [cmax_round * N] ordered keys of the per-scenario margins (chance-constrained
+  // verdict only: the FP32 or FP64 rollout margin, replaced by the FP64 value
+  // for rechecked scenarios)
+  unsigned long long* per_key;
   double* scratch;         // small staging area (trajectories, draws)
   size_t scratch_bytes;
   // adjoint
@@ -253,6 +266,9 @@ hipError_t launch_decide(const Problem& pr, const DevBuffers& b, hipStream_t st)
 hipError_t launch_finalize(const Problem& pr, int closed_loop, const DevBuffers& b,
                            hipStream_t st, int setup_next = 0, int when_done = 0);
 hipError_t launch_collect(const DevBuffers& b, int M, double* out_dev, hipStream_t st);
+// Chance-constrained verdict: (q + 1)-th smallest margin key of each candidate
+// (all = 0: only candidates still admissible).
+hipError_t launch_select_q(const DevBuffers& b, int N, int cmax_round, int all, hipStream_t st);
 hipError_t launch_draws(const Problem& pr, uint32_t t, int k0, int nk, int j0, int nj,
                         float* w_dev, double* th_dev, const DevBuffers& b, hipStream_t st);
 hipError_t launch_equilibrium(const Problem& pr, const DevBuffers& b, double v, double* out_dev,

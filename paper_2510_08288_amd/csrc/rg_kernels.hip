@@ -45,6 +45,7 @@ struct RollArgs {
   DevSearch* srch;
   float* per_m;
   int32_t* per_j;
+  unsigned long long* per_key;  // chance-constrained verdict: per-scenario margin keys
   int2* rlist;
   // checkpoints of one candidate's scenarios for the segment derivative:
   // ckpt[(s * n + i) * N + k] = state component i of scenario k at step s * Kc
@@ -369,18 +370,27 @@ __global__ void __launch_bounds__(256) k_rollout(const RollArgs<KIND, T> a) {
   __shared__ unsigned long long sh[16];
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t t = a.st->t;
+  const int q = S->q;  // chance-constrained verdict: up to q violating scenarios
   T m = t_inf<T>();
   int jb = 0, ns = 0;
   if (k < a.N) {
     bool stopped = false;  // the candidate died while this wave ran (no recheck needed)
-    m = rollout_lane<KIND, T, RNG, INJ, RollArgs<KIND, T>, CKPT, true>(
-        a, early, (T)S->v[c], k, t, &S->dead[c], jb, ns, nullptr, ck, &stopped);
+    if (q > 0) {
+      // a violating lane stops alone; the candidate dies once more than q did
+      m = rollout_lane<KIND, T, RNG, INJ, RollArgs<KIND, T>, CKPT, false>(
+          a, early, (T)S->v[c], k, t, early ? &S->dead[c] : nullptr, jb, ns, nullptr, ck);
+      a.per_key[(size_t)c * a.N + k] = ord64((double)m);
+    } else {
+      m = rollout_lane<KIND, T, RNG, INJ, RollArgs<KIND, T>, CKPT, true>(
+          a, early, (T)S->v[c], k, t, &S->dead[c], jb, ns, nullptr, ck, &stopped);
+    }
     if (a.record) {
       a.per_m[(size_t)c * a.N + k] = (float)m;
       a.per_j[(size_t)c * a.N + k] = jb;
     }
     if (m < -a.band) {
-      __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (q == 0 || atomicAdd(&S->nviol[c], 1) >= q)
+        __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else if (m < a.band && !stopped) {
       const int idx = atomicAdd(&S->n_recheck, 1);
       a.rlist[idx] = make_int2(c, k);
@@ -806,11 +816,19 @@ __global__ void __launch_bounds__(64) k_recheck(const RollArgs<KIND, double> a,
       continue;
     int jb = 0, ns = 0;
     const int early = a.early;
-    const double m = rollout_lane<KIND, double, RNG, INJ>(a, early, S->v[c], k, t,
-                                                          early ? &S->fail64[c] : nullptr, jb,
-                                                          ns, nullptr);
+    const int q = S->q;
+    // chance-constrained verdict: one FP64 violation refuses the candidate only
+    // once more than q scenarios violate, so the lane does not stop on others'
+    const double m = rollout_lane<KIND, double, RNG, INJ>(
+        a, early, S->v[c], k, t, early && q == 0 ? &S->fail64[c] : nullptr, jb, ns, nullptr);
     atomicMin(&S->key64[c], ord64(m));
-    if (m < 0.0) __hip_atomic_store(&S->fail64[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (q > 0) {
+      a.per_key[(size_t)c * a.N + k] = ord64(m);
+      if (m < 0.0 && S->nviol[c] + atomicAdd(&S->nviol64[c], 1) >= q)
+        __hip_atomic_store(&S->fail64[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (m < 0.0) {
+      __hip_atomic_store(&S->fail64[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
   if (decide) last_block_decides<KIND>(ctl);
 }
@@ -925,6 +943,10 @@ __device__ __forceinline__ bool cand_feasible(const DevSearch* S, int c) {
 }
 
 __device__ __forceinline__ double cand_worst_p(const DevSearch* S, int c, int precision) {
+  if (S->q > 0) {  // chance-constrained: the (q + 1)-th smallest scenario margin
+    const double wq = S->keyq[c] == ~0ull ? INFINITY : unord64(S->keyq[c]);
+    return (S->mss[c] < wq) ? S->mss[c] : wq;
+  }
   double w;
   const double kall = S->key_all[c] == ~0ull ? INFINITY : key_margin(S->key_all[c], precision);
   if (S->dead[c] || S->key64[c] == ~0ull) {
@@ -1003,6 +1025,9 @@ __device__ void prepare_candidates(const typename Plant<KIND, double>::Coef& pc,
     S->key64[c] = ~0ull;
     S->dead[c] = 0;
     S->fail64[c] = 0;
+    S->nviol[c] = 0;
+    S->nviol64[c] = 0;
+    S->keyq[c] = ~0ull;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1462,6 +1487,57 @@ __global__ void __launch_bounds__(64) k_finalize(const RollArgs<KIND, double> a,
 // rg_margin: worst margin of each listed candidate.
 __global__ void k_collect(const DevSearch* S, int M, double* out) {
   for (int c = threadIdx.x; c < M; c += blockDim.x) out[c] = cand_worst(S, c);
+}
+
+// Chance-constrained verdict: the (q + 1)-th smallest of a candidate's N
+// per-scenario margin keys (one workgroup per candidate), by radix selection
+// on the 64-bit ordered keys, eight bits per pass from the top: each pass
+// counts the keys that share the prefix found so far into 256 bins and keeps
+// the bin holding the wanted rank.  Exact, duplicates included.  In decision
+// mode (all == 0) only candidates still admissible are selected: every one of
+// their lanes ran (violating lanes only up to their first violation, which
+// keeps them below every admissible lane).
+__global__ void __launch_bounds__(256) k_select_q(DevSearch* S, const unsigned long long* per_key,
+                                                  int N, int all) {
+  const int c = blockIdx.x;
+  __shared__ int hist[256];
+  __shared__ unsigned long long s_prefix;
+  __shared__ int s_rank;
+  if (S->done || c >= S->n_cand) return;  // uniform over the workgroup
+  const int q = S->q;
+  if (q <= 0) return;
+  if ((!all && !cand_feasible(S, c)) || q >= N) {
+    if (threadIdx.x == 0) S->keyq[c] = ~0ull;
+    return;
+  }
+  const unsigned long long* keys = per_key + (size_t)c * N;
+  if (threadIdx.x == 0) {
+    s_prefix = 0ull;
+    s_rank = q;
+  }
+  unsigned long long mask = 0ull;
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    const unsigned long long prefix = s_prefix;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+      const unsigned long long key = keys[i];
+      if ((key & mask) == prefix) atomicAdd(&hist[(int)((key >> shift) & 255ull)], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int rank = s_rank, bin = 0;
+      while (bin < 255 && rank >= hist[bin]) {
+        rank -= hist[bin];
+        ++bin;
+      }
+      s_rank = rank;
+      s_prefix = prefix | ((unsigned long long)bin << shift);
+    }
+    mask |= 255ull << shift;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) S->keyq[c] = s_prefix;
 }
 
 struct ThetaNominal {
@@ -2271,6 +2347,7 @@ static RollArgs<KIND, T> make_args(const Problem& pr, double band, int early, in
   a.srch = b.srch;
   a.per_m = b.per_m;
   a.per_j = b.per_j;
+  a.per_key = b.per_key;
   a.rlist = b.rlist;
   return a;
 }
@@ -2539,6 +2616,11 @@ hipError_t launch_finalize(const Problem& pr, int closed_loop, const DevBuffers&
                        make_ctl<K>(pr, b, closed_loop), setup_next, when_done);
     return hipGetLastError();
   });
+}
+
+hipError_t launch_select_q(const DevBuffers& b, int N, int cmax_round, int all, hipStream_t st) {
+  hipLaunchKernelGGL(k_select_q, dim3(cmax_round), dim3(256), 0, st, b.srch, b.per_key, N, all);
+  return hipGetLastError();
 }
 
 hipError_t launch_collect(const DevBuffers& b, int M, double* out_dev, hipStream_t st) {

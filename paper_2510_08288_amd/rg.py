@@ -62,7 +62,7 @@ class rg_options(C.Structure):
                 ("refine", C.c_int32), ("early_exit", C.c_int32), ("block", C.c_int32),
                 ("max_T", C.c_int32), ("lanes", C.c_int32), ("Kc", C.c_int32),
                 ("persistent_wgs", C.c_int32), ("predict", C.c_int32),
-                ("speculate", C.c_int32)]
+                ("speculate", C.c_int32), ("chance_q", C.c_int32)]
 
 
 class rg_instance_desc(C.Structure):
@@ -169,7 +169,8 @@ class Governor:
                  K: int = 12, search: int = SEARCH_BISECT, depth: int = 0, M: int = 64,
                  refine: int = 6, early_exit: bool = True, block: int = 0, max_T: int = 256,
                  rng_mode: int = RNG_STREAM, lanes: int = 0, Kc: int = 50,
-                 predict: bool = True, speculate: int = 7, torch_workspace: bool = True):
+                 predict: bool = True, speculate: int = 7, chance_q: int = 0,
+                 torch_workspace: bool = True):
         import torch
         self.L = load_library()
         self.problem = problem
@@ -192,6 +193,7 @@ class Governor:
         opt.Kc = Kc
         opt.predict = int(predict)
         opt.speculate = int(speculate)
+        opt.chance_q = int(chance_q)
         h = _vp()
         rc = self.L.rg_create(C.byref(plant), C.byref(scen), C.byref(cons), int(p.H), float(p.dt),
                               C.byref(opt), C.byref(h))

@@ -1,0 +1,97 @@
+"""GPU parity of the chance-constrained verdict (at most q of N scenarios may
+violate; q = 0 is the robust verdict) against the FP64 oracle: kappa of the
+bisection identical for several q, both precisions and both plants, the
+order-statistic margin M_q of explicit candidates within 1e-5, and a closed
+loop checked update by update."""
+import numpy as np
+import pytest
+
+from paper_2510_08288_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_2510_08288_amd import rg
+    rg.load_library()
+    return rg
+
+
+def _lq4_wide(N=300, H=400):
+    # a box wide enough that the scenario rollouts, not the steady state, bind
+    return W.lq4_problem(seed=24, N=N, H=H, dt=0.005, eps=0.01, w_half=0.4)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("q", [1, 3, 17, 299, 300, 400])
+def test_bisection_kappa_equals_oracle(R, oracle_mod, precision, q):
+    p = _lq4_wide()
+    o = oracle_mod.Oracle(p, nthreads=8)
+    x0, r, vp = np.zeros(4), 0.8, 0.3
+    g = R.Governor(p, precision=precision, chance_q=q)
+    assert g.options.lanes == 1
+    res = g.step(x0, r, vp)
+    g.close()
+    ref = o.bisect_q(x0, r, vp, 0, 12, q)
+    assert res["kappa"] == ref["kappa"], (q, res["kappa"], ref["kappa"])
+    assert res["status"] == ref["status"] and res["bisect_passes"] == ref["passes"]
+    if ref["status"] == 0:
+        assert abs(res["worst"] - ref["worst"]) <= TOL32 * max(1.0, abs(ref["worst"]))
+
+
+@pytest.mark.parametrize("q", [2, 9])
+def test_fc9_kappa_equals_oracle(R, oracle_mod, q):
+    p = W.fc9_problem(N=256, H=300, dt=0.002, w_half=0.05)
+    o = oracle_mod.Oracle(p, nthreads=8)
+    x0 = o.steady_margin(0.5)[1]
+    g = R.Governor(p, chance_q=q)
+    res = g.step(x0, 2.0, 0.5)
+    g.close()
+    ref = o.bisect_q(x0, 2.0, 0.5, 0, 12, q)
+    assert res["kappa"] == ref["kappa"], (q, res["kappa"], ref["kappa"])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_margin_order_statistic(R, oracle_mod, precision):
+    p = _lq4_wide(N=333, H=257)
+    o = oracle_mod.Oracle(p, nthreads=8)
+    x0, r, vp = np.array([0.1, -0.2, 0.05, 0.3]), 0.9, 0.2
+    kappas = [0.0, 0.5, 0.8125, 1.0]
+    for q in [1, 5, 40, 332, 333]:
+        g = R.Governor(p, precision=precision, chance_q=q)
+        out = g.margin(x0, r, vp, kappas)
+        g.close()
+        for i, kap in enumerate(kappas):
+            Mq, _, _ = o.candidate_q(x0, o.candidate_v(kap, r, vp), 0, q)
+            assert abs(out["margins"][i] - Mq) <= TOL32 * max(1.0, abs(Mq)), (q, kap)
+
+
+def test_q0_matches_the_robust_governor(R):
+    p = _lq4_wide(N=256, H=300)
+    a = R.Governor(p, lanes=1).step(np.zeros(4), 0.8, 0.3)
+    b = R.Governor(p, chance_q=0).step(np.zeros(4), 0.8, 0.3)
+    assert a["kappa"] == b["kappa"] and a["worst"] == b["worst"]
+
+
+def test_closed_loop_each_update_equals_oracle(R, oracle_mod):
+    p = _lq4_wide(N=160, H=250)
+    r_seq = W.reference_sequence(11, 12, switch_every=3, lo=-1.5, hi=1.5)
+    q = 4
+    g = R.Governor(p, chance_q=q)
+    a = g.closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    g.close()
+    g = R.Governor(p, chance_q=q)
+    b = g.closed_loop(np.zeros(4), 0.0, r_seq, use_graph=False)
+    g.close()
+    assert np.array_equal(a["kappa"], b["kappa"]) and np.array_equal(a["x"], b["x"])
+    o = oracle_mod.Oracle(p, nthreads=8)
+    v_prev = 0.0
+    for s in range(len(r_seq)):
+        ref = o.bisect_q(a["x"][s], r_seq[s], v_prev, s, 12, q)
+        assert a["kappa"][s] == ref["kappa"], (s, a["kappa"][s], ref["kappa"])
+        v_prev = a["v"][s]
