@@ -71,11 +71,19 @@ def test_margin_order_statistic(R, oracle_mod, precision):
             assert abs(out["margins"][i] - Mq) <= TOL32 * max(1.0, abs(Mq)), (q, kap)
 
 
-def test_q0_matches_the_robust_governor(R):
+@pytest.mark.parametrize("lanes", [1, 4])
+def test_q0_matches_the_robust_governor(R, lanes):
+    # same layout: bit-identical; the quad layout's FP64 recheck sums in another
+    # order than the one-lane recheck, so across layouts the worst margin agrees
+    # to rounding only
     p = _lq4_wide(N=256, H=300)
     a = R.Governor(p, lanes=1).step(np.zeros(4), 0.8, 0.3)
-    b = R.Governor(p, chance_q=0).step(np.zeros(4), 0.8, 0.3)
-    assert a["kappa"] == b["kappa"] and a["worst"] == b["worst"]
+    b = R.Governor(p, chance_q=0, lanes=lanes).step(np.zeros(4), 0.8, 0.3)
+    assert a["kappa"] == b["kappa"]
+    if lanes == 1:
+        assert a["worst"] == b["worst"]
+    else:
+        assert abs(a["worst"] - b["worst"]) <= 1e-12 * max(1.0, abs(a["worst"]))
 
 
 def test_closed_loop_each_update_equals_oracle(R, oracle_mod):
