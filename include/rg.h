@@ -77,14 +77,31 @@ enum rg_precision {
 enum rg_search {
     RG_SEARCH_BISECT = 0, /* Alg. 1 on the worst margin: kappa = 1 probe, then K halvings */
     RG_SEARCH_GRID = 1,   /* Alg. 3 / Eq. (5): M-point grid, then `refine` halvings */
-    RG_SEARCH_NEWTON = 2  /* safeguarded Newton on the worst margin M(kappa), derivative from
+    RG_SEARCH_NEWTON = 2, /* safeguarded Newton on the worst margin M(kappa), derivative from
                              the adjoint of the arg-min rollout (or the steady-state term):
                              each device round tests the iterate kappa_N, kappa_N -/+ 2^-K and
                              the bracket midpoint; a step at or past a bracket end moves
                              2^-K inside that end, a non-negative or non-finite slope falls
                              back to the midpoint (status RG_S_FALLBACK); stops at a bracket
                              of 2^-K (at most K+2 rounds).  FP32 precision only. */
+    RG_SEARCH_ALG2 = 3    /* Alg. 2: every scenario runs Alg. 1 (kappa = 1 probe, K halvings)
+                             on its own verdict (its rollout margin and the steady-state test),
+                             one GPU lane per scenario with no barrier between candidates;
+                             kappa = the smallest per-scenario result.  Equals BISECT when
+                             feasibility is monotone in kappa.  FP32 verdicts within the band
+                             are re-simulated in FP64 by the same lane.  rg_step only
+                             (rg_closed_loop, rg_autotune: RG_E_NOTSUP); K <= 16 (the
+                             steady-state margins of the 2^K tree nodes are tabulated first);
+                             chance_q must be 0.  The result's worst_margin is NaN (no
+                             candidate is evaluated over all scenarios; -inf if infeasible),
+                             candidates = bisect_passes = the single-scenario evaluations
+                             summed over scenarios. */
 };
+/* rg_step_info.flags */
+#define RG_FLAG_GRID_NONMONOTONE 1 /* RG_SEARCH_GRID: a grid row below the returned row i* was
+                                      refused (Eq. (5) takes the largest all-admissible row
+                                      regardless), i.e. feasibility is not monotone in kappa
+                                      on the grid */
 
 /* ---- descriptors -------------------------------------------------------------- */
 typedef struct rg_plant {
@@ -172,6 +189,7 @@ typedef struct rg_step_info {
     uint32_t t;            /* RG step counter used for the draws */
     uint64_t lane_steps;   /* RK4 steps executed by FP32/FP64 rollout lanes (speculative
                               candidates and early exits included; rechecks excluded) */
+    int32_t flags;         /* RG_FLAG_* diagnostics of the step */
 } rg_step_info;
 
 /* Kernel timing collected while profiling is on (rg_set_profiling). */

@@ -26,7 +26,9 @@ def build(verbose: bool = False) -> str:
         cmd = [HIPCC] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), file=sys.stderr)
-        subprocess.run(cmd, check=True, stderr=None if verbose else subprocess.PIPE)
+        proc = subprocess.run(cmd, stderr=None if verbose else subprocess.PIPE, text=True)
+        if proc.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {src}:\n{proc.stderr or ''}")
         objs.append(obj)
     tmp = LIB + ".tmp"
     subprocess.run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs,

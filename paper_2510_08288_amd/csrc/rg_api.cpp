@@ -90,10 +90,13 @@ bool finite_array(const double* a, int n) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Alg. 2 tabulates the steady-state margins of the 2^K bisection-tree nodes.
+constexpr int kAlg2MaxK = 16;
+
 // Workspace layout: offsets of each buffer inside one allocation.
 struct Layout {
   size_t st, srch, res, r_seq, x_hist, wpair[kPairs], thpair[kPairs], rlist, per_m, per_j, per_key;
-  size_t scratch;
+  size_t alg2_mss, scratch;
   size_t grad, adj_k, adj_w, adj_m, adj_dv, adj_dth, adj_ckpt, adj_seg;
   size_t seg_m, seg_j, seg_r, seg_x, seg_a, seg_cv, seg_ct, seg_scr, total;
 };
@@ -125,6 +128,7 @@ Layout layout_of(const rg_handle* h) {
   L.per_m = take(sizeof(float) * (size_t)kCMax * N);
   L.per_j = take(sizeof(int32_t) * (size_t)kCMax * N);
   L.per_key = take(h->opt.chance_q > 0 ? sizeof(unsigned long long) * (size_t)kCMax * N : 0);
+  L.alg2_mss = take(h->opt.search == RG_SEARCH_ALG2 ? sizeof(double) << h->opt.K : 0);
   L.scratch = take(sizeof(double) * kCMax * 4);
   const size_t n = (size_t)pr.p.n, Kc = (size_t)h->opt.Kc;
   L.grad = take(sizeof(DevGrad));
@@ -179,6 +183,7 @@ void plan(rg_handle* h) {
   LaunchCfg c;
   c.lanes = lanes;
   c.block = h->opt.block > 0 ? h->opt.block : 256;
+  c.chance = h->opt.chance_q > 0 ? 1 : 0;
   const int tree = (1 << d) - 1;
   if (h->opt.search == RG_SEARCH_NEWTON) {
     c.cmax_round = 4;
@@ -259,6 +264,7 @@ int ensure_workspace(rg_handle* h) {
   b.per_m = (float*)(base + L.per_m);
   b.per_j = (int32_t*)(base + L.per_j);
   b.per_key = h->opt.chance_q > 0 ? (unsigned long long*)(base + L.per_key) : nullptr;
+  b.alg2_mss = h->opt.search == RG_SEARCH_ALG2 ? (double*)(base + L.alg2_mss) : nullptr;
   b.scratch = (double*)(base + L.scratch);
   b.scratch_bytes = sizeof(double) * kCMax * 4;
   b.grad = (DevGrad*)(base + L.grad);
@@ -430,6 +436,26 @@ hipError_t enqueue_round(rg_handle* h) {
   return launch_finalize(h->pr, 1, b, h->stream, 1, 1);
 }
 
+// One RG step under Alg. 2: this step's draws (streamed mode), then the
+// per-scenario bisections and the result record.
+hipError_t enqueue_alg2(rg_handle* h) {
+  hipError_t e;
+  if (h->pr.s.rng_mode == RG_RNG_STREAM && (e = launch_gen(h->pr, h->b, h->stream)) != hipSuccess)
+    return e;
+  const int prec = h->opt.precision;
+  const double band = prec == RG_PREC_F32_RECHECK ? h->opt.band : 0.0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->profiling) {
+    if ((e = next_event(h, &e0)) != hipSuccess || (e = next_event(h, &e1)) != hipSuccess) return e;
+    if ((e = hipEventRecord(e0, h->stream)) != hipSuccess) return e;
+  }
+  if ((e = launch_alg2(h->pr, band, prec, h->opt.early_exit, h->opt.K, h->cfg.block, h->b,
+                       h->stream)) != hipSuccess)
+    return e;
+  if (h->profiling && (e = hipEventRecord(e1, h->stream)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
 int reset_search_schedule(rg_handle* h);
 
 void fill_info(const DevResult& R, rg_step_info* info) {
@@ -444,6 +470,7 @@ void fill_info(const DevResult& R, rg_step_info* info) {
   info->bisect_passes = R.passes_alg1;
   info->t = R.t;
   info->lane_steps = R.lane_steps;
+  info->flags = R.flags;
 }
 
 }  // namespace
@@ -521,8 +548,11 @@ int rg_create(const rg_plant* plant, const rg_scenarios* scen, const rg_constrai
     return fail(nullptr, RG_E_INVAL, "bad precision");
   if (!(o.band >= 0.0) || !std::isfinite(o.band)) return fail(nullptr, RG_E_INVAL, "bad band");
   if (o.K < 0 || o.K > 40) return fail(nullptr, RG_E_INVAL, "K must be in [0, 40]");
-  if (o.search != RG_SEARCH_BISECT && o.search != RG_SEARCH_GRID && o.search != RG_SEARCH_NEWTON)
+  if (o.search != RG_SEARCH_BISECT && o.search != RG_SEARCH_GRID && o.search != RG_SEARCH_NEWTON &&
+      o.search != RG_SEARCH_ALG2)
     return fail(nullptr, RG_E_INVAL, "bad search");
+  if (o.search == RG_SEARCH_ALG2 && o.K > kAlg2MaxK)
+    return fail(nullptr, RG_E_NOTSUP, "Alg. 2 keeps K <= 16 (steady-state table of 2^K nodes)");
   if (o.search == RG_SEARCH_NEWTON && o.precision != RG_PREC_F32_RECHECK)
     return fail(nullptr, RG_E_NOTSUP, "Newton search runs on the FP32 rollouts and adjoint");
   if (o.depth < 0 || o.depth > 6) return fail(nullptr, RG_E_INVAL, "depth must be in [0, 6]");
@@ -540,6 +570,8 @@ int rg_create(const rg_plant* plant, const rg_scenarios* scen, const rg_constrai
   if (o.chance_q < 0) return fail(nullptr, RG_E_INVAL, "chance_q must be >= 0");
   if (o.chance_q > 0 && o.search == RG_SEARCH_NEWTON)
     return fail(nullptr, RG_E_NOTSUP, "the chance-constrained verdict has no Newton search");
+  if (o.chance_q > 0 && o.search == RG_SEARCH_ALG2)
+    return fail(nullptr, RG_E_NOTSUP, "Alg. 2 bisects each scenario on the robust verdict");
 
   rg_handle* h = new (std::nothrow) rg_handle;
   if (!h) return fail(nullptr, RG_E_NOMEM, "host allocation");
@@ -642,7 +674,7 @@ int rg_step(rg_handle* h, const double* x, double r, double v_prev, double* v_ou
   int rc = ensure_workspace(h);
   if (rc) return rc;
   if ((rc = upload_state(h, x, r, v_prev))) return rc;
-  hipError_t e = enqueue_step(h, h->pr, h->b, h->profiling);
+  hipError_t e = h->opt.search == RG_SEARCH_ALG2 ? enqueue_alg2(h) : enqueue_step(h, h->pr, h->b, h->profiling);
   if (e != hipSuccess) return fail_hip(h, "enqueue RG step", e);
   h->gen_t = (long long)h->t;
   DevResult R;
@@ -708,6 +740,8 @@ int rg_closed_loop(rg_handle* h, const double* x0, double v0, const double* r_se
   if (!x0 || !r_seq || !v_out || T < 1) return fail(h, RG_E_INVAL, "bad arguments");
   if (!finite_array(x0, h->pr.p.n) || !std::isfinite(v0) || !finite_array(r_seq, T))
     return fail(h, RG_E_INVAL, "non-finite input");
+  if (h->opt.search == RG_SEARCH_ALG2)
+    return fail(h, RG_E_NOTSUP, "Alg. 2 runs single RG steps (rg_step)");
   int rc = ensure_workspace(h);
   if (rc) return rc;
   const int n = h->pr.p.n;
@@ -952,6 +986,8 @@ int rg_autotune(rg_handle* h, const double* x0, double v0, const double* r_seq, 
   if (!h) return RG_E_INVAL;
   if (!x0 || !r_seq || T < 1) return fail(h, RG_E_INVAL, "bad arguments");
   if (h->profiling) return fail(h, RG_E_STATE, "autotune with profiling enabled");
+  if (h->opt.search == RG_SEARCH_ALG2)
+    return fail(h, RG_E_NOTSUP, "Alg. 2 has no launch schedule to tune");
   int rc = ensure_workspace(h);
   if (rc) return rc;
   const rg_options own = h->opt;

@@ -102,6 +102,9 @@ struct DevSearch {
   int32_t nviol[kCMax];
   int32_t nviol64[kCMax];
   unsigned long long keyq[kCMax];
+  // Diagnostics of the current step (bit 0: the grid of Alg. 3 refused a row
+  // below the row it returns, so feasibility was not monotone in kappa there)
+  int32_t flags;
 };
 
 // Result record of one RG step.
@@ -110,6 +113,7 @@ struct DevResult {
   int32_t status, rounds, candidates, rechecks, passes_alg1;
   uint32_t t;
   unsigned long long lane_steps;
+  int32_t flags;
 };
 
 // Gradient of a candidate's margin (rg_grad, Newton search).
@@ -166,6 +170,7 @@ struct DevBuffers {
   // verdict only: the FP32 or FP64 rollout margin, replaced by the FP64 value
   // for rechecked scenarios)
   unsigned long long* per_key;
+  double* alg2_mss;        // [2^K] steady-state margins of the bisection tree's nodes (Alg. 2)
   double* scratch;         // small staging area (trajectories, draws)
   size_t scratch_bytes;
   // adjoint
@@ -193,6 +198,7 @@ struct LaunchCfg {
   int block;               // threads per rollout workgroup
   int cmax_round;          // largest candidate count of any round
   int rounds;              // device rounds per RG step
+  int chance;              // 1: chance-constrained verdict (q > 0), its own rollout kernels
 };
 
 // One instance of a batch (device memory, read-only in the kernels).  The
@@ -266,6 +272,10 @@ hipError_t launch_decide(const Problem& pr, const DevBuffers& b, hipStream_t st)
 hipError_t launch_finalize(const Problem& pr, int closed_loop, const DevBuffers& b,
                            hipStream_t st, int setup_next = 0, int when_done = 0);
 hipError_t launch_collect(const DevBuffers& b, int M, double* out_dev, hipStream_t st);
+// Alg. 2: per-scenario bisection (K halvings after the kappa = 1 probe) in one
+// lane per scenario, the minimum over scenarios, and the result record.
+hipError_t launch_alg2(const Problem& pr, double band, int precision, int early_exit, int K,
+                       int block, const DevBuffers& b, hipStream_t st);
 // Chance-constrained verdict: (q + 1)-th smallest margin key of each candidate
 // (all = 0: only candidates still admissible).
 hipError_t launch_select_q(const DevBuffers& b, int N, int cmax_round, int all, hipStream_t st);

@@ -357,8 +357,11 @@ __device__ __forceinline__ bool refused_by_steady_state(int early, DevSearch* S,
 }
 
 // Main rollout kernel: blockIdx.y = candidate of the round, blockIdx.x * block
-// + threadIdx.x = scenario.
-template <int KIND, class T, int RNG, int INJ, int CKPT>
+// + threadIdx.x = scenario.  CHANCE = 1 is the chance-constrained verdict
+// (handles with q > 0): lanes stop on their own and every lane's margin key is
+// kept.  It is a separate instantiation so that the robust kernel carries one
+// rollout body only (two bodies double the 9-state kernel's registers).
+template <int KIND, class T, int RNG, int INJ, int CKPT, int CHANCE = 0>
 __global__ void __launch_bounds__(256) k_rollout(const RollArgs<KIND, T> a) {
   if (gen_rows<KIND>(a)) return;
   DevSearch* S = a.srch;
@@ -370,12 +373,12 @@ __global__ void __launch_bounds__(256) k_rollout(const RollArgs<KIND, T> a) {
   __shared__ unsigned long long sh[16];
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t t = a.st->t;
-  const int q = S->q;  // chance-constrained verdict: up to q violating scenarios
+  const int q = CHANCE ? S->q : 0;  // chance-constrained verdict: up to q violating scenarios
   T m = t_inf<T>();
   int jb = 0, ns = 0;
   if (k < a.N) {
     bool stopped = false;  // the candidate died while this wave ran (no recheck needed)
-    if (q > 0) {
+    if constexpr (CHANCE) {
       // a violating lane stops alone; the candidate dies once more than q did
       m = rollout_lane<KIND, T, RNG, INJ, RollArgs<KIND, T>, CKPT, false>(
           a, early, (T)S->v[c], k, t, early ? &S->dead[c] : nullptr, jb, ns, nullptr, ck);
@@ -1093,6 +1096,7 @@ __device__ void setup_body(const typename Plant<KIND, double>::Coef& pc, DevStat
     S->passes_alg1 = 0;
     S->lane_steps = 0ull;
     S->fallbacks = 0;
+    S->flags = 0;
     if (decided) {
       S->done = 1;
       S->found = 1;
@@ -1281,6 +1285,10 @@ __device__ void decide_body(const typename Plant<KIND, double>::Coef& pc, const 
       int istar = -1;
       for (int i = 0; i < M; ++i)
         if (s_ok[i]) istar = i;
+      // Eq. (5) takes the largest all-admissible row even when a row below it
+      // was refused; say so in the step's diagnostics
+      for (int i = 0; i < istar; ++i)
+        if (!s_ok[i]) S->flags |= 1;
       S->passes_alg1 += M;
       if (istar < 0) {
         finished = true;
@@ -1452,6 +1460,7 @@ __device__ void finalize_body(const RollArgs<KIND, double>& a, DevResult* res, d
   R.passes_alg1 = S->passes_alg1;
   R.t = st->t;
   R.lane_steps = S->lane_steps;
+  R.flags = S->flags;
   res[idx] = R;
   if (closed_loop) {
     double x[P::n];
@@ -1538,6 +1547,143 @@ __global__ void __launch_bounds__(256) k_select_q(DevSearch* S, const unsigned l
     __syncthreads();
   }
   if (threadIdx.x == 0) S->keyq[c] = s_prefix;
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 2: each scenario runs the bisection of Alg. 1 on its own verdict (its
+// rollout margin together with the steady-state test): the kappa = 1 probe,
+// then K halvings; the result is the smallest per-scenario kappa.  One lane per
+// scenario walks its own path through the bisection tree with no barrier
+// between lanes, then one minimum over the grid.
+//
+// Tree nodes: node 0 is the kappa = 1 probe; heap node i >= 1 at depth
+// d = floor(log2 i) is the midpoint bisection reaches there,
+// kappa = (2 (i - 2^d) + 1) / 2^(d + 1) (exact: every bracket end is dyadic);
+// an admitted node continues at 2i + 1, a refused one at 2i.  The steady-state
+// margins of all 2^K nodes are computed first, one thread per node, so a lane
+// reads its node's margin instead of running Newton's method itself.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double alg2_node_kappa(int i) {
+  if (i == 0) return 1.0;
+  const int d = 31 - __builtin_clz((unsigned)i);
+  return ldexp((double)(2 * (i - (1 << d)) + 1), -(d + 1));
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(64) k_alg2_setup(const CtlArgs<KIND> ctl, double* mss_tab,
+                                                   int nodes) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  DevSearch* S = ctl.srch;
+  if (i == 0) {
+    S->key_all[0] = ~0ull;
+    S->n_recheck = 0;
+    S->lane_steps = 0ull;
+    S->passes_alg1 = 0;
+    S->flags = 0;
+  }
+  if (i < nodes) {
+    const double v = cand_v(alg2_node_kappa(i), ctl.st->r, ctl.st->v_prev);
+    mss_tab[i] = steady_margin<KIND>(ctl.pc, S, v);
+  }
+}
+
+// One lane per scenario.  T = float: a verdict whose FP32 margin lies within
+// the band of zero is re-simulated in FP64 by the same lane (a64); T = double:
+// FP64 throughout (a64 unused).
+template <int KIND, class T, int RNG, int INJ>
+__global__ void __launch_bounds__(256) k_alg2(const RollArgs<KIND, T> a,
+                                              const RollArgs<KIND, double> a64,
+                                              const double* mss_tab, int K) {
+  __shared__ unsigned long long sh[16];
+  DevSearch* S = a.srch;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t t = a.st->t;
+  const double r = a.st->r, vp = a.st->v_prev;
+  unsigned long long key = ~0ull;
+  int passes = 0, rechecks = 0;
+  unsigned long long steps = 0ull;
+  if (k < a.N) {
+    auto admits = [&](int node, double kap) -> bool {
+      passes += 1;
+      if (!(mss_tab[node] >= 0.0)) return false;  // refused by the steady-state test
+      const double v = cand_v(kap, r, vp);
+      int jb = 0, ns = 0;
+      const T m = rollout_lane<KIND, T, RNG, INJ>(a, a.early, (T)v, k, t, nullptr, jb, ns, nullptr);
+      steps += (unsigned long long)ns;
+      if constexpr (std::is_same<T, double>::value) {
+        return m >= 0.0;
+      } else {
+        if (m >= a.band) return true;
+        if (m < -a.band) return false;
+        rechecks += 1;
+        const double m64 =
+            rollout_lane<KIND, double, RNG, INJ>(a64, a64.early, v, k, t, nullptr, jb, ns, nullptr);
+        return m64 >= 0.0;
+      }
+    };
+    double kap = 1.0;
+    if (!admits(0, 1.0)) {
+      double lo = 0.0, hi = 1.0;
+      int node = 1;
+      for (int h = 0; h < K; ++h) {
+        const double mid = midpoint(lo, hi);
+        if (admits(node, mid)) {
+          lo = mid;
+          node = 2 * node + 1;
+        } else {
+          hi = mid;
+          node = 2 * node;
+        }
+      }
+      kap = lo;  // 0 when no candidate of this scenario was admitted
+    }
+    // kappa >= 0: its bit pattern orders like the value
+    key = (unsigned long long)__double_as_longlong(kap);
+  }
+  const unsigned long long kmin = block_min_u64(key, sh);
+  int wp = passes, wr = rechecks;
+  unsigned long long ws = steps;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    wp += __shfl_xor(wp, off);
+    wr += __shfl_xor(wr, off);
+    const uint32_t lo = __shfl_xor((uint32_t)ws, off);
+    const uint32_t hi = __shfl_xor((uint32_t)(ws >> 32), off);
+    ws += ((unsigned long long)hi << 32) | lo;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&S->passes_alg1, wp);
+    atomicAdd(&S->n_recheck, wr);
+    atomicAdd(&S->lane_steps, ws);
+  }
+  if (threadIdx.x == 0) atomicMin(&S->key_all[0], kmin);
+}
+
+// Result record of an Alg. 2 step: kappa = 0 means some scenario admitted no
+// candidate (status infeasible, v = v_prev).  No candidate is evaluated over
+// all scenarios, so the worst margin is not defined (NaN; -inf when
+// infeasible).
+__global__ void k_alg2_finalize(DevSearch* S, DevState* st, DevResult* res) {
+  if (threadIdx.x != 0) return;
+  const double kap = __longlong_as_double((long long)S->key_all[0]);
+  const int status = kap == 0.0 ? 1 : 0;
+  DevResult R;
+  R.kappa = kap;
+  R.v = status ? st->v_prev : cand_v(kap, st->r, st->v_prev);
+  R.worst = status ? -INFINITY : __longlong_as_double(0x7ff8000000000000ll);
+  R.status = status;
+  R.rounds = 1;
+  R.candidates = S->passes_alg1;
+  R.rechecks = S->n_recheck;
+  R.passes_alg1 = S->passes_alg1;
+  R.t = st->t;
+  R.lane_steps = S->lane_steps;
+  R.flags = 0;
+  res[0] = R;
+  S->kappa_res = kap;
+  S->v_res = R.v;
+  S->done = 1;
+  st->t = st->t + 1;
 }
 
 struct ThetaNominal {
@@ -2301,6 +2447,7 @@ __global__ void k_batch_finalize(BatchBuffers b) {
   R.passes_alg1 = S->passes_alg1;
   R.t = b.st[i].t;
   R.lane_steps = S->lane_steps;
+  R.flags = S->flags;
   b.res[i] = R;
   b.st[i].t = b.st[i].t + 1;
 }
@@ -2517,14 +2664,19 @@ hipError_t launch_rollout(const Problem& pr, double band, int precision, int ear
           a.Kc = Kc;
           a.ckpt_cand = ckpt_cand;
           set_gen(a);
-          if (ckpt)
+          if (cfg.chance)  // no Newton search, hence no checkpoints
+            hipLaunchKernelGGL((k_rollout<K, float, R, I, 0, 1>), grid, dim3(cfg.block), 0, st, a);
+          else if (ckpt)
             hipLaunchKernelGGL((k_rollout<K, float, R, I, 1>), grid, dim3(cfg.block), 0, st, a);
           else
             hipLaunchKernelGGL((k_rollout<K, float, R, I, 0>), grid, dim3(cfg.block), 0, st, a);
         } else {
           auto a = make_args<K, double>(pr, 0.0, early_exit, record, b);
           set_gen(a);
-          hipLaunchKernelGGL((k_rollout<K, double, R, I, 0>), grid, dim3(cfg.block), 0, st, a);
+          if (cfg.chance)
+            hipLaunchKernelGGL((k_rollout<K, double, R, I, 0, 1>), grid, dim3(cfg.block), 0, st, a);
+          else
+            hipLaunchKernelGGL((k_rollout<K, double, R, I, 0>), grid, dim3(cfg.block), 0, st, a);
         }
         return hipGetLastError();
       });
@@ -2733,6 +2885,36 @@ hipError_t launch_equilibrium(const Problem& pr, const DevBuffers& b, double v, 
   return by_kind(pr.p.kind, [&](auto kc) {
     constexpr int K = decltype(kc)::value;
     hipLaunchKernelGGL(k_equilibrium<K>, dim3(1), dim3(64), 0, st, make_ctl<K>(pr, b, 0), v, out_dev);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_alg2(const Problem& pr, double band, int precision, int early_exit, int K,
+                       int block, const DevBuffers& b, hipStream_t st) {
+  return by_kind(pr.p.kind, [&](auto kc) {
+    constexpr int KD = decltype(kc)::value;
+    const int nodes = 1 << K;
+    hipLaunchKernelGGL(k_alg2_setup<KD>, dim3(div_up(nodes, 64)), dim3(64), 0, st,
+                       make_ctl<KD>(pr, b, 0), b.alg2_mss, nodes);
+    const dim3 grid(div_up((size_t)pr.s.N, (size_t)block));
+    auto a64 = make_args<KD, double>(pr, 0.0, early_exit, 0, b);
+    hipError_t e = by_bit(pr.s.rng_mode, [&](auto rc) {
+      constexpr int R = decltype(rc)::value;
+      return by_bit(pr.s.inject, [&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        if (precision == 0) {
+          auto a = make_args<KD, float>(pr, band, early_exit, 0, b);
+          hipLaunchKernelGGL((k_alg2<KD, float, R, I>), grid, dim3(block), 0, st, a, a64,
+                             (const double*)b.alg2_mss, K);
+        } else {
+          hipLaunchKernelGGL((k_alg2<KD, double, R, I>), grid, dim3(block), 0, st, a64, a64,
+                             (const double*)b.alg2_mss, K);
+        }
+        return hipGetLastError();
+      });
+    });
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_alg2_finalize, dim3(1), dim3(64), 0, st, b.srch, b.st, b.res);
     return hipGetLastError();
   });
 }

@@ -30,6 +30,8 @@ PREC_F64 = 1
 SEARCH_BISECT = 0
 SEARCH_GRID = 1
 SEARCH_NEWTON = 2
+SEARCH_ALG2 = 3
+FLAG_GRID_NONMONOTONE = 1
 RNG_STREAM = 0
 RNG_INLINE = 1
 
@@ -74,7 +76,7 @@ class rg_step_info(C.Structure):
     _fields_ = [("kappa", C.c_double), ("v", C.c_double), ("worst_margin", C.c_double),
                 ("status", C.c_int32), ("rounds", C.c_int32), ("candidates", C.c_int32),
                 ("rechecks", C.c_int32), ("bisect_passes", C.c_int32), ("t", C.c_uint32),
-                ("lane_steps", C.c_uint64)]
+                ("lane_steps", C.c_uint64), ("flags", C.c_int32)]
 
 
 class rg_profile(C.Structure):
@@ -153,7 +155,7 @@ def _ptr(a: np.ndarray, t=_dp):
 def _info_dict(info: rg_step_info) -> dict:
     return dict(worst=info.worst_margin, rounds=info.rounds, candidates=info.candidates,
                 rechecks=info.rechecks, bisect_passes=info.bisect_passes, t=info.t,
-                lane_steps=info.lane_steps)
+                lane_steps=info.lane_steps, flags=info.flags)
 
 
 def default_options() -> rg_options:
@@ -321,7 +323,8 @@ class Governor:
         infos = (rg_step_info * T)()
         self._check(self.L.rg_closed_loop(self.h, _ptr(x0), float(v0), _ptr(r), T, _ptr(v),
                                           _ptr(kap), _ptr(xs), infos, int(use_graph)))
-        keys = ["status", "rounds", "candidates", "rechecks", "bisect_passes", "lane_steps", "t"]
+        keys = ["status", "rounds", "candidates", "rechecks", "bisect_passes", "lane_steps", "t",
+                "flags"]
         out = {k: np.array([getattr(infos[i], k) for i in range(T)]) for k in keys}
         out["worst"] = np.array([infos[i].worst_margin for i in range(T)])
         out.update(v=v, kappa=kap, x=xs)

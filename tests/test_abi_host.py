@@ -122,7 +122,7 @@ def test_create_rejects_bad_horizon_and_options(lib):
     assert _create(lib, p, dt=float("nan"))[0] == R.RG_E_INVAL
     for field, value, code in [("K", -1, R.RG_E_INVAL), ("depth", 9, R.RG_E_INVAL),
                                ("block", 100, R.RG_E_INVAL), ("block", 512, R.RG_E_INVAL),
-                               ("precision", 4, R.RG_E_INVAL), ("search", 3, R.RG_E_INVAL),
+                               ("precision", 4, R.RG_E_INVAL), ("search", 4, R.RG_E_INVAL),
                                ("Kc", 0, R.RG_E_INVAL), ("lanes", 2, R.RG_E_INVAL), ("predict", 2, R.RG_E_INVAL),
                                ("speculate", 8, R.RG_E_INVAL),
                                ("band", float("inf"), R.RG_E_INVAL), ("max_T", 0, R.RG_E_INVAL)]:
@@ -141,6 +141,24 @@ def test_create_rejects_bad_horizon_and_options(lib):
     o.precision = 0
     rc, h = _create(lib, p, opt=o)
     assert rc == 0 and lib.rg_destroy(h) == 0
+    # Alg. 2 tabulates the steady state of 2^K tree nodes (K <= 16) and bisects
+    # each scenario on the robust verdict
+    o = R.rg_options()
+    lib.rg_default_options(C.byref(o))
+    o.search, o.K = R.SEARCH_ALG2, 17
+    assert _create(lib, p, opt=o)[0] == R.RG_E_NOTSUP
+    o.K, o.chance_q = 16, 2
+    assert _create(lib, p, opt=o)[0] == R.RG_E_NOTSUP
+    o.chance_q = 0
+    rc, h = _create(lib, p, opt=o)
+    assert rc == 0
+    dp = C.POINTER(C.c_double)
+    x, r, v = np.zeros(4), np.zeros(3), np.zeros(3)
+    assert lib.rg_closed_loop(h, x.ctypes.data_as(dp), 0.0, r.ctypes.data_as(dp), 3,
+                              v.ctypes.data_as(dp), None, None, None, 0) == R.RG_E_NOTSUP
+    assert lib.rg_autotune(h, x.ctypes.data_as(dp), 0.0, r.ctypes.data_as(dp), 3, 1, None,
+                           None) == R.RG_E_NOTSUP
+    assert lib.rg_destroy(h) == 0
 
 
 def test_create_rejects_nonfinite_data(lib):
@@ -219,3 +237,32 @@ def test_batch_create_validates_and_step_reports_switched_off(lib):
     h2 = C.c_void_p()
     assert lib.rg_batch_create(descs, 2, None, C.byref(h2)) == R.RG_E_INVAL
     assert b"instance 1" in lib.rg_batch_last_error(None)
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C layout (sizes and
+    every field offset, from a host C program compiled against include/rg.h)."""
+    import subprocess
+    structs = {"rg_plant": R.rg_plant, "rg_scenarios": R.rg_scenarios,
+               "rg_constraints": R.rg_constraints, "rg_options": R.rg_options,
+               "rg_step_info": R.rg_step_info, "rg_profile": R.rg_profile,
+               "rg_instance_desc": R.rg_instance_desc}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rg.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for ln in filter(None, out):
+        name, field, value = ln.split()
+        cls = structs[name]
+        if field == "size":
+            assert C.sizeof(cls) == int(value), name
+        else:
+            assert getattr(cls, field).offset == int(value), (name, field)
