@@ -262,6 +262,25 @@ int rg_reset(rg_handle* h);
 int rg_step(rg_handle* h, const double* x, double r, double v_prev, double* v_out,
             double* kappa_out, rg_step_info* info);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, tight serving loops): rg_step without a workspace.  Same
+ * arguments, outputs, status and effect on t as rg_step, and the same kappa, v
+ * and worst margin.  It allocates nothing: the search record, the result
+ * record and the FP64 recheck list live in one static device array of 8 MiB
+ * per GPU (held until the process ends), and the scenario draws are
+ * regenerated inside the kernels (bit-identical to the streamed draws).  Runs
+ * on the current device; the handle's stream must belong to it.  Every call
+ * starts from a fresh search record (no first-round prediction from earlier
+ * steps; results do not depend on it).  All calls on one GPU share the array,
+ * so calls that overlap in time on one GPU (threads, streams, handles) race:
+ * serialise them.  RG_E_NOTSUP when the recheck list, 8 B x N x (candidates
+ * per device round), does not fit beside the 14 KB of records (for example
+ * N = 4096 at the default 13 candidates per round needs 0.43 MB; the limit is
+ * about 1e6 scenario-candidate pairs), and for the Newton search, Alg. 2 and
+ * the chance-constrained verdict; RG_E_STATE while profiling is on. */
+int rg_step_noalloc(rg_handle* h, const double* x, double r, double v_prev, double* v_out,
+                    double* kappa_out, rg_step_info* info);
+
 /* Worst margins of explicit candidates without searching (Alg. 3 step 5 for a
  * given list): margins[i] = min(min_k m^k(v_i), m_ss(v_i)) with v_i from
  * kappa[i] (each in [0, 1]), full horizon, t unchanged.  per_scenario

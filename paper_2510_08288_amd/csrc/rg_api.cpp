@@ -8,6 +8,7 @@
 #include <cstring>
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -475,7 +476,120 @@ void fill_info(const DevResult& R, rg_step_info* info) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Allocation-free RG step (rg_step_noalloc)
+// ---------------------------------------------------------------------------
+// Its search state, result record and recheck list live in this file-scope
+// device array instead of a workspace: one copy per GPU, held until the process
+// ends and shared by every allocation-free call on that GPU.  In host code the
+// name `scratch` is only a stand-in for the symbol; kernels receive the device
+// address that hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;  // 8 MiB
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};  // device address of `scratch`, per device
+
+// Device address of the current device's copy of `scratch` (looked up once per
+// device, with that device current).
+hipError_t noalloc_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+
+// Offsets inside `scratch`: state, search record, result, recheck list (one
+// entry per candidate and scenario of the largest round at most).
+struct NoAllocLayout {
+  size_t st, srch, res, rlist, total;
+};
+
+NoAllocLayout noalloc_layout(const rg_handle* h) {
+  NoAllocLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  L.st = take(sizeof(DevState));
+  L.srch = take(sizeof(DevSearch));
+  L.res = take(sizeof(DevResult));
+  L.rlist = take(sizeof(int2) * (size_t)h->cfg.cmax_round * (size_t)h->pr.s.N);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
 extern "C" {
+
+int rg_step_noalloc(rg_handle* h, const double* x, double r, double v_prev, double* v_out,
+                    double* kappa_out, rg_step_info* info) {
+  if (!h) return RG_E_INVAL;
+  if (!x || !v_out) return fail(h, RG_E_INVAL, "NULL x or v_out");
+  if (!finite_array(x, h->pr.p.n) || !std::isfinite(r) || !std::isfinite(v_prev))
+    return fail(h, RG_E_INVAL, "non-finite input");
+  if (h->opt.search != RG_SEARCH_BISECT && h->opt.search != RG_SEARCH_GRID)
+    return fail(h, RG_E_NOTSUP, "the allocation-free step runs bisection or the grid search");
+  if (h->opt.chance_q > 0)
+    return fail(h, RG_E_NOTSUP, "the allocation-free step runs the robust verdict");
+  if (h->profiling) return fail(h, RG_E_STATE, "the allocation-free step does not profile");
+  const NoAllocLayout L = noalloc_layout(h);
+  if (L.total > kNoAllocScratchBytes)
+    return fail(h, RG_E_NOTSUP,
+                "the allocation-free step needs " + std::to_string(L.total) +
+                    " bytes of device scratch (recheck list: 8 B x N x candidates per round), "
+                    "more than its " + std::to_string(kNoAllocScratchBytes) + " bytes");
+  void* base = nullptr;
+  hipError_t e = noalloc_scratch(&base);
+  if (e != hipSuccess) return fail_hip(h, "device scratch address", e);
+  char* p = (char*)base;
+  DevBuffers b{};
+  b.st = (DevState*)(p + L.st);
+  b.srch = (DevSearch*)(p + L.srch);
+  b.res = (DevResult*)(p + L.res);
+  b.rlist = (int2*)(p + L.rlist);
+  // draws regenerated inside the kernels (no draw buffer); bit-identical to
+  // the streamed draws
+  Problem pr = h->pr;
+  pr.s.rng_mode = RG_RNG_INLINE;
+  // every call starts from a fresh search record: the array keeps whatever the
+  // last call on this GPU (any handle) left in it
+  fill_search(h, h->srch_tmpl, 0);
+  DevState s;
+  memset(&s, 0, sizeof(s));
+  for (int i = 0; i < h->pr.p.n; ++i) s.x[i] = x[i];
+  s.v_prev = v_prev;
+  s.r = r;
+  s.t = h->t;
+  HIPCHK(h, hipMemcpyAsync(b.srch, h->srch_tmpl, sizeof(DevSearch), hipMemcpyHostToDevice,
+                           h->stream));
+  HIPCHK(h, hipMemcpyAsync(b.st, &s, sizeof(s), hipMemcpyHostToDevice, h->stream));
+  e = enqueue_step(h, pr, b, false);
+  if (e != hipSuccess) return fail_hip(h, "enqueue allocation-free RG step", e);
+  DevResult R;
+  HIPCHK(h, hipMemcpyAsync(&R, b.res, sizeof(R), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->t += 1;
+  *v_out = R.v;
+  if (kappa_out) *kappa_out = R.kappa;
+  fill_info(R, info);
+  return R.status == 0 ? RG_OK : RG_S_INFEASIBLE;
+}
 
 int rg_default_options(rg_options* opt) {
   if (!opt) return RG_E_INVAL;

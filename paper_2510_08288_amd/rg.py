@@ -114,6 +114,8 @@ def load_library(path: str = LIB_PATH, with_torch: bool = True) -> C.CDLL:
     L.rg_reset.argtypes = [_vp]
     L.rg_get_step.argtypes = [_vp, C.POINTER(C.c_uint32)]
     L.rg_step.argtypes = [_vp, _dp, C.c_double, C.c_double, _dp, _dp, C.POINTER(rg_step_info)]
+    L.rg_step_noalloc.argtypes = [_vp, _dp, C.c_double, C.c_double, _dp, _dp,
+                                  C.POINTER(rg_step_info)]
     L.rg_margin.argtypes = [_vp, _dp, C.c_double, C.c_double, _dp, C.c_int32, _dp, _fp, _ip]
     L.rg_closed_loop.argtypes = [_vp, _dp, C.c_double, _dp, C.c_int32, _dp, _dp, _dp,
                                  C.POINTER(rg_step_info), C.c_int32]
@@ -258,6 +260,17 @@ class Governor:
         info = rg_step_info()
         rc = self._check(self.L.rg_step(self.h, _ptr(x), float(r), float(v_prev), C.byref(v),
                                         C.byref(kap), C.byref(info)))
+        return dict(v=v.value, kappa=kap.value, status=rc, **_info_dict(info))
+
+    def step_noalloc(self, x, r: float, v_prev: float) -> dict:
+        """rg_step_noalloc: the same RG step with no device allocation (static
+        device scratch, draws regenerated in the kernels)."""
+        x = _f64(x)
+        v = C.c_double()
+        kap = C.c_double()
+        info = rg_step_info()
+        rc = self._check(self.L.rg_step_noalloc(self.h, _ptr(x), float(r), float(v_prev),
+                                                C.byref(v), C.byref(kap), C.byref(info)))
         return dict(v=v.value, kappa=kap.value, status=rc, **_info_dict(info))
 
     def margin(self, x, r: float, v_prev: float, kappas: Sequence[float],
