@@ -84,6 +84,11 @@ enum rg_search {
                              2^-K inside that end, a non-negative or non-finite slope falls
                              back to the midpoint (status RG_S_FALLBACK); stops at a bracket
                              of 2^-K (at most K+2 rounds).  FP32 precision only. */
+    RG_SEARCH_NEWTON_TAN = 4, /* the same safeguarded Newton search, its derivative from the
+                             forward tangent dx/dv carried by the iterate's FP32 rollout lanes
+                             (full horizon, no checkpoints, no reverse sweep; rg_tangent):
+                             about twice the iterate row's forward work instead of the
+                             adjoint's separate launches.  FP32 precision only. */
     RG_SEARCH_ALG2 = 3    /* Alg. 2: every scenario runs Alg. 1 (kappa = 1 probe, K halvings)
                              on its own verdict (its rollout margin and the steady-state test),
                              one GPU lane per scenario with no barrier between candidates;
@@ -350,6 +355,20 @@ int rg_get_profile(const rg_handle* h, rg_profile* out);
  * handle with the chance-constrained verdict (chance_q > 0). */
 int rg_grad(rg_handle* h, const double* x, double r, double v_prev, double kappa,
             const float* upstream, double* margin_out, double* dkappa_out, double* dtheta_out);
+
+/* Forward-mode counterpart of rg_grad (not in the paper; it backs
+ * RG_SEARCH_NEWTON_TAN): one FP32 rollout of every scenario under the candidate
+ * kappa carries the tangent dx/dv of the discrete RK4 map (draws held fixed)
+ * over the full horizon.  Outputs (nullable except dkappa_out), each [N]:
+ * m_out = the scenario's FP32 margin m^k, dm_dv_out = dm^k/dv at its first
+ * minimising step and row, j_out = that step; margin_out = M(kappa) (FP64
+ * recheck within the band, steady-state term included); dkappa_out = dM/dkappa
+ * = dM/dv (r - v_prev) of the active term (the arg-min scenario's tangent, or
+ * the steady-state implicit derivative when that term is smaller).  FP32
+ * precision only (else RG_E_NOTSUP); t is not advanced. */
+int rg_tangent(rg_handle* h, const double* x, double r, double v_prev, double kappa,
+               float* m_out, float* dm_dv_out, int32_t* j_out, double* margin_out,
+               double* dkappa_out);
 
 /* Replace the nominal uncertain coefficients theta_nom ([n_theta], FC9 only);
  * scenario k then uses theta_nom * factor_k with unchanged factors.

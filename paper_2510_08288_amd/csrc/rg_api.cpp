@@ -91,13 +91,16 @@ bool finite_array(const double* a, int n) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Both Newton searches: the adjoint-driven one and the forward-tangent one.
+bool is_newton(int search) { return search == RG_SEARCH_NEWTON || search == RG_SEARCH_NEWTON_TAN; }
+
 // Alg. 2 tabulates the steady-state margins of the 2^K bisection-tree nodes.
 constexpr int kAlg2MaxK = 16;
 
 // Workspace layout: offsets of each buffer inside one allocation.
 struct Layout {
   size_t st, srch, res, r_seq, x_hist, wpair[kPairs], thpair[kPairs], rlist, per_m, per_j, per_key;
-  size_t alg2_mss, scratch;
+  size_t alg2_mss, tan_dv, scratch;
   size_t grad, adj_k, adj_w, adj_m, adj_dv, adj_dth, adj_ckpt, adj_seg;
   size_t seg_m, seg_j, seg_r, seg_x, seg_a, seg_cv, seg_ct, seg_scr, total;
 };
@@ -130,6 +133,7 @@ Layout layout_of(const rg_handle* h) {
   L.per_j = take(sizeof(int32_t) * (size_t)kCMax * N);
   L.per_key = take(h->opt.chance_q > 0 ? sizeof(unsigned long long) * (size_t)kCMax * N : 0);
   L.alg2_mss = take(h->opt.search == RG_SEARCH_ALG2 ? sizeof(double) << h->opt.K : 0);
+  L.tan_dv = take(sizeof(float) * N);
   L.scratch = take(sizeof(double) * kCMax * 4);
   const size_t n = (size_t)pr.p.n, Kc = (size_t)h->opt.Kc;
   L.grad = take(sizeof(DevGrad));
@@ -186,7 +190,8 @@ void plan(rg_handle* h) {
   c.block = h->opt.block > 0 ? h->opt.block : 256;
   c.chance = h->opt.chance_q > 0 ? 1 : 0;
   const int tree = (1 << d) - 1;
-  if (h->opt.search == RG_SEARCH_NEWTON) {
+  c.tan = h->opt.search == RG_SEARCH_NEWTON_TAN ? 1 : 0;
+  if (is_newton(h->opt.search)) {
     c.cmax_round = 4;
     c.rounds = h->opt.K + 2;
   } else if (h->opt.search == RG_SEARCH_GRID) {
@@ -213,7 +218,7 @@ void plan(rg_handle* h) {
 void fill_search(const rg_handle* h, DevSearch* S, int32_t spec_depth) {
   memset(S, 0, sizeof(DevSearch));
   S->mode = h->opt.search == RG_SEARCH_GRID ? kGrid
-            : h->opt.search == RG_SEARCH_NEWTON ? kNewton : kBisect;
+            : is_newton(h->opt.search) ? kNewton : kBisect;
   S->delta = std::ldexp(1.0, -h->opt.K);
   S->predict = h->opt.search == RG_SEARCH_BISECT ? h->opt.predict : 0;
   S->pred = std::nan("");
@@ -266,6 +271,7 @@ int ensure_workspace(rg_handle* h) {
   b.per_j = (int32_t*)(base + L.per_j);
   b.per_key = h->opt.chance_q > 0 ? (unsigned long long*)(base + L.per_key) : nullptr;
   b.alg2_mss = h->opt.search == RG_SEARCH_ALG2 ? (double*)(base + L.alg2_mss) : nullptr;
+  b.tan_dv = (float*)(base + L.tan_dv);
   b.scratch = (double*)(base + L.scratch);
   b.scratch_bytes = sizeof(double) * kCMax * 4;
   b.grad = (DevGrad*)(base + L.grad);
@@ -360,7 +366,7 @@ hipError_t enqueue_step(rg_handle* h, const Problem& pr, const DevBuffers& b, bo
   // draws and round-0 setup share a launch in stream mode
   e = streamed ? launch_gen_setup(pr, b, 0, h->stream) : launch_setup(pr, b, 0, h->stream);
   if (e != hipSuccess) return e;
-  const bool newton = h->opt.search == RG_SEARCH_NEWTON;
+  const bool newton = is_newton(h->opt.search);
   // with FP32 rollouts the recheck launch ends with the decision (the Newton
   // decision needs the derivative first)
   const bool chance = h->opt.chance_q > 0;
@@ -380,7 +386,9 @@ hipError_t enqueue_step(rg_handle* h, const Problem& pr, const DevBuffers& b, bo
         (e = launch_recheck(pr, h->opt.early_exit, h->cfg, b, h->stream, fused_decide)) !=
             hipSuccess)
       return e;
-    if (newton) {  // derivative of the Newton iterate's worst margin (segment adjoint)
+    if (newton && h->cfg.tan) {  // derivative from the tangent the rollout carried
+      if ((e = launch_tan_grad(pr, b, -1, h->stream)) != hipSuccess) return e;
+    } else if (newton) {  // derivative of the Newton iterate's worst margin (segment adjoint)
       if ((e = launch_grad_prepare(pr, b, -1, 1, h->stream)) != hipSuccess) return e;
       if ((e = launch_seg_grad(pr, h->opt.Kc, -1, b, h->stream)) != hipSuccess) return e;
       if ((e = launch_grad_reduce(b, 1, pr.p.nth, -1, h->stream)) != hipSuccess) return e;
@@ -410,7 +418,7 @@ hipError_t enqueue_round(rg_handle* h) {
   // any non-null target switches the draw workgroups on; the kernel picks the buffer
   float* gen_w = streamed ? b.wpair[0] : nullptr;
   float* gen_th = streamed ? b.thpair[0] : nullptr;
-  const bool newton = h->opt.search == RG_SEARCH_NEWTON;
+  const bool newton = is_newton(h->opt.search);
   const bool chance = h->opt.chance_q > 0;
   const bool fused_decide = prec == RG_PREC_F32_RECHECK && !newton && !chance;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -426,7 +434,9 @@ hipError_t enqueue_round(rg_handle* h) {
       (e = launch_recheck(h->pr, h->opt.early_exit, h->cfg, b, h->stream, fused_decide)) !=
           hipSuccess)
     return e;
-  if (newton) {
+  if (newton && h->cfg.tan) {
+    if ((e = launch_tan_grad(h->pr, b, -1, h->stream)) != hipSuccess) return e;
+  } else if (newton) {
     if ((e = launch_grad_prepare(h->pr, b, -1, 1, h->stream)) != hipSuccess) return e;
     if ((e = launch_seg_grad(h->pr, h->opt.Kc, -1, b, h->stream)) != hipSuccess) return e;
     if ((e = launch_grad_reduce(b, 1, h->pr.p.nth, -1, h->stream)) != hipSuccess) return e;
@@ -663,11 +673,11 @@ int rg_create(const rg_plant* plant, const rg_scenarios* scen, const rg_constrai
   if (!(o.band >= 0.0) || !std::isfinite(o.band)) return fail(nullptr, RG_E_INVAL, "bad band");
   if (o.K < 0 || o.K > 40) return fail(nullptr, RG_E_INVAL, "K must be in [0, 40]");
   if (o.search != RG_SEARCH_BISECT && o.search != RG_SEARCH_GRID && o.search != RG_SEARCH_NEWTON &&
-      o.search != RG_SEARCH_ALG2)
+      o.search != RG_SEARCH_ALG2 && o.search != RG_SEARCH_NEWTON_TAN)
     return fail(nullptr, RG_E_INVAL, "bad search");
   if (o.search == RG_SEARCH_ALG2 && o.K > kAlg2MaxK)
     return fail(nullptr, RG_E_NOTSUP, "Alg. 2 keeps K <= 16 (steady-state table of 2^K nodes)");
-  if (o.search == RG_SEARCH_NEWTON && o.precision != RG_PREC_F32_RECHECK)
+  if (is_newton(o.search) && o.precision != RG_PREC_F32_RECHECK)
     return fail(nullptr, RG_E_NOTSUP, "Newton search runs on the FP32 rollouts and adjoint");
   if (o.depth < 0 || o.depth > 6) return fail(nullptr, RG_E_INVAL, "depth must be in [0, 6]");
   if (o.search == RG_SEARCH_GRID && (o.M < 2 || o.M > kCMax - 1))
@@ -682,7 +692,7 @@ int rg_create(const rg_plant* plant, const rg_scenarios* scen, const rg_constrai
   if (o.speculate < 0 || o.speculate > kSpecMax)
     return fail(nullptr, RG_E_INVAL, "speculate must be 0.." + std::to_string(kSpecMax));
   if (o.chance_q < 0) return fail(nullptr, RG_E_INVAL, "chance_q must be >= 0");
-  if (o.chance_q > 0 && o.search == RG_SEARCH_NEWTON)
+  if (o.chance_q > 0 && is_newton(o.search))
     return fail(nullptr, RG_E_NOTSUP, "the chance-constrained verdict has no Newton search");
   if (o.chance_q > 0 && o.search == RG_SEARCH_ALG2)
     return fail(nullptr, RG_E_NOTSUP, "Alg. 2 bisects each scenario on the robust verdict");
@@ -983,6 +993,7 @@ int rg_grad(rg_handle* h, const double* x, double r, double v_prev, double kappa
   if ((rc = ensure_draws(h))) return rc;
   LaunchCfg cfg = h->cfg;
   cfg.cmax_round = 1;
+  cfg.tan = 0;  // reverse mode: the rollout keeps checkpoints
   HIPCHK(h, hipMemcpyAsync((char*)h->b.srch + offsetof(DevSearch, kappa), &kappa, sizeof(double),
                            hipMemcpyHostToDevice, h->stream));
   HIPCHK(h, launch_setup_list(h->pr, h->b, 1, h->stream));
@@ -1018,6 +1029,50 @@ int rg_grad(rg_handle* h, const double* x, double r, double v_prev, double kappa
   *dkappa_out = G.dM_dkappa;
   if (dtheta_out)
     for (int c = 0; c < h->pr.p.nth; ++c) dtheta_out[c] = G.dM_dth[c];
+  return RG_OK;
+}
+
+int rg_tangent(rg_handle* h, const double* x, double r, double v_prev, double kappa,
+               float* m_out, float* dm_dv_out, int32_t* j_out, double* margin_out,
+               double* dkappa_out) {
+  if (!h) return RG_E_INVAL;
+  if (!x || !dkappa_out) return fail(h, RG_E_INVAL, "NULL x or dkappa_out");
+  if (!finite_array(x, h->pr.p.n) || !std::isfinite(r) || !std::isfinite(v_prev))
+    return fail(h, RG_E_INVAL, "non-finite input");
+  if (!(kappa >= 0.0 && kappa <= 1.0)) return fail(h, RG_E_INVAL, "kappa outside [0, 1]");
+  if (h->opt.chance_q > 0)
+    return fail(h, RG_E_NOTSUP, "rg_tangent differentiates the robust worst margin (chance_q = 0)");
+  if (h->opt.precision != RG_PREC_F32_RECHECK)
+    return fail(h, RG_E_NOTSUP, "the tangent rollout runs in FP32 (precision F32_RECHECK)");
+  const int N = h->pr.s.N;
+  int rc = ensure_workspace(h);
+  if (rc) return rc;
+  if ((rc = upload_state(h, x, r, v_prev))) return rc;
+  if ((rc = ensure_draws(h))) return rc;
+  LaunchCfg cfg = h->cfg;
+  cfg.cmax_round = 1;
+  cfg.tan = 1;
+  HIPCHK(h, hipMemcpyAsync((char*)h->b.srch + offsetof(DevSearch, kappa), &kappa, sizeof(double),
+                           hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, launch_setup_list(h->pr, h->b, 1, h->stream));
+  // candidate 0 carries the tangent over the full horizon; near-band lanes are
+  // re-simulated in FP64 for the margin value
+  HIPCHK(h, launch_rollout(h->pr, h->opt.band, RG_PREC_F32_RECHECK, 0, 0, cfg, h->b, h->stream, 0,
+                           h->opt.Kc));
+  HIPCHK(h, launch_recheck(h->pr, 0, cfg, h->b, h->stream));
+  HIPCHK(h, launch_tan_grad(h->pr, h->b, 0, h->stream));
+  DevGrad G;
+  HIPCHK(h, hipMemcpyAsync(&G, h->b.grad, sizeof(G), hipMemcpyDeviceToHost, h->stream));
+  if (m_out)
+    HIPCHK(h, hipMemcpyAsync(m_out, h->b.per_m, sizeof(float) * N, hipMemcpyDeviceToHost, h->stream));
+  if (dm_dv_out)
+    HIPCHK(h, hipMemcpyAsync(dm_dv_out, h->b.tan_dv, sizeof(float) * N, hipMemcpyDeviceToHost,
+                             h->stream));
+  if (j_out)
+    HIPCHK(h, hipMemcpyAsync(j_out, h->b.per_j, sizeof(int32_t) * N, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (margin_out) *margin_out = G.M;
+  *dkappa_out = G.dM_dkappa;
   return RG_OK;
 }
 
@@ -1117,7 +1172,7 @@ int rg_autotune(rg_handle* h, const double* x0, double v0, const double* r_seq, 
       for (int depth = dlo; depth <= dhi; ++depth) {
         for (int predict : {1, 0}) {
           if (predict && h->opt.search != RG_SEARCH_BISECT) continue;
-          if (h->opt.search == RG_SEARCH_NEWTON && depth != dlo) continue;  // depth unused
+          if (is_newton(h->opt.search) && depth != dlo) continue;  // depth unused
           for (int speculate : {kSpecMax, 3, 1, 0}) {
             if (speculate && !(predict && lanes == 4)) continue;
             rg_options o = own;

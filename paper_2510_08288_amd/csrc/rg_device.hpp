@@ -190,6 +190,26 @@ struct Plant<1, T> {
     for (int i = 0; i < 4; ++i) s += (double)al[i] * (double)c.B[i];
     vb += s;
   }
+  // Forward mode: out = J(x) dx + df/dv (a unit change of the set-point).
+  __device__ static void jvp(const Coef& c, const Lane&, const T* x, const T* dx, T* out) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      T a = c.B[i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a = t_fma(t_fma(2 * c.G[4 * i + j], x[j], c.A[4 * i + j]), dx[j], a);
+      out[i] = a;
+    }
+  }
+  // dy = (dh/dx) dx.
+  __device__ static void output_tan(const Coef& c, const T*, const T* dx, T* dy) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      T a = c.C[4 * i] * dx[0];
+#pragma unroll
+      for (int j = 1; j < 4; ++j) a = t_fma(c.C[4 * i + j], dx[j], a);
+      dy[i] = a;
+    }
+  }
   // dm/dx of the margin row m = g_r - F_r h(x) (F row given).
   __device__ static void out_grad(const Coef& c, const T* Fr, const T*, T* gx) {
 #pragma unroll
@@ -346,6 +366,44 @@ struct Plant<2, T> {
     tb[18] += -(double)al[6] * (double)x[6] * ((double)x[0] - (double)c.p1ref);
     tb[19] += -(double)al[8] * ((double)x[8] - 1.0) * v;
   }
+  // Forward mode: out = J(x) dx + df/dv (a unit change of the set-point), with
+  // the lane's coefficients; the orifice flow has derivative 0 where the
+  // valve is closed (p_l <= p_{l+1}).
+  __device__ static void jvp(const Coef& c, const Lane& L, const T* x, const T* dx, T* out) {
+    T sd[9], dq[7];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      const T tz = t_tanh(x[j] - c.xbar[j]);
+      sd[j] = (1 - tz * tz) * dx[j];
+    }
+    dq[0] = c.c_q0 * dx[6];
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+      const T dn = (l < 5) ? x[l + 1] : c.p_amb;
+      const T dp = x[l] - dn;
+      const T ddp = (l < 5) ? dx[l] - dx[l + 1] : dx[l];
+      dq[l + 1] = dp > (T)0 ? L.kq[l] / (2 * t_sqrt(dp)) * ddp : (T)0;
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      T a = -L.a[i] * dx[i];
+#pragma unroll
+      for (int j = 0; j < 9; ++j) a = t_fma(c.W[9 * i + j], sd[j], a);
+      T dphi;
+      if (i < 6) dphi = dq[i] - dq[i + 1];
+      else if (i == 6) dphi = L.b[0] - L.mu[0] * (dx[6] * (x[0] - c.p1ref) + x[6] * dx[0]);
+      else if (i == 7) dphi = L.b[1] * (x[6] + L.v * dx[6]);
+      else dphi = L.b[2] - L.mu[1] * ((x[8] - (T)1) + L.v * dx[8]);
+      out[i] = a + dphi;
+    }
+  }
+  // dy = (dh/dx) dx.
+  __device__ static void output_tan(const Coef& c, const T* x, const T* dx, T* dy) {
+    const T den = t_fma(c.d1, x[8], c.d0);
+    dy[0] = c.c_q0 * (dx[6] * den - x[6] * c.d1 * dx[8]) / (den * den);
+    dy[1] = dx[0];
+    dy[2] = dx[6];
+  }
   __device__ static void out_grad(const Coef& c, const T* Fr, const T* x, T* gx) {
 #pragma unroll
     for (int j = 0; j < 9; ++j) gx[j] = 0;
@@ -431,6 +489,52 @@ __device__ __forceinline__ void rk4_step(const typename Plant<KIND, T>::Coef& c,
   P::deriv(c, L, s, xs, k);
 #pragma unroll
   for (int i = 0; i < P::n; ++i) x[i] = t_fma(h6, acc[i] + k[i], x[i]);
+}
+
+// One RK4 step of the state together with its forward tangent dx (the
+// derivative with respect to the set-point): the state update has the same
+// operations, in the same order, as rk4_step.
+template <int KIND, class T>
+__device__ __forceinline__ void rk4_step_tan(const typename Plant<KIND, T>::Coef& c,
+                                             const typename Plant<KIND, T>::Lane& L, const T* s,
+                                             T h, T hh, T h6, T* x, T* dx) {
+  using P = Plant<KIND, T>;
+  constexpr int n = P::n;
+  T k[n], acc[n], xs[n], d[n], dacc[n], dxs[n];
+  P::deriv(c, L, s, x, k);
+  P::jvp(c, L, x, dx, d);
+#pragma unroll
+  for (int i = 0; i < n; ++i) {
+    acc[i] = k[i];
+    xs[i] = t_fma(hh, k[i], x[i]);
+    dacc[i] = d[i];
+    dxs[i] = t_fma(hh, d[i], dx[i]);
+  }
+  P::deriv(c, L, s, xs, k);
+  P::jvp(c, L, xs, dxs, d);
+#pragma unroll
+  for (int i = 0; i < n; ++i) {
+    acc[i] = t_fma((T)2, k[i], acc[i]);
+    xs[i] = t_fma(hh, k[i], x[i]);
+    dacc[i] = t_fma((T)2, d[i], dacc[i]);
+    dxs[i] = t_fma(hh, d[i], dx[i]);
+  }
+  P::deriv(c, L, s, xs, k);
+  P::jvp(c, L, xs, dxs, d);
+#pragma unroll
+  for (int i = 0; i < n; ++i) {
+    acc[i] = t_fma((T)2, k[i], acc[i]);
+    xs[i] = t_fma(h, k[i], x[i]);
+    dacc[i] = t_fma((T)2, d[i], dacc[i]);
+    dxs[i] = t_fma(h, d[i], dx[i]);
+  }
+  P::deriv(c, L, s, xs, k);
+  P::jvp(c, L, xs, dxs, d);
+#pragma unroll
+  for (int i = 0; i < n; ++i) {
+    x[i] = t_fma(h6, acc[i] + k[i], x[i]);
+    dx[i] = t_fma(h6, dacc[i] + d[i], dx[i]);
+  }
 }
 
 // Reverse sweep of one RK4 step at x with forcing s: lam <- (dPhi/dx)^T lam,

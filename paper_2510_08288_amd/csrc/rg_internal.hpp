@@ -171,6 +171,7 @@ struct DevBuffers {
   // for rechecked scenarios)
   unsigned long long* per_key;
   double* alg2_mss;        // [2^K] steady-state margins of the bisection tree's nodes (Alg. 2)
+  float* tan_dv;           // [N] forward tangent dm/dv of the tangent candidate's scenarios
   double* scratch;         // small staging area (trajectories, draws)
   size_t scratch_bytes;
   // adjoint
@@ -199,6 +200,7 @@ struct LaunchCfg {
   int cmax_round;          // largest candidate count of any round
   int rounds;              // device rounds per RG step
   int chance;              // 1: chance-constrained verdict (q > 0), its own rollout kernels
+  int tan;                 // 1: derivatives by the forward tangent fused into the rollout
 };
 
 // One instance of a batch (device memory, read-only in the kernels).  The
@@ -291,6 +293,9 @@ hipError_t launch_adjoint(const Problem& pr, int Kc, int max_entries, const DevB
 // record) from the checkpoints the rollout kept: segment kernels.
 hipError_t launch_seg_grad(const Problem& pr, int Kc, int cand, const DevBuffers& b,
                            hipStream_t st);
+// dM/dkappa of candidate cand (-1: the Newton iterate) from the forward tangent
+// its rollout kept (or the steady-state term), into b.grad.
+hipError_t launch_tan_grad(const Problem& pr, const DevBuffers& b, int cand, hipStream_t st);
 hipError_t launch_grad_reduce(const DevBuffers& b, int max_entries, int nth, int cand,
                               hipStream_t st);
 hipError_t launch_trajectory(const Problem& pr, double v, const int32_t* k_list_dev, int nk,

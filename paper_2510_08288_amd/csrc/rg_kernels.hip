@@ -58,6 +58,9 @@ struct RollArgs {
   uint32_t gen_ofs;  // the draws generated are those of step t + gen_ofs
   float* gen_w;
   float* gen_th;
+  // forward tangent (CKPT = 2): per scenario of the tangent candidate, dm/dv
+  // (tan_dv[k]), the margin (per_m[k]) and its minimising step (per_j[k])
+  float* tan_dv;
   // ring != 0 (closed loop): the draws of step s are in wring[s % kPairs],
   // selected from the step counter on the device (wbuf, gen_w and gen_th are
   // then unused; gen_w != nullptr only switches the draw workgroups on)
@@ -326,6 +329,85 @@ __device__ __forceinline__ T rollout_lane(const A& a, int early, T v, int k, uin
   return best;
 }
 
+// One scenario rollout in FP32 over the full horizon with the forward tangent
+// of the state with respect to the set-point carried along (not in the paper:
+// it gives the derivative the Newton search needs in the same pass).  Returns
+// the running-minimum margin as rollout_lane does; dm receives the derivative
+// of that minimum: -F_r* (dh/dx) dx/dv at its first minimising step j* (jbest)
+// and row r*.  The state update is that of rollout_lane.
+template <int KIND, int RNG, int INJ, class A>
+__device__ __forceinline__ float rollout_lane_tan(const A& a, float v, int k, uint32_t t,
+                                                  float& dm, int& jbest, int& nsteps) {
+  using P = Plant<KIND, float>;
+  float th[P::nth > 0 ? P::nth : 1];
+  if constexpr (P::nth > 0) {
+    float f[P::nth];
+    if (RNG == 0) {
+      const float* tb = step_th(a, t);
+#pragma unroll
+      for (int c = 0; c < P::nth; ++c) f[c] = tb[(size_t)c * a.N + k];
+    } else {
+      draw_theta_factor<P::nth>(a.seed, a.inst, t, (uint32_t)k, a.thlo, a.thspan, f);
+    }
+#pragma unroll
+    for (int c = 0; c < P::nth; ++c) th[c] = a.pc.thnom[c] * f[c];
+  }
+  typename P::Lane L;
+  P::lane_init(a.pc, th, v, L);
+  float x[P::n], dx[P::n], y[P::ny], dy[P::ny];
+#pragma unroll
+  for (int i = 0; i < P::n; ++i) {
+    x[i] = (float)a.st->x[i];
+    dx[i] = 0.f;  // x_t does not depend on the candidate
+  }
+  // margin at a step and its derivative through the minimising row
+  auto margin_tan = [&](float& m, float& dmj) {
+    int r = 0;
+    P::output(a.pc, L, x, y);
+    m = margin_rows_arg<P::ny>(a.F, a.g, y, r);
+    P::output_tan(a.pc, x, dx, dy);
+    float fy = a.F[r * P::ny] * dy[0];
+#pragma unroll
+    for (int i = 1; i < P::ny; ++i) fy = __builtin_fmaf(a.F[r * P::ny + i], dy[i], fy);
+    dmj = -fy;
+  };
+  float best, dbest;
+  margin_tan(best, dbest);
+  if (best != best) best = -INFINITY;
+  jbest = 0;
+  const float* wb = RNG == 0 ? step_w(a, t) : nullptr;
+  float w[P::nw];
+  int j = 0;
+  for (; j < a.H; ++j) {
+    if (RNG == 0) {
+#pragma unroll
+      for (int c = 0; c < P::nw; ++c) w[c] = wb[((size_t)j * P::nw + c) * a.N + k];
+    } else {
+      draw_w<P::nw>(a.seed, a.inst, t, 0u, (uint32_t)k, (uint32_t)j, a.wlo, a.wspan, w);
+    }
+    float s[P::n];
+    if (INJ == 0) P::force(a.pc, L, w, s);
+    else P::force0(a.pc, L, s);
+    rk4_step_tan<KIND, float>(a.pc, L, s, a.h, a.hh, a.h6, x, dx);
+    if (INJ == 1) P::post(a.pc, w, x);
+    float m, dmj;
+    margin_tan(m, dmj);
+    m = (m == m) ? m : -INFINITY;
+    if (m < best) {
+      best = m;
+      dbest = dmj;
+      jbest = j + 1;
+    }
+  }
+  nsteps = j;
+  bool finite = true;
+#pragma unroll
+  for (int i = 0; i < P::n; ++i) finite = finite && (x[i] - x[i] == 0.f);
+  if (!finite) best = -INFINITY;
+  dm = dbest;
+  return best;
+}
+
 // Wave64 + workgroup minimum of a 64-bit key; returns the minimum in thread 0.
 __device__ __forceinline__ unsigned long long block_min_u64(unsigned long long v,
                                                              unsigned long long* sh) {
@@ -367,8 +449,11 @@ __global__ void __launch_bounds__(256) k_rollout(const RollArgs<KIND, T> a) {
   DevSearch* S = a.srch;
   const int c = blockIdx.y;
   if (S->done || c >= S->n_cand) return;  // uniform over the workgroup
-  const bool ck = CKPT && c == (a.ckpt_cand >= 0 ? a.ckpt_cand : S->nk_idx);
-  const int early = a.early && !S->full[c];
+  // CKPT = 1: that candidate keeps checkpoints (adjoint); CKPT = 2: its lanes
+  // carry the forward tangent instead (full horizon, no early exit)
+  const bool ck = CKPT == 1 && c == (a.ckpt_cand >= 0 ? a.ckpt_cand : S->nk_idx);
+  const bool tan_row = CKPT == 2 && c == (a.ckpt_cand >= 0 ? a.ckpt_cand : S->nk_idx);
+  const int early = a.early && !S->full[c] && !tan_row;
   if (refused_by_steady_state(early, S, c)) return;
   __shared__ unsigned long long sh[16];
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -378,7 +463,15 @@ __global__ void __launch_bounds__(256) k_rollout(const RollArgs<KIND, T> a) {
   int jb = 0, ns = 0;
   if (k < a.N) {
     bool stopped = false;  // the candidate died while this wave ran (no recheck needed)
-    if constexpr (CHANCE) {
+    if (CKPT == 2 && std::is_same<T, float>::value && tan_row) {
+      if constexpr (CKPT == 2 && std::is_same<T, float>::value) {
+        float dm = 0.f;
+        m = rollout_lane_tan<KIND, RNG, INJ>(a, (float)S->v[c], k, t, dm, jb, ns);
+        a.tan_dv[k] = dm;
+        a.per_m[k] = (float)m;
+        a.per_j[k] = jb;
+      }
+    } else if constexpr (CHANCE) {
       // a violating lane stops alone; the candidate dies once more than q did
       m = rollout_lane<KIND, T, RNG, INJ, RollArgs<KIND, T>, CKPT, false>(
           a, early, (T)S->v[c], k, t, early ? &S->dead[c] : nullptr, jb, ns, nullptr, ck);
@@ -465,6 +558,46 @@ __device__ __forceinline__ float quad_min(float m) {
   return min2(m, dpp<kSwap2>(m));
 }
 
+// Forward tangent in the quad layout: lane q carries dx_q/dv beside x_q.  A
+// stage's tangent row i is B_i + sum_q (A[i][q] + 2 G[i][q] x_q) dx_q, formed
+// in the same slots and butterflies as the state.
+__device__ __forceinline__ float quad_tan(const QuadLane& L, float b, float x, float d) {
+  const float x2 = x + x;
+  const float c2 = __builtin_fmaf(L.g2, x2, L.a2) * d;
+  const float c3 = __builtin_fmaf(L.g3, x2, L.a3) * d;
+  float c0 = __builtin_fmaf(__builtin_fmaf(L.g0, x2, L.a0), d, b);
+  float c1 = __builtin_fmaf(L.g1, x2, L.a1) * d;
+  c1 = c1 + dpp<kSwap2>(c3);
+  c0 = c0 + dpp<kSwap2>(c2);
+  return c0 + dpp<kSwap1>(c1);
+}
+
+// Quad minimum of (margin, derivative, step) over the lanes' rows: the smallest
+// margin, ties to the earlier step, then to the lower row (lane).
+__device__ __forceinline__ void quad_min_tan(float& m, float& d, int& j, int q) {
+  int r = q;
+  auto take = [&](float m2, float d2, int j2, int r2) {
+    if (m2 < m || (m2 == m && (j2 < j || (j2 == j && r2 < r)))) {
+      m = m2;
+      d = d2;
+      j = j2;
+      r = r2;
+    }
+  };
+  {
+    const float m2 = dpp<kSwap1>(m), d2 = dpp<kSwap1>(d);
+    const int j2 = __builtin_amdgcn_update_dpp(0, j, kSwap1, 0xf, 0xf, true);
+    const int r2 = __builtin_amdgcn_update_dpp(0, r, kSwap1, 0xf, 0xf, true);
+    take(m2, d2, j2, r2);
+  }
+  {
+    const float m2 = dpp<kSwap2>(m), d2 = dpp<kSwap2>(d);
+    const int j2 = __builtin_amdgcn_update_dpp(0, j, kSwap2, 0xf, 0xf, true);
+    const int r2 = __builtin_amdgcn_update_dpp(0, r, kSwap2, 0xf, 0xf, true);
+    take(m2, d2, j2, r2);
+  }
+}
+
 template <int RNG, int INJ, int RECORD, int CKPT>
 __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, float> a,
                                                          const QuadCoef qc) {
@@ -473,8 +606,11 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
   DevSearch* S = a.srch;
   const int c = blockIdx.y;
   if (S->done || c >= S->n_cand) return;  // uniform over the workgroup
-  const bool ck = CKPT && c == (a.ckpt_cand >= 0 ? a.ckpt_cand : S->nk_idx);
-  const int early = a.early && !S->full[c];
+  // CKPT = 1: that candidate keeps checkpoints (adjoint); CKPT = 2: its lanes
+  // carry the forward tangent instead (full horizon, no early exit)
+  const bool ck = CKPT == 1 && c == (a.ckpt_cand >= 0 ? a.ckpt_cand : S->nk_idx);
+  const bool tan_row = CKPT == 2 && c == (a.ckpt_cand >= 0 ? a.ckpt_cand : S->nk_idx);
+  const int early = a.early && !S->full[c] && !tan_row;
   if (refused_by_steady_state(early, S, c)) return;
   __shared__ unsigned long long sh[16];
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -487,7 +623,77 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
   float best = INFINITY;
   int jb = 0, ns = 0;
   bool stopped = false;  // the candidate died while this wave ran (no recheck needed)
-  if (k < a.N) {  // whole quads are active or inactive together
+  if (CKPT == 2 && tan_row && k < a.N) {
+    // tangent candidate: state and dx/dv over the full horizon; each lane
+    // keeps its row's running minimum with derivative and first step
+    QuadLane L;
+    L.a0 = qc.a[q][0]; L.a1 = qc.a[q][1]; L.a2 = qc.a[q][2]; L.a3 = qc.a[q][3];
+    L.g0 = qc.g[q][0]; L.g1 = qc.g[q][1]; L.g2 = qc.g[q][2]; L.g3 = qc.g[q][3];
+    const float d0 = qc.d[q][0], d1 = qc.d[q][1], d2 = qc.d[q][2], d3 = qc.d[q][3];
+    const float e0 = qc.e[q][0], e1 = qc.e[q][1], grow = qc.grow[q], bq0 = qc.b[q];
+    const float bv = bq0 * (float)S->v[c];
+    const float h = a.h, hh = a.hh, h6 = a.h6;
+    float x = (float)a.st->x[q], dx = 0.f;
+    auto row_sum = [&](float xv, float g0v) {
+      const float c2 = d2 * xv, c3 = d3 * xv;
+      float c0 = __builtin_fmaf(d0, xv, g0v);
+      float c1 = d1 * xv;
+      c1 = c1 + dpp<kSwap2>(c3);
+      c0 = c0 + dpp<kSwap2>(c2);
+      return c0 + dpp<kSwap1>(c1);
+    };
+    float bq = row_sum(x, grow), dbq = row_sum(dx, 0.f);
+    int jq = 0;
+    const float* wsrc_t = step_w(a, t);
+    for (int j = 0; j < a.H; ++j) {
+      float w0, w1;
+      if (RNG == 0) {
+        w0 = wsrc_t[(size_t)(2 * j) * a.N + k];
+        w1 = wsrc_t[(size_t)(2 * j + 1) * a.N + k];
+      } else {
+        const Words r = philox10((uint32_t)k, (uint32_t)j, t, 0u, a.seed, a.inst);
+        w0 = box_draw(r.v[0], a.wlo[0], a.wspan[0]);
+        w1 = box_draw(r.v[1], a.wlo[1], a.wspan[1]);
+      }
+      const float sf = INJ == 0 ? __builtin_fmaf(e1, w1, __builtin_fmaf(e0, w0, bv)) : bv;
+      const float k1 = quad_deriv(L, sf, x), t1 = quad_tan(L, bq0, x, dx);
+      float acc = k1, dacc = t1;
+      float xs = __builtin_fmaf(hh, k1, x), ds = __builtin_fmaf(hh, t1, dx);
+      const float k2 = quad_deriv(L, sf, xs), t2 = quad_tan(L, bq0, xs, ds);
+      acc = __builtin_fmaf(2.f, k2, acc);
+      dacc = __builtin_fmaf(2.f, t2, dacc);
+      xs = __builtin_fmaf(hh, k2, x);
+      ds = __builtin_fmaf(hh, t2, dx);
+      const float k3 = quad_deriv(L, sf, xs), t3 = quad_tan(L, bq0, xs, ds);
+      acc = __builtin_fmaf(2.f, k3, acc);
+      dacc = __builtin_fmaf(2.f, t3, dacc);
+      xs = __builtin_fmaf(h, k3, x);
+      ds = __builtin_fmaf(h, t3, dx);
+      const float k4 = quad_deriv(L, sf, xs), t4 = quad_tan(L, bq0, xs, ds);
+      x = __builtin_fmaf(h6, acc + k4, x);
+      dx = __builtin_fmaf(h6, dacc + t4, dx);
+      if (INJ == 1) x = x + (e0 * w0 + e1 * w1);
+      const float mr = row_sum(x, grow);
+      const float dmr = row_sum(dx, 0.f);
+      if (mr < bq) {
+        bq = mr;
+        dbq = dmr;
+        jq = j + 1;
+      }
+    }
+    ns = a.H;
+    quad_min_tan(bq, dbq, jq, q);
+    best = bq;
+    float bad = x - x;
+    bad = bad + dpp<kSwap1>(bad);
+    bad = bad + dpp<kSwap2>(bad);
+    if (!(bad == 0.f) || best != best) best = -INFINITY;
+    if (q == 0) {
+      a.tan_dv[k] = dbq;
+      a.per_m[k] = best;
+      a.per_j[k] = jq;
+    }
+  } else if (k < a.N) {  // whole quads are active or inactive together
     QuadLane L;
     L.a0 = qc.a[q][0]; L.a1 = qc.a[q][1]; L.a2 = qc.a[q][2]; L.a3 = qc.a[q][3];
     L.g0 = qc.g[q][0]; L.g1 = qc.g[q][1]; L.g2 = qc.g[q][2]; L.g3 = qc.g[q][3];
@@ -2221,6 +2427,38 @@ __global__ void __launch_bounds__(256) k_grad_reduce(DevGrad* G, const double* d
 }
 
 
+// Derivative of the worst margin M(kappa) of candidate `cand` (-1: the Newton
+// iterate) from the forward tangent the rollout left: the active term is the
+// arg-min scenario's rollout margin (its tangent) or, when smaller, the
+// steady-state margin (implicit derivative in FP64); then dM/dkappa =
+// dM/dv (r - v_prev).
+template <int KIND>
+__global__ void k_tan_grad(const CtlArgs<KIND> a, DevGrad* G, const float* tan_dv, int cand) {
+  if (threadIdx.x != 0) return;
+  DevSearch* S = a.srch;
+  if (cand < 0) {
+    if (S->done) return;
+    cand = S->nk_idx;
+  }
+  G->M = cand_worst_p(S, cand, 0);
+  for (int c = 0; c < kMaxTh; ++c) G->dM_dth[c] = 0.0;
+  G->n_entries = 0;
+  const unsigned long long key = S->key_all[cand];
+  const double roll = key == ~0ull ? INFINITY : key_margin(key, 0);
+  if (S->mss[cand] < roll || key == ~0ull) {
+    double dv, dth[kMaxTh];
+    steady_grad<KIND>(a.pc, S, S->v[cand], &dv, dth);
+    G->dM_dv = dv;
+    for (int c = 0; c < kMaxTh; ++c) G->dM_dth[c] = dth[c];
+    G->k_star = -1;
+  } else {
+    const int ks = (int)(uint32_t)(key & 0xffffffffu);
+    G->k_star = ks;
+    G->dM_dv = (double)tan_dv[ks];
+  }
+  G->dM_dkappa = G->dM_dv * (a.st->r - a.st->v_prev);
+}
+
 // Equilibrium f(x, v, 0, theta_nom) = 0 by the steady-state Newton iteration;
 // out[0..n) = x_ss, out[n] = 1 if converged.
 template <int KIND>
@@ -2496,6 +2734,7 @@ static RollArgs<KIND, T> make_args(const Problem& pr, double band, int early, in
   a.per_j = b.per_j;
   a.per_key = b.per_key;
   a.rlist = b.rlist;
+  a.tan_dv = b.tan_dv;
   return a;
 }
 
@@ -2641,7 +2880,9 @@ hipError_t launch_rollout(const Problem& pr, double band, int precision, int ear
         constexpr int I = decltype(ic)::value;
         return by_bit(record, [&](auto dc) {
           constexpr int D = decltype(dc)::value;
-          if (ckpt)
+          if (ckpt && cfg.tan)
+            hipLaunchKernelGGL((k_rollout_lq4_quad<R, I, D, 2>), grid, dim3(cfg.block), 0, st, a, qc);
+          else if (ckpt)
             hipLaunchKernelGGL((k_rollout_lq4_quad<R, I, D, 1>), grid, dim3(cfg.block), 0, st, a, qc);
           else
             hipLaunchKernelGGL((k_rollout_lq4_quad<R, I, D, 0>), grid, dim3(cfg.block), 0, st, a, qc);
@@ -2666,6 +2907,8 @@ hipError_t launch_rollout(const Problem& pr, double band, int precision, int ear
           set_gen(a);
           if (cfg.chance)  // no Newton search, hence no checkpoints
             hipLaunchKernelGGL((k_rollout<K, float, R, I, 0, 1>), grid, dim3(cfg.block), 0, st, a);
+          else if (ckpt && cfg.tan)
+            hipLaunchKernelGGL((k_rollout<K, float, R, I, 2>), grid, dim3(cfg.block), 0, st, a);
           else if (ckpt)
             hipLaunchKernelGGL((k_rollout<K, float, R, I, 1>), grid, dim3(cfg.block), 0, st, a);
           else
@@ -2869,6 +3112,15 @@ hipError_t launch_seg_grad(const Problem& pr, int Kc, int cand, const DevBuffers
         return hipGetLastError();
       });
     });
+  });
+}
+
+hipError_t launch_tan_grad(const Problem& pr, const DevBuffers& b, int cand, hipStream_t st) {
+  return by_kind(pr.p.kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    hipLaunchKernelGGL(k_tan_grad<K>, dim3(1), dim3(64), 0, st, make_ctl<K>(pr, b, 0), b.grad,
+                       (const float*)b.tan_dv, cand);
+    return hipGetLastError();
   });
 }
 

@@ -31,6 +31,7 @@ SEARCH_BISECT = 0
 SEARCH_GRID = 1
 SEARCH_NEWTON = 2
 SEARCH_ALG2 = 3
+SEARCH_NEWTON_TAN = 4
 FLAG_GRID_NONMONOTONE = 1
 RNG_STREAM = 0
 RNG_INLINE = 1
@@ -124,6 +125,7 @@ def load_library(path: str = LIB_PATH, with_torch: bool = True) -> C.CDLL:
     L.rg_autotune.argtypes = [_vp, _dp, C.c_double, _dp, C.c_int32, C.c_int32,
                               C.POINTER(rg_options), C.POINTER(C.c_double)]
     L.rg_grad.argtypes = [_vp, _dp, C.c_double, C.c_double, C.c_double, _fp, _dp, _dp, _dp]
+    L.rg_tangent.argtypes = [_vp, _dp, C.c_double, C.c_double, C.c_double, _fp, _fp, _ip, _dp, _dp]
     L.rg_set_theta.argtypes = [_vp, _dp]
     L.rg_equilibrium.argtypes = [_vp, C.c_double, _dp]
     L.rg_batch_create.argtypes = [C.POINTER(rg_instance_desc), C.c_int32, C.POINTER(rg_options),
@@ -301,6 +303,21 @@ class Governor:
                                    None if up is None else _ptr(up, _fp), C.byref(M), C.byref(dk),
                                    _ptr(dth)))
         return dict(M=M.value, dkappa=dk.value, dtheta=dth[: self.problem.n_theta])
+
+    def tangent(self, x, r: float, v_prev: float, kappa: float) -> dict:
+        """rg_tangent: per-scenario FP32 margins, their forward-mode dm/dv and
+        minimising steps, M(kappa) and dM/dkappa."""
+        x = _f64(x)
+        N = self.problem.N
+        m = np.zeros(N, dtype=np.float32)
+        dv = np.zeros(N, dtype=np.float32)
+        j = np.zeros(N, dtype=np.int32)
+        M = C.c_double()
+        dk = C.c_double()
+        self._check(self.L.rg_tangent(self.h, _ptr(x), float(r), float(v_prev), float(kappa),
+                                      _ptr(m, _fp), _ptr(dv, _fp), _ptr(j, _ip), C.byref(M),
+                                      C.byref(dk)))
+        return dict(m=m, dm_dv=dv, j=j, M=M.value, dkappa=dk.value)
 
     def autotune(self, x0, v0: float, r_seq, apply: bool = True) -> dict:
         """Time the closed loop over r_seq under each launch schedule (rg_autotune);

@@ -122,7 +122,7 @@ def test_create_rejects_bad_horizon_and_options(lib):
     assert _create(lib, p, dt=float("nan"))[0] == R.RG_E_INVAL
     for field, value, code in [("K", -1, R.RG_E_INVAL), ("depth", 9, R.RG_E_INVAL),
                                ("block", 100, R.RG_E_INVAL), ("block", 512, R.RG_E_INVAL),
-                               ("precision", 4, R.RG_E_INVAL), ("search", 4, R.RG_E_INVAL),
+                               ("precision", 4, R.RG_E_INVAL), ("search", 5, R.RG_E_INVAL),
                                ("Kc", 0, R.RG_E_INVAL), ("lanes", 2, R.RG_E_INVAL), ("predict", 2, R.RG_E_INVAL),
                                ("speculate", 8, R.RG_E_INVAL),
                                ("band", float("inf"), R.RG_E_INVAL), ("max_T", 0, R.RG_E_INVAL)]:
