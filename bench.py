@@ -137,9 +137,9 @@ def run_form(args):
     p = wl["problem"]
     r_seq = wl["r_seq"]
     T = len(r_seq)
-    kw = (dict(precision=rg.PREC_F32_RECHECK, search=rg.SEARCH_NEWTON)
-          if args.form == "fp32_adjoint_newton"
-          else dict(precision=rg.PREC_F64, depth=1, predict=False))
+    kw = {"fp32_adjoint_newton": dict(precision=rg.PREC_F32_RECHECK, search=rg.SEARCH_NEWTON),
+          "fp32_tangent_newton": dict(precision=rg.PREC_F32_RECHECK, search=rg.SEARCH_NEWTON_TAN),
+          "fp64_sequential_bisection": dict(precision=rg.PREC_F64, depth=1, predict=False)}[args.form]
     gm = rg.Governor(p, band=wl["band"], K=wl["K"], max_T=256, **kw)
     x0 = np.asarray(wl["x0"], dtype=np.float64)
     _loop(gm, x0, wl["v_prev"], r_seq, True)  # captures the graphs
@@ -198,6 +198,8 @@ def run_extras(args):
     U = args.extra_updates
     forms = {"fp32_adjoint_newton": dict(precision=rg.PREC_F32_RECHECK, search=rg.SEARCH_NEWTON,
                                          Kc=wa["Kc"]),
+             "fp32_tangent_newton": dict(precision=rg.PREC_F32_RECHECK,
+                                         search=rg.SEARCH_NEWTON_TAN),
              "fp64_sequential_bisection": dict(precision=rg.PREC_F64, depth=1, predict=False),
              "fp32_speculative_bisection": dict(precision=rg.PREC_F32_RECHECK)}
     c4 = {"workload": wa["name"], "updates": U}
@@ -223,11 +225,12 @@ def run_extras(args):
                     "value": sum(r["bisect_passes"] for r in res) * pa.N * pa.H / el,
                     "rounds_per_update": float(np.mean([r["rounds"] for r in res])),
                     "kappa": [float(k) for k in kap[name]]}
-    dn = np.abs(kap["fp32_adjoint_newton"] - kap["fp64_sequential_bisection"])
-    c4["newton_vs_fp64_bisection_max_abs_kappa_diff"] = float(np.max(dn))
-    c4["newton_kappa_within_2^-12"] = bool(np.all(dn <= 2.0 ** -wa["K"] + 1e-15))
-    c4["newton_speedup_vs_fp64_bisection"] = (c4["fp64_sequential_bisection"]["ms_per_update"] /
-                                             c4["fp32_adjoint_newton"]["ms_per_update"])
+    for nm in ["fp32_adjoint_newton", "fp32_tangent_newton"]:
+        dn = np.abs(kap[nm] - kap["fp64_sequential_bisection"])
+        c4[nm]["max_abs_kappa_diff_vs_fp64_bisection"] = float(np.max(dn))
+        c4[nm]["kappa_within_2^-12"] = bool(np.all(dn <= 2.0 ** -wa["K"] + 1e-15))
+        c4[nm]["speedup_vs_fp64_bisection"] = (c4["fp64_sequential_bisection"]["ms_per_update"] /
+                                               c4[nm]["ms_per_update"])
     out["fc9_adjoint_n16384_h1000"] = c4
     # the 9-state grid workload (64-point grid + 6 refinements)
     wg = W.workload_fc9_grid()
@@ -257,7 +260,89 @@ def run_extras(args):
         "rollout_tflops": (prof["lane_steps"] * FLOP_PER_STEP_FC9 / (prof["rollout_ms"] * 1e-3) / 1e12
                            if prof["rollout_ms"] > 0 else 0.0),
         "flop_per_scenario_step": FLOP_PER_STEP_FC9, "unit": "scenario-steps/s"}
+    out.update(run_more_extras(rg, W, np, torch))
     print(json.dumps(out))
+
+
+def _median_ms(fn, reps):
+    import torch
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        times.append(time.perf_counter() - t0)
+    return float(sorted(times)[len(times) // 2]) * 1e3
+
+
+def run_more_extras(rg, W, np, torch):
+    """Alg. 2 (per-scenario bisection), the chance-constrained verdict and the
+    allocation-free step, each timed on the workloads above."""
+    out = {}
+    # Alg. 2 on the 64-scenario FP64 update and on one update of the 4-state
+    # bench workload (a state where the search runs: kappa strictly inside)
+    w1 = W.workload_lq4_fp64_single()
+    wl = W.workload_lq4_closed_loop(T=40)
+    xs = np.array([0.12, -0.05, 0.3, -0.2])
+    alg2 = {}
+    for name, prob, prec, x, r, vp, t in [
+            ("lq4_fp64_n64_h500", w1["problem"], rg.PREC_F64, w1["x0"], w1["r"], w1["v_prev"], 0),
+            ("lq4_n4096_h2000_one_update", wl["problem"], rg.PREC_F32_RECHECK, xs, 1.9, 0.4, 26)]:
+        res = {}
+        for form, kw in [("alg2", dict(search=rg.SEARCH_ALG2)), ("bisection", dict())]:
+            g = rg.Governor(prob, precision=prec, K=12, **kw)
+            last = {}
+
+            def one():
+                g.set_step(t)
+                last.update(g.step(x, r, vp))
+            ms = _median_ms(one, 9)
+            g.close()
+            res[form] = {"ms_per_update": ms, "kappa": last["kappa"],
+                         "passes": last["bisect_passes"]}
+        res["same_kappa"] = res["alg2"]["kappa"] == res["bisection"]["kappa"]
+        alg2[name] = res
+    out["alg2_per_scenario_bisection"] = alg2
+    # chance-constrained verdict (at most q of N scenarios may violate) on the
+    # 4-state bench closed loop, first 50 updates, graph replay
+    wc = W.workload_lq4_closed_loop(T=50)
+    cc = {}
+    for q in (0, 4, 41):
+        g = rg.Governor(wc["problem"], band=wc["band"], K=wc["K"], chance_q=q, max_T=256)
+        g.closed_loop(wc["x0"], wc["v_prev"], wc["r_seq"], use_graph=True)  # capture
+        g.reset()
+        g.set_step(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = g.closed_loop(wc["x0"], wc["v_prev"], wc["r_seq"], use_graph=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        g.close()
+        cc[f"q={q}"] = {"ms_per_update": el / len(wc["r_seq"]) * 1e3,
+                        "mean_kappa": float(np.mean(o["kappa"])),
+                        "infeasible_updates": int(np.sum(o["status"] != 0))}
+    cc["updates"] = len(wc["r_seq"])
+    cc["N"] = wc["problem"].N
+    out["chance_constrained_lq4_closed_loop"] = cc
+    # allocation-free step against rg_step on one update of the bench workload
+    ga = rg.Governor(wl["problem"], band=wl["band"], K=wl["K"], torch_workspace=False)
+    gb = rg.Governor(wl["problem"], band=wl["band"], K=wl["K"])
+    ra, rb = {}, {}
+
+    def na():
+        ga.set_step(26)
+        ra.update(ga.step_noalloc(xs, 1.9, 0.4))
+
+    def st():
+        gb.set_step(26)
+        gb.reset()
+        rb.update(gb.step(xs, 1.9, 0.4))
+    out["noalloc_step_lq4_n4096_h2000"] = {"noalloc_ms": _median_ms(na, 9),
+                                           "rg_step_ms": _median_ms(st, 9),
+                                           "same_kappa": ra["kappa"] == rb["kappa"]}
+    ga.close()
+    gb.close()
+    return out
 
 
 def progress(msg):
@@ -287,7 +372,8 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="rollout workgroup (0: library choice)")
     ap.add_argument("--speculate", type=int, default=-1,
                     help="speculation depth with --no-autotune (-1: library default)")
-    ap.add_argument("--form", choices=["fp32_adjoint_newton", "fp64_sequential_bisection"],
+    ap.add_argument("--form", choices=["fp32_adjoint_newton", "fp32_tangent_newton",
+                                       "fp64_sequential_bisection"],
                     default=None, help=argparse.SUPPRESS)
     ap.add_argument("--extras-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--extra-updates", type=int, default=3,
@@ -388,7 +474,7 @@ def main():
 
     modes, extras = {}, {}
     if not args.no_extras:
-        for label in ["fp32_adjoint_newton", "fp64_sequential_bisection"]:
+        for label in ["fp32_adjoint_newton", "fp32_tangent_newton", "fp64_sequential_bisection"]:
             om = child(args, "--form", label)
             kap = np.asarray(om.pop("kappa"))
             om["same_closed_loop_as_headline"] = bool(np.array_equal(kap, out["kappa"]))

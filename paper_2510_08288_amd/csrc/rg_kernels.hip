@@ -376,15 +376,20 @@ __device__ __forceinline__ float rollout_lane_tan(const A& a, float v, int k, ui
   if (best != best) best = -INFINITY;
   jbest = 0;
   const float* wb = RNG == 0 ? step_w(a, t) : nullptr;
-  float w[P::nw];
-  int j = 0;
-  for (; j < a.H; ++j) {
+  auto load = [&](int jj, float* w) {
     if (RNG == 0) {
 #pragma unroll
-      for (int c = 0; c < P::nw; ++c) w[c] = wb[((size_t)j * P::nw + c) * a.N + k];
+      for (int c = 0; c < P::nw; ++c) w[c] = wb[((size_t)jj * P::nw + c) * a.N + k];
     } else {
-      draw_w<P::nw>(a.seed, a.inst, t, 0u, (uint32_t)k, (uint32_t)j, a.wlo, a.wspan, w);
+      draw_w<P::nw>(a.seed, a.inst, t, 0u, (uint32_t)k, (uint32_t)jj, a.wlo, a.wspan, w);
     }
+  };
+  // the next step's draws are in flight while this step computes
+  float w[P::nw], wn[P::nw];
+  if (a.H > 0) load(0, w);
+  int j = 0;
+  for (; j < a.H; ++j) {
+    if (j + 1 < a.H) load(j + 1, wn);
     float s[P::n];
     if (INJ == 0) P::force(a.pc, L, w, s);
     else P::force0(a.pc, L, s);
@@ -398,6 +403,8 @@ __device__ __forceinline__ float rollout_lane_tan(const A& a, float v, int k, ui
       dbest = dmj;
       jbest = j + 1;
     }
+#pragma unroll
+    for (int c = 0; c < P::nw; ++c) w[c] = wn[c];
   }
   nsteps = j;
   bool finite = true;
@@ -645,16 +652,22 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
     float bq = row_sum(x, grow), dbq = row_sum(dx, 0.f);
     int jq = 0;
     const float* wsrc_t = step_w(a, t);
-    for (int j = 0; j < a.H; ++j) {
-      float w0, w1;
+    auto ld = [&](int j, float& u0, float& u1) {
       if (RNG == 0) {
-        w0 = wsrc_t[(size_t)(2 * j) * a.N + k];
-        w1 = wsrc_t[(size_t)(2 * j + 1) * a.N + k];
+        u0 = wsrc_t[(size_t)(2 * j) * a.N + k];
+        u1 = wsrc_t[(size_t)(2 * j + 1) * a.N + k];
       } else {
         const Words r = philox10((uint32_t)k, (uint32_t)j, t, 0u, a.seed, a.inst);
-        w0 = box_draw(r.v[0], a.wlo[0], a.wspan[0]);
-        w1 = box_draw(r.v[1], a.wlo[1], a.wspan[1]);
+        u0 = box_draw(r.v[0], a.wlo[0], a.wspan[0]);
+        u1 = box_draw(r.v[1], a.wlo[1], a.wspan[1]);
       }
+    };
+    // draws of steps j + 1 and j + 2 are in flight while step j computes
+    float w0 = 0.f, w1 = 0.f, n0 = 0.f, n1 = 0.f, f0 = 0.f, f1 = 0.f;
+    if (a.H > 0) ld(0, w0, w1);
+    if (a.H > 1) ld(1, n0, n1);
+    for (int j = 0; j < a.H; ++j) {
+      if (j + 2 < a.H) ld(j + 2, f0, f1);
       const float sf = INJ == 0 ? __builtin_fmaf(e1, w1, __builtin_fmaf(e0, w0, bv)) : bv;
       const float k1 = quad_deriv(L, sf, x), t1 = quad_tan(L, bq0, x, dx);
       float acc = k1, dacc = t1;
@@ -680,6 +693,10 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
         dbq = dmr;
         jq = j + 1;
       }
+      w0 = n0;
+      w1 = n1;
+      n0 = f0;
+      n1 = f1;
     }
     ns = a.H;
     quad_min_tan(bq, dbq, jq, q);

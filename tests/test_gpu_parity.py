@@ -422,7 +422,7 @@ def test_closed_loop_with_failing_probes_matches_oracle(R, O):
         v_prev = a["v"][s]
 
 
-@pytest.mark.parametrize("mode", ["f64_bisect", "grid", "newton"])
+@pytest.mark.parametrize("mode", ["f64_bisect", "grid", "newton", "newton_tan"])
 def test_closed_loop_search_forms_graph_equals_eager(R, O, mode):
     # Every search form runs the closed loop as generic rounds (a step takes
     # as many as its search needs).  Graph replay and plain launches give
@@ -432,7 +432,8 @@ def test_closed_loop_search_forms_graph_equals_eager(R, O, mode):
     r_seq = W.reference_sequence(3, 10, switch_every=3, lo=-2.0, hi=2.0)
     kw = {"f64_bisect": dict(precision=R.PREC_F64, predict=False),
           "grid": dict(search=R.SEARCH_GRID, M=17, refine=4),
-          "newton": dict(search=R.SEARCH_NEWTON)}[mode]
+          "newton": dict(search=R.SEARCH_NEWTON),
+          "newton_tan": dict(search=R.SEARCH_NEWTON_TAN)}[mode]
     a = _gov(R, p, **kw).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
     b = _gov(R, p, **kw).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=False)
     for key in ("kappa", "v", "x"):
@@ -445,7 +446,7 @@ def test_closed_loop_search_forms_graph_equals_eager(R, O, mode):
             ref = o.grid(a["x"][s], r_seq[s], v_prev, s, 17, 4)
         else:
             ref = o.bisect(a["x"][s], r_seq[s], v_prev, s, 12)
-        if mode == "newton":
+        if mode in ("newton", "newton_tan"):
             # Newton's result is the admissible end of a bracket of width <= 2^-12
             assert abs(a["kappa"][s] - ref["kappa"]) <= 2.0 ** -12, (s, a["kappa"][s], ref["kappa"])
         else:
