@@ -342,7 +342,52 @@ def run_more_extras(rg, W, np, torch):
                                            "same_kappa": ra["kappa"] == rb["kappa"]}
     ga.close()
     gb.close()
+    out["batch_1024_lq4_fc9"] = run_batch(rg, W, np, torch)
     return out
+
+
+def run_batch(rg, W, np, torch, steps=2):
+    """Batched serving: 1024 independent instances (512 four-state, 512
+    nine-state), N ~ U{256..8192}, H ~ U{200..3000}, dt = 0.005, own seeds,
+    states and references; every batched RG step replayed from one captured
+    graph.  The first step captures the graph and is not timed."""
+    insts = W.batch_instances(count=1024)
+    probs = [b.problem for b in insts]
+    # the 9-state instances start at the nominal equilibrium of their v_prev
+    # (shared plant): one device equilibrium serves them all
+    ge = rg.Governor(probs[1])
+    x_fc9 = ge.equilibrium(insts[1].v_prev)
+    ge.close()
+    xs = [b.x0 if b.x0 is not None else x_fc9 for b in insts]
+    rs = [b.r for b in insts]
+    vps = [b.v_prev for b in insts]
+    t0 = time.perf_counter()
+    bt = rg.Batch(probs)
+    bt.step(xs, rs, vps, use_graph=True)  # allocates, captures, runs step 0
+    torch.cuda.synchronize()
+    first = time.perf_counter() - t0
+    outs = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        outs.append(bt.step(xs, rs, vps, use_graph=True))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    depth = bt.options.depth
+    bt.close()
+    NH = np.array([p.N * p.H for p in probs], dtype=np.float64)
+    nominal = sum(float(np.sum(o["bisect_passes"] * NH)) for o in outs)
+    executed = sum(float(np.sum(o["lane_steps"])) for o in outs)
+    return {"instances": len(probs), "steps_timed": steps,
+            "ms_per_batched_step": el / steps * 1e3,
+            "instance_updates_per_s": len(probs) * steps / el,
+            "value": nominal / el, "unit": "scenario-steps/s",
+            "executed_scenario_steps_per_s": executed / el,
+            "mean_rounds": float(np.mean([np.mean(o["rounds"]) for o in outs])),
+            "infeasible_instance_updates": int(sum(np.sum(o["status"] != 0) for o in outs)),
+            "mean_kappa_lq4": float(np.mean([np.mean(o["kappa"][0::2]) for o in outs])),
+            "mean_kappa_fc9": float(np.mean([np.mean(o["kappa"][1::2]) for o in outs])),
+            "first_step_with_capture_s": first,
+            "sum_N_x_H": float(np.sum(NH)), "depth_instance0": int(depth)}
 
 
 def progress(msg):

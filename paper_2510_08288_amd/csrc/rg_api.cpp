@@ -1306,25 +1306,36 @@ int rg_trajectory(rg_handle* h, const double* x, double v, const int32_t* k_list
   return RG_OK;
 }
 
+}  // extern "C"
+
 // ---------------------------------------------------------------------------
 // Batched serving
 // ---------------------------------------------------------------------------
-// The batched device step (k_batch_* kernels) is switched off: its first device
-// run ended in a memory fault that a host emulation of the same kernels (ASan and
-// bounds checks, same inputs) does not reproduce, so no cause is identified yet.
-// Creation, options and validation stay available.
-constexpr bool kBatchDeviceEnabled = false;
+// Many independent governors stepped together.  Every instance runs the
+// single-instance RG step, with the kernels of rg_step, on its own search
+// record and recheck list, carved from one device allocation; the draws are
+// regenerated inside the kernels (a batch of a thousand instances could not
+// hold their draw buffers).  The instances' launch chains are spread over
+// kBatchStreams streams of default priority, so several instances' kernels run
+// at once.  One batched step (fork to the streams, every instance's chain,
+// join) is captured once as a HIP graph and replayed; states go up and results
+// come back in one copy each.
+constexpr int kBatchStreams = 4;
 
 struct rg_batch {
   int count = 0;
   rg_options opt{};
-  std::vector<Problem> probs;
-  std::vector<int> noff;          // offset of each instance's state in the packed x array
-  std::vector<uint32_t> t;        // per-instance RG step counters
-  int cmax_round = 0, rounds = 0, grid = 0, tile = 256;
-  hipStream_t stream = nullptr;
+  std::vector<rg_handle*> inst;  // per instance: problem, plan and carved buffers
+  std::vector<int> noff;         // offset of each instance's state in the packed x array
+  std::vector<uint32_t> t;       // per-instance RG step counters
+  hipStream_t stream = nullptr;  // the caller's stream (NULL: own_stream)
+  hipStream_t own_stream = nullptr;
+  hipStream_t side[kBatchStreams] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kBatchStreams] = {};
   void* mem = nullptr;
-  BatchBuffers b{};
+  DevState* st = nullptr;   // [count]
+  DevResult* res = nullptr; // [count]
   hipGraphExec_t graph = nullptr;
   std::string err;
 };
@@ -1337,43 +1348,116 @@ int bfail(rg_batch* bt, int code, const std::string& msg) {
   return code;
 }
 
-void fill_desc(const Problem& pr, InstDesc& d) {
-  memset(&d, 0, sizeof(d));
-  const int ncoef = pr.p.kind == RG_PLANT_LQ4 ? 52 : 115;
-  for (int i = 0; i < ncoef; ++i) {
-    d.c64[i] = pr.p.coeffs[i];
-    d.c32[i] = (float)pr.p.coeffs[i];
+// Search levels per device round for an instance of a batch: enough candidates
+// that the instances running at once (one per stream) fill the chip, as
+// depth_for does for a handle of its own.
+int batch_depth(int N, int lanes, int K) {
+  const double budget = 2.0 * 256 * 4 * 64 / kBatchStreams;
+  const double per_cand = (double)N * lanes;
+  int dmax = 1;
+  while (dmax < 6 && ((1 << (dmax + 1)) - 1) * per_cand <= budget) ++dmax;
+  if (K <= 0) return 1;
+  const int rounds = (K + dmax - 1) / dmax;
+  return (K + rounds - 1) / rounds;
+}
+
+void batch_release(rg_batch* bt) {
+  if (bt->graph) (void)hipGraphExecDestroy(bt->graph);
+  bt->graph = nullptr;
+  for (hipStream_t& s : bt->side) {
+    if (s) (void)hipStreamDestroy(s);
+    s = nullptr;
   }
-  for (int r = 0; r < kNC; ++r) {
-    for (int y = 0; y < pr.p.ny; ++y) {
-      d.F64[r * pr.p.ny + y] = pr.c.F[r * pr.p.ny + y];
-      d.F32[r * pr.p.ny + y] = (float)pr.c.F[r * pr.p.ny + y];
-    }
-    d.g64[r] = pr.c.g[r];
-    d.g32[r] = (float)pr.c.g[r];
+  if (bt->own_stream) (void)hipStreamDestroy(bt->own_stream);
+  bt->own_stream = nullptr;
+  if (bt->fork) (void)hipEventDestroy(bt->fork);
+  bt->fork = nullptr;
+  for (hipEvent_t& e : bt->join) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
   }
-  d.hd = pr.dt;
-  d.hhd = pr.dt * 0.5;
-  d.h6d = pr.dt / 6.0;
-  d.h = (float)pr.dt;
-  d.hh = (float)(pr.dt * 0.5);
-  d.h6 = (float)(pr.dt / 6.0);
-  for (int c = 0; c < pr.p.nw; ++c) {
-    d.wlo[c] = (float)pr.s.wlo[c];
-    d.wspan[c] = (float)(pr.s.whi[c] - pr.s.wlo[c]);
+  if (bt->mem) (void)hipFree(bt->mem);
+  bt->mem = nullptr;
+  for (rg_handle* h : bt->inst) rg_destroy(h);  // no workspace of their own
+  bt->inst.clear();
+}
+
+// Device memory and streams, on the first step.
+int batch_ensure_memory(rg_batch* bt) {
+  if (bt->mem) return RG_OK;
+  const int count = bt->count;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t o_st = take(sizeof(DevState) * count);
+  const size_t o_srch = take(sizeof(DevSearch) * count);
+  const size_t o_res = take(sizeof(DevResult) * count);
+  std::vector<size_t> o_rl(count);
+  for (int i = 0; i < count; ++i) {
+    const rg_handle* h = bt->inst[i];
+    o_rl[i] = take(sizeof(int2) * (size_t)h->cfg.cmax_round * (size_t)h->pr.s.N);
   }
-  d.thlo = (float)(1.0 - pr.s.theta_rel);
-  d.thspan = (float)(2.0 * pr.s.theta_rel);
-  d.kind = pr.p.kind;
-  d.n = pr.p.n;
-  d.N = pr.s.N;
-  d.H = pr.H;
-  d.inject = pr.s.inject;
-  d.seed = pr.s.seed;
-  d.instance = pr.s.instance;
+  hipError_t e = hipMalloc(&bt->mem, off);
+  if (e != hipSuccess) {
+    bt->mem = nullptr;
+    return bfail(bt, RG_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  if (!bt->own_stream) e = hipStreamCreateWithFlags(&bt->own_stream, hipStreamNonBlocking);
+  for (int s = 0; s < kBatchStreams && e == hipSuccess; ++s)
+    e = hipStreamCreateWithFlags(&bt->side[s], hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->fork, hipEventDisableTiming);
+  for (int s = 0; s < kBatchStreams && e == hipSuccess; ++s)
+    e = hipEventCreateWithFlags(&bt->join[s], hipEventDisableTiming);
+  if (e != hipSuccess) return bfail(bt, RG_E_HIP, std::string("batch streams: ") + hipGetErrorString(e));
+  char* base = (char*)bt->mem;
+  bt->st = (DevState*)(base + o_st);
+  bt->res = (DevResult*)(base + o_res);
+  DevSearch* srch = (DevSearch*)(base + o_srch);
+  std::vector<DevSearch> tmpl(count);
+  for (int i = 0; i < count; ++i) {
+    rg_handle* h = bt->inst[i];
+    DevBuffers b{};
+    b.st = bt->st + i;
+    b.srch = srch + i;
+    b.res = bt->res + i;
+    b.rlist = (int2*)(base + o_rl[i]);
+    h->b = b;
+    h->ws = bt->mem;  // carved from the batch's allocation: never freed by the handle
+    h->ws_owned = false;
+    h->ws_ready = true;
+    h->stream = bt->side[i % kBatchStreams];
+    fill_search(h, &tmpl[i], 0);
+  }
+  const hipStream_t ms = bt->stream ? bt->stream : bt->own_stream;
+  e = hipMemcpyAsync(srch, tmpl.data(), sizeof(DevSearch) * count, hipMemcpyHostToDevice, ms);
+  if (e == hipSuccess) e = hipStreamSynchronize(ms);
+  if (e != hipSuccess) return bfail(bt, RG_E_HIP, std::string("batch upload: ") + hipGetErrorString(e));
+  return RG_OK;
+}
+
+// One batched step on the main stream: fork to the side streams, every
+// instance's RG step on its stream, join.
+hipError_t batch_enqueue(rg_batch* bt, hipStream_t ms) {
+  hipError_t e = hipEventRecord(bt->fork, ms);
+  for (int s = 0; s < kBatchStreams && e == hipSuccess; ++s)
+    e = hipStreamWaitEvent(bt->side[s], bt->fork, 0);
+  for (int i = 0; i < bt->count && e == hipSuccess; ++i) {
+    rg_handle* h = bt->inst[i];
+    e = enqueue_step(h, h->pr, h->b, false);
+  }
+  for (int s = 0; s < kBatchStreams && e == hipSuccess; ++s) {
+    e = hipEventRecord(bt->join[s], bt->side[s]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ms, bt->join[s], 0);
+  }
+  return e;
 }
 
 }  // namespace
+
+extern "C" {
 
 int rg_batch_create(const rg_instance_desc* descs, int32_t count, const rg_options* opt,
                     rg_batch** out) {
@@ -1383,9 +1467,8 @@ int rg_batch_create(const rg_instance_desc* descs, int32_t count, const rg_optio
   rg_options o;
   rg_default_options(&o);
   if (opt) o = *opt;
-  if (o.precision != RG_PREC_F32_RECHECK)
-    return bfail(nullptr, RG_E_NOTSUP, "batches run FP32 rollouts with the FP64 recheck");
-  if (o.search != RG_SEARCH_BISECT) return bfail(nullptr, RG_E_NOTSUP, "batches use bisection");
+  if (o.search != RG_SEARCH_BISECT && o.search != RG_SEARCH_GRID)
+    return bfail(nullptr, RG_E_NOTSUP, "batches use bisection or the grid search");
   if (o.chance_q != 0) return bfail(nullptr, RG_E_NOTSUP, "batches use the robust verdict");
   if (o.block != 0 && o.block != 64 && o.block != 128 && o.block != 256)
     return bfail(nullptr, RG_E_INVAL, "block must be 64, 128 or 256");
@@ -1393,43 +1476,32 @@ int rg_batch_create(const rg_instance_desc* descs, int32_t count, const rg_optio
   rg_batch* bt = new (std::nothrow) rg_batch;
   if (!bt) return bfail(nullptr, RG_E_NOMEM, "host allocation");
   bt->count = count;
-  bt->tile = o.block ? o.block : 256;
-  long long lanes = 0;
+  bt->opt = o;
   int noff = 0;
   for (int i = 0; i < count; ++i) {
     rg_scenarios s = descs[i].scen;
     s.rng_mode = RG_RNG_INLINE;
     rg_options oi = o;
-    oi.depth = 1;
+    oi.speculate = 0;
+    oi.max_T = 1;
+    if (o.depth == 0) {
+      const bool quad = descs[i].plant.kind == RG_PLANT_LQ4 && o.precision == RG_PREC_F32_RECHECK &&
+                        o.lanes != 1;
+      oi.depth = batch_depth(descs[i].scen.N, quad ? 4 : 1,
+                             o.search == RG_SEARCH_GRID ? o.refine : o.K);
+    }
     rg_handle* h = nullptr;
     const int rc = rg_create(&descs[i].plant, &s, &descs[i].cons, descs[i].H, descs[i].dt, &oi, &h);
     if (rc != RG_OK) {
       std::string m = std::string("instance ") + std::to_string(i) + ": " + g_create_error;
+      batch_release(bt);
       delete bt;
       return bfail(nullptr, rc, m);
     }
-    bt->probs.push_back(h->pr);
-    rg_destroy(h);
+    bt->inst.push_back(h);
     bt->noff.push_back(noff);
-    noff += bt->probs.back().p.n;
-    lanes += descs[i].scen.N;
+    noff += h->pr.p.n;
   }
-  // search plan: a round already holds sum_i N_i lanes per candidate, so
-  // speculative levels only when that is below the chip's capacity
-  int d = o.depth;
-  if (d == 0) {
-    const double budget = 2.0 * 256 * 4 * 64;
-    d = 1;
-    while (d < 6 && ((1 << (d + 1)) - 1) * (double)lanes <= budget) ++d;
-    const int rounds = o.K > 0 ? (o.K + d - 1) / d : 1;
-    d = o.K > 0 ? (o.K + rounds - 1) / rounds : 1;
-  }
-  o.depth = d;
-  const int d0 = o.K < d ? o.K : d;
-  bt->cmax_round = std::max(1 << d0, (1 << d) - 1);
-  bt->rounds = 1 + (o.K - d0 + d - 1) / d;
-  bt->grid = o.persistent_wgs > 0 ? o.persistent_wgs : 4 * 256;
-  bt->opt = o;
   bt->t.assign(count, 0u);
   *out = bt;
   return RG_OK;
@@ -1437,8 +1509,7 @@ int rg_batch_create(const rg_instance_desc* descs, int32_t count, const rg_optio
 
 int rg_batch_destroy(rg_batch* bt) {
   if (!bt) return RG_OK;
-  if (bt->graph) (void)hipGraphExecDestroy(bt->graph);
-  if (bt->mem) (void)hipFree(bt->mem);
+  batch_release(bt);
   delete bt;
   return RG_OK;
 }
@@ -1459,146 +1530,57 @@ int rg_batch_set_step(rg_batch* bt, int32_t i, uint32_t t) {
   return RG_OK;
 }
 
-static int batch_ensure_memory(rg_batch* bt) {
-  if (bt->mem) return RG_OK;
-  const int count = bt->count;
-  // instances by decreasing cost per scenario tile (horizon x plant weight)
-  std::vector<int32_t> order(count);
-  std::iota(order.begin(), order.end(), 0);
-  auto cost = [&](int i) {
-    return (double)bt->probs[i].H * (bt->probs[i].p.kind == RG_PLANT_FC9 ? 4.0 : 1.0);
-  };
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
-  std::vector<int32_t> tile_start(count + 1, 0);
-  size_t lanes = 0;
-  for (int s = 0; s < count; ++s) {
-    const int i = order[s];
-    tile_start[s + 1] = tile_start[s] + (bt->probs[i].s.N + bt->tile - 1) / bt->tile;
-    lanes += (size_t)bt->probs[i].s.N;
-  }
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    size_t o = off;
-    off = align256(off + bytes);
-    return o;
-  };
-  const size_t o_desc = take(sizeof(InstDesc) * count);
-  const size_t o_st = take(sizeof(DevState) * count);
-  const size_t o_srch = take(sizeof(DevSearch) * count);
-  const size_t o_res = take(sizeof(DevResult) * count);
-  const size_t o_order = take(sizeof(int32_t) * count);
-  const size_t o_tiles = take(sizeof(int32_t) * (count + 1));
-  const size_t o_cnt = take(sizeof(int32_t) * 4);
-  const size_t o_rlist = take(sizeof(int4) * lanes * (size_t)bt->cmax_round);
-  hipError_t e = hipMalloc(&bt->mem, off);
-  if (e != hipSuccess) return bfail(bt, RG_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-  char* base = (char*)bt->mem;
-  BatchBuffers& b = bt->b;
-  b.count = count;
-  b.desc = (InstDesc*)(base + o_desc);
-  b.st = (DevState*)(base + o_st);
-  b.srch = (DevSearch*)(base + o_srch);
-  b.res = (DevResult*)(base + o_res);
-  b.order = (int32_t*)(base + o_order);
-  b.tile_start = (int32_t*)(base + o_tiles);
-  b.counters = (int32_t*)(base + o_cnt);
-  b.rlist = (int4*)(base + o_rlist);
-  b.total_tiles = tile_start[count];
-  b.tile = bt->tile;
-  std::vector<InstDesc> desc(count);
-  std::vector<DevSearch> srch(count);
-  for (int i = 0; i < count; ++i) {
-    const Problem& pr = bt->probs[i];
-    fill_desc(pr, desc[i]);
-    DevSearch& S = srch[i];
-    memset(&S, 0, sizeof(S));
-    for (int e = 0; e < kMssCache; ++e) S.mss_v[e] = std::nan("");
-    S.mode = kBisect;
-    S.K = bt->opt.K;
-    S.depth = bt->opt.depth;
-    S.precision = RG_PREC_F32_RECHECK;
-    S.ss_check = pr.c.ss_check;
-    S.n_c = pr.c.n_c;
-    S.ny = pr.p.ny;
-    S.eps = pr.c.eps;
-    for (int r = 0; r < kNC; ++r) S.g[r] = pr.c.g[r];
-    for (int q = 0; q < kNC * kMaxY; ++q) S.F[q] = pr.c.F[q];
-    S.delta = std::ldexp(1.0, -bt->opt.K);
-    S.predict = 0;
-    S.pred = std::nan("");
-    S.done = 1;
-  }
-  e = hipMemcpyAsync(b.desc, desc.data(), sizeof(InstDesc) * count, hipMemcpyHostToDevice, bt->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(b.srch, srch.data(), sizeof(DevSearch) * count, hipMemcpyHostToDevice, bt->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(b.order, order.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, bt->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(b.tile_start, tile_start.data(), sizeof(int32_t) * (count + 1),
-                       hipMemcpyHostToDevice, bt->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(bt->stream);
-  if (e != hipSuccess) return bfail(bt, RG_E_HIP, std::string("batch upload: ") + hipGetErrorString(e));
-  return RG_OK;
-}
-
-static hipError_t batch_enqueue(rg_batch* bt) {
-  hipError_t e = launch_batch_setup(bt->b, bt->stream);
-  for (int r = 0; r < bt->rounds && e == hipSuccess; ++r)
-    e = launch_batch_round(bt->b, bt->cmax_round, bt->opt.band, bt->opt.early_exit, bt->grid,
-                           bt->stream);
-  if (e == hipSuccess) e = launch_batch_finalize(bt->b, bt->stream);
-  return e;
-}
-
 int rg_batch_step(rg_batch* bt, const double* x, const double* r, const double* v_prev,
                   double* v_out, double* kappa_out, rg_step_info* info_out, int32_t use_graph) {
   if (!bt) return RG_E_INVAL;
   if (!x || !r || !v_prev || !v_out) return bfail(bt, RG_E_INVAL, "NULL argument");
   const int count = bt->count;
   for (int i = 0; i < count; ++i) {
-    if (!finite_array(x + bt->noff[i], bt->probs[i].p.n) || !std::isfinite(r[i]) ||
+    if (!finite_array(x + bt->noff[i], bt->inst[i]->pr.p.n) || !std::isfinite(r[i]) ||
         !std::isfinite(v_prev[i]))
       return bfail(bt, RG_E_INVAL, "non-finite input");
   }
-  if (!kBatchDeviceEnabled)
-    return bfail(bt, RG_E_NOTSUP,
-                 "the batched device step is switched off: its kernels faulted on the device "
-                 "and the cause is not yet identified");
   int rc = batch_ensure_memory(bt);
   if (rc) return rc;
+  const hipStream_t ms = bt->stream ? bt->stream : bt->own_stream;
   std::vector<DevState> st(count);
   for (int i = 0; i < count; ++i) {
     memset(&st[i], 0, sizeof(DevState));
-    for (int q = 0; q < bt->probs[i].p.n; ++q) st[i].x[q] = x[bt->noff[i] + q];
+    for (int q = 0; q < bt->inst[i]->pr.p.n; ++q) st[i].x[q] = x[bt->noff[i] + q];
     st[i].v_prev = v_prev[i];
     st[i].r = r[i];
     st[i].t = bt->t[i];
   }
-  hipError_t e = hipMemcpyAsync(bt->b.st, st.data(), sizeof(DevState) * count,
-                                hipMemcpyHostToDevice, bt->stream);
+  hipError_t e = hipMemcpyAsync(bt->st, st.data(), sizeof(DevState) * count,
+                                hipMemcpyHostToDevice, ms);
   if (e != hipSuccess) return bfail(bt, RG_E_HIP, std::string("upload: ") + hipGetErrorString(e));
   if (use_graph) {
     if (!bt->graph) {
       hipGraph_t g = nullptr;
-      e = hipStreamBeginCapture(bt->stream, hipStreamCaptureModeThreadLocal);
+      e = hipStreamBeginCapture(ms, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return bfail(bt, RG_E_HIP, std::string("capture: ") + hipGetErrorString(e));
-      hipError_t e1 = batch_enqueue(bt);
-      hipError_t e2 = hipStreamEndCapture(bt->stream, &g);
-      if (e1 != hipSuccess || e2 != hipSuccess)
+      hipError_t e1 = batch_enqueue(bt, ms);
+      hipError_t e2 = hipStreamEndCapture(ms, &g);
+      if (e1 != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
         return bfail(bt, RG_E_HIP, std::string("capture batch step: ") +
                                        hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+      }
       e = hipGraphInstantiate(&bt->graph, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
-      if (e != hipSuccess) return bfail(bt, RG_E_HIP, std::string("instantiate: ") + hipGetErrorString(e));
+      if (e != hipSuccess) {
+        bt->graph = nullptr;
+        return bfail(bt, RG_E_HIP, std::string("instantiate: ") + hipGetErrorString(e));
+      }
     }
-    e = hipGraphLaunch(bt->graph, bt->stream);
+    e = hipGraphLaunch(bt->graph, ms);
   } else {
-    e = batch_enqueue(bt);
+    e = batch_enqueue(bt, ms);
   }
   if (e != hipSuccess) return bfail(bt, RG_E_HIP, std::string("batch step: ") + hipGetErrorString(e));
   std::vector<DevResult> R(count);
-  e = hipMemcpyAsync(R.data(), bt->b.res, sizeof(DevResult) * count, hipMemcpyDeviceToHost, bt->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(bt->stream);
+  e = hipMemcpyAsync(R.data(), bt->res, sizeof(DevResult) * count, hipMemcpyDeviceToHost, ms);
+  if (e == hipSuccess) e = hipStreamSynchronize(ms);
   if (e != hipSuccess) return bfail(bt, RG_E_HIP, std::string("batch results: ") + hipGetErrorString(e));
   for (int i = 0; i < count; ++i) {
     v_out[i] = R[i].v;
@@ -1612,6 +1594,7 @@ int rg_batch_step(rg_batch* bt, const double* x, const double* r, const double* 
 int rg_batch_get_options(const rg_batch* bt, rg_options* out) {
   if (!bt || !out) return RG_E_INVAL;
   *out = bt->opt;
+  if (!bt->inst.empty()) out->depth = bt->inst[0]->opt.depth;
   return RG_OK;
 }
 

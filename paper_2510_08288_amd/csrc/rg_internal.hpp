@@ -203,40 +203,6 @@ struct LaunchCfg {
   int tan;                 // 1: derivatives by the forward tangent fused into the rollout
 };
 
-// One instance of a batch (device memory, read-only in the kernels).  The
-// coefficient arrays have the layout of Plant<KIND, T>::Coef.
-struct InstDesc {
-  double c64[kMaxCoef + 1];
-  double F64[kNC * kMaxY], g64[kNC];
-  double hd, hhd, h6d;
-  float c32[kMaxCoef + 1];
-  float F32[kNC * kMaxY], g32[kNC];
-  float h, hh, h6;
-  float wlo[kMaxW], wspan[kMaxW];
-  float thlo, thspan;
-  int32_t kind, n, N, H, inject;
-  uint32_t seed, instance;
-};
-
-struct BatchBuffers {
-  int32_t count;
-  InstDesc* desc;          // [count]
-  DevState* st;            // [count]
-  DevSearch* srch;         // [count]
-  DevResult* res;          // [count]
-  int32_t* order;          // [count] instances by decreasing cost
-  int32_t* tile_start;     // [count + 1] first scenario tile of each ordered instance
-  int32_t total_tiles;
-  int32_t tile;            // scenarios per tile (= rollout workgroup size)
-  int32_t* counters;       // [0] task queue head, [1] recheck list length
-  int4* rlist;             // (instance, candidate, scenario) near-band entries
-};
-
-// ---- launchers implemented in rg_kernels.hip --------------------------------
-hipError_t launch_batch_setup(const BatchBuffers& b, hipStream_t st);
-hipError_t launch_batch_round(const BatchBuffers& b, int cmax_round, double band, int early,
-                              int grid, hipStream_t st);
-hipError_t launch_batch_finalize(const BatchBuffers& b, hipStream_t st);
 // Everything a launch needs about the problem (host copy).
 struct Problem {
   PlantDesc p;
@@ -246,6 +212,7 @@ struct Problem {
   double dt;
 };
 
+// ---- launchers implemented in rg_kernels.hip --------------------------------
 // Draws of step t + t_ofs (t: the device step counter) into b.wbuf / b.thbuf.
 hipError_t launch_gen(const Problem& pr, const DevBuffers& b, hipStream_t st, uint32_t t_ofs = 0);
 // Whether launch_rollout runs the LQ4 quad kernel for this configuration.

@@ -2509,205 +2509,6 @@ __global__ void k_equilibrium(const CtlArgs<KIND> a, double v, double* out) {
 }
 
 // ---------------------------------------------------------------------------
-// Batched serving: many independent governors (uneven N, H, plant kind) per
-// launch.  A persistent rollout kernel pops (scenario tile, candidate) tasks
-// from one atomic queue; tiles are ordered by decreasing instance cost so the
-// longest work starts first.  Draws are generated inline (no per-instance
-// buffers).  Setup / decide run one workgroup per instance.
-// ---------------------------------------------------------------------------
-template <int KIND, class T>
-struct DescView {
-  using P = Plant<KIND, T>;
-  const typename P::Coef& pc;
-  const T* F;
-  const T* g;
-  T h, hh, h6, band;
-  int H, N;
-  uint32_t seed, inst;
-  const float* wlo;
-  const float* wspan;
-  float thlo, thspan;
-  const float* wbuf;
-  const float* thbuf;
-  const DevState* st;
-  int ring = 0;  // batches draw inline: no closed-loop draw ring
-  float* const* wring = nullptr;
-  float* const* thring = nullptr;
-};
-
-template <int KIND>
-__device__ __forceinline__ DescView<KIND, float> view32(const InstDesc& d, const DevState* st,
-                                                        float band) {
-  return DescView<KIND, float>{
-      *reinterpret_cast<const typename Plant<KIND, float>::Coef*>(d.c32),
-      d.F32, d.g32, d.h, d.hh, d.h6, band, d.H, d.N, d.seed, d.instance, d.wlo, d.wspan,
-      d.thlo, d.thspan, nullptr, nullptr, st};
-}
-template <int KIND>
-__device__ __forceinline__ DescView<KIND, double> view64(const InstDesc& d, const DevState* st) {
-  return DescView<KIND, double>{
-      *reinterpret_cast<const typename Plant<KIND, double>::Coef*>(d.c64),
-      d.F64, d.g64, d.hd, d.hhd, d.h6d, 0.0, d.H, d.N, d.seed, d.instance, d.wlo, d.wspan,
-      d.thlo, d.thspan, nullptr, nullptr, st};
-}
-template <int KIND>
-__device__ __forceinline__ const typename Plant<KIND, double>::Coef& coef64(const InstDesc& d) {
-  return *reinterpret_cast<const typename Plant<KIND, double>::Coef*>(d.c64);
-}
-
-__global__ void __launch_bounds__(64) k_batch_setup(BatchBuffers b) {
-  const int i = blockIdx.x;
-  const InstDesc& d = b.desc[i];
-  if (d.kind == 1) setup_body<1>(coef64<1>(d), &b.st[i], &b.srch[i], nullptr, 0);
-  else setup_body<2>(coef64<2>(d), &b.st[i], &b.srch[i], nullptr, 0);
-}
-
-__global__ void k_batch_reset(BatchBuffers b) {
-  if (threadIdx.x == 0) {
-    b.counters[0] = 0;
-    b.counters[1] = 0;
-  }
-}
-
-template <int KIND, int INJ>
-__device__ __forceinline__ void batch_task(const BatchBuffers& b, int i, int c, int tile,
-                                           int early, float band, unsigned long long* sh) {
-  const InstDesc& d = b.desc[i];
-  DevSearch* S = &b.srch[i];
-  const DevState* st = &b.st[i];
-  const auto a = view32<KIND>(d, st, band);
-  const int k = tile * b.tile + threadIdx.x;
-  float m = INFINITY;
-  int jb = 0, ns = 0;
-  if (k < d.N) {
-    m = rollout_lane<KIND, float, 1, INJ>(a, early, (float)S->v[c], k, st->t,
-                                          early ? &S->dead[c] : nullptr, jb, ns, nullptr);
-    if (m < -band) {
-      __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else if (m < band) {
-      const int idx = atomicAdd(&b.counters[1], 1);
-      b.rlist[idx] = make_int4(i, c, k, 0);
-    }
-  }
-  const unsigned long long key = lane_key(m, k);
-  const unsigned long long kall = block_min_u64(key, sh);
-  const unsigned long long kfar = block_min_u64((m >= band) ? key : ~0ull, sh);
-  int wsum = ns;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off);
-  if ((threadIdx.x & 63) == 0) atomicAdd(&S->lane_steps, (unsigned long long)wsum);
-  if (threadIdx.x == 0) {
-    atomicMin(&S->key_all[c], kall);
-    if (kfar != ~0ull) atomicMin(&S->key_far[c], kfar);
-  }
-}
-
-// Persistent: every workgroup pops tasks until the queue is empty (each
-// workgroup reaches the exit test once per task, so the grid always drains).
-__global__ void __launch_bounds__(256) k_batch_rollout(BatchBuffers b, int cmax, float band,
-                                                       int early_opt) {
-  __shared__ int s_task;
-  __shared__ unsigned long long sh[16];
-  const int n_tasks = b.total_tiles * cmax;
-  for (;;) {
-    if (threadIdx.x == 0) s_task = atomicAdd(&b.counters[0], 1);
-    __syncthreads();
-    const int task = s_task;
-    __syncthreads();
-    if (task >= n_tasks) break;
-    const int gtile = task / cmax;
-    const int c = task - gtile * cmax;
-    int lo = 0, hi = b.count;  // last ordered instance whose first tile <= gtile
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (b.tile_start[mid] <= gtile) lo = mid;
-      else hi = mid;
-    }
-    const int i = b.order[lo];
-    const int tile = gtile - b.tile_start[lo];
-    DevSearch* S = &b.srch[i];
-    if (S->done || c >= S->n_cand) continue;
-    const int early = early_opt && !S->full[c];
-    if (early && S->mss[c] < 0.0) {
-      if (threadIdx.x == 0)
-        __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      continue;
-    }
-    const InstDesc& d = b.desc[i];
-    if (d.kind == 1) {
-      if (d.inject == 0) batch_task<1, 0>(b, i, c, tile, early, band, sh);
-      else batch_task<1, 1>(b, i, c, tile, early, band, sh);
-    } else {
-      if (d.inject == 0) batch_task<2, 0>(b, i, c, tile, early, band, sh);
-      else batch_task<2, 1>(b, i, c, tile, early, band, sh);
-    }
-  }
-}
-
-template <int KIND, int INJ>
-__device__ __forceinline__ void batch_recheck_one(const BatchBuffers& b, int i, int c, int k,
-                                                  int early) {
-  const InstDesc& d = b.desc[i];
-  DevSearch* S = &b.srch[i];
-  const auto a = view64<KIND>(d, &b.st[i]);
-  int jb = 0, ns = 0;
-  const int e = early && !S->full[c];
-  const double m = rollout_lane<KIND, double, 1, INJ>(a, e, S->v[c], k, b.st[i].t,
-                                                      e ? &S->fail64[c] : nullptr, jb, ns, nullptr);
-  atomicMin(&S->key64[c], ord64(m));
-  if (m < 0.0) __hip_atomic_store(&S->fail64[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__global__ void __launch_bounds__(64) k_batch_recheck(BatchBuffers b, int early) {
-  const int n = b.counters[1];
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
-    const int4 en = b.rlist[e];
-    const int i = en.x, c = en.y, k = en.z;
-    DevSearch* S = &b.srch[i];
-    if (S->done) continue;
-    if (early && !S->full[c] &&
-        (__hip_atomic_load(&S->dead[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
-         __hip_atomic_load(&S->fail64[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
-      continue;
-    const InstDesc& d = b.desc[i];
-    if (d.kind == 1) {
-      if (d.inject == 0) batch_recheck_one<1, 0>(b, i, c, k, early);
-      else batch_recheck_one<1, 1>(b, i, c, k, early);
-    } else {
-      if (d.inject == 0) batch_recheck_one<2, 0>(b, i, c, k, early);
-      else batch_recheck_one<2, 1>(b, i, c, k, early);
-    }
-  }
-}
-
-__global__ void __launch_bounds__(64) k_batch_decide(BatchBuffers b) {
-  const int i = blockIdx.x;
-  const InstDesc& d = b.desc[i];
-  if (d.kind == 1) decide_body<1>(coef64<1>(d), &b.st[i], &b.srch[i], nullptr);
-  else decide_body<2>(coef64<2>(d), &b.st[i], &b.srch[i], nullptr);
-}
-
-__global__ void k_batch_finalize(BatchBuffers b) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= b.count) return;
-  const DevSearch* S = &b.srch[i];
-  DevResult R;
-  R.kappa = S->kappa_res;
-  R.v = S->v_res;
-  R.worst = S->worst_res;
-  R.status = S->status;
-  R.rounds = S->rounds_total;
-  R.candidates = S->cand_total;
-  R.rechecks = S->rechecks_total;
-  R.passes_alg1 = S->passes_alg1;
-  R.t = b.st[i].t;
-  R.lane_steps = S->lane_steps;
-  R.flags = S->flags;
-  b.res[i] = R;
-  b.st[i].t = b.st[i].t + 1;
-}
-
-// ---------------------------------------------------------------------------
 // Host-side argument filling and launchers
 // ---------------------------------------------------------------------------
 template <int KIND, class T>
@@ -3186,26 +2987,6 @@ hipError_t launch_alg2(const Problem& pr, double band, int precision, int early_
     hipLaunchKernelGGL(k_alg2_finalize, dim3(1), dim3(64), 0, st, b.srch, b.st, b.res);
     return hipGetLastError();
   });
-}
-
-hipError_t launch_batch_setup(const BatchBuffers& b, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_setup, dim3(b.count), dim3(64), 0, st, b);
-  return hipGetLastError();
-}
-
-hipError_t launch_batch_round(const BatchBuffers& b, int cmax_round, double band, int early,
-                              int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, b);
-  hipLaunchKernelGGL(k_batch_rollout, dim3(grid), dim3(b.tile), 0, st, b, cmax_round, (float)band,
-                     early);
-  hipLaunchKernelGGL(k_batch_recheck, dim3(1024), dim3(64), 0, st, b, early);
-  hipLaunchKernelGGL(k_batch_decide, dim3(b.count), dim3(64), 0, st, b);
-  return hipGetLastError();
-}
-
-hipError_t launch_batch_finalize(const BatchBuffers& b, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_finalize, dim3(div_up(b.count, 256)), dim3(256), 0, st, b);
-  return hipGetLastError();
 }
 
 hipError_t launch_trajectory(const Problem& pr, double v, const int32_t* k_list_dev, int nk,

@@ -180,8 +180,12 @@ def batch_instances(count: int = 1024, seed: int = 99, n_min: int = 256, n_max: 
                     h_min: int = 200, h_max: int = 3000, dt: float = 0.005,
                     max_count: Optional[int] = None) -> List[BatchInstance]:
     """Independent RG instances, half LQ4 and half FC9, N ~ U{n_min..n_max},
-    H ~ U{h_min..h_max}, each with its own plant seed, scenario seed, state and
-    reference."""
+    H ~ U{h_min..h_max}, each with its own scenario seed and reference (LQ4
+    instances also their own plant seed).  LQ4 instances start at x = 0 with
+    v_prev = 0.  FC9 instances start with v_prev = 0.5 at the nominal
+    equilibrium of that set-point (as the 9-state grid and adjoint workloads);
+    their x0 is None here and the caller fills it in (all FC9 instances share
+    the nominal plant, so one equilibrium serves them all)."""
     rng = np.random.default_rng(seed)
     out: List[BatchInstance] = []
     for i in range(count):
@@ -195,9 +199,9 @@ def batch_instances(count: int = 1024, seed: int = 99, n_min: int = 256, n_max: 
             v_prev = 0.0
         else:
             p = fc9_problem(N=N, H=H, dt=dt, scen_seed=int(rng.integers(1, 1 << 31)), instance=i)
-            x0 = FC9_XBAR.copy()
+            x0 = None
             r = float(rng.uniform(0.5, 2.0))
-            v_prev = 0.0
+            v_prev = 0.5
         out.append(BatchInstance(problem=p, x0=x0, v_prev=v_prev, r=r))
     return out
 

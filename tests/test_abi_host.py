@@ -207,7 +207,7 @@ def test_calls_reject_bad_arguments_before_device_work(lib):
     assert lib.rg_destroy(h) == 0
 
 
-def test_batch_create_validates_and_step_reports_switched_off(lib):
+def test_batch_create_and_step_validate_on_the_host(lib):
     ps = [W.lq4_problem(N=40, H=20), W.fc9_problem(N=30, H=10)]
     descs = (R.rg_instance_desc * 2)()
     keep = []
@@ -229,10 +229,17 @@ def test_batch_create_validates_and_step_reports_switched_off(lib):
     xn[5] = np.nan
     assert lib.rg_batch_step(h, xn.ctypes.data_as(dp), r.ctypes.data_as(dp), vp.ctypes.data_as(dp),
                              v.ctypes.data_as(dp), None, None, 0) == R.RG_E_INVAL
-    assert lib.rg_batch_step(h, x.ctypes.data_as(dp), r.ctypes.data_as(dp), vp.ctypes.data_as(dp),
-                             v.ctypes.data_as(dp), None, None, 0) == R.RG_E_NOTSUP
-    assert b"switched off" in lib.rg_batch_last_error(h)
+    assert lib.rg_batch_step(h, x.ctypes.data_as(dp), None, vp.ctypes.data_as(dp),
+                             v.ctypes.data_as(dp), None, None, 0) == R.RG_E_INVAL
+    assert lib.rg_batch_set_step(h, 2, 5) == R.RG_E_INVAL   # two instances
     assert lib.rg_batch_destroy(h) == 0
+    # Newton, Alg. 2 and the chance-constrained verdict are not batched
+    for field, value in [("search", R.SEARCH_NEWTON), ("search", R.SEARCH_ALG2), ("chance_q", 3)]:
+        o = R.rg_options()
+        lib.rg_default_options(C.byref(o))
+        setattr(o, field, value)
+        h3 = C.c_void_p()
+        assert lib.rg_batch_create(descs, 2, C.byref(o), C.byref(h3)) == R.RG_E_NOTSUP
     descs[1].scen.N = 0
     h2 = C.c_void_p()
     assert lib.rg_batch_create(descs, 2, None, C.byref(h2)) == R.RG_E_INVAL
