@@ -384,17 +384,19 @@ int rg_equilibrium(rg_handle* h, double v, double* x_out);
 
 /* A batch of `count` independent governors (own plant, scenarios, constraints,
  * H and dt each; the paper notes one small governor gains little from a GPU,
- * Sec. IV-B).  Each RG step of the batch runs every instance's RG step (the
- * kernels of rg_step, bisection or grid search) on search state and recheck
- * lists carved from one device allocation, with the draws regenerated inside
- * the kernels (the scenarios' rng_mode is ignored).  The instances' launch
- * chains are spread over four streams of default priority so that several
- * instances run at once; search depth per instance (opt.depth = 0) is chosen
- * so that the instances running together fill the chip.  opt: search BISECT or
- * GRID, chance_q 0 (else RG_E_NOTSUP); block as for rg_create; persistent_wgs
- * is accepted and unused.  Every descriptor is validated as by rg_create (error
- * names the instance; message via rg_batch_last_error(NULL)).  No device memory
- * is allocated here. */
+ * Sec. IV-B).  Each instance keeps its own search record and FP64 recheck list
+ * in one device allocation, and its draws are regenerated inside the kernels
+ * (the scenarios' rng_mode is ignored).  One search round of the whole batch is
+ * one flat rollout launch per group of instances with the same plant kind and
+ * injection (all their scenario tiles in one grid, FP32, one lane per
+ * scenario), then each instance's FP64 recheck and decision.  All instances
+ * use one search depth (opt.depth = 0: from the sum of N over the batch; large
+ * batches evaluate one candidate per round) and no first-round prediction.
+ * opt: precision F32_RECHECK, search BISECT or GRID, chance_q 0 (else
+ * RG_E_NOTSUP); block is the scenario tile (64, 128, 256); persistent_wgs is
+ * accepted and unused.  Every descriptor is validated as by rg_create (error
+ * names the instance; message via rg_batch_last_error(NULL)).  No device
+ * memory is allocated here. */
 int rg_batch_create(const rg_instance_desc* descs, int32_t count, const rg_options* opt,
                     rg_batch** out);
 int rg_batch_destroy(rg_batch* b);
@@ -402,13 +404,13 @@ int rg_batch_destroy(rg_batch* b);
 int rg_batch_set_stream(rg_batch* b, void* hip_stream);
 /* Per-instance RG step counter (draw selection); starts at 0, +1 per rg_batch_step. */
 int rg_batch_set_step(rg_batch* b, int32_t instance, uint32_t t);
-/* The options in force (depth: that of instance 0). */
+/* The options in force (depth resolved). */
 int rg_batch_get_options(const rg_batch* b, rg_options* out);
 /* One RG step of every instance.  x: the instances' states packed in order
  * (n_i values each); r, v_prev, v_out: [count]; kappa_out and info_out
  * ([count]) nullable.  use_graph = 1 captures the step once as a HIP graph
- * (fork to the streams, every instance's step, join) and replays it.  The
- * first call allocates the batch's device memory and streams.  Blocking. */
+ * and replays it.  The first call allocates the batch's device memory.
+ * Blocking. */
 int rg_batch_step(rg_batch* b, const double* x, const double* r, const double* v_prev,
                   double* v_out, double* kappa_out, rg_step_info* info_out, int32_t use_graph);
 const char* rg_batch_last_error(const rg_batch* b);

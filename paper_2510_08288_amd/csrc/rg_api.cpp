@@ -1311,16 +1311,27 @@ int rg_trajectory(rg_handle* h, const double* x, double v, const int32_t* k_list
 // ---------------------------------------------------------------------------
 // Batched serving
 // ---------------------------------------------------------------------------
-// Many independent governors stepped together.  Every instance runs the
-// single-instance RG step, with the kernels of rg_step, on its own search
-// record and recheck list, carved from one device allocation; the draws are
-// regenerated inside the kernels (a batch of a thousand instances could not
-// hold their draw buffers).  The instances' launch chains are spread over
-// kBatchStreams streams of default priority, so several instances' kernels run
-// at once.  One batched step (fork to the streams, every instance's chain,
-// join) is captured once as a HIP graph and replayed; states go up and results
-// come back in one copy each.
-constexpr int kBatchStreams = 4;
+// Many independent governors stepped together.  Each instance keeps its own
+// search record, result record and recheck list, carved from one device
+// allocation, and its draws are regenerated inside the kernels (a batch of a
+// thousand instances could not hold draw buffers).  One search round of the
+// whole batch is one flat rollout launch per group of instances with the same
+// plant kind and disturbance injection (every instance's scenario tiles side by
+// side in one grid, each workgroup reading its instance's argument block from
+// device memory), then one flat launch per group for the FP64 recheck and the
+// round's decision (one workgroup per instance).  A batched step starts with
+// the instances' round-0 setup and ends with their result records (one launch
+// per group each); it is captured once as a HIP graph and replayed.
+struct BatchGroup {
+  int kind = 0, inject = 0, tiles = 0, cmax = 0;
+  std::vector<int> members;     // batch indices of the group's instances
+  void* args = nullptr;         // device: the members' FP32 rollout argument blocks
+  void* args64 = nullptr;       // device: their FP64 recheck argument blocks
+  void* ctl = nullptr;          // device: their control blocks (setup, decision)
+  DevResult** resptr = nullptr; // device [members]: their result records
+  int32_t* tile_inst = nullptr; // device [tiles]: member of each workgroup column
+  int32_t* tile_first = nullptr;// device [members]: first tile of each member
+};
 
 struct rg_batch {
   int count = 0;
@@ -1328,11 +1339,11 @@ struct rg_batch {
   std::vector<rg_handle*> inst;  // per instance: problem, plan and carved buffers
   std::vector<int> noff;         // offset of each instance's state in the packed x array
   std::vector<uint32_t> t;       // per-instance RG step counters
+  std::vector<BatchGroup> groups;
+  int tile = 256;                // scenarios per rollout workgroup
+  int rounds = 0;                // device rounds per batched step (the largest plan)
   hipStream_t stream = nullptr;  // the caller's stream (NULL: own_stream)
   hipStream_t own_stream = nullptr;
-  hipStream_t side[kBatchStreams] = {};
-  hipEvent_t fork = nullptr;
-  hipEvent_t join[kBatchStreams] = {};
   void* mem = nullptr;
   DevState* st = nullptr;   // [count]
   DevResult* res = nullptr; // [count]
@@ -1348,41 +1359,18 @@ int bfail(rg_batch* bt, int code, const std::string& msg) {
   return code;
 }
 
-// Search levels per device round for an instance of a batch: enough candidates
-// that the instances running at once (one per stream) fill the chip, as
-// depth_for does for a handle of its own.
-int batch_depth(int N, int lanes, int K) {
-  const double budget = 2.0 * 256 * 4 * 64 / kBatchStreams;
-  const double per_cand = (double)N * lanes;
-  int dmax = 1;
-  while (dmax < 6 && ((1 << (dmax + 1)) - 1) * per_cand <= budget) ++dmax;
-  if (K <= 0) return 1;
-  const int rounds = (K + dmax - 1) / dmax;
-  return (K + rounds - 1) / rounds;
-}
-
 void batch_release(rg_batch* bt) {
   if (bt->graph) (void)hipGraphExecDestroy(bt->graph);
   bt->graph = nullptr;
-  for (hipStream_t& s : bt->side) {
-    if (s) (void)hipStreamDestroy(s);
-    s = nullptr;
-  }
   if (bt->own_stream) (void)hipStreamDestroy(bt->own_stream);
   bt->own_stream = nullptr;
-  if (bt->fork) (void)hipEventDestroy(bt->fork);
-  bt->fork = nullptr;
-  for (hipEvent_t& e : bt->join) {
-    if (e) (void)hipEventDestroy(e);
-    e = nullptr;
-  }
   if (bt->mem) (void)hipFree(bt->mem);
   bt->mem = nullptr;
   for (rg_handle* h : bt->inst) rg_destroy(h);  // no workspace of their own
   bt->inst.clear();
 }
 
-// Device memory and streams, on the first step.
+// Device memory, argument blocks and tile tables, on the first step.
 int batch_ensure_memory(rg_batch* bt) {
   if (bt->mem) return RG_OK;
   const int count = bt->count;
@@ -1400,18 +1388,25 @@ int batch_ensure_memory(rg_batch* bt) {
     const rg_handle* h = bt->inst[i];
     o_rl[i] = take(sizeof(int2) * (size_t)h->cfg.cmax_round * (size_t)h->pr.s.N);
   }
+  const size_t ng = bt->groups.size();
+  std::vector<size_t> o_args(ng), o_a64(ng), o_ctl(ng), o_rp(ng), o_ti(ng), o_tf(ng);
+  for (size_t g = 0; g < ng; ++g) {
+    const BatchGroup& G = bt->groups[g];
+    const size_t nm = G.members.size();
+    o_args[g] = take(flat_args_size(G.kind) * nm);
+    o_a64[g] = take(flat_args64_size(G.kind) * nm);
+    o_ctl[g] = take(flat_ctl_size(G.kind) * nm);
+    o_rp[g] = take(sizeof(DevResult*) * nm);
+    o_ti[g] = take(sizeof(int32_t) * (size_t)G.tiles);
+    o_tf[g] = take(sizeof(int32_t) * nm);
+  }
   hipError_t e = hipMalloc(&bt->mem, off);
   if (e != hipSuccess) {
     bt->mem = nullptr;
     return bfail(bt, RG_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
   }
   if (!bt->own_stream) e = hipStreamCreateWithFlags(&bt->own_stream, hipStreamNonBlocking);
-  for (int s = 0; s < kBatchStreams && e == hipSuccess; ++s)
-    e = hipStreamCreateWithFlags(&bt->side[s], hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->fork, hipEventDisableTiming);
-  for (int s = 0; s < kBatchStreams && e == hipSuccess; ++s)
-    e = hipEventCreateWithFlags(&bt->join[s], hipEventDisableTiming);
-  if (e != hipSuccess) return bfail(bt, RG_E_HIP, std::string("batch streams: ") + hipGetErrorString(e));
+  if (e != hipSuccess) return bfail(bt, RG_E_HIP, std::string("batch stream: ") + hipGetErrorString(e));
   char* base = (char*)bt->mem;
   bt->st = (DevState*)(base + o_st);
   bt->res = (DevResult*)(base + o_res);
@@ -1428,30 +1423,73 @@ int batch_ensure_memory(rg_batch* bt) {
     h->ws = bt->mem;  // carved from the batch's allocation: never freed by the handle
     h->ws_owned = false;
     h->ws_ready = true;
-    h->stream = bt->side[i % kBatchStreams];
     fill_search(h, &tmpl[i], 0);
   }
   const hipStream_t ms = bt->stream ? bt->stream : bt->own_stream;
   e = hipMemcpyAsync(srch, tmpl.data(), sizeof(DevSearch) * count, hipMemcpyHostToDevice, ms);
+  // argument blocks and tables of each group (host staging kept until the copies end)
+  std::vector<std::vector<char>> st_a(ng), st_a64(ng), st_c(ng);
+  std::vector<std::vector<DevResult*>> st_rp(ng);
+  std::vector<std::vector<int32_t>> st_ti(ng), st_tf(ng);
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ms);
+  };
+  for (size_t g = 0; g < ng; ++g) {
+    BatchGroup& G = bt->groups[g];
+    const size_t nm = G.members.size();
+    const size_t asz = flat_args_size(G.kind), a64 = flat_args64_size(G.kind),
+                 csz = flat_ctl_size(G.kind);
+    st_a[g].assign(asz * nm, 0);
+    st_a64[g].assign(a64 * nm, 0);
+    st_c[g].assign(csz * nm, 0);
+    st_rp[g].resize(nm);
+    st_tf[g].resize(nm);
+    st_ti[g].reserve(G.tiles);
+    for (size_t m = 0; m < nm; ++m) {
+      const rg_handle* h = bt->inst[G.members[m]];
+      flat_fill_args(h->pr, bt->opt.band, bt->opt.early_exit, h->b, st_a[g].data() + m * asz);
+      flat_fill_args64(h->pr, bt->opt.early_exit, h->b, st_a64[g].data() + m * a64);
+      flat_fill_ctl(h->pr, h->b, st_c[g].data() + m * csz);
+      st_rp[g][m] = h->b.res;
+      st_tf[g][m] = (int32_t)st_ti[g].size();
+      const int nt = (h->pr.s.N + bt->tile - 1) / bt->tile;
+      for (int q = 0; q < nt; ++q) st_ti[g].push_back((int32_t)m);
+    }
+    G.args = base + o_args[g];
+    G.args64 = base + o_a64[g];
+    G.ctl = base + o_ctl[g];
+    G.resptr = (DevResult**)(base + o_rp[g]);
+    G.tile_inst = (int32_t*)(base + o_ti[g]);
+    G.tile_first = (int32_t*)(base + o_tf[g]);
+    up(G.args, st_a[g].data(), st_a[g].size());
+    up(G.args64, st_a64[g].data(), st_a64[g].size());
+    up(G.ctl, st_c[g].data(), st_c[g].size());
+    up(G.resptr, st_rp[g].data(), sizeof(DevResult*) * nm);
+    up(G.tile_inst, st_ti[g].data(), sizeof(int32_t) * st_ti[g].size());
+    up(G.tile_first, st_tf[g].data(), sizeof(int32_t) * nm);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(ms);
   if (e != hipSuccess) return bfail(bt, RG_E_HIP, std::string("batch upload: ") + hipGetErrorString(e));
   return RG_OK;
 }
 
-// One batched step on the main stream: fork to the side streams, every
-// instance's RG step on its stream, join.
+// One batched step on stream ms.
 hipError_t batch_enqueue(rg_batch* bt, hipStream_t ms) {
-  hipError_t e = hipEventRecord(bt->fork, ms);
-  for (int s = 0; s < kBatchStreams && e == hipSuccess; ++s)
-    e = hipStreamWaitEvent(bt->side[s], bt->fork, 0);
-  for (int i = 0; i < bt->count && e == hipSuccess; ++i) {
-    rg_handle* h = bt->inst[i];
-    e = enqueue_step(h, h->pr, h->b, false);
+  hipError_t e = hipSuccess;
+  for (const BatchGroup& G : bt->groups)
+    if (e == hipSuccess) e = launch_flat_setup(G.kind, G.ctl, (int)G.members.size(), ms);
+  for (int r = 0; r < bt->rounds && e == hipSuccess; ++r) {
+    for (const BatchGroup& G : bt->groups)
+      if (e == hipSuccess)
+        e = launch_flat_rollout(G.kind, G.inject, G.args, G.tile_inst, G.tile_first, G.tiles,
+                                G.cmax, bt->tile, ms);
+    for (const BatchGroup& G : bt->groups)
+      if (e == hipSuccess)
+        e = launch_flat_recheck(G.kind, G.inject, G.args64, G.ctl, (int)G.members.size(), ms);
   }
-  for (int s = 0; s < kBatchStreams && e == hipSuccess; ++s) {
-    e = hipEventRecord(bt->join[s], bt->side[s]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(ms, bt->join[s], 0);
-  }
+  for (const BatchGroup& G : bt->groups)
+    if (e == hipSuccess)
+      e = launch_flat_finalize(G.kind, G.ctl, G.resptr, (int)G.members.size(), ms);
   return e;
 }
 
@@ -1467,29 +1505,45 @@ int rg_batch_create(const rg_instance_desc* descs, int32_t count, const rg_optio
   rg_options o;
   rg_default_options(&o);
   if (opt) o = *opt;
+  if (o.precision != RG_PREC_F32_RECHECK)
+    return bfail(nullptr, RG_E_NOTSUP, "batches run FP32 rollouts with the FP64 recheck");
   if (o.search != RG_SEARCH_BISECT && o.search != RG_SEARCH_GRID)
     return bfail(nullptr, RG_E_NOTSUP, "batches use bisection or the grid search");
   if (o.chance_q != 0) return bfail(nullptr, RG_E_NOTSUP, "batches use the robust verdict");
   if (o.block != 0 && o.block != 64 && o.block != 128 && o.block != 256)
     return bfail(nullptr, RG_E_INVAL, "block must be 64, 128 or 256");
   if (o.persistent_wgs < 0) return bfail(nullptr, RG_E_INVAL, "persistent_wgs must be >= 0");
+  // search plan shared by the instances: a round already holds sum_i N_i lanes
+  // per candidate, so speculative levels only while that is below the chip's
+  // capacity (about two waves per SIMD)
+  double lanes = 0.0;
+  for (int i = 0; i < count; ++i) lanes += descs[i].scen.N > 0 ? descs[i].scen.N : 0;
+  int d = o.depth;
+  const int goal = o.search == RG_SEARCH_GRID ? o.refine : o.K;
+  if (d == 0) {
+    const double budget = 2.0 * 256 * 4 * 64;
+    int dmax = 1;
+    while (dmax < 6 && ((1 << (dmax + 1)) - 1) * lanes <= budget) ++dmax;
+    const int rounds = goal > 0 ? (goal + dmax - 1) / dmax : 1;
+    d = goal > 0 ? (goal + rounds - 1) / rounds : 1;
+  }
   rg_batch* bt = new (std::nothrow) rg_batch;
   if (!bt) return bfail(nullptr, RG_E_NOMEM, "host allocation");
   bt->count = count;
   bt->opt = o;
+  bt->opt.depth = d;
+  bt->tile = o.block ? o.block : 256;
   int noff = 0;
   for (int i = 0; i < count; ++i) {
     rg_scenarios s = descs[i].scen;
     s.rng_mode = RG_RNG_INLINE;
     rg_options oi = o;
+    oi.depth = d;
+    oi.lanes = 1;       // the flat rollout runs one lane per scenario
+    oi.predict = 0;     // each round one node per level: no extra candidates
     oi.speculate = 0;
     oi.max_T = 1;
-    if (o.depth == 0) {
-      const bool quad = descs[i].plant.kind == RG_PLANT_LQ4 && o.precision == RG_PREC_F32_RECHECK &&
-                        o.lanes != 1;
-      oi.depth = batch_depth(descs[i].scen.N, quad ? 4 : 1,
-                             o.search == RG_SEARCH_GRID ? o.refine : o.K);
-    }
+    oi.block = bt->tile;
     rg_handle* h = nullptr;
     const int rc = rg_create(&descs[i].plant, &s, &descs[i].cons, descs[i].H, descs[i].dt, &oi, &h);
     if (rc != RG_OK) {
@@ -1501,6 +1555,20 @@ int rg_batch_create(const rg_instance_desc* descs, int32_t count, const rg_optio
     bt->inst.push_back(h);
     bt->noff.push_back(noff);
     noff += h->pr.p.n;
+    if (h->cfg.rounds > bt->rounds) bt->rounds = h->cfg.rounds;
+    // group by plant kind and injection
+    BatchGroup* G = nullptr;
+    for (BatchGroup& g : bt->groups)
+      if (g.kind == h->pr.p.kind && g.inject == h->pr.s.inject) G = &g;
+    if (!G) {
+      bt->groups.emplace_back();
+      G = &bt->groups.back();
+      G->kind = h->pr.p.kind;
+      G->inject = h->pr.s.inject;
+    }
+    G->members.push_back(i);
+    G->tiles += (h->pr.s.N + bt->tile - 1) / bt->tile;
+    if (h->cfg.cmax_round > G->cmax) G->cmax = h->cfg.cmax_round;
   }
   bt->t.assign(count, 0u);
   *out = bt;
@@ -1594,7 +1662,6 @@ int rg_batch_step(rg_batch* bt, const double* x, const double* r, const double* 
 int rg_batch_get_options(const rg_batch* bt, rg_options* out) {
   if (!bt || !out) return RG_E_INVAL;
   *out = bt->opt;
-  if (!bt->inst.empty()) out->depth = bt->inst[0]->opt.depth;
   return RG_OK;
 }
 

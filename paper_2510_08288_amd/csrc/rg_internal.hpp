@@ -265,6 +265,27 @@ hipError_t launch_seg_grad(const Problem& pr, int Kc, int cand, const DevBuffers
 hipError_t launch_tan_grad(const Problem& pr, const DevBuffers& b, int cand, hipStream_t st);
 hipError_t launch_grad_reduce(const DevBuffers& b, int max_entries, int nth, int cand,
                               hipStream_t st);
+// Batched serving: per-instance FP32 rollout argument blocks (host side), and
+// the flat rollout launch over a group of instances of one plant kind and
+// injection (grid: tiles x cmax, workgroup `block` = the tile size).
+size_t flat_args_size(int kind);
+void flat_fill_args(const Problem& pr, double band, int early, const DevBuffers& b, void* out);
+hipError_t launch_flat_rollout(int kind, int inject, const void* args_dev, const int* tile_inst,
+                               const int* tile_first, int tiles, int cmax, int block,
+                               hipStream_t st);
+// FP64 recheck argument blocks and control blocks of the instances, and the
+// flat launches over a group: recheck + decision (one workgroup per instance),
+// round-0 setup (one workgroup per instance), result records (res_dev: the
+// instances' result record addresses, device array).
+size_t flat_args64_size(int kind);
+size_t flat_ctl_size(int kind);
+void flat_fill_args64(const Problem& pr, int early, const DevBuffers& b, void* out);
+void flat_fill_ctl(const Problem& pr, const DevBuffers& b, void* out);
+hipError_t launch_flat_recheck(int kind, int inject, const void* args64_dev, const void* ctl_dev,
+                               int count, hipStream_t st);
+hipError_t launch_flat_setup(int kind, const void* ctl_dev, int count, hipStream_t st);
+hipError_t launch_flat_finalize(int kind, const void* ctl_dev, DevResult* const* res_dev, int count,
+                                hipStream_t st);
 hipError_t launch_trajectory(const Problem& pr, double v, const int32_t* k_list_dev, int nk,
                              int precision, double* traj_dev, const DevBuffers& b,
                              hipStream_t st);

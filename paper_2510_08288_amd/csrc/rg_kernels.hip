@@ -438,9 +438,11 @@ __device__ __forceinline__ unsigned long long block_min_u64(unsigned long long v
 
 // In decision mode a candidate whose FP64 steady-state test already fails is
 // refused without simulating it (the verdict of Alg. 1 needs both tests).
-__device__ __forceinline__ bool refused_by_steady_state(int early, DevSearch* S, int c) {
+// bx: the workgroup's scenario tile (tile 0 raises the flag).
+__device__ __forceinline__ bool refused_by_steady_state(int early, DevSearch* S, int c,
+                                                        int bx = -1) {
   if (!early || !(S->mss[c] < 0.0)) return false;
-  if (blockIdx.x == 0 && threadIdx.x == 0)
+  if ((bx < 0 ? (int)blockIdx.x : bx) == 0 && threadIdx.x == 0)
     __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return true;
 }
@@ -450,20 +452,20 @@ __device__ __forceinline__ bool refused_by_steady_state(int early, DevSearch* S,
 // (handles with q > 0): lanes stop on their own and every lane's margin key is
 // kept.  It is a separate instantiation so that the robust kernel carries one
 // rollout body only (two bodies double the 9-state kernel's registers).
-template <int KIND, class T, int RNG, int INJ, int CKPT, int CHANCE = 0>
-__global__ void __launch_bounds__(256) k_rollout(const RollArgs<KIND, T> a) {
-  if (gen_rows<KIND>(a)) return;
+// Body of one rollout workgroup: candidate row c, scenario tile bx (scenarios
+// bx * blockDim.x + threadIdx.x).
+template <int KIND, class T, int RNG, int INJ, int CKPT, int CHANCE>
+__device__ __forceinline__ void rollout_block(const RollArgs<KIND, T>& a, const int c,
+                                              const int bx, unsigned long long* sh) {
   DevSearch* S = a.srch;
-  const int c = blockIdx.y;
   if (S->done || c >= S->n_cand) return;  // uniform over the workgroup
   // CKPT = 1: that candidate keeps checkpoints (adjoint); CKPT = 2: its lanes
   // carry the forward tangent instead (full horizon, no early exit)
   const bool ck = CKPT == 1 && c == (a.ckpt_cand >= 0 ? a.ckpt_cand : S->nk_idx);
   const bool tan_row = CKPT == 2 && c == (a.ckpt_cand >= 0 ? a.ckpt_cand : S->nk_idx);
   const int early = a.early && !S->full[c] && !tan_row;
-  if (refused_by_steady_state(early, S, c)) return;
-  __shared__ unsigned long long sh[16];
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (refused_by_steady_state(early, S, c, bx)) return;
+  const int k = bx * blockDim.x + threadIdx.x;
   const uint32_t t = a.st->t;
   const int q = CHANCE ? S->q : 0;  // chance-constrained verdict: up to q violating scenarios
   T m = t_inf<T>();
@@ -511,6 +513,28 @@ __global__ void __launch_bounds__(256) k_rollout(const RollArgs<KIND, T> a) {
     atomicMin(&S->key_all[c], kall);
     if (kfar != ~0ull) atomicMin(&S->key_far[c], kfar);
   }
+}
+
+template <int KIND, class T, int RNG, int INJ, int CKPT, int CHANCE = 0>
+__global__ void __launch_bounds__(256) k_rollout(const RollArgs<KIND, T> a) {
+  if (gen_rows<KIND>(a)) return;
+  __shared__ unsigned long long sh[16];
+  rollout_block<KIND, T, RNG, INJ, CKPT, CHANCE>(a, blockIdx.y, blockIdx.x, sh);
+}
+
+// Batched serving: one launch per search round covers every instance of a
+// (plant, disturbance injection) group.  Workgroup g of the flat grid takes
+// scenario tile g - tile_first[i] of instance i = tile_inst[g], with the
+// instance's own argument block from device memory; row blockIdx.y is the
+// candidate (instances with fewer candidates in the round return at once).
+// FP32, robust verdict, draws regenerated in the lanes.
+template <int KIND, int INJ>
+__global__ void __launch_bounds__(256) k_flat_rollout(const RollArgs<KIND, float>* __restrict__ args,
+                                                      const int* __restrict__ tile_inst,
+                                                      const int* __restrict__ tile_first) {
+  __shared__ unsigned long long sh[16];
+  const int i = tile_inst[blockIdx.x];
+  rollout_block<KIND, float, 1, INJ, 0, 0>(args[i], blockIdx.y, (int)blockIdx.x - tile_first[i], sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1057,6 +1081,71 @@ __global__ void __launch_bounds__(64) k_recheck(const RollArgs<KIND, double> a,
     }
   }
   if (decide) last_block_decides<KIND>(ctl);
+}
+
+// Batched serving: the FP64 recheck of every instance of a group in one launch,
+// one workgroup per instance (its own near-band list, as k_recheck), which then
+// takes that instance's decision for the round (as the last workgroup of
+// k_recheck does).  The workgroup's own rechecks are published by a
+// device-scope fence before the decision reads the verdicts.
+template <int KIND, int INJ>
+__global__ void __launch_bounds__(64) k_flat_recheck(const RollArgs<KIND, double>* __restrict__ args,
+                                                     const CtlArgs<KIND>* __restrict__ ctl) {
+  const RollArgs<KIND, double>& a = args[blockIdx.x];
+  DevSearch* S = a.srch;
+  if (S->done) return;  // uniform: nothing writes it before the decision below
+  const int n = S->n_recheck;
+  const uint32_t t = a.st->t;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int2 e = a.rlist[i];
+    const int c = e.x, k = e.y;
+    if (a.early &&
+        (__hip_atomic_load(&S->dead[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+         __hip_atomic_load(&S->fail64[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
+      continue;
+    int jb = 0, ns = 0;
+    const double m = rollout_lane<KIND, double, 1, INJ>(
+        a, a.early, S->v[c], k, t, a.early ? &S->fail64[c] : nullptr, jb, ns, nullptr);
+    atomicMin(&S->key64[c], ord64(m));
+    if (m < 0.0) __hip_atomic_store(&S->fail64[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __threadfence();
+  __syncthreads();
+  const CtlArgs<KIND>& cl = ctl[blockIdx.x];
+  decide_body<KIND>(cl.pc, cl.st, cl.srch, cl.grad);
+}
+
+// Batched serving: round-0 setup of every instance of a group, one workgroup
+// per instance (as k_setup).
+template <int KIND>
+__global__ void __launch_bounds__(128) k_flat_setup(const CtlArgs<KIND>* __restrict__ ctl) {
+  const CtlArgs<KIND>& a = ctl[blockIdx.x];
+  setup_body<KIND>(a.pc, a.st, a.srch, a.r_seq, a.closed_loop);
+}
+
+// Batched serving: the result record of every instance of a group (as
+// k_finalize outside the closed loop), one thread per instance.
+template <int KIND>
+__global__ void k_flat_finalize(const CtlArgs<KIND>* __restrict__ ctl, DevResult* const* __restrict__ res,
+                                int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const DevSearch* S = ctl[i].srch;
+  DevState* st = ctl[i].st;
+  DevResult R;
+  R.kappa = S->kappa_res;
+  R.v = S->v_res;
+  R.worst = S->worst_res;
+  R.status = S->status;
+  R.rounds = S->rounds_total;
+  R.candidates = S->cand_total;
+  R.rechecks = S->rechecks_total;
+  R.passes_alg1 = S->passes_alg1;
+  R.t = st->t;
+  R.lane_steps = S->lane_steps;
+  R.flags = S->flags;
+  *res[i] = R;
+  st->t = st->t + 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -2986,6 +3075,91 @@ hipError_t launch_alg2(const Problem& pr, double band, int precision, int early_
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_alg2_finalize, dim3(1), dim3(64), 0, st, b.srch, b.st, b.res);
     return hipGetLastError();
+  });
+}
+
+size_t flat_args_size(int kind) {
+  return kind == 1 ? sizeof(RollArgs<1, float>) : sizeof(RollArgs<2, float>);
+}
+
+void flat_fill_args(const Problem& pr, double band, int early, const DevBuffers& b, void* out) {
+  if (pr.p.kind == 1) {
+    const RollArgs<1, float> a = make_args<1, float>(pr, band, early, 0, b);
+    memcpy(out, &a, sizeof(a));
+  } else {
+    const RollArgs<2, float> a = make_args<2, float>(pr, band, early, 0, b);
+    memcpy(out, &a, sizeof(a));
+  }
+}
+
+size_t flat_args64_size(int kind) {
+  return kind == 1 ? sizeof(RollArgs<1, double>) : sizeof(RollArgs<2, double>);
+}
+size_t flat_ctl_size(int kind) { return kind == 1 ? sizeof(CtlArgs<1>) : sizeof(CtlArgs<2>); }
+
+void flat_fill_args64(const Problem& pr, int early, const DevBuffers& b, void* out) {
+  if (pr.p.kind == 1) {
+    const RollArgs<1, double> a = make_args<1, double>(pr, 0.0, early, 0, b);
+    memcpy(out, &a, sizeof(a));
+  } else {
+    const RollArgs<2, double> a = make_args<2, double>(pr, 0.0, early, 0, b);
+    memcpy(out, &a, sizeof(a));
+  }
+}
+
+void flat_fill_ctl(const Problem& pr, const DevBuffers& b, void* out) {
+  if (pr.p.kind == 1) {
+    const CtlArgs<1> a = make_ctl<1>(pr, b, 0);
+    memcpy(out, &a, sizeof(a));
+  } else {
+    const CtlArgs<2> a = make_ctl<2>(pr, b, 0);
+    memcpy(out, &a, sizeof(a));
+  }
+}
+
+hipError_t launch_flat_recheck(int kind, int inject, const void* args64_dev, const void* ctl_dev,
+                               int count, hipStream_t st) {
+  return by_kind(kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    return by_bit(inject, [&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      hipLaunchKernelGGL((k_flat_recheck<K, I>), dim3(count), dim3(64), 0, st,
+                         (const RollArgs<K, double>*)args64_dev, (const CtlArgs<K>*)ctl_dev);
+      return hipGetLastError();
+    });
+  });
+}
+
+hipError_t launch_flat_setup(int kind, const void* ctl_dev, int count, hipStream_t st) {
+  return by_kind(kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    hipLaunchKernelGGL(k_flat_setup<K>, dim3(count), dim3(128), 0, st, (const CtlArgs<K>*)ctl_dev);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_flat_finalize(int kind, const void* ctl_dev, DevResult* const* res_dev, int count,
+                                hipStream_t st) {
+  return by_kind(kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    hipLaunchKernelGGL(k_flat_finalize<K>, dim3(div_up(count, 64)), dim3(64), 0, st,
+                       (const CtlArgs<K>*)ctl_dev, res_dev, count);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_flat_rollout(int kind, int inject, const void* args_dev, const int* tile_inst,
+                               const int* tile_first, int tiles, int cmax, int block,
+                               hipStream_t st) {
+  const dim3 grid(tiles, cmax);
+  return by_kind(kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    return by_bit(inject, [&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      hipLaunchKernelGGL((k_flat_rollout<K, I>), grid, dim3(block), 0, st,
+                         (const RollArgs<K, float>*)args_dev, tile_inst, tile_first);
+      return hipGetLastError();
+    });
   });
 }
 
