@@ -429,6 +429,12 @@ int rg_draws(rg_handle* h, uint32_t t, int32_t k0, int32_t nk, int32_t j0, int32
 int rg_trajectory(rg_handle* h, const double* x, double v, const int32_t* k_list, int32_t nk,
                   int32_t precision, double* traj);
 
+/* The FP64 tanh the FP64 rollouts, rechecks and steady-state solves of the
+ * 9-state plant use, evaluated on the current device for x[0..n) into y
+ * (host arrays; for tests of its accuracy).  Blocking; allocates and frees
+ * device memory. */
+int rg_fp64_tanh(const double* x, double* y, int32_t n);
+
 /* Static text for a status code. */
 const char* rg_status_string(int status);
 

@@ -168,10 +168,12 @@ int lanes_for(const rg_handle* h) {
 
 int depth_for(const rg_handle* h, int lanes) {
   if (h->opt.depth > 0) return h->opt.depth;
-  // Enough candidates per round to give every SIMD of the chip about two
-  // wavefronts, then the smallest depth that needs no more rounds.
+  // Enough candidates per round to give every SIMD of the chip up to four
+  // wavefronts (a round of few candidates is bound by one wave's latency, so
+  // more waves per SIMD come almost free), then the smallest depth that needs
+  // no more rounds.
   const int goal = h->opt.search == RG_SEARCH_GRID ? h->opt.refine : h->opt.K;
-  const double lanes_budget = 2.0 * 256 * 4 * 64;
+  const double lanes_budget = 4.0 * 256 * 4 * 64;
   const double per_cand = (double)h->pr.s.N * lanes;
   int dmax = 1;
   while (dmax < 6 && ((1 << (dmax + 1)) - 1) * per_cand <= lanes_budget) ++dmax;
@@ -1572,6 +1574,19 @@ int rg_batch_create(const rg_instance_desc* descs, int32_t count, const rg_optio
   }
   bt->t.assign(count, 0u);
   *out = bt;
+  return RG_OK;
+}
+
+int rg_fp64_tanh(const double* x, double* y, int32_t n) {
+  if (!x || !y || n < 1) return fail(nullptr, RG_E_INVAL, "bad arguments");
+  double* d = nullptr;
+  hipError_t e = hipMalloc(&d, sizeof(double) * 2 * (size_t)n);
+  if (e != hipSuccess) return fail(nullptr, RG_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  e = hipMemcpy(d, x, sizeof(double) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_eval_tanh64(d, d + n, n, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(y, d + n, sizeof(double) * n, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(nullptr, RG_E_HIP, std::string("rg_fp64_tanh: ") + hipGetErrorString(e));
   return RG_OK;
 }
 

@@ -103,7 +103,43 @@ __device__ __forceinline__ float t_tanh(float z) {
   const float r = __builtin_amdgcn_rcpf(e + 1.0f);
   return __builtin_copysignf(__builtin_fmaf(-2.0f, r, 1.0f), z);
 }
-__device__ __forceinline__ double t_tanh(double z) { return tanh(z); }
+// FP64 tanh of the FP64 rollouts and steady-state solves (written here, not
+// the library's): tanh|z| = t / (t + 2) with t = expm1(2|z|), which has no
+// cancellation at small |z|, carrying the sign of z; 1 once 2|z| >= 40 (then
+// 1 - tanh|z| < 2^-56).  expm1(x), x >= 0: Cody-Waite reduction x = k ln2 + r
+// with |r| <= ln2 / 2 and ln 2 split into a 32-bit head (k ln2_head is exact)
+// and its remainder; expm1(r) by its Taylor series to degree 13 in Horner form
+// (truncation below 2^-56 relative on that interval); then
+// expm1(x) = 2^k expm1(r) + (2^k - 1).  Within 3 ulp of tanh over the
+// arguments the rollouts meet (checked against an extended-precision
+// reference in the tests).
+__device__ __forceinline__ double t_tanh(double z) {
+  const double x = 2.0 * fabs(z);
+  if (!(x < 40.0)) return x == x ? copysign(1.0, z) : z;
+  constexpr double kLn2Head = 0x1.62e42ff0p-1;         // ln 2 to 32 significant bits
+  constexpr double kLn2Tail = -0x1.718432a1b0e26p-35;  // ln 2 - kLn2Head
+  constexpr double kInvLn2 = 0x1.71547652b82fep+0;
+  const double k = rint(x * kInvLn2);
+  double r = fma(-k, kLn2Head, x);
+  r = fma(-k, kLn2Tail, r);
+  double p = 1.0 / 6227020800.0;  // 1/13!
+  p = fma(p, r, 1.0 / 479001600.0);
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  const double em = p * r;  // expm1(r)
+  const double two_k = ldexp(1.0, (int)k);
+  const double t = fma(two_k, em, two_k - 1.0);
+  return copysign(t / (t + 2.0), z);
+}
 __device__ __forceinline__ float t_sqrt(float z) { return __builtin_amdgcn_sqrtf(z); }
 __device__ __forceinline__ double t_sqrt(double z) { return sqrt(z); }
 __device__ __forceinline__ float t_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }

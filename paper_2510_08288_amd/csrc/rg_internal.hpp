@@ -268,6 +268,7 @@ hipError_t launch_grad_reduce(const DevBuffers& b, int max_entries, int nth, int
 // Batched serving: per-instance FP32 rollout argument blocks (host side), and
 // the flat rollout launch over a group of instances of one plant kind and
 // injection (grid: tiles x cmax, workgroup `block` = the tile size).
+hipError_t launch_eval_tanh64(const double* x_dev, double* y_dev, int n, hipStream_t st);
 size_t flat_args_size(int kind);
 void flat_fill_args(const Problem& pr, double band, int early, const DevBuffers& b, void* out);
 hipError_t launch_flat_rollout(int kind, int inject, const void* args_dev, const int* tile_inst,

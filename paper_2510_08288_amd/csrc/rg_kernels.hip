@@ -3078,6 +3078,17 @@ hipError_t launch_alg2(const Problem& pr, double band, int precision, int early_
   });
 }
 
+// The FP64 tanh of the FP64 rollouts, evaluated on the device (tests).
+__global__ void k_eval_tanh64(const double* x, double* y, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = t_tanh(x[i]);
+}
+
+hipError_t launch_eval_tanh64(const double* x_dev, double* y_dev, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_eval_tanh64, dim3(div_up((size_t)n, 256)), dim3(256), 0, st, x_dev, y_dev, n);
+  return hipGetLastError();
+}
+
 size_t flat_args_size(int kind) {
   return kind == 1 ? sizeof(RollArgs<1, float>) : sizeof(RollArgs<2, float>);
 }

@@ -140,6 +140,7 @@ def load_library(path: str = LIB_PATH, with_torch: bool = True) -> C.CDLL:
     L.rg_get_profile.argtypes = [_vp, C.POINTER(rg_profile)]
     L.rg_draws.argtypes = [_vp, C.c_uint32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _fp, _dp]
     L.rg_trajectory.argtypes = [_vp, _dp, C.c_double, _ip, C.c_int32, C.c_int32, _dp]
+    L.rg_fp64_tanh.argtypes = [_dp, _dp, C.c_int32]
     L.rg_status_string.argtypes = [C.c_int]
     L.rg_status_string.restype = C.c_char_p
     L.rg_last_error.argtypes = [_vp]
@@ -160,6 +161,17 @@ def _info_dict(info: rg_step_info) -> dict:
     return dict(worst=info.worst_margin, rounds=info.rounds, candidates=info.candidates,
                 rechecks=info.rechecks, bisect_passes=info.bisect_passes, t=info.t,
                 lane_steps=info.lane_steps, flags=info.flags)
+
+
+def fp64_tanh(x) -> np.ndarray:
+    """rg_fp64_tanh: the device FP64 tanh of the 9-state plant's FP64 paths."""
+    L = load_library()
+    x = _f64(np.asarray(x).reshape(-1))
+    y = np.zeros_like(x)
+    rc = L.rg_fp64_tanh(_ptr(x), _ptr(y), x.size)
+    if rc < 0:
+        raise RGError(rc, L.rg_last_error(None).decode())
+    return y
 
 
 def default_options() -> rg_options:

@@ -181,3 +181,23 @@ def test_set_theta_refreshes_cached_steady_state(R, oracle_mod):
             ref = ref_o.candidate(x0, ref_o.candidate_v(k, 1.2, 0.5), 0)[0]
             assert abs(m[i] - ref) <= 1e-9 * max(1.0, abs(ref)), (new, k, m[i], ref)
     g.close()
+
+
+def test_fp64_tanh_within_3_ulp(R):
+    # the project-written FP64 tanh of the 9-state plant's FP64 paths against an
+    # extended-precision reference
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.prec = 120
+    rng = np.random.default_rng(3)
+    x = np.concatenate([rng.uniform(-1, 1, 4000) * 10.0 ** rng.uniform(-12, 1.4, 4000),
+                        [0.0, -0.0, 1e-300, 0.3465735902799727, 0.35, -0.7, 19.99, 20.01, 50.0,
+                         -50.0, np.inf, -np.inf, np.nan]])
+    y = R.fp64_tanh(x)
+    assert np.isnan(y[-1]) and y[-2] == -1.0 and y[-3] == 1.0 and y[-4] == -1.0
+    assert y[4000] == 0.0 and y[4001] == 0.0 and np.signbit(y[4001])
+    for xi, yi in zip(x[:-3], y[:-3]):
+        ref = float(mpmath.tanh(mpmath.mpf(float(xi))))
+        if ref == 0.0:
+            assert yi == 0.0
+            continue
+        assert abs(yi - ref) <= 3 * np.spacing(abs(ref)), (xi, yi, ref)
