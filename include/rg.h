@@ -391,10 +391,12 @@ int rg_equilibrium(rg_handle* h, double v, double* x_out);
  * injection (all their scenario tiles in one grid, FP32, one lane per
  * scenario), then each instance's FP64 recheck and decision.  All instances
  * use one search depth (opt.depth = 0: from the sum of N over the batch; large
- * batches evaluate one candidate per round) and no first-round prediction.
- * opt: precision F32_RECHECK, search BISECT or GRID, chance_q 0 (else
- * RG_E_NOTSUP); block is the scenario tile (64, 128, 256); persistent_wgs is
- * accepted and unused.  Every descriptor is validated as by rg_create (error
+ * batches evaluate one candidate per round).  opt: precision F32_RECHECK,
+ * search BISECT or GRID, chance_q 0 (else RG_E_NOTSUP); block is the scenario
+ * tile (64, 128, 256); predict as for rg_create; persistent_wgs is accepted
+ * and unused.  opt = NULL: the defaults of rg_default_options except block =
+ * 64 and predict = 0 (a batch's rounds are throughput-bound, so the least
+ * candidates per round is fastest).  Every descriptor is validated as by rg_create (error
  * names the instance; message via rg_batch_last_error(NULL)).  No device
  * memory is allocated here. */
 int rg_batch_create(const rg_instance_desc* descs, int32_t count, const rg_options* opt,

@@ -1506,6 +1506,11 @@ int rg_batch_create(const rg_instance_desc* descs, int32_t count, const rg_optio
   if (!descs || count < 1) return bfail(nullptr, RG_E_INVAL, "no instances");
   rg_options o;
   rg_default_options(&o);
+  // A batch's rounds are throughput-bound: one candidate per instance and round
+  // does the least work (measured: first-round prediction or deeper trees only
+  // add candidates), so the defaults differ from a single handle's.
+  o.predict = 0;
+  o.block = 64;
   if (opt) o = *opt;
   if (o.precision != RG_PREC_F32_RECHECK)
     return bfail(nullptr, RG_E_NOTSUP, "batches run FP32 rollouts with the FP64 recheck");
@@ -1534,7 +1539,7 @@ int rg_batch_create(const rg_instance_desc* descs, int32_t count, const rg_optio
   bt->count = count;
   bt->opt = o;
   bt->opt.depth = d;
-  bt->tile = o.block ? o.block : 256;
+  bt->tile = o.block ? o.block : 64;
   int noff = 0;
   for (int i = 0; i < count; ++i) {
     rg_scenarios s = descs[i].scen;
@@ -1542,7 +1547,6 @@ int rg_batch_create(const rg_instance_desc* descs, int32_t count, const rg_optio
     rg_options oi = o;
     oi.depth = d;
     oi.lanes = 1;       // the flat rollout runs one lane per scenario
-    oi.predict = 0;     // each round one node per level: no extra candidates
     oi.speculate = 0;
     oi.max_T = 1;
     oi.block = bt->tile;

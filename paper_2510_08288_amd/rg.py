@@ -401,7 +401,8 @@ class Batch:
     """Many independent governors stepped together (``rg_batch_*``)."""
 
     def __init__(self, problems, K: int = 12, band: float = 1e-4, depth: int = 0, block: int = 0,
-                 persistent_wgs: int = 0, early_exit: bool = True):
+                 persistent_wgs: int = 0, early_exit: bool = True, predict: bool = False,
+                 search: int = SEARCH_BISECT, M: int = 64, refine: int = 6):
         import torch
         self.L = load_library()
         self.problems = list(problems)
@@ -420,8 +421,9 @@ class Batch:
             descs[i].H = int(p.H)
             descs[i].dt = float(p.dt)
         opt = default_options()
-        opt.K, opt.band, opt.depth, opt.block = K, band, depth, block
+        opt.K, opt.band, opt.depth, opt.block = K, band, depth, block if block else 64
         opt.persistent_wgs, opt.early_exit = persistent_wgs, int(early_exit)
+        opt.predict, opt.search, opt.M, opt.refine = int(predict), search, M, refine
         h = _vp()
         rc = self.L.rg_batch_create(descs, len(self.problems), C.byref(opt), C.byref(h))
         if rc < 0:

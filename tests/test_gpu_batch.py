@@ -87,3 +87,28 @@ def test_batch_mixed_generator_matches_oracle(R, oracle_mod):
     # the search runs in both plant kinds: some instances settle strictly inside (0, 1)
     kap = np.concatenate([o["kappa"] for o in outs])
     assert np.any((kap > 0) & (kap < 1)) and np.any(kap[1::2] > 0)
+
+
+@pytest.mark.parametrize("depth,predict,block", [(1, False, 64), (2, True, 128), (3, False, 256)])
+def test_batch_schedules_keep_kappa(R, oracle_mod, depth, predict, block):
+    # search depth, first-round prediction and the scenario tile change only
+    # which candidates run when: every instance's kappa is that of the default
+    probs, xs, rs, vps = _mixed(oracle_mod, count=8, seed=21)
+    ref = R.Batch(probs)
+    a = [ref.step(xs, rs, vps, use_graph=True)["kappa"] for _ in range(2)]
+    ref.close()
+    b = R.Batch(probs, depth=depth, predict=predict, block=block)
+    assert b.options.depth == depth and b.options.predict == int(predict)
+    c = [b.step(xs, rs, vps, use_graph=True)["kappa"] for _ in range(2)]
+    b.close()
+    assert all(np.array_equal(x, y) for x, y in zip(a, c))
+
+
+def test_batch_grid_search_matches_single_governors(R, oracle_mod):
+    probs, xs, rs, vps = _mixed(oracle_mod, count=6, seed=13)
+    b = R.Batch(probs, search=R.SEARCH_GRID, M=17, refine=3)
+    out = b.step(xs, rs, vps, use_graph=False)
+    b.close()
+    for i, p in enumerate(probs):
+        ref = oracle_mod.Oracle(p, nthreads=8).grid(xs[i], rs[i], vps[i], 0, 17, 3)
+        assert out["kappa"][i] == ref["kappa"], (i, out["kappa"][i], ref["kappa"])
