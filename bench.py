@@ -390,6 +390,46 @@ def run_batch(rg, W, np, torch, steps=2):
             "sum_N_x_H": float(np.sum(NH)), "depth_instance0": int(depth)}
 
 
+def run_paper_sweep(args):
+    """Shape of the paper's GPU timing experiment (Sec. IV-B): the 9-state plant
+    with the grid search of Alg. 3 (M = 32 points, no refinement), H = 1024,
+    dt = 0.01, N = 1..32 and 32..8192 in steps of 32; per N the median of five
+    blocking RG steps with the draws generated into device memory first
+    (streamed) and with the draws generated inside the rollout lanes (inline).
+    Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    from paper_2510_08288_amd import rg, workloads as W
+
+    Ns = list(range(1, 33)) + list(range(64, 8193, 32))
+    rows = []
+    x0 = None
+    for N in Ns:
+        p = W.fc9_problem(N=N, H=1024, dt=0.01)
+        row = {"N": N}
+        for label, mode in [("streamed_ms", rg.RNG_STREAM), ("inline_ms", rg.RNG_INLINE)]:
+            g = rg.Governor(p, search=rg.SEARCH_GRID, M=32, refine=0, rng_mode=mode)
+            if x0 is None:
+                x0 = g.equilibrium(0.5)
+            times = []
+            for rep in range(6):
+                g.set_step(0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res = g.step(x0, 2.0, 0.5)
+                times.append(time.perf_counter() - t0)
+            g.close()
+            row[label] = float(np.median(times[1:])) * 1e3
+            row["kappa"] = res["kappa"]
+        # every N has workspaces of its own size: hand them back to the device
+        torch.cuda.empty_cache()
+        rows.append(row)
+        if N % 1024 == 0 or N == 32:
+            progress(f"paper sweep N={N}: {row}")
+    print(json.dumps({"workload": "fc9_grid_m32_h1024_dt0.01", "rows": rows}))
+
+
 def progress(msg):
     """One progress line on stderr (the JSON line alone goes to stdout)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -421,6 +461,9 @@ def main():
                                        "fp64_sequential_bisection"],
                     default=None, help=argparse.SUPPRESS)
     ap.add_argument("--extras-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--paper-sweep", action="store_true",
+                    help="only the paper-shaped sweep of RG-step time against N (9-state grid, "
+                         "M = 32) and exit")
     ap.add_argument("--extra-updates", type=int, default=3,
                     help="updates timed per form on the 9-state workloads")
     ap.add_argument("--no-extras", action="store_true",
@@ -450,6 +493,8 @@ def main():
         return run_form(args)
     if args.extras_only:
         return run_extras(args)
+    if args.paper_sweep:
+        return run_paper_sweep(args)
     if args.copy_calibration > 0:
         src = torch.ones(args.copy_calibration, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

@@ -259,6 +259,7 @@ class Governor:
         if getattr(self, "h", None):
             self.L.rg_destroy(self.h)
             self.h = None
+        self.workspace = None  # the handle is gone: its device memory may go too
 
     def __del__(self):
         try:
