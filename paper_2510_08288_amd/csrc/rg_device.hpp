@@ -106,39 +106,46 @@ __device__ __forceinline__ float t_tanh(float z) {
 // FP64 tanh of the FP64 rollouts and steady-state solves (written here, not
 // the library's): tanh|z| = t / (t + 2) with t = expm1(2|z|), which has no
 // cancellation at small |z|, carrying the sign of z; 1 once 2|z| >= 40 (then
-// 1 - tanh|z| < 2^-56).  expm1(x), x >= 0: Cody-Waite reduction x = k ln2 + r
-// with |r| <= ln2 / 2 and ln 2 split into a 32-bit head (k ln2_head is exact)
-// and its remainder; expm1(r) by its Taylor series to degree 13 in Horner form
-// (truncation below 2^-56 relative on that interval); then
-// expm1(x) = 2^k expm1(r) + (2^k - 1).  Within 3 ulp of tanh over the
-// arguments the rollouts meet (checked against an extended-precision
-// reference in the tests).
+// 1 - tanh|z| < 2^-56).  expm1(x), 0 <= x <= 40: Cody-Waite reduction
+// x = k ln2 + r with |r| <= ln2 / 2 and ln 2 split into a 32-bit head (k ln2_head
+// is exact) and its remainder; expm1(r) = r p(r) with p the Taylor series of
+// expm1(r) / r to degree 12 (truncation below 2^-56 relative on that interval),
+// its tail evaluated in Estrin's scheme (dependent depth 6 instead of Horner's
+// 12: the FP64 rechecks are bound by this latency); then
+// expm1(x) = 2^k expm1(r) + (2^k - 1).
+// Branch-free: arguments at or beyond 40 (and NaN) run the same arithmetic on
+// 40 and are replaced at the end.  Within 3 ulp of tanh over the arguments the
+// rollouts meet (checked against an extended-precision reference in the tests).
 __device__ __forceinline__ double t_tanh(double z) {
-  const double x = 2.0 * fabs(z);
-  if (!(x < 40.0)) return x == x ? copysign(1.0, z) : z;
+  const double ax = 2.0 * fabs(z);
+  const double x = fmin(ax, 40.0);
   constexpr double kLn2Head = 0x1.62e42ff0p-1;         // ln 2 to 32 significant bits
   constexpr double kLn2Tail = -0x1.718432a1b0e26p-35;  // ln 2 - kLn2Head
   constexpr double kInvLn2 = 0x1.71547652b82fep+0;
   const double k = rint(x * kInvLn2);
   double r = fma(-k, kLn2Head, x);
   r = fma(-k, kLn2Tail, r);
-  double p = 1.0 / 6227020800.0;  // 1/13!
-  p = fma(p, r, 1.0 / 479001600.0);
-  p = fma(p, r, 1.0 / 39916800.0);
-  p = fma(p, r, 1.0 / 3628800.0);
-  p = fma(p, r, 1.0 / 362880.0);
-  p = fma(p, r, 1.0 / 40320.0);
-  p = fma(p, r, 1.0 / 5040.0);
-  p = fma(p, r, 1.0 / 720.0);
-  p = fma(p, r, 1.0 / 120.0);
-  p = fma(p, r, 1.0 / 24.0);
-  p = fma(p, r, 1.0 / 6.0);
-  p = fma(p, r, 0.5);
-  p = fma(p, r, 1.0);
+  // p(r) = sum_n r^n / (n + 1)!, n = 0..12, as 1 + r (1/2 + r s(r)) with the
+  // tail s (degree 10) in Estrin's scheme: its rounding errors enter p scaled
+  // by r^2, and the two outer steps round as Horner's last two do
+  const double r2 = r * r, r4 = r2 * r2, r8 = r4 * r4;
+  const double e1 = fma(1.0 / 24.0, r, 1.0 / 6.0);
+  const double e2 = fma(1.0 / 720.0, r, 1.0 / 120.0);
+  const double e3 = fma(1.0 / 40320.0, r, 1.0 / 5040.0);
+  const double e4 = fma(1.0 / 3628800.0, r, 1.0 / 362880.0);
+  const double e5 = fma(1.0 / 479001600.0, r, 1.0 / 39916800.0);
+  const double f1 = fma(e2, r2, e1);
+  const double f2 = fma(e4, r2, e3);
+  const double f3 = fma(1.0 / 6227020800.0, r2, e5);
+  const double g1 = fma(f2, r4, f1);
+  const double sr = fma(f3, r8, g1);
+  const double p = fma(fma(sr, r, 0.5), r, 1.0);
   const double em = p * r;  // expm1(r)
   const double two_k = ldexp(1.0, (int)k);
   const double t = fma(two_k, em, two_k - 1.0);
-  return copysign(t / (t + 2.0), z);
+  const double th = copysign(t / (t + 2.0), z);
+  const double sat = ax == ax ? copysign(1.0, z) : z;
+  return ax < 40.0 ? th : sat;
 }
 __device__ __forceinline__ float t_sqrt(float z) { return __builtin_amdgcn_sqrtf(z); }
 __device__ __forceinline__ double t_sqrt(double z) { return sqrt(z); }
@@ -319,31 +326,53 @@ struct Plant<2, T> {
 #pragma unroll
     for (int i = 0; i < 9; ++i) s[i] = (T)0;
   }
+  // Component i of the derivative from the pieces of the evaluation point:
+  // z_i, the vector tz = tanh(z), the orifice flows q_i = qa qb and
+  // q_{i+1} = qk qr as factor pairs (i < 6), and the states x0, x6, x8.  Every
+  // product-sum is an explicit fma and nothing here is contracted, so the
+  // one-lane derivative below and the FP64 recheck that gives each component
+  // its own lane round alike.
+  __device__ static T comp(int i, T ai, const T* wrow, T si, T zi, const T* tz, T qa, T qb,
+                           T qk, T qr, T x0, T x6, T x8, const Lane& L, T p1ref) {
+#pragma clang fp contract(off)
+    T a = t_fma(-ai, zi, si);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) a = t_fma(wrow[j], tz[j], a);
+    // phi_i = A B + C in one form for every row; every candidate is computed
+    // and then selected (no branch where i varies over the lanes)
+    const T c0 = -(qk * qr);
+    const T a6 = -(L.mu[0] * x6), b6 = x0 - p1ref, c6 = L.b[0] * L.v;
+    const T a7 = L.b[1] * L.v;
+    const T a8 = -(L.mu[1] * (x8 - (T)1)), c8 = L.b[2] * L.v;
+    const bool lo = i < 6, r6 = i == 6, r7 = i == 7;
+    const T A = lo ? qa : (r6 ? a6 : (r7 ? a7 : a8));
+    const T B = lo ? qb : (r6 ? b6 : (r7 ? x6 : L.v));
+    const T C = lo ? c0 : (r6 ? c6 : (r7 ? (T)0 : c8));
+    return a + t_fma(A, B, C);
+  }
+  // Square-root factor of the orifice flow q_{l+1}: sqrt(max(p_l - p_{l+1}, 0))
+  // with p_7 = p_amb.
+  __device__ static T orifice(T pl, T pn) {
+    const T dp = pl - pn;
+    return t_sqrt(dp > (T)0 ? dp : (T)0);
+  }
   __device__ static void deriv(const Coef& c, const Lane& L, const T* s, const T* x, T* xd) {
-    T z[9], tz[9], q[7];
+    T z[9], tz[9], r[6];
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
       z[j] = x[j] - c.xbar[j];
       tz[j] = t_tanh(z[j]);
     }
-    q[0] = c.c_q0 * x[6];
 #pragma unroll
-    for (int l = 0; l < 6; ++l) {
-      const T dn = (l < 5) ? x[l + 1] : c.p_amb;
-      const T dp = x[l] - dn;
-      q[l + 1] = L.kq[l] * t_sqrt(dp > (T)0 ? dp : (T)0);
-    }
+    for (int l = 0; l < 6; ++l) r[l] = orifice(x[l], (l < 5) ? x[l + 1] : c.p_amb);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      T a = t_fma(-L.a[i], z[i], s[i]);
-#pragma unroll
-      for (int j = 0; j < 9; ++j) a = t_fma(c.W[9 * i + j], tz[j], a);
-      T phi;
-      if (i < 6) phi = q[i] - q[i + 1];
-      else if (i == 6) phi = L.b[0] * L.v - L.mu[0] * x[6] * (x[0] - c.p1ref);
-      else if (i == 7) phi = L.b[1] * L.v * x[6];
-      else phi = L.b[2] * L.v - L.mu[1] * (x[8] - (T)1) * L.v;
-      xd[i] = a + phi;
+      const T qa = i == 0 ? c.c_q0 : (i < 6 ? L.kq[i > 0 ? i - 1 : 0] : (T)0);
+      const T qb = i == 0 ? x[6] : (i < 6 ? r[i > 0 ? i - 1 : 0] : (T)0);
+      const T qk = i < 6 ? L.kq[i < 6 ? i : 0] : (T)0;
+      const T qr = i < 6 ? r[i < 6 ? i : 0] : (T)0;
+      xd[i] = comp(i, L.a[i], &c.W[9 * i], s[i], z[i], tz, qa, qb, qk, qr, x[0], x[6], x[8], L,
+                   c.p1ref);
     }
   }
   __device__ static void post(const Coef&, const T* w, T* x) {

@@ -329,6 +329,188 @@ __device__ __forceinline__ T rollout_lane(const A& a, int early, T v, int k, uin
   return best;
 }
 
+// ---------------------------------------------------------------------------
+// FP64 rollout of one 9-state scenario by a group of 16 lanes, for the recheck
+// of a few near-band scenarios (one lane per scenario would leave every
+// serial RK4 step on one lane).  Lane i of the group owns state component i;
+// lanes 9..15 repeat component 8 and nothing reads them.  At every derivative
+// evaluation each lane computes its own tanh and orifice factors, the group
+// exchanges (x_i, tanh z_i) through its 16 LDS slots (the orifice factors
+// through DPP row shifts), and each lane forms its component with
+// Plant<2>::comp, the arithmetic of the one-lane rollout; every
+// lane computes the margin from the exchanged state.  The result equals that
+// of rollout_lane<2, double> bit for bit.  Control flow is uniform over the
+// group: every branch depends on exchanged values or on a ballot over gmask.
+// ---------------------------------------------------------------------------
+// A double moved between lanes by DPP (CTRL: quad permutations, row shifts),
+// 0 where the source lane lies outside the row.
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ __forceinline__ void group_sync() {
+  // The group is part of one wave, whose LDS accesses complete in program
+  // order; this only keeps the compiler from moving them across.
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int RNG, int INJ>
+__device__ double rollout_fc9_group(const RollArgs<2, double>& a, int early, double v, int k,
+                                    uint32_t t, int32_t* stop_flag, double2* xch, int li,
+                                    unsigned long long gmask) {
+  using P = Plant<2, double>;
+  const int i = li < 9 ? li : 8;
+  double th[P::nth];
+  {
+    float f[P::nth];
+    if (RNG == 0) {
+      const float* tb = step_th(a, t);
+#pragma unroll
+      for (int c = 0; c < P::nth; ++c) f[c] = tb[(size_t)c * a.N + k];
+    } else {
+      draw_theta_factor<P::nth>(a.seed, a.inst, t, (uint32_t)k, a.thlo, a.thspan, f);
+    }
+#pragma unroll
+    for (int c = 0; c < P::nth; ++c) th[c] = a.pc.thnom[c] * (double)f[c];
+  }
+  P::Lane L;
+  P::lane_init(a.pc, th, v, L);
+  // this lane's coefficients: a_i, xbar_i, row i of W, k_{i-1} and k_i of the
+  // orifice flows q_i and q_{i+1}, the draw bounds of w_i
+  double ai = L.a[0], xb = a.pc.xbar[0], kql = 0.0, kqh = L.kq[0], wrow[9];
+  float wlo = a.wlo[0], wsp = a.wspan[0];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) wrow[j] = a.pc.W[j];
+#pragma unroll
+  for (int r = 1; r < 9; ++r) {
+    const bool on = i == r;
+    ai = on ? L.a[r] : ai;
+    xb = on ? a.pc.xbar[r] : xb;
+    wlo = on ? a.wlo[r] : wlo;
+    wsp = on ? a.wspan[r] : wsp;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) wrow[j] = on ? a.pc.W[9 * r + j] : wrow[j];
+    if (r < 6) kqh = on ? L.kq[r] : kqh;
+    if (r < 6) kql = on ? L.kq[r - 1] : kql;
+  }
+  // exchange of the evaluation point: X and TZ receive (x_j, tanh z_j) of
+  // every component; rh = r_i and rl = r_{i-1}, the orifice factors of q_{i+1}
+  // and q_i, come from the neighbouring lanes by DPP row shifts
+  double X[9], TZ[9], rl, rh;
+  auto exch = [&](double xv) {
+    const double xn = dpp64<0x101>(xv);  // row_shl:1, x_{i+1}
+    rh = P::orifice(xv, i < 5 ? xn : a.pc.p_amb);
+    rl = dpp64<0x111>(rh);  // row_shr:1, r_{i-1}
+    xch[li] = make_double2(xv, t_tanh(xv - xb));
+    group_sync();
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      const double2 e = xch[j];
+      X[j] = e.x;
+      TZ[j] = e.y;
+    }
+    group_sync();
+  };
+  // component i of the derivative at the exchanged point (own component xv)
+  auto eval = [&](double xv, double si) {
+    const double qa = i == 0 ? a.pc.c_q0 : kql;
+    const double qb = i == 0 ? X[6] : rl;
+    return P::comp(i, ai, wrow, si, xv - xb, TZ, qa, qb, kqh, rh, X[0], X[6], X[8], L,
+                   a.pc.p1ref);
+  };
+  const float* wb = RNG == 0 ? step_w(a, t) : nullptr;
+  const int wq = i & 3;
+  auto load = [&](int j) -> float {
+    if (RNG == 0) return wb[((size_t)j * P::nw + i) * a.N + k];
+    const Words r = philox10((uint32_t)k, (uint32_t)j, t, (uint32_t)(i >> 2), a.seed, a.inst);
+    const uint32_t word = wq == 0 ? r.v[0] : (wq == 1 ? r.v[1] : (wq == 2 ? r.v[2] : r.v[3]));
+    return box_draw(word, wlo, wsp);
+  };
+  double xv = a.st->x[i];
+  exch(xv);
+  double y[P::ny];
+  P::output(a.pc, L, X, y);
+  double best = margin_rows<P::ny>(a.F, a.g, y);
+  if (best != best) best = -INFINITY;
+  float wc = a.H > 0 ? load(0) : 0.0f, wn = 0.0f;
+  for (int j = 0; j < a.H; ++j) {
+    if (j + 1 < a.H) wn = load(j + 1);
+    const double si = INJ == 0 ? (double)wc : 0.0;
+    double kk = eval(xv, si);
+    double acc = kk;
+    double xs = t_fma(a.hh, kk, xv);
+    exch(xs);
+    kk = eval(xs, si);
+    acc = t_fma(2.0, kk, acc);
+    xs = t_fma(a.hh, kk, xv);
+    exch(xs);
+    kk = eval(xs, si);
+    acc = t_fma(2.0, kk, acc);
+    xs = t_fma(a.h, kk, xv);
+    exch(xs);
+    kk = eval(xs, si);
+    xv = t_fma(a.h6, acc + kk, xv);
+    if (INJ == 1) xv = xv + (double)wc;
+    exch(xv);
+    P::output(a.pc, L, X, y);
+    double m = margin_rows<P::ny>(a.F, a.g, y);
+    m = (m == m) ? m : -INFINITY;
+    if (m < best) best = m;
+    if (early) {
+      if (best < -a.band) break;
+      if ((j & 31) == 31 && stop_flag) {
+        const bool f = __hip_atomic_load(stop_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        if (__builtin_amdgcn_ballot_w64(f) & gmask) break;
+      }
+    }
+    wc = wn;
+  }
+  bool finite = true;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) finite = finite && (X[j] - X[j] == 0.0);
+  if (!finite) best = -INFINITY;
+  return best;
+}
+
+// The FP64 recheck of near-band entries [g0, n) with stride gstride over
+// groups of 16 lanes (rollout_fc9_group), with the verdict updates of
+// k_recheck made by the group's first lane.  blockDim.x is a multiple of 16
+// and at most 64.
+template <int RNG, int INJ>
+__device__ void recheck_fc9_groups(const RollArgs<2, double>& a, DevSearch* S, int n, uint32_t t,
+                                   int g0, int gstride) {
+  __shared__ double2 xch[64];
+  const int li = threadIdx.x & 15;
+  double2* slot = xch + (threadIdx.x & ~15);
+  const unsigned long long gmask = 0xffffull << (threadIdx.x & 48);
+  const int q = S->q;
+  for (int e = g0; e < n; e += gstride) {
+    const int2 en = a.rlist[e];
+    const int c = en.x, k = en.y;
+    const bool skip =
+        a.early && (__hip_atomic_load(&S->dead[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                    __hip_atomic_load(&S->fail64[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (__builtin_amdgcn_ballot_w64(skip) & gmask) continue;
+    const double m = rollout_fc9_group<RNG, INJ>(
+        a, a.early, S->v[c], k, t, a.early && q == 0 ? &S->fail64[c] : nullptr, slot, li, gmask);
+    if (li != 0) continue;
+    atomicMin(&S->key64[c], ord64(m));
+    if (q > 0) {
+      a.per_key[(size_t)c * a.N + k] = ord64(m);
+      if (m < 0.0 && S->nviol[c] + atomicAdd(&S->nviol64[c], 1) >= q)
+        __hip_atomic_store(&S->fail64[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (m < 0.0) {
+      __hip_atomic_store(&S->fail64[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 // One scenario rollout in FP32 over the full horizon with the forward tangent
 // of the state with respect to the set-point carried along (not in the paper:
 // it gives the derivative the Newton search needs in the same pass).  Returns
@@ -366,9 +548,18 @@ __device__ __forceinline__ float rollout_lane_tan(const A& a, float v, int k, ui
     P::output(a.pc, L, x, y);
     m = margin_rows_arg<P::ny>(a.F, a.g, y, r);
     P::output_tan(a.pc, x, dx, dy);
-    float fy = a.F[r * P::ny] * dy[0];
+    // row r of F by selection (a per-lane index into the argument block would
+    // place the block in scratch memory)
+    float fr[P::ny];
 #pragma unroll
-    for (int i = 1; i < P::ny; ++i) fy = __builtin_fmaf(a.F[r * P::ny + i], dy[i], fy);
+    for (int i = 0; i < P::ny; ++i) fr[i] = a.F[i];
+#pragma unroll
+    for (int rr = 1; rr < kNC; ++rr)
+#pragma unroll
+      for (int i = 0; i < P::ny; ++i) fr[i] = rr == r ? a.F[rr * P::ny + i] : fr[i];
+    float fy = fr[0] * dy[0];
+#pragma unroll
+    for (int i = 1; i < P::ny; ++i) fy = __builtin_fmaf(fr[i], dy[i], fy);
     dmj = -fy;
   };
   float best, dbest;
@@ -913,14 +1104,6 @@ struct QuadCoef64 {
   double grow[4];
 };
 
-template <int CTRL>
-__device__ __forceinline__ double dpp64(double x) {
-  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, true);
-  return __builtin_bit_cast(double, ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-
 __device__ __forceinline__ double min2d(double a, double b) { return b < a ? b : a; }
 
 __device__ __forceinline__ double quad_min64(double m) {
@@ -1054,6 +1237,16 @@ __global__ void __launch_bounds__(64) k_recheck(const RollArgs<KIND, double> a,
   if (S->done) return;
   const int n = S->n_recheck;
   const uint32_t t = a.st->t;
+  if constexpr (KIND == 2) {
+    // up to two entries per group of 16 lanes: the cooperative rollout
+    const int groups = (int)(gridDim.x * blockDim.x) >> 4;
+    if (n <= 2 * groups) {
+      recheck_fc9_groups<RNG, INJ>(a, S, n, t, (int)(blockIdx.x * blockDim.x + threadIdx.x) >> 4,
+                                   groups);
+      if (decide) last_block_decides<KIND>(ctl);
+      return;
+    }
+  }
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int2 e = a.rlist[i];
     const int c = e.x, k = e.y;
@@ -1096,6 +1289,17 @@ __global__ void __launch_bounds__(64) k_flat_recheck(const RollArgs<KIND, double
   if (S->done) return;  // uniform: nothing writes it before the decision below
   const int n = S->n_recheck;
   const uint32_t t = a.st->t;
+  if constexpr (KIND == 2) {
+    // few entries: the cooperative rollout, four groups of 16 lanes
+    if (n <= 8) {
+      recheck_fc9_groups<1, INJ>(a, S, n, t, (int)threadIdx.x >> 4, (int)blockDim.x >> 4);
+      __threadfence();
+      __syncthreads();
+      const CtlArgs<KIND>& cl = ctl[blockIdx.x];
+      decide_body<KIND>(cl.pc, cl.st, cl.srch, cl.grad);
+      return;
+    }
+  }
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const int2 e = a.rlist[i];
     const int c = e.x, k = e.y;
@@ -2885,7 +3089,10 @@ hipError_t launch_recheck(const Problem& pr, int early_exit, const LaunchCfg& cf
       });
     });
   }
-  const int blocks = div_up(cap < 16384 ? cap : 16384, 64);
+  // 9-state plant: up to one group of 16 lanes per possible entry (four per
+  // workgroup, at most 256 workgroups), for the cooperative FP64 rollout
+  const int blocks = pr.p.kind == 2 ? (int)(div_up(cap, 4) < 256 ? div_up(cap, 4) : 256)
+                                    : (int)div_up(cap < 16384 ? cap : 16384, 64);
   return by_kind(pr.p.kind, [&](auto kc) {
     constexpr int K = decltype(kc)::value;
     return by_bit(pr.s.rng_mode, [&](auto rc) {
