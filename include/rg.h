@@ -154,8 +154,13 @@ typedef struct rg_options {
     int32_t early_exit;    /* 1: a candidate stops once one lane is below -band */
     int32_t block;         /* threads per workgroup for rollouts (64..256, multiple of 64; 0 = auto) */
     int32_t max_T;         /* closed-loop steps kept on the device per chunk (default 256) */
-    int32_t lanes;         /* lanes per scenario of FP32 LQ4 rollouts: 1, 4 (one scenario per
-                              quad, state split across lanes), 0 = auto */
+    int32_t lanes;         /* lanes per scenario of FP32 rollouts with the robust verdict:
+                              1; 4 for LQ4 (one scenario per quad, state split across
+                              lanes); 16 for FC9 (one scenario per group of 16 lanes, one
+                              lane per state component; not with the tangent-driven Newton
+                              search); 0 = auto (LQ4: 4; FC9: 16 while a round holds at
+                              most 16384 scenario-candidate pairs, else 1).  Margins are
+                              bit-identical across layouts */
     int32_t Kc;            /* adjoint checkpoint interval in RK4 steps (default 50) */
     int32_t persistent_wgs;/* batches: workgroups of the persistent rollout kernel (0 = auto) */
     int32_t predict;       /* bisection: 1 (default) makes the first device round of a step
@@ -319,7 +324,8 @@ int rg_get_options(const rg_handle* h, rg_options* out);
  * (x0, v0) under r_seq (as rg_closed_loop, graph replay, starting at the
  * handle's step counter, which is restored afterwards) for every candidate
  * schedule (three runs: the first captures the graphs, the faster of the other
- * two counts): lanes per scenario (1 or 4, LQ4 FP32 only), rollout
+ * two counts): lanes per scenario (1 or 4 for LQ4, 1 or 16 for FC9; FP32 robust
+ * verdict only), rollout
  * workgroup (128 or 256 threads), device search depth (2..5; 1..3 for the grid
  * refinement), first-round prediction (on/off, bisection only) and the
  * speculation depth (7, 3, 1, 0; with prediction and 4 lanes).  Schedules

@@ -157,13 +157,23 @@ Layout layout_of(const rg_handle* h) {
   return L;
 }
 
+// Scenario-candidate pairs of one round below which the 9-state FP32 rollouts
+// run one scenario per group of 16 lanes (auto lanes): one lane per scenario
+// leaves the chip mostly idle there and each round is bound by the latency of
+// a whole RK4 step on one lane.
+constexpr double kGroupPairsMax = 16384;
+
 int lanes_for(const rg_handle* h) {
+  const bool f32_robust = h->opt.precision == RG_PREC_F32_RECHECK && h->opt.chance_q == 0;
   // the quad kernel stops a wave at its first violation: robust verdict only
-  const bool quad_ok = h->pr.p.kind == RG_PLANT_LQ4 && h->opt.precision == RG_PREC_F32_RECHECK &&
-                       h->opt.chance_q == 0;
+  const bool quad_ok = h->pr.p.kind == RG_PLANT_LQ4 && f32_robust;
+  // the 9-state groups: robust verdict; the forward tangent runs on one lane
+  const bool group_ok =
+      h->pr.p.kind == RG_PLANT_FC9 && f32_robust && h->opt.search != RG_SEARCH_NEWTON_TAN;
   if (h->opt.lanes == 4) return quad_ok ? 4 : 1;
+  if (h->opt.lanes == 16) return group_ok ? 16 : 1;
   if (h->opt.lanes == 1) return 1;
-  return quad_ok ? 4 : 1;
+  return quad_ok ? 4 : (group_ok ? 16 : 1);
 }
 
 int depth_for(const rg_handle* h, int lanes) {
@@ -182,8 +192,21 @@ int depth_for(const rg_handle* h, int lanes) {
   return (goal + rounds - 1) / rounds;
 }
 
+void plan_with(rg_handle* h, int lanes);
+
 void plan(rg_handle* h) {
-  const int lanes = lanes_for(h);
+  const bool auto_lanes = h->opt.lanes == 0;
+  const int depth0 = h->opt.depth;  // 0: auto
+  plan_with(h, lanes_for(h));
+  // auto: 9-state groups only for rounds of few scenario-candidate pairs
+  if (auto_lanes && h->cfg.lanes == 16 &&
+      (double)h->cfg.cmax_round * h->pr.s.N > kGroupPairsMax) {
+    h->opt.depth = depth0;
+    plan_with(h, 1);
+  }
+}
+
+void plan_with(rg_handle* h, int lanes) {
   const int d = depth_for(h, lanes);
   h->opt.depth = d;
   h->opt.lanes = lanes;
@@ -688,7 +711,8 @@ int rg_create(const rg_plant* plant, const rg_scenarios* scen, const rg_constrai
   if (o.block != 0 && (o.block < 64 || o.block > 256 || (o.block & 63)))
     return fail(nullptr, RG_E_INVAL, "block must be a multiple of 64 in [64, 256]");
   if (o.max_T < 1 || o.max_T > 65536) return fail(nullptr, RG_E_INVAL, "max_T must be in [1, 65536]");
-  if (o.lanes != 0 && o.lanes != 1 && o.lanes != 4) return fail(nullptr, RG_E_INVAL, "lanes must be 0, 1 or 4");
+  if (o.lanes != 0 && o.lanes != 1 && o.lanes != 4 && o.lanes != 16)
+    return fail(nullptr, RG_E_INVAL, "lanes must be 0, 1, 4 or 16");
   if (o.Kc < 1 || o.Kc > 4096) return fail(nullptr, RG_E_INVAL, "Kc must be in [1, 4096]");
   if (o.predict != 0 && o.predict != 1) return fail(nullptr, RG_E_INVAL, "predict must be 0 or 1");
   if (o.speculate < 0 || o.speculate > kSpecMax)
@@ -1163,11 +1187,14 @@ int rg_autotune(rg_handle* h, const double* x0, double v0, const double* r_seq, 
   if (rc) return rc;
   const rg_options own = h->opt;
   const uint32_t t0 = h->t;
-  const bool quad_ok = h->pr.p.kind == RG_PLANT_LQ4 && h->opt.precision == RG_PREC_F32_RECHECK &&
-                       h->opt.chance_q == 0;
+  const bool f32_robust = h->opt.precision == RG_PREC_F32_RECHECK && h->opt.chance_q == 0;
+  const bool quad_ok = h->pr.p.kind == RG_PLANT_LQ4 && f32_robust;
+  const bool group_ok =
+      h->pr.p.kind == RG_PLANT_FC9 && f32_robust && h->opt.search != RG_SEARCH_NEWTON_TAN;
   std::vector<rg_options> cands;
-  for (int lanes : {4, 1}) {
+  for (int lanes : {4, 16, 1}) {
     if (lanes == 4 && !quad_ok) continue;
+    if (lanes == 16 && !group_ok) continue;
     for (int block : {256, 128}) {
       const bool grid = h->opt.search == RG_SEARCH_GRID;
       const int dlo = grid ? 1 : 2, dhi = grid ? 3 : 5;

@@ -330,26 +330,38 @@ __device__ __forceinline__ T rollout_lane(const A& a, int early, T v, int k, uin
 }
 
 // ---------------------------------------------------------------------------
-// FP64 rollout of one 9-state scenario by a group of 16 lanes, for the recheck
-// of a few near-band scenarios (one lane per scenario would leave every
-// serial RK4 step on one lane).  Lane i of the group owns state component i;
-// lanes 9..15 repeat component 8 and nothing reads them.  At every derivative
-// evaluation each lane computes its own tanh and orifice factors, the group
-// exchanges (x_i, tanh z_i) through its 16 LDS slots (the orifice factors
-// through DPP row shifts), and each lane forms its component with
-// Plant<2>::comp, the arithmetic of the one-lane rollout; every
-// lane computes the margin from the exchanged state.  The result equals that
-// of rollout_lane<2, double> bit for bit.  Control flow is uniform over the
-// group: every branch depends on exchanged values or on a ballot over gmask.
+// Rollout of one 9-state scenario by a group of 16 lanes (a DPP row), for the
+// FP64 recheck of a few near-band scenarios and for FP32 rounds with few
+// scenarios: one lane per scenario would leave every serial RK4 step on one
+// lane while most of the chip idles.  Lane i of the group owns state
+// component i; lanes 9..15 repeat component 8 and nothing reads them.  At every
+// derivative evaluation each lane computes its own tanh and orifice factors,
+// the group exchanges (x_i, tanh z_i) through its 16 LDS slots (the orifice
+// factors through DPP row shifts), and each lane forms its component with
+// Plant<2>::comp, the arithmetic of the one-lane rollout; every lane computes
+// the margin from the exchanged state.  The result equals that of
+// rollout_lane<2, T> bit for bit.  Control flow is uniform over the group
+// (over the wave with WAVE): every branch depends on exchanged values or on a
+// ballot.
 // ---------------------------------------------------------------------------
-// A double moved between lanes by DPP (CTRL: quad permutations, row shifts),
-// 0 where the source lane lies outside the row.
+// A float or double moved between lanes by DPP (CTRL: quad permutations, row
+// shifts), 0 where the source lane lies outside the row.
+template <int CTRL>
+__device__ __forceinline__ float dpp_row(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL,
+                                                               0xf, 0xf, true));
+}
 template <int CTRL>
 __device__ __forceinline__ double dpp64(double x) {
   const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
   const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, true);
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, true);
   return __builtin_bit_cast(double, ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_row(double x) {
+  return dpp64<CTRL>(x);
 }
 
 __device__ __forceinline__ void group_sync() {
@@ -360,13 +372,31 @@ __device__ __forceinline__ void group_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int RNG, int INJ>
-__device__ double rollout_fc9_group(const RollArgs<2, double>& a, int early, double v, int k,
-                                    uint32_t t, int32_t* stop_flag, double2* xch, int li,
-                                    unsigned long long gmask) {
-  using P = Plant<2, double>;
+template <class T>
+struct Pair;
+template <>
+struct Pair<float> {
+  using type = float2;
+};
+template <>
+struct Pair<double> {
+  using type = double2;
+};
+
+// WAVE (FP32 rollouts of one candidate): the whole wave stops at the first
+// violation of any of its groups, as rollout_lane's WAVE form, and stop_flag
+// is that candidate's dead flag; otherwise (FP64 rechecks) the group stops on
+// its own and stop_flag is only read.  CKPT with ck: checkpoints as
+// rollout_lane's (lane i stores component i).  jbest and nsteps as
+// rollout_lane's.
+template <class T, int RNG, int INJ, bool WAVE = false, int CKPT = 0>
+__device__ T rollout_fc9_group(const RollArgs<2, T>& a, int early, T v, int k, uint32_t t,
+                               int32_t* stop_flag, typename Pair<T>::type* xch, int li,
+                               unsigned long long gmask, int& jbest, int& nsteps, bool ck = false,
+                               bool* stopped = nullptr) {
+  using P = Plant<2, T>;
   const int i = li < 9 ? li : 8;
-  double th[P::nth];
+  T th[P::nth];
   {
     float f[P::nth];
     if (RNG == 0) {
@@ -377,13 +407,13 @@ __device__ double rollout_fc9_group(const RollArgs<2, double>& a, int early, dou
       draw_theta_factor<P::nth>(a.seed, a.inst, t, (uint32_t)k, a.thlo, a.thspan, f);
     }
 #pragma unroll
-    for (int c = 0; c < P::nth; ++c) th[c] = a.pc.thnom[c] * (double)f[c];
+    for (int c = 0; c < P::nth; ++c) th[c] = a.pc.thnom[c] * (T)f[c];
   }
-  P::Lane L;
+  typename P::Lane L;
   P::lane_init(a.pc, th, v, L);
   // this lane's coefficients: a_i, xbar_i, row i of W, k_{i-1} and k_i of the
   // orifice flows q_i and q_{i+1}, the draw bounds of w_i
-  double ai = L.a[0], xb = a.pc.xbar[0], kql = 0.0, kqh = L.kq[0], wrow[9];
+  T ai = L.a[0], xb = a.pc.xbar[0], kql = (T)0, kqh = L.kq[0], wrow[9];
   float wlo = a.wlo[0], wsp = a.wspan[0];
 #pragma unroll
   for (int j = 0; j < 9; ++j) wrow[j] = a.pc.W[j];
@@ -402,25 +432,28 @@ __device__ double rollout_fc9_group(const RollArgs<2, double>& a, int early, dou
   // exchange of the evaluation point: X and TZ receive (x_j, tanh z_j) of
   // every component; rh = r_i and rl = r_{i-1}, the orifice factors of q_{i+1}
   // and q_i, come from the neighbouring lanes by DPP row shifts
-  double X[9], TZ[9], rl, rh;
-  auto exch = [&](double xv) {
-    const double xn = dpp64<0x101>(xv);  // row_shl:1, x_{i+1}
+  T X[9], TZ[9], rl, rh;
+  auto exch = [&](T xv) {
+    const T xn = dpp_row<0x101>(xv);  // row_shl:1, x_{i+1}
     rh = P::orifice(xv, i < 5 ? xn : a.pc.p_amb);
-    rl = dpp64<0x111>(rh);  // row_shr:1, r_{i-1}
-    xch[li] = make_double2(xv, t_tanh(xv - xb));
+    rl = dpp_row<0x111>(rh);  // row_shr:1, r_{i-1}
+    typename Pair<T>::type e;
+    e.x = xv;
+    e.y = t_tanh(xv - xb);
+    xch[li] = e;
     group_sync();
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
-      const double2 e = xch[j];
-      X[j] = e.x;
-      TZ[j] = e.y;
+      const typename Pair<T>::type f = xch[j];
+      X[j] = f.x;
+      TZ[j] = f.y;
     }
     group_sync();
   };
   // component i of the derivative at the exchanged point (own component xv)
-  auto eval = [&](double xv, double si) {
-    const double qa = i == 0 ? a.pc.c_q0 : kql;
-    const double qb = i == 0 ? X[6] : rl;
+  auto eval = [&](T xv, T si) {
+    const T qa = i == 0 ? a.pc.c_q0 : kql;
+    const T qb = i == 0 ? X[6] : rl;
     return P::comp(i, ai, wrow, si, xv - xb, TZ, qa, qb, kqh, rh, X[0], X[6], X[8], L,
                    a.pc.p1ref);
   };
@@ -432,49 +465,96 @@ __device__ double rollout_fc9_group(const RollArgs<2, double>& a, int early, dou
     const uint32_t word = wq == 0 ? r.v[0] : (wq == 1 ? r.v[1] : (wq == 2 ? r.v[2] : r.v[3]));
     return box_draw(word, wlo, wsp);
   };
-  double xv = a.st->x[i];
+  T xv = (T)a.st->x[i];
   exch(xv);
-  double y[P::ny];
+  T y[P::ny];
   P::output(a.pc, L, X, y);
-  double best = margin_rows<P::ny>(a.F, a.g, y);
-  if (best != best) best = -INFINITY;
+  T best = margin_rows<P::ny>(a.F, a.g, y);
+  if (best != best) best = -t_inf<T>();
+  jbest = 0;
+  int ck_left = 0, ck_seg = 0;  // steps to the next checkpoint, its index
+  if constexpr (CKPT) {
+    if (ck) {
+      if (li < 9) a.ckpt[(size_t)i * a.N + k] = (float)xv;
+      ck_left = a.Kc;
+    }
+  }
   float wc = a.H > 0 ? load(0) : 0.0f, wn = 0.0f;
-  for (int j = 0; j < a.H; ++j) {
+  int j = 0;
+  bool stop_seen = false;  // dead flag read at the start of an 8-step block, tested at its end
+  for (; j < a.H; ++j) {
     if (j + 1 < a.H) wn = load(j + 1);
-    const double si = INJ == 0 ? (double)wc : 0.0;
-    double kk = eval(xv, si);
-    double acc = kk;
-    double xs = t_fma(a.hh, kk, xv);
+    if (WAVE && early && (j & 7) == 0)
+      stop_seen = __hip_atomic_load(stop_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    const T si = INJ == 0 ? (T)wc : (T)0;
+    T kk = eval(xv, si);
+    T acc = kk;
+    T xs = t_fma(a.hh, kk, xv);
     exch(xs);
     kk = eval(xs, si);
-    acc = t_fma(2.0, kk, acc);
+    acc = t_fma((T)2, kk, acc);
     xs = t_fma(a.hh, kk, xv);
     exch(xs);
     kk = eval(xs, si);
-    acc = t_fma(2.0, kk, acc);
+    acc = t_fma((T)2, kk, acc);
     xs = t_fma(a.h, kk, xv);
     exch(xs);
     kk = eval(xs, si);
     xv = t_fma(a.h6, acc + kk, xv);
-    if (INJ == 1) xv = xv + (double)wc;
+    if (INJ == 1) xv = xv + (T)wc;
     exch(xv);
     P::output(a.pc, L, X, y);
-    double m = margin_rows<P::ny>(a.F, a.g, y);
-    m = (m == m) ? m : -INFINITY;
-    if (m < best) best = m;
+    T m = margin_rows<P::ny>(a.F, a.g, y);
+    m = (m == m) ? m : -t_inf<T>();
+    if (m < best) {
+      best = m;
+      jbest = j + 1;
+    }
+    if constexpr (CKPT) {
+      if (ck && --ck_left == 0) {
+        ck_left = a.Kc;
+        ++ck_seg;
+        if (li < 9) a.ckpt[((size_t)ck_seg * P::n + i) * a.N + k] = (float)xv;
+      }
+    }
     if (early) {
-      if (best < -a.band) break;
-      if ((j & 31) == 31 && stop_flag) {
-        const bool f = __hip_atomic_load(stop_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-        if (__builtin_amdgcn_ballot_w64(f) & gmask) break;
+      if constexpr (WAVE) {
+        // every group of the wave evaluates the same candidate
+        const bool viol = best < -a.band;
+        if (__builtin_amdgcn_ballot_w64(viol) != 0) {
+          if (viol && li == 0)
+            __hip_atomic_store(stop_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          *stopped = true;
+          ++j;
+          break;
+        }
+        if ((j & 7) == 7 && __builtin_amdgcn_ballot_w64(stop_seen) != 0) {
+          *stopped = true;
+          ++j;
+          break;
+        }
+      } else {
+        if (best < -a.band) {
+          ++j;
+          break;
+        }
+        if ((j & 31) == 31 && stop_flag) {
+          const bool f =
+              __hip_atomic_load(stop_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+          if (__builtin_amdgcn_ballot_w64(f) & gmask) {
+            ++j;
+            break;
+          }
+        }
       }
     }
     wc = wn;
   }
+  nsteps = j;
   bool finite = true;
 #pragma unroll
-  for (int j = 0; j < 9; ++j) finite = finite && (X[j] - X[j] == 0.0);
-  if (!finite) best = -INFINITY;
+  for (int jj = 0; jj < 9; ++jj) finite = finite && (X[jj] - X[jj] == (T)0);
+  if (!finite) best = -t_inf<T>();
   return best;
 }
 
@@ -497,8 +577,10 @@ __device__ void recheck_fc9_groups(const RollArgs<2, double>& a, DevSearch* S, i
         a.early && (__hip_atomic_load(&S->dead[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
                     __hip_atomic_load(&S->fail64[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     if (__builtin_amdgcn_ballot_w64(skip) & gmask) continue;
-    const double m = rollout_fc9_group<RNG, INJ>(
-        a, a.early, S->v[c], k, t, a.early && q == 0 ? &S->fail64[c] : nullptr, slot, li, gmask);
+    int jb = 0, ns = 0;
+    const double m = rollout_fc9_group<double, RNG, INJ>(
+        a, a.early, S->v[c], k, t, a.early && q == 0 ? &S->fail64[c] : nullptr, slot, li, gmask,
+        jb, ns);
     if (li != 0) continue;
     atomicMin(&S->key64[c], ord64(m));
     if (q > 0) {
@@ -711,6 +793,60 @@ __global__ void __launch_bounds__(256) k_rollout(const RollArgs<KIND, T> a) {
   if (gen_rows<KIND>(a)) return;
   __shared__ unsigned long long sh[16];
   rollout_block<KIND, T, RNG, INJ, CKPT, CHANCE>(a, blockIdx.y, blockIdx.x, sh);
+}
+
+// 9-state FP32 rollouts with one scenario per group of 16 lanes
+// (rollout_fc9_group), robust verdict: blockIdx.y = candidate, 16 scenarios
+// per 256 lanes.  The per-scenario bookkeeping is rollout_block's, made by the
+// group's first lane; the margins equal the one-lane kernel's bit for bit.
+// CKPT = 1: the checkpoint candidate's groups store the adjoint's checkpoints.
+template <int RNG, int INJ, int CKPT>
+__global__ void __launch_bounds__(256) k_rollout_fc9_group(const RollArgs<2, float> a) {
+  if (gen_rows<2>(a)) return;
+  __shared__ unsigned long long sh[16];
+  __shared__ float2 xch[256];
+  DevSearch* S = a.srch;
+  const int c = blockIdx.y;
+  if (S->done || c >= S->n_cand) return;  // uniform over the workgroup
+  const bool ck = CKPT == 1 && c == (a.ckpt_cand >= 0 ? a.ckpt_cand : S->nk_idx);
+  const int early = a.early && !S->full[c];
+  if (refused_by_steady_state(early, S, c)) return;
+  const int li = threadIdx.x & 15;
+  const int k = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 4);
+  const unsigned long long gmask = 0xffffull << (threadIdx.x & 48);
+  const uint32_t t = a.st->t;
+  float m = INFINITY;
+  int jb = 0, ns = 0;
+  if (k < a.N) {  // whole groups are active or inactive together
+    bool stopped = false;  // the candidate died while this wave ran (no recheck needed)
+    m = rollout_fc9_group<float, RNG, INJ, true, CKPT>(a, early, (float)S->v[c], k, t, &S->dead[c],
+                                                       xch + (threadIdx.x & ~15u), li, gmask, jb,
+                                                       ns, ck, &stopped);
+    if (li == 0) {
+      if (a.record) {
+        a.per_m[(size_t)c * a.N + k] = m;
+        a.per_j[(size_t)c * a.N + k] = jb;
+      }
+      if (m < -a.band) {
+        __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else if (m < a.band && !stopped) {
+        const int idx = atomicAdd(&S->n_recheck, 1);
+        a.rlist[idx] = make_int2(c, k);
+      }
+    }
+  }
+  const bool own = li == 0 && k < a.N;
+  const unsigned long long key = own ? lane_key(m, k) : ~0ull;
+  const unsigned long long kall = block_min_u64(key, sh);
+  const unsigned long long kfar = block_min_u64((own && m >= a.band) ? key : ~0ull, sh);
+  int wsum = li == 0 ? ns : 0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off);
+  if ((threadIdx.x & 63) == 0) atomicAdd(&S->lane_steps, (unsigned long long)wsum);
+  if (threadIdx.x == 0) {
+    atomicMin(&S->key_all[c], kall);
+    if (kfar != ~0ull) atomicMin(&S->key_far[c], kfar);
+  }
 }
 
 // Batched serving: one launch per search round covers every instance of a
@@ -2999,6 +3135,27 @@ hipError_t launch_rollout(const Problem& pr, double band, int precision, int ear
             hipLaunchKernelGGL((k_rollout_lq4_quad<R, I, D, 0>), grid, dim3(cfg.block), 0, st, a, qc);
           return hipGetLastError();
         });
+      });
+    });
+  }
+  if (cfg.lanes == 16 && precision == 0 && pr.p.kind == 2 && !cfg.chance && !(ckpt && cfg.tan)) {
+    // 9-state plant, one scenario per group of 16 lanes
+    const int gx = div_up((size_t)pr.s.N * 16, (size_t)cfg.block);
+    const dim3 grid(gx, cfg.cmax_round + gen_rows_for((size_t)gx * cfg.block));
+    auto a = make_args<2, float>(pr, band, early_exit, record, b);
+    a.ckpt = b.adj_ckpt;
+    a.Kc = Kc;
+    a.ckpt_cand = ckpt_cand;
+    set_gen(a);
+    return by_bit(pr.s.rng_mode, [&](auto rc) {
+      constexpr int R = decltype(rc)::value;
+      return by_bit(pr.s.inject, [&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        if (ckpt)
+          hipLaunchKernelGGL((k_rollout_fc9_group<R, I, 1>), grid, dim3(cfg.block), 0, st, a);
+        else
+          hipLaunchKernelGGL((k_rollout_fc9_group<R, I, 0>), grid, dim3(cfg.block), 0, st, a);
+        return hipGetLastError();
       });
     });
   }
