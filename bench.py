@@ -343,6 +343,11 @@ def run_more_extras(rg, W, np, torch):
     ga.close()
     gb.close()
     out["batch_1024_lq4_fc9"] = run_batch(rg, W, np, torch)
+    # points of the paper-shaped sweep (bench.py --paper-sweep runs all 288)
+    ns = [1, 32, 256, 512, 1024, 1312, 2048, 4096, 8192]
+    out["paper_sweep_fc9_grid_m32_h1024"] = {
+        "rows": paper_sweep_rows(ns, [("streamed_ms", rg.RNG_STREAM)], log_every=1 << 30),
+        "timing": "median of five blocking rg_step calls after one warm-up, fresh handle per N"}
     return out
 
 
@@ -390,43 +395,57 @@ def run_batch(rg, W, np, torch, steps=2):
             "sum_N_x_H": float(np.sum(NH)), "depth_instance0": int(depth)}
 
 
-def run_paper_sweep(args):
-    """Shape of the paper's GPU timing experiment (Sec. IV-B): the 9-state plant
-    with the grid search of Alg. 3 (M = 32 points, no refinement), H = 1024,
-    dt = 0.01, N = 1..32 and 32..8192 in steps of 32; per N the median of five
-    blocking RG steps with the draws generated into device memory first
-    (streamed) and with the draws generated inside the rollout lanes (inline).
-    Prints one JSON line."""
+def paper_sweep_rows(Ns, modes, reps=6, log_every=1024):
+    """RG-step time of the 9-state grid search (Alg. 3, M = 32 points, no
+    refinement), H = 1024, dt = 0.01, from the nominal equilibrium of v = 0.5
+    towards r = 2.0, for each N in Ns: a fresh handle per N and draw mode, the
+    median of reps - 1 blocking steps after one warm-up."""
     import numpy as np
     import torch
 
     from paper_2510_08288_amd import rg, workloads as W
 
-    Ns = list(range(1, 33)) + list(range(64, 8193, 32))
     rows = []
     x0 = None
     for N in Ns:
         p = W.fc9_problem(N=N, H=1024, dt=0.01)
         row = {"N": N}
-        for label, mode in [("streamed_ms", rg.RNG_STREAM), ("inline_ms", rg.RNG_INLINE)]:
+        for label, mode in modes:
             g = rg.Governor(p, search=rg.SEARCH_GRID, M=32, refine=0, rng_mode=mode)
             if x0 is None:
                 x0 = g.equilibrium(0.5)
             times = []
-            for rep in range(6):
+            for rep in range(reps):
                 g.set_step(0)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 res = g.step(x0, 2.0, 0.5)
                 times.append(time.perf_counter() - t0)
+            row["lanes"] = int(g.options.lanes)
             g.close()
             row[label] = float(np.median(times[1:])) * 1e3
             row["kappa"] = res["kappa"]
+            row["rechecks"] = res["rechecks"]
         # every N has workspaces of its own size: hand them back to the device
         torch.cuda.empty_cache()
         rows.append(row)
-        if N % 1024 == 0 or N == 32:
+        if N % log_every == 0 or N == 32:
             progress(f"paper sweep N={N}: {row}")
+    return rows
+
+
+def run_paper_sweep(args):
+    """Shape of the paper's GPU timing experiment (Sec. IV-B): the 9-state plant
+    with the grid search of Alg. 3 (M = 32 points, no refinement), H = 1024,
+    dt = 0.01, N = 1..32 and 32..8192 in steps of 32 (or the --sweep-n list);
+    per N the median of five blocking RG steps with the draws generated into
+    device memory first (streamed) and with the draws generated inside the
+    rollout lanes (inline).  Prints one JSON line."""
+    from paper_2510_08288_amd import rg
+
+    Ns = ([int(n) for n in args.sweep_n.split(",")] if args.sweep_n
+          else list(range(1, 33)) + list(range(64, 8193, 32)))
+    rows = paper_sweep_rows(Ns, [("streamed_ms", rg.RNG_STREAM), ("inline_ms", rg.RNG_INLINE)])
     print(json.dumps({"workload": "fc9_grid_m32_h1024_dt0.01", "rows": rows}))
 
 
@@ -464,6 +483,7 @@ def main():
     ap.add_argument("--paper-sweep", action="store_true",
                     help="only the paper-shaped sweep of RG-step time against N (9-state grid, "
                          "M = 32) and exit")
+    ap.add_argument("--sweep-n", default="", help="comma-separated N list for --paper-sweep")
     ap.add_argument("--extra-updates", type=int, default=3,
                     help="updates timed per form on the 9-state workloads")
     ap.add_argument("--no-extras", action="store_true",

@@ -159,7 +159,7 @@ typedef struct rg_options {
                               lanes); 16 for FC9 (one scenario per group of 16 lanes, one
                               lane per state component; not with the tangent-driven Newton
                               search); 0 = auto (LQ4: 4; FC9: 16 while a round holds at
-                              most 16384 scenario-candidate pairs, else 1).  Margins are
+                              most 32768 scenario-candidate pairs, else 1).  Margins are
                               bit-identical across layouts */
     int32_t Kc;            /* adjoint checkpoint interval in RK4 steps (default 50) */
     int32_t persistent_wgs;/* batches: workgroups of the persistent rollout kernel (0 = auto) */

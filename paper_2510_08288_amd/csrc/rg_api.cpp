@@ -157,11 +157,15 @@ Layout layout_of(const rg_handle* h) {
   return L;
 }
 
-// Scenario-candidate pairs of one round below which the 9-state FP32 rollouts
+// Scenario-candidate pairs of one round up to which the 9-state FP32 rollouts
 // run one scenario per group of 16 lanes (auto lanes): one lane per scenario
 // leaves the chip mostly idle there and each round is bound by the latency of
-// a whole RK4 step on one lane.
-constexpr double kGroupPairsMax = 16384;
+// a whole RK4 step on one lane; with more pairs the groups' extra instructions
+// (exchanges, lanes 9..15) cost more than the latency they save (measured:
+// the 32-point grid at H = 1024 is 2.7x faster with groups at 16384 pairs,
+// 2.0x at 32768, slower from about 100000; the adjoint Newton search 1.7x
+// faster at N = 4096 and 10 % slower at N = 16384).
+constexpr double kGroupPairsMax = 32768;
 
 int lanes_for(const rg_handle* h) {
   const bool f32_robust = h->opt.precision == RG_PREC_F32_RECHECK && h->opt.chance_q == 0;
