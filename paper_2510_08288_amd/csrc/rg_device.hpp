@@ -295,6 +295,7 @@ struct Plant<2, T> {
   struct Lane {
     T a[9], kq[6], b[3], mu[2];
     T v;
+    const T* W;  // the coupling matrix the derivative reads (c.W, or a copy in registers)
   };
   __host__ __device__ static const T* nominal_theta(const Coef& c) { return c.thnom; }
   static void load(Coef& c, const double* s) {
@@ -317,6 +318,7 @@ struct Plant<2, T> {
     L.mu[0] = th[18];
     L.mu[1] = th[19];
     L.v = v;
+    L.W = c.W;
   }
   __device__ static void force(const Coef&, const Lane&, const T* w, T* s) {
 #pragma unroll
@@ -371,7 +373,7 @@ struct Plant<2, T> {
       const T qb = i == 0 ? x[6] : (i < 6 ? r[i > 0 ? i - 1 : 0] : (T)0);
       const T qk = i < 6 ? L.kq[i < 6 ? i : 0] : (T)0;
       const T qr = i < 6 ? r[i < 6 ? i : 0] : (T)0;
-      xd[i] = comp(i, L.a[i], &c.W[9 * i], s[i], z[i], tz, qa, qb, qk, qr, x[0], x[6], x[8], L,
+      xd[i] = comp(i, L.a[i], &L.W[9 * i], s[i], z[i], tz, qa, qb, qk, qr, x[0], x[6], x[8], L,
                    c.p1ref);
     }
   }
@@ -398,7 +400,7 @@ struct Plant<2, T> {
     for (int j = 0; j < 9; ++j) {
       T acc = 0;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) acc = t_fma(c.W[9 * i + j], al[i], acc);
+      for (int i = 0; i < 9; ++i) acc = t_fma(L.W[9 * i + j], al[i], acc);
       xb[j] = t_fma(-L.a[j], al[j], acc * (1 - tz[j] * tz[j]));
       tb[j] += -(double)al[j] * (double)z[j];
     }
@@ -453,7 +455,7 @@ struct Plant<2, T> {
     for (int i = 0; i < 9; ++i) {
       T a = -L.a[i] * dx[i];
 #pragma unroll
-      for (int j = 0; j < 9; ++j) a = t_fma(c.W[9 * i + j], sd[j], a);
+      for (int j = 0; j < 9; ++j) a = t_fma(L.W[9 * i + j], sd[j], a);
       T dphi;
       if (i < 6) dphi = dq[i] - dq[i + 1];
       else if (i == 6) dphi = L.b[0] - L.mu[0] * (dx[6] * (x[0] - c.p1ref) + x[6] * dx[0]);

@@ -182,6 +182,39 @@ __device__ __forceinline__ bool gen_rows(const A& a) {
   return true;
 }
 
+// A float or double moved between lanes by DPP (CTRL: quad permutations, row
+// shifts), 0 where the source lane lies outside the row.
+template <int CTRL>
+__device__ __forceinline__ float dpp_row(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL,
+                                                               0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_row(double x) {
+  return dpp64<CTRL>(x);
+}
+
+// 9-state plant: a copy of the coupling matrix W in vector registers (identity
+// DPP moves make the copies lane values), which the derivative then reads: 81
+// uniform values beside the other coefficients exceed the scalar registers, and
+// spilled scalars are restored at every use (a sixth of the one-lane FP32 loop).
+template <int KIND, class T, class Coef, class Lane>
+__device__ __forceinline__ void w_in_vgprs(const Coef& pc, T* wv, Lane& L) {
+  if constexpr (KIND == 2) {
+#pragma unroll
+    for (int c = 0; c < 81; ++c) wv[c] = dpp_row<0xE4>(pc.W[c]);
+    L.W = wv;
+  }
+}
+
 // Forward declarations: the recheck kernels end with the round's decision.
 template <int KIND>
 __device__ void decide_body(const typename Plant<KIND, double>::Coef& pc, const DevState* st,
@@ -202,7 +235,8 @@ __device__ void true_plant_step(const RollArgs<KIND, double>& a, const double* x
 // wave stops as soon as any of its lanes sees one, and raises the flag at once
 // for the other waves (which read it every 8 steps).  Without WAVE, lanes
 // stop on their own and stop_flag is only read.
-template <int KIND, class T, int RNG, int INJ, class A, int CKPT = 0, bool WAVE = false>
+template <int KIND, class T, int RNG, int INJ, class A, int CKPT = 0, bool WAVE = false,
+          bool WREG = false>
 __device__ __forceinline__ T rollout_lane(const A& a, int early, T v, int k, uint32_t t,
                                           int32_t* stop_flag, int& jbest, int& nsteps,
                                           double* traj, bool ck = false,
@@ -223,6 +257,9 @@ __device__ __forceinline__ T rollout_lane(const A& a, int early, T v, int k, uin
   }
   typename P::Lane L;
   P::lane_init(a.pc, th, v, L);
+  // WREG (the FP32 rollout kernels): W in vector registers
+  T wv[KIND == 2 && WREG ? 81 : 1];
+  if constexpr (WREG) w_in_vgprs<KIND>(a.pc, wv, L);
   T x[P::n];
 #pragma unroll
   for (int i = 0; i < P::n; ++i) x[i] = (T)a.st->x[i];
@@ -344,26 +381,6 @@ __device__ __forceinline__ T rollout_lane(const A& a, int early, T v, int k, uin
 // (over the wave with WAVE): every branch depends on exchanged values or on a
 // ballot.
 // ---------------------------------------------------------------------------
-// A float or double moved between lanes by DPP (CTRL: quad permutations, row
-// shifts), 0 where the source lane lies outside the row.
-template <int CTRL>
-__device__ __forceinline__ float dpp_row(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL,
-                                                               0xf, 0xf, true));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp64(double x) {
-  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, true);
-  return __builtin_bit_cast(double, ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_row(double x) {
-  return dpp64<CTRL>(x);
-}
-
 __device__ __forceinline__ void group_sync() {
   // The group is part of one wave, whose LDS accesses complete in program
   // order; this only keeps the compiler from moving them across.
@@ -755,11 +772,13 @@ __device__ __forceinline__ void rollout_block(const RollArgs<KIND, T>& a, const 
       }
     } else if constexpr (CHANCE) {
       // a violating lane stops alone; the candidate dies once more than q did
-      m = rollout_lane<KIND, T, RNG, INJ, RollArgs<KIND, T>, CKPT, false>(
+      m = rollout_lane<KIND, T, RNG, INJ, RollArgs<KIND, T>, CKPT, false,
+                       std::is_same<T, float>::value>(
           a, early, (T)S->v[c], k, t, early ? &S->dead[c] : nullptr, jb, ns, nullptr, ck);
       a.per_key[(size_t)c * a.N + k] = ord64((double)m);
     } else {
-      m = rollout_lane<KIND, T, RNG, INJ, RollArgs<KIND, T>, CKPT, true>(
+      m = rollout_lane<KIND, T, RNG, INJ, RollArgs<KIND, T>, CKPT, true,
+                       std::is_same<T, float>::value>(
           a, early, (T)S->v[c], k, t, &S->dead[c], jb, ns, nullptr, ck, &stopped);
     }
     if (a.record) {
@@ -2421,6 +2440,8 @@ __global__ void __launch_bounds__(64) k_adjoint(const RollArgs<KIND, float> a, c
   }
   typename P::Lane Ln;
   P::lane_init(a.pc, th, v, Ln);
+  float wv[KIND == 2 ? 81 : 1];
+  w_in_vgprs<KIND>(a.pc, wv, Ln);
   const float* wb = RNG == 0 ? step_w(a, t) : nullptr;
   auto load_w = [&](int j, float* w) {
     if (RNG == 0) {
