@@ -126,3 +126,26 @@ def test_auto_lanes_choose_groups_for_small_rounds(R):
     assert (small.options.lanes, large.options.lanes, tan.options.lanes) == (16, 1, 1)
     for g in (small, large, tan):
         g.close()
+
+
+@pytest.mark.parametrize("N,H", [(1, 1), (1, 200), (17, 3), (257, 5), (33, 150)])
+def test_fp32_groups_edge_sizes(R, oracle_mod, N, H):
+    # one group, ragged workgroups (16 scenarios per 256 lanes), short horizons
+    p = W.fc9_problem(N=N, H=H, dt=0.002)
+    x0 = W.FC9_XBAR + np.array([0.05, -0.04, 0.03, 0.0, -0.02, 0.01, 0.08, 0.0, -0.05])
+    kap = np.array([0.1, 0.7])
+    print(f"[groups] edge N={N} H={H}", flush=True)
+    out = {}
+    for lanes in (1, 16):
+        g = R.Governor(p, lanes=lanes)
+        out[lanes] = g.margin(x0, 1.9, 0.5, kap, per_scenario=True)
+        g.close()
+    assert np.array_equal(out[1]["per_scenario"], out[16]["per_scenario"])
+    assert np.array_equal(out[1]["margins"], out[16]["margins"])
+    o = oracle_mod.Oracle(p, nthreads=4)
+    xs = o.steady_margin(0.5)[1]
+    g = R.Governor(p, lanes=16)
+    res = g.step(xs, 1.9, 0.5)
+    g.close()
+    ref = o.bisect(xs, 1.9, 0.5, 0, 12)
+    assert res["kappa"] == ref["kappa"] and res["status"] == ref["status"]
