@@ -149,3 +149,23 @@ def test_fp32_groups_edge_sizes(R, oracle_mod, N, H):
     g.close()
     ref = o.bisect(xs, 1.9, 0.5, 0, 12)
     assert res["kappa"] == ref["kappa"] and res["status"] == ref["status"]
+
+
+def test_flat_recheck_wide_band_both_layouts(R, oracle_mod):
+    # batched serving: a band wider than every margin makes the FP64 recheck
+    # give every verdict; with one candidate per round the instances with at
+    # most 8 entries run the group form of the flat recheck, the N = 40
+    # instance the one-lane form.  kappa must be the FP64 oracle's.
+    Ns = [2, 3, 4, 40]
+    probs = [W.fc9_problem(N=N, H=300, dt=0.002, scen_seed=300 + i, instance=i)
+             for i, N in enumerate(Ns)]
+    x0 = oracle_mod.Oracle(probs[0]).steady_margin(0.5)[1]
+    xs, rs, vps = [x0] * len(Ns), [1.9, 1.7, 1.5, 1.9], [0.5] * len(Ns)
+    print("[groups] flat recheck, wide band, N =", Ns, flush=True)
+    b = R.Batch(probs, band=50.0, depth=1)
+    out = b.step(xs, rs, vps, use_graph=False)
+    b.close()
+    for i, p in enumerate(probs):
+        ref = oracle_mod.Oracle(p, nthreads=8).bisect(xs[i], rs[i], vps[i], 0, 12)
+        assert out["kappa"][i] == ref["kappa"], (i, out["kappa"][i], ref["kappa"])
+        assert out["status"][i] == ref["status"]
