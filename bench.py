@@ -490,7 +490,7 @@ def main():
                     help="skip the other workloads and the alternative search forms")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default schedule instead of the autotuned one")
-    ap.add_argument("--tune-steps", type=int, default=50,
+    ap.add_argument("--tune-steps", type=int, default=200,
                     help="closed-loop updates the autotuner times each schedule on")
     ap.add_argument("--autotune-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",

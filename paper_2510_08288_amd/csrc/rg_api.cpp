@@ -76,6 +76,20 @@ int32_t spec_allowed(const rg_handle* h) {
   return ok ? h->opt.speculate : 0;
 }
 
+// Later steps a held step speculates on: each adds a whole first round (the
+// probe and K midpoints) within the candidates of one round.  Held rounds are
+// already two-thirds throughput-bound (many candidates die early, the small
+// ones run long), so one step ahead pays and more do not (200-update bench
+// loop: 0.292 ms per update without, 0.276 with one step, 0.283 with two,
+// 0.286 with three).
+constexpr int32_t kHoldMax = 1;
+int32_t hold_allowed(const rg_handle* h) {
+  int32_t d = spec_allowed(h);
+  if (d > kHoldMax) d = kHoldMax;
+  while (d > 0 && (1 + h->opt.K) * (1 + d) > kCMax) --d;
+  return d;
+}
+
 void drop_graphs(rg_handle* h) {
   for (hipGraphExec_t& g : h->round_graph) {
     if (g) (void)hipGraphExecDestroy(g);
@@ -240,11 +254,15 @@ void plan_with(rg_handle* h, int lanes) {
   // a probe-only round 0 holds the probe and the probes of the next steps
   const int sp = spec_allowed(h);
   if (1 + sp > h->cfg.cmax_round) h->cfg.cmax_round = 1 + sp;
+  // a held step's round 0 holds its own first round and those of the next steps
+  const int hd = hold_allowed(h);
+  if (hd > 0 && (1 + h->opt.K) * (1 + hd) > h->cfg.cmax_round)
+    h->cfg.cmax_round = (1 + h->opt.K) * (1 + hd);
 }
 
 // Search record of a fresh handle: configuration, no step in progress, no
 // prediction, empty steady-state cache.
-void fill_search(const rg_handle* h, DevSearch* S, int32_t spec_depth) {
+void fill_search(const rg_handle* h, DevSearch* S, int32_t spec_depth, int32_t spec_hold) {
   memset(S, 0, sizeof(DevSearch));
   S->mode = h->opt.search == RG_SEARCH_GRID ? kGrid
             : is_newton(h->opt.search) ? kNewton : kBisect;
@@ -265,6 +283,7 @@ void fill_search(const rg_handle* h, DevSearch* S, int32_t spec_depth) {
   S->done = 1;
   for (int i = 0; i < kMssCache; ++i) S->mss_v[i] = std::nan("");  // empty cache
   S->spec_depth = spec_depth;
+  S->spec_hold = spec_hold;
   S->spec_n = 0;
   S->spec_used = 0;
   S->band = h->opt.band;
@@ -320,7 +339,7 @@ int ensure_workspace(rg_handle* h) {
   b.seg_ct = (double*)(base + L.seg_ct);
   b.seg_scr = (float*)(base + L.seg_scr);
   // Search configuration.
-  fill_search(h, h->srch_tmpl, spec_allowed(h));
+  fill_search(h, h->srch_tmpl, spec_allowed(h), hold_allowed(h));
   hipError_t e =
       hipMemcpyAsync(b.srch, h->srch_tmpl, sizeof(DevSearch), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -608,7 +627,7 @@ int rg_step_noalloc(rg_handle* h, const double* x, double r, double v_prev, doub
   pr.s.rng_mode = RG_RNG_INLINE;
   // every call starts from a fresh search record: the array keeps whatever the
   // last call on this GPU (any handle) left in it
-  fill_search(h, h->srch_tmpl, 0);
+  fill_search(h, h->srch_tmpl, 0, 0);
   DevState s;
   memset(&s, 0, sizeof(s));
   for (int i = 0; i < h->pr.p.n; ++i) s.x[i] = x[i];
@@ -1146,9 +1165,10 @@ namespace {
 // Reset the device search record's schedule fields and prediction state.
 int reset_search_schedule(rg_handle* h) {
   if (h->ws_ready) {
-    const int32_t spec[3] = {spec_allowed(h), 0, 0};  // spec_depth, spec_n, spec_used
-    static_assert(offsetof(DevSearch, spec_used) == offsetof(DevSearch, spec_depth) + 8,
-                  "spec_depth, spec_n and spec_used are adjacent");
+    // spec_depth, spec_hold, spec_kind, spec_base, spec_per, spec_n, spec_used
+    const int32_t spec[7] = {spec_allowed(h), hold_allowed(h), 0, 0, 0, 0, 0};
+    static_assert(offsetof(DevSearch, spec_used) == offsetof(DevSearch, spec_depth) + 24,
+                  "the speculation fields are adjacent");
     HIPCHK(h, hipMemcpyAsync((char*)h->b.srch + offsetof(DevSearch, spec_depth), spec, sizeof(spec),
                              hipMemcpyHostToDevice, h->stream));
     const int32_t depth = h->opt.depth;
@@ -1456,7 +1476,7 @@ int batch_ensure_memory(rg_batch* bt) {
     h->ws = bt->mem;  // carved from the batch's allocation: never freed by the handle
     h->ws_owned = false;
     h->ws_ready = true;
-    fill_search(h, &tmpl[i], 0);
+    fill_search(h, &tmpl[i], 0, 0);
   }
   const hipStream_t ms = bt->stream ? bt->stream : bt->own_stream;
   e = hipMemcpyAsync(srch, tmpl.data(), sizeof(DevSearch) * count, hipMemcpyHostToDevice, ms);

@@ -77,12 +77,21 @@ struct DevSearch {
   // Workgroups of the current recheck launch that have finished; the last one
   // takes the round's decision and resets the count.
   uint32_t blocks_done;
-  // Closed loop, probe-only round 0: candidates 1..spec_n are the kappa = 1
-  // probes of the next spec_n steps, candidate j simulated from x_spec[j - 1],
-  // the state step t + j starts in if steps t..t + j - 1 all have kappa = 1,
-  // under the draws of step t + j.  The following steps consume them in order.
-  int32_t spec_depth;                 // allowed speculation depth (set by the host)
-  int32_t spec_n;                     // probes of later steps run in the last live round
+  // Closed loop, round 0 speculating on the next spec_n steps: candidates
+  // spec_base + (j - 1) * spec_per .. + spec_per - 1 belong to step t + j,
+  // simulated from x_spec[j - 1] under the draws of step t + j.  spec_kind 1:
+  // the previous kappa was 1, step t + j's kappa = 1 probe alone (spec_per = 1),
+  // from the state it starts in if steps t..t + j - 1 all take kappa = 1.
+  // spec_kind 2: the previous kappa was 0 (the governor holds v), step t + j's
+  // whole first round (the probe and the K midpoints towards 0, spec_per =
+  // 1 + K), from the state it starts in if steps t..t + j - 1 all hold v.  The
+  // following steps consume them in order while the assumption holds.
+  int32_t spec_depth;                 // allowed depth of kappa = 1 speculation (set by the host)
+  int32_t spec_hold;                  // allowed depth of hold speculation (set by the host)
+  int32_t spec_kind;                  // 1: kappa = 1 probes, 2: holds
+  int32_t spec_base;                  // first speculative candidate
+  int32_t spec_per;                   // speculative candidates per later step
+  int32_t spec_n;                     // later steps speculated on in the last live round
   int32_t spec_used;                  // of those, consumed by the steps since
   double r_spec[kSpecMax];            // their references
   double x_spec[kSpecMax][kMaxN];     // their start states

@@ -726,6 +726,13 @@ __device__ __forceinline__ unsigned long long block_min_u64(unsigned long long v
   return v;
 }
 
+// Step offset of candidate c: 0 for the step's own candidates, j for a
+// speculative candidate of step t + j (closed loop, round 0).
+__device__ __forceinline__ int cand_step(const DevSearch* S, int c) {
+  const int r = c - S->spec_base;
+  return (S->spec_n > 0 && r >= 0 && r < S->spec_n * S->spec_per) ? 1 + r / S->spec_per : 0;
+}
+
 // In decision mode a candidate whose FP64 steady-state test already fails is
 // refused without simulating it (the verdict of Alg. 1 needs both tests).
 // bx: the workgroup's scenario tile (tile 0 raises the flag).
@@ -992,8 +999,8 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
   __shared__ unsigned long long sh[16];
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = gid >> 2, q = gid & 3;
-  // speculative probe of step t + sj (sj >= 1): its own start state and draws
-  const int sj = (c >= 1 && c <= S->spec_n) ? c : 0;
+  // speculative candidate of step t + sj (sj >= 1): its own start state and draws
+  const int sj = cand_step(S, c);
   const bool spec = sj > 0;
   const uint32_t t = a.st->t + (uint32_t)sj;
   const float* wsrc = step_w(a, t);  // speculative probes exist only in the closed loop (ring)
@@ -1673,7 +1680,7 @@ template <int KIND>
 __device__ void prepare_candidates(const typename Plant<KIND, double>::Coef& pc, const DevState* st,
                                    DevSearch* S) {
   const double r = st->r, vp = st->v_prev;
-  __shared__ double s_cv[kMssCache], s_cm[kMssCache];
+  __shared__ double s_cv[kMssCache], s_cm[kMssCache], s_v[kCMax];
   __shared__ int s_miss[kCMax];
   for (int i = threadIdx.x; i < kMssCache; i += blockDim.x) {
     s_cv[i] = S->mss_v[i];
@@ -1683,7 +1690,10 @@ __device__ void prepare_candidates(const typename Plant<KIND, double>::Coef& pc,
   const int n = S->n_cand;
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
     if (S->mode != kNewton) S->full[c] = 0;
-    const double v = (c >= 1 && c <= S->spec_n) ? S->r_spec[c - 1] : cand_v(S->kappa[c], r, vp);
+    // a speculative candidate of step t + j: that step's reference; its v_prev
+    // is this step's (holds), or any (kappa = 1 gives v = r)
+    const int sj = cand_step(S, c);
+    const double v = cand_v(S->kappa[c], sj ? S->r_spec[sj - 1] : r, vp);
     S->v[c] = v;
     int hit = -1;
     for (int i = 0; i < kMssCache; ++i) {
@@ -1693,7 +1703,10 @@ __device__ void prepare_candidates(const typename Plant<KIND, double>::Coef& pc,
       }
     }
     S->mss[c] = hit >= 0 ? s_cm[hit] : steady_margin<KIND>(pc, S, v);
-    if (c < kCMax) s_miss[c] = hit < 0;
+    if (c < kCMax) {
+      s_miss[c] = hit < 0;
+      s_v[c] = v;
+    }
     S->key_all[c] = ~0ull;
     S->key_far[c] = ~0ull;
     S->key64[c] = ~0ull;
@@ -1709,9 +1722,9 @@ __device__ void prepare_candidates(const typename Plant<KIND, double>::Coef& pc,
     int next = S->mss_next;
     for (int c = 0; c < n && c < kCMax; ++c) {
       if (!s_miss[c]) continue;
-      const double v = S->v[c];
+      const double v = s_v[c];
       bool dup = false;  // the same set-point twice in one round
-      for (int e = 0; e < c; ++e) dup = dup || (s_miss[e] && S->v[e] == v);
+      for (int e = 0; e < c; ++e) dup = dup || (s_miss[e] && s_v[e] == v);
       if (dup) continue;
       S->mss_v[next] = v;
       S->mss_m[next] = S->mss[c];
@@ -1728,24 +1741,55 @@ __device__ void setup_body(const typename Plant<KIND, double>::Coef& pc, DevStat
                            const RollArgs<KIND, double>* pa = nullptr) {
   if (threadIdx.x == 0) {
     if (closed_loop) st->r = r_seq[st->cl_index];
-    // Was this step's kappa = 1 probe already evaluated by an earlier round
-    // (speculatively, from the state this step starts in when the steps before
-    // it all have kappa = 1)?  Its verdict counts only if the previous kappa
-    // was 1 and every scenario of the probe kept an FP32 margin of at least
-    // the band (no FP64 recheck needed); Alg. 1 then returns kappa = 1 on its
-    // first evaluation.
+    // Was this step's first round already evaluated by an earlier round
+    // (speculatively, from the state this step starts in if the steps before
+    // it did as assumed)?  A speculative candidate never gets an FP64 recheck,
+    // so its verdict counts only when it is certain without one: refused by a
+    // lane below -band or by the steady-state test, or admitted with every
+    // scenario's FP32 margin at least the band.  The result is then the one
+    // Alg. 1 reaches from those verdicts: kappa = 1 if the probe is admitted;
+    // after holds, kappa = 0 if the probe and every midpoint towards 0 are
+    // refused, or 2^-K if only the last is admitted.
     bool decided = false;
-    double spec_worst = 0.0;
-    if (closed_loop && S->spec_used < S->spec_n) {
-      const int c = 1 + S->spec_used;
-      const double kall =
-          S->key_all[c] == ~0ull ? INFINITY : key_margin(S->key_all[c], S->precision);
-      if (S->done && S->kappa_res == 1.0 && !S->dead[c] && !S->fail64[c] && S->mss[c] >= 0.0 &&
-          kall >= S->band) {
+    int spec_found = 0, spec_passes = 0;
+    double spec_kappa = 0.0, spec_worst = -INFINITY;
+    if (closed_loop && S->done && S->spec_used < S->spec_n) {
+      const int base = S->spec_base + S->spec_used * S->spec_per;
+      auto kall_of = [&](int c) {
+        return S->key_all[c] == ~0ull ? INFINITY : key_margin(S->key_all[c], S->precision);
+      };
+      auto verdict = [&](int c) {  // 1 admitted, 0 refused, -1 not certain
+        if (S->fail64[c]) return -1;
+        if (S->dead[c] || S->mss[c] < 0.0) return 0;
+        return kall_of(c) >= S->band ? 1 : -1;
+      };
+      auto admit = [&](int c, int passes) {
         decided = true;
+        spec_found = 1;
+        spec_kappa = S->kappa[c];
+        const double kall = kall_of(c);
         spec_worst = kall < S->mss[c] ? kall : S->mss[c];
-        S->spec_used += 1;
+        spec_passes = passes;
+      };
+      if (S->spec_kind == 1) {
+        if (S->kappa_res == 1.0 && verdict(base) == 1) admit(base, 1);
+      } else if (S->kappa_res == 0.0) {  // the previous step held v
+        const int vb = verdict(base);
+        if (vb == 1) {
+          admit(base, 1);
+        } else if (vb == 0) {
+          const int K = S->K;
+          int l = 1;
+          while (l <= K && verdict(base + l) == 0) ++l;
+          if (l > K) {
+            decided = true;
+            spec_passes = 1 + K;
+          } else if (l == K && verdict(base + K) == 1) {
+            admit(base + K, 1 + K);
+          }
+        }
       }
+      if (decided) S->spec_used += 1;
     }
     if (!decided) {
       S->spec_n = 0;
@@ -1770,13 +1814,14 @@ __device__ void setup_body(const typename Plant<KIND, double>::Coef& pc, DevStat
     S->flags = 0;
     if (decided) {
       S->done = 1;
-      S->found = 1;
-      S->lo = 1.0;
-      S->kappa_res = 1.0;
-      S->pred = 1.0;
-      S->v_res = st->r;  // cand_v at kappa = 1
+      S->found = spec_found;
+      S->status = spec_found ? 0 : 1;
+      S->lo = spec_kappa;
+      S->kappa_res = spec_kappa;
+      S->pred = spec_kappa;
+      S->v_res = spec_found ? cand_v(spec_kappa, st->r, st->v_prev) : st->v_prev;
       S->worst_res = spec_worst;
-      S->passes_alg1 = 1;
+      S->passes_alg1 = spec_passes;
       S->n_cand = 0;
     } else if (S->mode == kNewton) {
       S->kappa[0] = 1.0;  // probe, carries the first derivative
@@ -1819,9 +1864,12 @@ __device__ void setup_body(const typename Plant<KIND, double>::Coef& pc, DevStat
             const double rp = j == 1 ? st->r : S->r_spec[j - 2];
             true_plant_step<KIND>(*pa, xp, rp, st->t + (uint32_t)(j - 1), S->x_spec[j - 1]);
             S->r_spec[j - 1] = r_seq[st->cl_index + j];
-            S->kappa[j] = -1.0;  // equals no midpoint: the walk never reads it
+            S->kappa[j] = 1.0;  // a later step's probe (the walk reads own candidates only)
           }
           if (d > 0) {
+            S->spec_kind = 1;
+            S->spec_base = 1;
+            S->spec_per = 1;
             S->spec_n = d;
             S->spec_used = 0;
             S->n_cand = 1 + d;
@@ -1835,6 +1883,34 @@ __device__ void setup_body(const typename Plant<KIND, double>::Coef& pc, DevStat
             else hi = m;
           }
           S->n_cand = 1 + S->K;
+          // The governor held v (kappa = 0): the round also runs the first
+          // rounds of the next steps (probe and midpoints towards 0), from the
+          // states they start in if they hold v too (the same FP64 true-plant
+          // steps as the result launch), under their draws.  Their tails run
+          // beside this step's on SIMDs the step alone leaves idle.
+          int d = pa && closed_loop && pr == 0.0 ? S->spec_hold : 0;
+          if (d > st->cl_len - 1 - st->cl_index) d = st->cl_len - 1 - st->cl_index;
+          const int per = 1 + S->K;
+          for (int j = 1; j <= d; ++j) {
+            const double* xp = j == 1 ? st->x : S->x_spec[j - 2];
+            true_plant_step<KIND>(*pa, xp, st->v_prev, st->t + (uint32_t)(j - 1), S->x_spec[j - 1]);
+            S->r_spec[j - 1] = r_seq[st->cl_index + j];
+            const int b = per * j;
+            double h = 1.0;
+            S->kappa[b] = 1.0;
+            for (int l = 1; l <= S->K; ++l) {
+              h = midpoint(0.0, h);
+              S->kappa[b + l] = h;
+            }
+          }
+          if (d > 0) {
+            S->spec_kind = 2;
+            S->spec_base = per;
+            S->spec_per = per;
+            S->spec_n = d;
+            S->spec_used = 0;
+            S->n_cand = per * (1 + d);
+          }
         }
       } else {
         const int d0 = S->K < S->depth ? S->K : S->depth;
@@ -1929,7 +2005,7 @@ __device__ void decide_body(const typename Plant<KIND, double>::Coef& pc, const 
   // so the sequential walk below reads no global memory in its loop.
   __shared__ int s_done, s_n;
   __shared__ double s_kappa[kCMax], s_worst[kCMax];
-  __shared__ unsigned char s_ok[kCMax];
+  __shared__ unsigned char s_ok[kCMax], s_own[kCMax];
   if (threadIdx.x == 0) {
     s_done = S->done;
     s_n = S->n_cand < kCMax ? S->n_cand : kCMax;
@@ -1941,6 +2017,7 @@ __device__ void decide_body(const typename Plant<KIND, double>::Coef& pc, const 
       s_kappa[c] = S->kappa[c];
       s_ok[c] = cand_feasible(S, c) ? 1 : 0;
       s_worst[c] = cand_worst(S, c);
+      s_own[c] = cand_step(S, c) == 0 ? 1 : 0;  // not a later step's speculative candidate
     }
   }
   __syncthreads();
@@ -1996,7 +2073,7 @@ __device__ void decide_body(const typename Plant<KIND, double>::Coef& pc, const 
           const double m = midpoint(lo, hi);
           int c = -1;
           for (int i = probe; i < n; ++i) {
-            if (s_kappa[i] == m) {
+            if (s_kappa[i] == m && s_own[i]) {
               c = i;
               break;
             }
