@@ -410,6 +410,29 @@ def test_speculation_keeps_closed_loop_identical(R, O, seed, r_seed, speculate):
         v_prev = a["v"][s]
 
 
+@pytest.mark.parametrize("r_seed", [2024, 8])
+def test_hold_speculation_keeps_closed_loop_identical(R, O, r_seed):
+    # references out of reach: the governor holds v (kappa = 0) for runs of
+    # updates, and a held update's round also runs the next update's first
+    # round, which then decides that update without a round of its own.
+    # Results are identical to those without speculation and kappa is the
+    # oracle's.
+    p = W.lq4_problem(seed=24, N=256, H=600, dt=0.005, eps=0.01)
+    r_seq = W.reference_sequence(r_seed, 40, switch_every=12, lo=-2.0, hi=2.0)
+    a = _gov(R, p, speculate=7).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    b = _gov(R, p, speculate=0).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    for key in ("kappa", "v", "x", "worst", "status"):
+        assert np.array_equal(a[key], b[key]), key
+    held_ahead = int(np.sum((a["kappa"] == 0.0) & (a["rounds"] == 0)))
+    assert held_ahead > 0, (a["kappa"], a["rounds"])
+    o = O.Oracle(p, nthreads=8)
+    v_prev = 0.0
+    for s in range(len(r_seq)):
+        ref = o.bisect(a["x"][s], r_seq[s], v_prev, s, 12)
+        assert a["kappa"][s] == ref["kappa"] and a["status"][s] == ref["status"], s
+        v_prev = a["v"][s]
+
+
 def test_closed_loop_with_failing_probes_matches_oracle(R, O):
     # reference switches: probe-only rounds that fail, then tree rounds
     p = W.lq4_problem(seed=7, N=256, H=300, dt=0.005, eps=0.01)
