@@ -235,7 +235,9 @@ void plan_with(rg_handle* h, int lanes) {
   const int tree = (1 << d) - 1;
   c.tan = h->opt.search == RG_SEARCH_NEWTON_TAN ? 1 : 0;
   if (is_newton(h->opt.search)) {
-    c.cmax_round = 4;
+    // four candidates per Newton round; with prediction, round 0 after a held
+    // step holds the probe and the K midpoints towards 0
+    c.cmax_round = h->opt.predict && 1 + h->opt.K > 4 ? 1 + h->opt.K : 4;
     c.rounds = h->opt.K + 2;
   } else if (h->opt.search == RG_SEARCH_GRID) {
     c.cmax_round = h->opt.M > tree ? h->opt.M : tree;
@@ -267,7 +269,7 @@ void fill_search(const rg_handle* h, DevSearch* S, int32_t spec_depth, int32_t s
   S->mode = h->opt.search == RG_SEARCH_GRID ? kGrid
             : is_newton(h->opt.search) ? kNewton : kBisect;
   S->delta = std::ldexp(1.0, -h->opt.K);
-  S->predict = h->opt.search == RG_SEARCH_BISECT ? h->opt.predict : 0;
+  S->predict = h->opt.search == RG_SEARCH_BISECT || is_newton(h->opt.search) ? h->opt.predict : 0;
   S->pred = std::nan("");
   S->K = h->opt.K;
   S->depth = h->opt.depth;
@@ -1172,7 +1174,8 @@ int reset_search_schedule(rg_handle* h) {
     HIPCHK(h, hipMemcpyAsync((char*)h->b.srch + offsetof(DevSearch, spec_depth), spec, sizeof(spec),
                              hipMemcpyHostToDevice, h->stream));
     const int32_t depth = h->opt.depth;
-    const int32_t predict = h->opt.search == RG_SEARCH_BISECT ? h->opt.predict : 0;
+    const int32_t predict =
+        h->opt.search == RG_SEARCH_BISECT || is_newton(h->opt.search) ? h->opt.predict : 0;
     const double none = std::nan("");
     HIPCHK(h, hipMemcpyAsync((char*)h->b.srch + offsetof(DevSearch, depth), &depth, sizeof(depth),
                              hipMemcpyHostToDevice, h->stream));
@@ -1224,7 +1227,7 @@ int rg_autotune(rg_handle* h, const double* x0, double v0, const double* r_seq, 
       const int dlo = grid ? 1 : 2, dhi = grid ? 3 : 5;
       for (int depth = dlo; depth <= dhi; ++depth) {
         for (int predict : {1, 0}) {
-          if (predict && h->opt.search != RG_SEARCH_BISECT) continue;
+          if (predict && h->opt.search != RG_SEARCH_BISECT && !is_newton(h->opt.search)) continue;
           if (is_newton(h->opt.search) && depth != dlo) continue;  // depth unused
           for (int speculate : {kSpecMax, 3, 1, 0}) {
             if (speculate && !(predict && lanes == 4)) continue;

@@ -1828,7 +1828,22 @@ __device__ void setup_body(const typename Plant<KIND, double>::Coef& pc, DevStat
       S->kappa[1] = 0.5;
       S->full[0] = 1;
       S->full[1] = 0;
-      S->n_cand = 2;
+      int n = 2;
+      // Prediction after a step that held v (kappa = 0): the round also runs
+      // the midpoints 2^-2 .. 2^-K of the bisection path towards 0.  When they
+      // are all refused, as every candidate of that path, the result is
+      // kappa = 0, the result of bisection itself; otherwise their verdicts
+      // narrow the bracket the Newton steps start from.
+      const double pr = S->pred;
+      if (S->predict && pr == 0.0) {
+        double m = 0.5;
+        for (int l = 2; l <= S->K && n < kCMax; ++l) {
+          m = midpoint(0.0, m);
+          S->kappa[n] = m;
+          S->full[n++] = 0;
+        }
+      }
+      S->n_cand = n;
       S->nk_idx = 0;
       S->probe = 1;
       S->tree_depth = 0;
@@ -1942,7 +1957,8 @@ __global__ void __launch_bounds__(128) k_setup_list(const CtlArgs<KIND> a, int M
   prepare_candidates<KIND>(a.pc, a.st, S);
 }
 
-// Safeguarded Newton on phi(kappa) = M(kappa): every verdict tightens
+// Safeguarded Newton on phi(kappa) = M(kappa): the verdicts of round 0 give
+// the bracket bisection has after them, every later verdict tightens
 // [lo, hi]; the next iterate is kappa_c - phi/phi' from this round's iterate
 // (adjoint derivative), moved to lo + delta or hi - delta when it lands at or
 // past that end, and the midpoint when the slope is not negative or not
@@ -1957,16 +1973,45 @@ __device__ bool newton_decide(DevSearch* S, const DevGrad* G) {
     S->worst_res = cand_worst(S, 0);
     return true;
   }
-  for (int c = 0; c < S->n_cand; ++c) {
-    const double kc = S->kappa[c];
-    if (cand_feasible(S, c)) {
-      if (kc > S->lo || (!S->found && kc >= S->lo)) {
-        S->lo = kc;
+  if (S->round == 0) {
+    // Round 0 holds the probe and midpoints of the bisection path (0.5, and
+    // after a held step every midpoint towards 0): walk them as bisection does,
+    // each level taking the verdict of its own midpoint, which needs no
+    // monotonicity of the verdicts.
+    double lo = S->lo, hi = S->hi;
+    for (;;) {
+      const double m = midpoint(lo, hi);
+      int c = -1;
+      for (int i = 1; i < S->n_cand; ++i) {
+        if (S->kappa[i] == m) {
+          c = i;
+          break;
+        }
+      }
+      if (c < 0) break;
+      if (cand_feasible(S, c)) {
+        lo = m;
         S->found = 1;
         S->worst_res = cand_worst(S, c);
+      } else {
+        hi = m;
       }
-    } else if (kc < S->hi) {
-      S->hi = kc;
+      if (hi - lo <= delta) break;
+    }
+    S->lo = lo;
+    S->hi = hi;
+  } else {
+    for (int c = 0; c < S->n_cand; ++c) {
+      const double kc = S->kappa[c];
+      if (cand_feasible(S, c)) {
+        if (kc > S->lo || (!S->found && kc >= S->lo)) {
+          S->lo = kc;
+          S->found = 1;
+          S->worst_res = cand_worst(S, c);
+        }
+      } else if (kc < S->hi) {
+        S->hi = kc;
+      }
     }
   }
   if (S->hi - S->lo <= delta || S->round + 1 >= S->K + 2) return true;
