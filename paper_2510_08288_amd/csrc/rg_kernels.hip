@@ -1834,17 +1834,22 @@ __device__ void setup_body(const typename Plant<KIND, double>::Coef& pc, DevStat
       // are all refused, as every candidate of that path, the result is
       // kappa = 0, the result of bisection itself; otherwise their verdicts
       // narrow the bracket the Newton steps start from.
+      // The probe then stops at its first violation like the others and the
+      // round computes no derivative (iterate index -1): the path decides the
+      // step, or the next round starts from its bracket with a midpoint.
       const double pr = S->pred;
-      if (S->predict && pr == 0.0) {
+      const bool held = S->predict && pr == 0.0;
+      if (held) {
         double m = 0.5;
         for (int l = 2; l <= S->K && n < kCMax; ++l) {
           m = midpoint(0.0, m);
           S->kappa[n] = m;
           S->full[n++] = 0;
         }
+        S->full[0] = 0;
       }
       S->n_cand = n;
-      S->nk_idx = 0;
+      S->nk_idx = held ? -1 : 0;
       S->probe = 1;
       S->tree_depth = 0;
       S->goal = S->K;
@@ -2015,9 +2020,13 @@ __device__ bool newton_decide(DevSearch* S, const DevGrad* G) {
     }
   }
   if (S->hi - S->lo <= delta || S->round + 1 >= S->K + 2) return true;
-  const double kap_c = S->kappa[S->nk_idx];
+  // no iterate this round (a held step's first round): a midpoint step,
+  // which is no fallback
+  const bool iterate = S->nk_idx >= 0;
+  const double kap_c = iterate ? S->kappa[S->nk_idx] : 0.0;
   const double phi = G->M, dphi = G->dM_dkappa;
-  bool ok = (phi == phi) && (dphi == dphi) && isfinite(phi) && isfinite(dphi) && dphi < 0.0;
+  bool ok = iterate && (phi == phi) && (dphi == dphi) && isfinite(phi) && isfinite(dphi) &&
+            dphi < 0.0;
   double kn = ok ? kap_c - phi / dphi : 0.5 * (S->lo + S->hi);
   // a step at or past a bracket end moves just inside that end (the root is next to it)
   if (ok && kn <= S->lo) kn = S->lo + delta;
@@ -2026,7 +2035,7 @@ __device__ bool newton_decide(DevSearch* S, const DevGrad* G) {
     kn = 0.5 * (S->lo + S->hi);
     ok = false;
   }
-  if (!ok) S->fallbacks += 1;
+  if (!ok && iterate) S->fallbacks += 1;
   const double cand[4] = {kn, kn - delta, kn + delta, 0.5 * (S->lo + S->hi)};
   int n = 0;
   for (int i = 0; i < 4; ++i) {
@@ -2547,7 +2556,7 @@ __global__ void __launch_bounds__(64) k_adjoint(const RollArgs<KIND, float> a, c
   const float wgt = g.w_list[e];
   const uint32_t t = a.st->t;
   const int cand = g.cand >= 0 ? g.cand : a.srch->nk_idx;
-  if (a.srch->done && g.cand < 0) return;
+  if ((a.srch->done || cand < 0) && g.cand < 0) return;
   const float v = (float)a.srch->v[cand];
   const size_t L = (size_t)g.lmax;
   float th[P::nth > 0 ? P::nth : 1], fac[P::nth > 0 ? P::nth : 1];
@@ -2740,6 +2749,7 @@ __device__ __forceinline__ bool seg_target(const DevSearch* S, const SegArgs& g,
                                            int& ks) {
   if (g.cand < 0 && S->done) return false;
   cand = g.cand >= 0 ? g.cand : S->nk_idx;
+  if (cand < 0) return false;  // no iterate this round
   ks = g.grad->k_star;
   return ks >= 0 && g.grad->n_entries > 0;
 }
@@ -2959,6 +2969,11 @@ __global__ void k_grad_prepare(const CtlArgs<KIND> a, DevGrad* G, int32_t* adj_k
   if (cand < 0) {
     if (S->done) return;
     cand = S->nk_idx;
+    if (cand < 0) {  // no iterate this round: nothing to differentiate
+      G->k_star = -1;
+      G->n_entries = 0;
+      return;
+    }
   }
   const double worst = cand_worst_p(S, cand, 0);  // gradients use the FP32 rollouts
   G->M = worst;
@@ -2991,7 +3006,7 @@ __global__ void k_grad_prepare(const CtlArgs<KIND> a, DevGrad* G, int32_t* adj_k
 __global__ void __launch_bounds__(256) k_grad_reduce(DevGrad* G, const double* dv, const double* dth,
                                                      int nth, const DevState* st,
                                                      const DevSearch* S, int cand) {
-  if (cand < 0 && S->done) return;  // Newton search already finished
+  if (cand < 0 && (S->done || S->nk_idx < 0)) return;  // finished, or no iterate this round
   __shared__ double sh[256];
   const int n = G->n_entries;
   const int tid = threadIdx.x;
@@ -3028,6 +3043,7 @@ __global__ void k_tan_grad(const CtlArgs<KIND> a, DevGrad* G, const float* tan_d
   if (cand < 0) {
     if (S->done) return;
     cand = S->nk_idx;
+    if (cand < 0) return;  // no iterate this round
   }
   G->M = cand_worst_p(S, cand, 0);
   for (int c = 0; c < kMaxTh; ++c) G->dM_dth[c] = 0.0;
