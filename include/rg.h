@@ -169,9 +169,13 @@ typedef struct rg_options {
                               1); later rounds use the speculative tree.  Only which
                               candidates are evaluated early changes: the result is that of
                               sequential bisection either way.  0: tree from round 0.
-                              Newton searches: after a step that held v (kappa = 0), 1 adds
-                              the midpoints 2^-2 .. 2^-K towards 0 to the first round; a step
-                              whose candidates are all refused ends there with kappa = 0. */
+                              Newton searches: after a step that held v (kappa = 0), 1 makes
+                              the first round test the kappa = 1 probe and the bisection path
+                              2^-1 .. 2^-K towards 0, every candidate stopping at its first
+                              violation, with no Newton iterate and no derivative; a step whose
+                              candidates are all refused ends there with kappa = 0, otherwise
+                              Newton continues from the bracket bisection has after that path.
+                              kappa stays within 2^-K of bisection's either way. */
     int32_t speculate;     /* closed loop, bisection with prediction, FP32 LQ4 rollouts on 4 lanes
                               per scenario, streamed draws: s in 0..7 (default 7) lets a round
                               that runs the kappa = 1 probe alone also run the probes of the next

@@ -1833,10 +1833,10 @@ __device__ void setup_body(const typename Plant<KIND, double>::Coef& pc, DevStat
       // the midpoints 2^-2 .. 2^-K of the bisection path towards 0.  When they
       // are all refused, as every candidate of that path, the result is
       // kappa = 0, the result of bisection itself; otherwise their verdicts
-      // narrow the bracket the Newton steps start from.
-      // The probe then stops at its first violation like the others and the
-      // round computes no derivative (iterate index -1): the path decides the
-      // step, or the next round starts from its bracket with a midpoint.
+      // narrow the bracket the Newton steps start from.  Such a round has no
+      // iterate (index -1) and takes no derivative: the probe stops at its
+      // first violation like the others, and the next round, if any, starts
+      // from the bracket's midpoint.
       const double pr = S->pred;
       const bool held = S->predict && pr == 0.0;
       if (held) {

@@ -433,6 +433,38 @@ def test_hold_speculation_keeps_closed_loop_identical(R, O, r_seed):
         v_prev = a["v"][s]
 
 
+@pytest.mark.parametrize("search", ["newton", "newton_tan"])
+def test_newton_after_held_steps_tracks_bisection(R, O, search):
+    # references out of reach: the governor holds v for runs of updates.  With
+    # first-round prediction, a Newton step after a held one tests the probe
+    # and the bisection path towards 0 with no iterate; steps that hold again
+    # end in that round.  kappa stays within 2^-12 of the oracle's bisection,
+    # the steps after a held one count no midpoint fallback, and without
+    # prediction the loop's kappa is within 2^-12 of bisection at every state.
+    p = W.lq4_problem(seed=24, N=256, H=600, dt=0.005, eps=0.01)
+    r_seq = W.reference_sequence(2024, 30, switch_every=12, lo=-2.0, hi=2.0)
+    mode = {"newton": R.SEARCH_NEWTON, "newton_tan": R.SEARCH_NEWTON_TAN}[search]
+    a = _gov(R, p, search=mode).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    b = _gov(R, p, search=mode, predict=False).closed_loop(np.zeros(4), 0.0, r_seq,
+                                                           use_graph=True)
+    prev0 = np.concatenate(([False], a["kappa"][:-1] == 0.0))
+    held = prev0 & (a["kappa"] == 0.0)
+    assert np.any(held) and np.all(a["rounds"][held] == 1), (a["kappa"], a["rounds"])
+    assert not np.any(a["status"][prev0] == R.RG_S_FALLBACK), a["status"]
+    assert np.sum(a["rounds"]) < np.sum(b["rounds"])
+    o = O.Oracle(p, nthreads=8)
+    v_prev = 0.0
+    for s in range(len(r_seq)):
+        ref = o.bisect(a["x"][s], r_seq[s], v_prev, s, 12)
+        assert abs(a["kappa"][s] - ref["kappa"]) <= 2.0 ** -12, (s, a["kappa"][s], ref["kappa"])
+        v_prev = a["v"][s]
+    v_prev = 0.0
+    for s in range(len(r_seq)):
+        ref = o.bisect(b["x"][s], r_seq[s], v_prev, s, 12)
+        assert abs(b["kappa"][s] - ref["kappa"]) <= 2.0 ** -12, (s, b["kappa"][s], ref["kappa"])
+        v_prev = b["v"][s]
+
+
 def test_closed_loop_with_failing_probes_matches_oracle(R, O):
     # reference switches: probe-only rounds that fail, then tree rounds
     p = W.lq4_problem(seed=7, N=256, H=300, dt=0.005, eps=0.01)
