@@ -95,13 +95,15 @@ __device__ __forceinline__ T t_inf() {
 }
 
 // FP32 rollouts: tanh from the hardware base-2 exponential and reciprocal,
-// tanh(z) = sign(z) (1 - 2 / (1 + e^{2|z|})), branch-free, absolute error a few
-// 2^-24 (relative error grows only where |tanh z| is itself below 1e-6); square
-// root from the hardware instruction (1 ulp).  FP64 paths use the library.
+// tanh(z) = 1 - 2 / (1 + e^{2z}), branch-free and with no sign handling (e^{2z}
+// overflows to +inf for large z, giving 1, and underflows to 0 for very
+// negative z, giving -1); absolute error a few 2^-24 (relative error grows
+// only where |tanh z| is itself below 1e-6); square root from the hardware
+// instruction (1 ulp).  FP64 paths use the FP64 tanh below.
 __device__ __forceinline__ float t_tanh(float z) {
-  const float e = __builtin_amdgcn_exp2f(fabsf(z) * 2.8853900817779268f);  // 2 log2(e) |z|
+  const float e = __builtin_amdgcn_exp2f(z * 2.8853900817779268f);  // 2 log2(e) z
   const float r = __builtin_amdgcn_rcpf(e + 1.0f);
-  return __builtin_copysignf(__builtin_fmaf(-2.0f, r, 1.0f), z);
+  return __builtin_fmaf(-2.0f, r, 1.0f);
 }
 // FP64 tanh of the FP64 rollouts and steady-state solves (written here, not
 // the library's): tanh|z| = t / (t + 2) with t = expm1(2|z|), which has no
@@ -337,20 +339,24 @@ struct Plant<2, T> {
   __device__ static T comp(int i, T ai, const T* wrow, T si, T zi, const T* tz, T qa, T qb,
                            T qk, T qr, T x0, T x6, T x8, const Lane& L, T p1ref) {
 #pragma clang fp contract(off)
-    T a = t_fma(-ai, zi, si);
-#pragma unroll
-    for (int j = 0; j < 9; ++j) a = t_fma(wrow[j], tz[j], a);
-    // phi_i = A B + C in one form for every row; every candidate is computed
-    // and then selected (no branch where i varies over the lanes)
-    const T c0 = -(qk * qr);
-    const T a6 = -(L.mu[0] * x6), b6 = x0 - p1ref, c6 = L.b[0] * L.v;
+    // phi_i = A B + C D in one form for every row (i < 6: q_i - q_{i+1};
+    // 6: b1 v - mu1 w1 (p1 - p1ref); 7: b2 v w1; 8: b3 v - mu2 (w3 - 1) v);
+    // every candidate is computed and then selected (no branch where i varies
+    // over the lanes).  The sum runs s_i + C D, - a_i z_i, the coupling
+    // terms, + A B: one fma per term.
+    const T a6 = -(L.mu[0] * x6), b6 = x0 - p1ref;
     const T a7 = L.b[1] * L.v;
-    const T a8 = -(L.mu[1] * (x8 - (T)1)), c8 = L.b[2] * L.v;
+    const T a8 = -(L.mu[1] * (x8 - (T)1));
     const bool lo = i < 6, r6 = i == 6, r7 = i == 7;
     const T A = lo ? qa : (r6 ? a6 : (r7 ? a7 : a8));
     const T B = lo ? qb : (r6 ? b6 : (r7 ? x6 : L.v));
-    const T C = lo ? c0 : (r6 ? c6 : (r7 ? (T)0 : c8));
-    return a + t_fma(A, B, C);
+    const T C = lo ? -qk : (r6 ? L.b[0] : L.b[2]);
+    const T D = lo ? qr : L.v;
+    T a = r7 ? si : t_fma(C, D, si);
+    a = t_fma(-ai, zi, a);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) a = t_fma(wrow[j], tz[j], a);
+    return t_fma(A, B, a);
   }
   // Square-root factor of the orifice flow q_{l+1}: sqrt(max(p_l - p_{l+1}, 0))
   // with p_7 = p_amb.
