@@ -105,6 +105,14 @@ __device__ __forceinline__ float t_tanh(float z) {
   const float r = __builtin_amdgcn_rcpf(e + 1.0f);
   return __builtin_fmaf(-2.0f, r, 1.0f);
 }
+// tanh(x - xbar) with the shift folded into the exponent: nk = -2 log2(e) xbar
+// (rounded once), so e^{2(x - xbar)} = 2^{fma(2 log2(e), x, nk)}; same error
+// terms as t_tanh plus the rounding of nk (a few 2^-24 |xbar| in the exponent).
+__device__ __forceinline__ float t_tanh_shift(float x, float nk) {
+  const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(2.8853900817779268f, x, nk));
+  const float r = __builtin_amdgcn_rcpf(e + 1.0f);
+  return __builtin_fmaf(-2.0f, r, 1.0f);
+}
 // FP64 tanh of the FP64 rollouts and steady-state solves (written here, not
 // the library's): tanh|z| = t / (t + 2) with t = expm1(2|z|), which has no
 // cancellation at small |z|, carrying the sign of z; 1 once 2|z| >= 40 (then
@@ -293,10 +301,13 @@ struct Plant<2, T> {
   struct Coef {
     T W[81], xbar[9], thnom[20];
     T c_q0, p_amb, d0, d1, p1ref;
+    T nkxbar[9];  // -2 log2(e) xbar (FP32 tanh with the shift in its exponent)
   };
   struct Lane {
     T a[9], kq[6], b[3], mu[2];
     T v;
+    T axb[9];    // a_i xbar_i: -a_i (x_i - xbar_i) = -a_i x_i + a_i xbar_i, the constant
+                 // part carried in the step forcing s_i
     const T* W;  // the coupling matrix the derivative reads (c.W, or a copy in registers)
   };
   __host__ __device__ static const T* nominal_theta(const Coef& c) { return c.thnom; }
@@ -309,6 +320,7 @@ struct Plant<2, T> {
     c.d0 = (T)s[112];
     c.d1 = (T)s[113];
     c.p1ref = (T)s[114];
+    for (int i = 0; i < 9; ++i) c.nkxbar[i] = (T)(-2.8853900817779268 * s[81 + i]);
   }
   __device__ static void lane_init(const Coef& c, const T* th, T v, Lane& L) {
 #pragma unroll
@@ -320,29 +332,39 @@ struct Plant<2, T> {
     L.mu[0] = th[18];
     L.mu[1] = th[19];
     L.v = v;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) L.axb[i] = L.a[i] * c.xbar[i];
     L.W = c.W;
   }
-  __device__ static void force(const Coef&, const Lane&, const T* w, T* s) {
+  // Step forcing of component i: w_i + a_i xbar_i (the derivative takes
+  // -a_i x_i, so the sum is w_i - a_i (x_i - xbar_i))
+  __device__ static void force(const Coef&, const Lane& L, const T* w, T* s) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) s[i] = w[i];
+    for (int i = 0; i < 9; ++i) s[i] = w[i] + L.axb[i];
   }
-  __device__ static void force0(const Coef&, const Lane&, T* s) {
+  __device__ static void force0(const Coef&, const Lane& L, T* s) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) s[i] = (T)0;
+    for (int i = 0; i < 9; ++i) s[i] = L.axb[i];
+  }
+  // tanh(x_j - xbar_j): FP32 with the shift in the exponent, FP64 on the difference
+  __device__ static T tanh_at(T x, T xbar, T nkxbar) {
+    if constexpr (sizeof(T) == 4) return t_tanh_shift(x, nkxbar);
+    else return t_tanh(x - xbar);
   }
   // Component i of the derivative from the pieces of the evaluation point:
-  // z_i, the vector tz = tanh(z), the orifice flows q_i = qa qb and
-  // q_{i+1} = qk qr as factor pairs (i < 6), and the states x0, x6, x8.  Every
+  // x_i (si carries a_i xbar_i), the vector tz = tanh(x - xbar), the orifice
+  // flows q_i = qa qb and q_{i+1} = qk qr as factor pairs (i < 6), and the
+  // states x0, x6, x8.  Every
   // product-sum is an explicit fma and nothing here is contracted, so the
   // one-lane derivative below and the FP64 recheck that gives each component
   // its own lane round alike.
-  __device__ static T comp(int i, T ai, const T* wrow, T si, T zi, const T* tz, T qa, T qb,
+  __device__ static T comp(int i, T ai, const T* wrow, T si, T xi, const T* tz, T qa, T qb,
                            T qk, T qr, T x0, T x6, T x8, const Lane& L, T p1ref) {
 #pragma clang fp contract(off)
     // phi_i = A B + C D in one form for every row (i < 6: q_i - q_{i+1};
     // 6: b1 v - mu1 w1 (p1 - p1ref); 7: b2 v w1; 8: b3 v - mu2 (w3 - 1) v);
     // every candidate is computed and then selected (no branch where i varies
-    // over the lanes).  The sum runs s_i + C D, - a_i z_i, the coupling
+    // over the lanes).  The sum runs s_i + C D, - a_i x_i, the coupling
     // terms, + A B: one fma per term.
     const T a6 = -(L.mu[0] * x6), b6 = x0 - p1ref;
     const T a7 = L.b[1] * L.v;
@@ -353,7 +375,7 @@ struct Plant<2, T> {
     const T C = lo ? -qk : (r6 ? L.b[0] : L.b[2]);
     const T D = lo ? qr : L.v;
     T a = r7 ? si : t_fma(C, D, si);
-    a = t_fma(-ai, zi, a);
+    a = t_fma(-ai, xi, a);
 #pragma unroll
     for (int j = 0; j < 9; ++j) a = t_fma(wrow[j], tz[j], a);
     return t_fma(A, B, a);
@@ -365,12 +387,9 @@ struct Plant<2, T> {
     return t_sqrt(dp > (T)0 ? dp : (T)0);
   }
   __device__ static void deriv(const Coef& c, const Lane& L, const T* s, const T* x, T* xd) {
-    T z[9], tz[9], r[6];
+    T tz[9], r[6];
 #pragma unroll
-    for (int j = 0; j < 9; ++j) {
-      z[j] = x[j] - c.xbar[j];
-      tz[j] = t_tanh(z[j]);
-    }
+    for (int j = 0; j < 9; ++j) tz[j] = tanh_at(x[j], c.xbar[j], c.nkxbar[j]);
 #pragma unroll
     for (int l = 0; l < 6; ++l) r[l] = orifice(x[l], (l < 5) ? x[l + 1] : c.p_amb);
 #pragma unroll
@@ -379,7 +398,7 @@ struct Plant<2, T> {
       const T qb = i == 0 ? x[6] : (i < 6 ? r[i > 0 ? i - 1 : 0] : (T)0);
       const T qk = i < 6 ? L.kq[i < 6 ? i : 0] : (T)0;
       const T qr = i < 6 ? r[i < 6 ? i : 0] : (T)0;
-      xd[i] = comp(i, L.a[i], &L.W[9 * i], s[i], z[i], tz, qa, qb, qk, qr, x[0], x[6], x[8], L,
+      xd[i] = comp(i, L.a[i], &L.W[9 * i], s[i], x[i], tz, qa, qb, qk, qr, x[0], x[6], x[8], L,
                    c.p1ref);
     }
   }
@@ -400,7 +419,7 @@ struct Plant<2, T> {
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
       z[j] = x[j] - c.xbar[j];
-      tz[j] = t_tanh(z[j]);
+      tz[j] = tanh_at(x[j], c.xbar[j], c.nkxbar[j]);
     }
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
@@ -446,7 +465,7 @@ struct Plant<2, T> {
     T sd[9], dq[7];
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
-      const T tz = t_tanh(x[j] - c.xbar[j]);
+      const T tz = tanh_at(x[j], c.xbar[j], c.nkxbar[j]);
       sd[j] = (1 - tz * tz) * dx[j];
     }
     dq[0] = c.c_q0 * dx[6];

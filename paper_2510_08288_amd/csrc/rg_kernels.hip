@@ -428,9 +428,11 @@ __device__ T rollout_fc9_group(const RollArgs<2, T>& a, int early, T v, int k, u
   }
   typename P::Lane L;
   P::lane_init(a.pc, th, v, L);
-  // this lane's coefficients: a_i, xbar_i, row i of W, k_{i-1} and k_i of the
-  // orifice flows q_i and q_{i+1}, the draw bounds of w_i
-  T ai = L.a[0], xb = a.pc.xbar[0], kql = (T)0, kqh = L.kq[0], wrow[9];
+  // this lane's coefficients: a_i, xbar_i (and its tanh exponent shift), a_i
+  // xbar_i, row i of W, k_{i-1} and k_i of the orifice flows q_i and q_{i+1},
+  // the draw bounds of w_i
+  T ai = L.a[0], xb = a.pc.xbar[0], nkxb = a.pc.nkxbar[0], axb = L.axb[0], kql = (T)0,
+    kqh = L.kq[0], wrow[9];
   float wlo = a.wlo[0], wsp = a.wspan[0];
 #pragma unroll
   for (int j = 0; j < 9; ++j) wrow[j] = a.pc.W[j];
@@ -439,6 +441,8 @@ __device__ T rollout_fc9_group(const RollArgs<2, T>& a, int early, T v, int k, u
     const bool on = i == r;
     ai = on ? L.a[r] : ai;
     xb = on ? a.pc.xbar[r] : xb;
+    nkxb = on ? a.pc.nkxbar[r] : nkxb;
+    axb = on ? L.axb[r] : axb;
     wlo = on ? a.wlo[r] : wlo;
     wsp = on ? a.wspan[r] : wsp;
 #pragma unroll
@@ -456,7 +460,7 @@ __device__ T rollout_fc9_group(const RollArgs<2, T>& a, int early, T v, int k, u
     rl = dpp_row<0x111>(rh);  // row_shr:1, r_{i-1}
     typename Pair<T>::type e;
     e.x = xv;
-    e.y = t_tanh(xv - xb);
+    e.y = P::tanh_at(xv, xb, nkxb);
     xch[li] = e;
     group_sync();
 #pragma unroll
@@ -471,8 +475,7 @@ __device__ T rollout_fc9_group(const RollArgs<2, T>& a, int early, T v, int k, u
   auto eval = [&](T xv, T si) {
     const T qa = i == 0 ? a.pc.c_q0 : kql;
     const T qb = i == 0 ? X[6] : rl;
-    return P::comp(i, ai, wrow, si, xv - xb, TZ, qa, qb, kqh, rh, X[0], X[6], X[8], L,
-                   a.pc.p1ref);
+    return P::comp(i, ai, wrow, si, xv, TZ, qa, qb, kqh, rh, X[0], X[6], X[8], L, a.pc.p1ref);
   };
   const float* wb = RNG == 0 ? step_w(a, t) : nullptr;
   const int wq = i & 3;
@@ -503,7 +506,7 @@ __device__ T rollout_fc9_group(const RollArgs<2, T>& a, int early, T v, int k, u
     if (j + 1 < a.H) wn = load(j + 1);
     if (WAVE && early && (j & 7) == 0)
       stop_seen = __hip_atomic_load(stop_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-    const T si = INJ == 0 ? (T)wc : (T)0;
+    const T si = INJ == 0 ? (T)wc + axb : axb;  // P::force / P::force0 of component i
     T kk = eval(xv, si);
     T acc = kk;
     T xs = t_fma(a.hh, kk, xv);
