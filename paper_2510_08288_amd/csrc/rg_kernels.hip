@@ -158,27 +158,31 @@ __global__ void __launch_bounds__(256) k_gen(RollArgs<KIND, float> a, float* wbu
   gen_body<KIND>(a, wbuf, thbuf, (size_t)blockIdx.x * blockDim.x + threadIdx.x, a.st->t + t_ofs);
 }
 
-// Draw rows of a rollout launch: the draws of step t + 1 (grid-stride over
-// the rows' threads).  Returns true in those rows.
+// Draw rows of a rollout launch (grid-stride over the rows' threads): the
+// draws of step t + gen_ofs, or in the closed loop (ring) those of the steps
+// the step's setup chose (gen_lo .. gen_lo + gen_n - 1, in its first round
+// only).  Returns true in those rows.
 template <int KIND, class A>
 __device__ __forceinline__ bool gen_rows(const A& a) {
   if (a.gen_row0 <= 0 || (int)blockIdx.y < a.gen_row0) return false;
-  const uint32_t t1 = a.st->t + a.gen_ofs;
-  float* gw = a.gen_w;
-  float* gth = a.gen_th;
-  if (a.ring) {  // once per step (its first round), while the chunk has steps left
+  uint32_t t1 = a.st->t + a.gen_ofs;
+  int nsteps = 1;
+  if (a.ring) {  // while the chunk has steps left
     if (a.srch->round != 0 || a.st->cl_index >= a.st->cl_len) return true;
-    gw = a.wring[t1 % kPairs];
-    gth = a.thring[t1 % kPairs];
+    t1 = a.st->gen_lo;
+    nsteps = a.st->gen_n;
   }
   const size_t nth = (size_t)(gridDim.y - a.gen_row0) * gridDim.x * blockDim.x;
   const size_t work = (size_t)a.H * a.N + (Plant<KIND, float>::nth > 0 ? (size_t)a.N : 0);
-  // streaming stores: these draws are read steps later, and lines left dirty in
-  // L2 would have to be written back by the device-scope fences in between
-  for (size_t i = ((size_t)(blockIdx.y - a.gen_row0) * gridDim.x + blockIdx.x) * blockDim.x +
-                  threadIdx.x;
-       i < work; i += nth)
-    gen_body<KIND>(a, gw, gth, i, t1, true);
+  const size_t i0 =
+      ((size_t)(blockIdx.y - a.gen_row0) * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
+  for (int g = 0; g < nsteps; ++g, ++t1) {
+    float* gw = a.ring ? a.wring[t1 % kPairs] : a.gen_w;
+    float* gth = a.ring ? a.thring[t1 % kPairs] : a.gen_th;
+    // streaming stores: these draws are read steps later, and lines left dirty
+    // in L2 would have to be written back by the device-scope fences in between
+    for (size_t i = i0; i < work; i += nth) gen_body<KIND>(a, gw, gth, i, t1, true);
+  }
   return true;
 }
 
@@ -1941,6 +1945,24 @@ __device__ void setup_body(const typename Plant<KIND, double>::Coef& pc, DevStat
         else S->tree_depth = 0;
         S->n_cand = 1 + ((1 << d0) - 1);
       }
+    }
+    if (closed_loop) {
+      // Draws of the ring.  Rounds of step t read steps t .. t + kSpecMax, so
+      // its first round must leave step t + kSpecMax + 1 generated for the
+      // next step.  A round with candidates (long, with SIMDs idle in its
+      // tail) generates as far as the ring allows, t + kPairs - 1; a step
+      // decided ahead, whose launch has nothing else to do, only what is
+      // missing.  Nothing past the chunk's last step.  The chunk's prologue
+      // generated t .. t + kSpecMax.
+      const uint32_t t = st->t;
+      if (st->cl_index == 0) st->gen_hi = t + (uint32_t)kSpecMax;
+      uint32_t want = t + (uint32_t)(S->n_cand > 0 ? kPairs - 1 : kSpecMax + 1);
+      const uint32_t last = t + (uint32_t)(st->cl_len - 1 - st->cl_index);
+      if (want > last) want = last;
+      const uint32_t lo = st->gen_hi + 1u;
+      st->gen_lo = lo;
+      st->gen_n = want >= lo ? (int32_t)(want - lo + 1u) : 0;
+      if (want >= lo) st->gen_hi = want;
     }
   }
   __syncthreads();
