@@ -3283,8 +3283,9 @@ hipError_t launch_rollout(const Problem& pr, double band, int precision, int ear
   const bool ckpt = ckpt_cand >= -1 && precision == 0;
   const bool gen = gen_w != nullptr && pr.s.rng_mode == 0;
   // rows of draw workgroups after the candidate rows: up to about 2^19 threads
-  // (an update decided ahead runs these rows alone; 4-state bench loop: 0.277
-  // ms per update with 2^17 threads, 0.271 with 2^18 or 2^19, 0.270 with 2^20)
+  // (measured when an update decided ahead ran these rows alone; 4-state bench
+  // loop: 0.277 ms per update with 2^17 threads, 0.271 with 2^18 or 2^19, 0.270
+  // with 2^20)
   auto gen_rows_for = [&](size_t row_threads) {
     if (!gen) return 0;
     size_t work = (size_t)pr.H * pr.s.N + (size_t)pr.s.N;
