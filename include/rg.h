@@ -154,13 +154,14 @@ typedef struct rg_options {
     int32_t early_exit;    /* 1: a candidate stops once one lane is below -band */
     int32_t block;         /* threads per workgroup for rollouts (64..256, multiple of 64; 0 = auto) */
     int32_t max_T;         /* closed-loop steps kept on the device per chunk (default 256) */
-    int32_t lanes;         /* lanes per scenario of FP32 rollouts with the robust verdict:
-                              1; 4 for LQ4 (one scenario per quad, state split across
-                              lanes); 16 for FC9 (one scenario per group of 16 lanes, one
-                              lane per state component; not with the tangent-driven Newton
-                              search); 0 = auto (LQ4: 4; FC9: 16 while a round holds at
-                              most 32768 scenario-candidate pairs, else 1).  Margins are
-                              bit-identical across layouts */
+    int32_t lanes;         /* lanes per scenario of FP32 rollouts: 1; 4 for LQ4 (one
+                              scenario per quad, state split across lanes; robust or
+                              chance-constrained verdict); 16 for FC9 (one scenario per group
+                              of 16 lanes, one lane per state component; robust verdict, not
+                              with the tangent-driven Newton search); 0 = auto (LQ4: 4; FC9:
+                              16 while a round holds at most 32768 scenario-candidate pairs,
+                              else 1).  kappa is the same in every layout; the 9-state
+                              groups' margins are bit-identical to one lane's */
     int32_t Kc;            /* adjoint checkpoint interval in RK4 steps (default 50) */
     int32_t persistent_wgs;/* batches: workgroups of the persistent rollout kernel (0 = auto) */
     int32_t predict;       /* bisection: 1 (default) makes the first device round of a step
@@ -189,9 +190,12 @@ typedef struct rg_options {
                               steady-state test passes and at most chance_q of the N scenario
                               rollouts leave Y; its worst margin is then the (chance_q + 1)-th
                               smallest scenario margin (or m_ss if smaller).  0 (default): the
-                              robust verdict, every scenario.  > 0: one lane per scenario,
-                              bisection or grid search (Newton: RG_E_NOTSUP), per-scenario
-                              margin keys in the workspace (8 B x 128 x N). */
+                              robust verdict, every scenario.  > 0: LQ4 FP32 rollouts on
+                              quads of lanes (a wave runs until all its scenarios violated
+                              or the candidate died), otherwise one lane per scenario; no
+                              speculation on later steps; bisection or grid search (Newton:
+                              RG_E_NOTSUP), per-scenario margin keys in the workspace
+                              (8 B x 128 x N). */
 } rg_options;
 
 typedef struct rg_step_info {

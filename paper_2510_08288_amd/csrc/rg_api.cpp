@@ -68,10 +68,11 @@ int fail_hip(rg_handle* h, const char* what, hipError_t e) {
   } while (0)
 
 // How many later steps' probes a probe-only round may also run (closed loop,
-// bisection with first-round prediction, FP32 quad rollouts on streamed draws).
+// bisection with first-round prediction, FP32 quad rollouts on streamed draws,
+// robust verdict).
 int32_t spec_allowed(const rg_handle* h) {
   const bool ok = h->opt.search == RG_SEARCH_BISECT && h->opt.predict &&
-                  h->pr.s.rng_mode == RG_RNG_STREAM &&
+                  h->pr.s.rng_mode == RG_RNG_STREAM && h->opt.chance_q == 0 &&
                   rollout_uses_quad(h->pr, h->cfg, h->opt.precision);
   return ok ? h->opt.speculate : 0;
 }
@@ -183,8 +184,8 @@ constexpr double kGroupPairsMax = 32768;
 
 int lanes_for(const rg_handle* h) {
   const bool f32_robust = h->opt.precision == RG_PREC_F32_RECHECK && h->opt.chance_q == 0;
-  // the quad kernel stops a wave at its first violation: robust verdict only
-  const bool quad_ok = h->pr.p.kind == RG_PLANT_LQ4 && f32_robust;
+  // the quad kernel: FP32 rollouts, robust or chance-constrained verdict
+  const bool quad_ok = h->pr.p.kind == RG_PLANT_LQ4 && h->opt.precision == RG_PREC_F32_RECHECK;
   // the 9-state groups: robust verdict; the forward tangent runs on one lane
   const bool group_ok =
       h->pr.p.kind == RG_PLANT_FC9 && f32_robust && h->opt.search != RG_SEARCH_NEWTON_TAN;

@@ -989,7 +989,12 @@ __device__ __forceinline__ void quad_min_tan(float& m, float& d, int& j, int q) 
   }
 }
 
-template <int RNG, int INJ, int RECORD, int CKPT>
+// CHANCE = 1: the chance-constrained verdict (handles with q > 0, no record,
+// no checkpoints): a quad that violates counts itself once and the candidate
+// dies once more than q did; a wave stops when all its quads have violated or
+// the candidate died, and every scenario's margin key is kept for the order
+// statistic.
+template <int RNG, int INJ, int RECORD, int CKPT, int CHANCE = 0>
 __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, float> a,
                                                          const QuadCoef qc) {
   constexpr int U = kQuadGroup;  // steps per group: one prefetch, one exit test per group
@@ -1014,6 +1019,7 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
   float best = INFINITY;
   int jb = 0, ns = 0;
   bool stopped = false;  // the candidate died while this wave ran (no recheck needed)
+  bool counted = false;  // CHANCE: this quad's violation is counted in nviol
   if (CKPT == 2 && tan_row && k < a.N) {
     // tangent candidate: state and dx/dv over the full horizon; each lane
     // keeps its row's running minimum with derivative and first step
@@ -1197,7 +1203,14 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
       if (early) {
         const float bg = RECORD ? best : quad_min(bq);
         const bool viol = bg < -a.band;
-        if (__builtin_amdgcn_ballot_w64(viol) != 0) {
+        if constexpr (CHANCE) {
+          if (viol && !counted) {
+            counted = true;
+            if (q == 0 && atomicAdd(&S->nviol[c], 1) >= S->q)
+              __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          if (__builtin_amdgcn_ballot_w64(!viol) == 0) return true;  // every quad violated
+        } else if (__builtin_amdgcn_ballot_w64(viol) != 0) {
           if (viol && q == 0)
             __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           stopped = true;
@@ -1243,8 +1256,10 @@ __global__ void __launch_bounds__(256) k_rollout_lq4_quad(const RollArgs<1, floa
       a.per_m[(size_t)c * a.N + k] = best;
       a.per_j[(size_t)c * a.N + k] = jb;
     }
+    if (CHANCE) a.per_key[(size_t)c * a.N + k] = ord64((double)best);
     if (best < -a.band) {
-      __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (!CHANCE || (!counted && atomicAdd(&S->nviol[c], 1) >= S->q))
+        __hip_atomic_store(&S->dead[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else if (best < a.band && !stopped && !spec) {  // a speculative probe is never rechecked
       const int idx = atomicAdd(&S->n_recheck, 1);
       a.rlist[idx] = make_int2(c, k);
@@ -3299,7 +3314,8 @@ hipError_t launch_rollout(const Problem& pr, double band, int precision, int ear
     a.gen_w = gen_w;
     a.gen_th = gen_th;
   };
-  if (cfg.lanes == 4 && precision == 0 && pr.p.kind == 1 && quad_draws_addressable(pr)) {
+  if (cfg.lanes == 4 && precision == 0 && pr.p.kind == 1 && quad_draws_addressable(pr) &&
+      !(cfg.chance && (record || ckpt))) {
     const int gx = div_up((size_t)pr.s.N * 4, (size_t)cfg.block);
     const dim3 grid(gx, cfg.cmax_round + gen_rows_for((size_t)gx * cfg.block));
     const QuadCoef qc = make_quad_coef(pr);
@@ -3314,7 +3330,10 @@ hipError_t launch_rollout(const Problem& pr, double band, int precision, int ear
         constexpr int I = decltype(ic)::value;
         return by_bit(record, [&](auto dc) {
           constexpr int D = decltype(dc)::value;
-          if (ckpt && cfg.tan)
+          if (cfg.chance)
+            hipLaunchKernelGGL((k_rollout_lq4_quad<R, I, 0, 0, 1>), grid, dim3(cfg.block), 0, st, a,
+                               qc);
+          else if (ckpt && cfg.tan)
             hipLaunchKernelGGL((k_rollout_lq4_quad<R, I, D, 2>), grid, dim3(cfg.block), 0, st, a, qc);
           else if (ckpt)
             hipLaunchKernelGGL((k_rollout_lq4_quad<R, I, D, 1>), grid, dim3(cfg.block), 0, st, a, qc);
@@ -3419,7 +3438,7 @@ hipError_t launch_recheck(const Problem& pr, int early_exit, const LaunchCfg& cf
   // Few workgroups: each of them counts itself on one device-scope counter at
   // the end (the last one decides), and near-band entries are rare; a
   // grid-stride loop takes any excess.
-  if (cfg.lanes == 4 && pr.p.kind == 1 && quad_draws_addressable(pr)) {
+  if (cfg.lanes == 4 && pr.p.kind == 1 && quad_draws_addressable(pr) && !cfg.chance) {
     const int qblocks = div_up((cap < 4096 ? cap : 4096) * 4, 256);
     const QuadCoef64 qc = make_quad_coef64(pr);
     auto a = make_args<1, double>(pr, 0.0, early_exit, 0, b);

@@ -27,14 +27,16 @@ def _lq4_wide(N=300, H=400):
     return W.lq4_problem(seed=24, N=N, H=H, dt=0.005, eps=0.01, w_half=0.4)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision,lanes", [(0, 0), (0, 1), (1, 0)])
 @pytest.mark.parametrize("q", [1, 3, 17, 299, 300, 400])
-def test_bisection_kappa_equals_oracle(R, oracle_mod, precision, q):
+def test_bisection_kappa_equals_oracle(R, oracle_mod, precision, lanes, q):
+    # FP32 rollouts take the quad layout by default (4 lanes per scenario), or
+    # one lane per scenario on request; FP64 rollouts one lane
     p = _lq4_wide()
     o = oracle_mod.Oracle(p, nthreads=8)
     x0, r, vp = np.zeros(4), 0.8, 0.3
-    g = R.Governor(p, precision=precision, chance_q=q)
-    assert g.options.lanes == 1
+    g = R.Governor(p, precision=precision, chance_q=q, lanes=lanes)
+    assert g.options.lanes == (4 if precision == 0 and lanes == 0 else 1)
     res = g.step(x0, r, vp)
     g.close()
     ref = o.bisect_q(x0, r, vp, 0, 12, q)
@@ -84,6 +86,26 @@ def test_q0_matches_the_robust_governor(R, lanes):
         assert a["worst"] == b["worst"]
     else:
         assert abs(a["worst"] - b["worst"]) <= 1e-12 * max(1.0, abs(a["worst"]))
+
+
+@pytest.mark.parametrize("N,H,q", [(256, 400, 3), (61, 333, 7)])
+def test_quad_and_one_lane_layouts_agree(R, N, H, q):
+    # the chance-constrained verdict on quads of lanes (a wave runs until all
+    # its quads violated or the candidate died) and on one lane per scenario:
+    # the same kappa, status and Alg. 1 passes at every update of a closed loop
+    # (ragged N: the last wave is partly empty)
+    p = _lq4_wide(N=N, H=H)
+    r_seq = W.reference_sequence(5, 10, switch_every=3, lo=-1.5, hi=1.5)
+    out = {}
+    for lanes in (4, 1):
+        g = R.Governor(p, chance_q=q, lanes=lanes)
+        assert g.options.lanes == lanes
+        out[lanes] = g.closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+        g.close()
+    for key in ("kappa", "v", "x", "status"):
+        assert np.array_equal(out[4][key], out[1][key]), key
+    assert np.any(out[4]["kappa"] < 1.0)
+    assert np.allclose(out[4]["worst"], out[1]["worst"], rtol=TOL32, atol=TOL32)
 
 
 def test_closed_loop_each_update_equals_oracle(R, oracle_mod):
