@@ -53,7 +53,7 @@ PEAK_FP32_NONPACKED_TFLOPS = 78.6
 # valid only for the kernel sources they were taken on (SHA-1 of the device sources
 # below, concatenated in this order).
 KERNEL_SOURCES = ("rg_kernels.hip", "rg_device.hpp", "rg_internal.hpp")
-HBM_TRAFFIC = {"kernels_sha1": "3fc1d15fc872ae30af2fb3f2add1fd297aa6748b", "bytes_per_launch": 110052352}
+HBM_TRAFFIC = {"kernels_sha1": "a134a1338c212e40d1d5e344d0f10e24f0d6a4b1", "bytes_per_launch": 110232143}
 FIXTURE = os.path.join(ROOT, "tests", "golden", "lq4_closed_loop_n4096_h2000.txt")
 
 
