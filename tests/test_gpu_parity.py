@@ -423,6 +423,11 @@ def test_hold_speculation_keeps_closed_loop_identical(R, O, r_seed):
     b = _gov(R, p, speculate=0).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
     for key in ("kappa", "v", "x", "worst", "status"):
         assert np.array_equal(a[key], b[key]), key
+    # held rounds generate draws a step further ahead: chunk ends (7 updates)
+    # cut that, and the results stay the same
+    c = _gov(R, p, speculate=7, max_T=7).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    for key in ("kappa", "v", "x", "worst", "status"):
+        assert np.array_equal(c[key], b[key]), key
     held_ahead = int(np.sum((a["kappa"] == 0.0) & (a["rounds"] == 0)))
     assert held_ahead > 0, (a["kappa"], a["rounds"])
     o = O.Oracle(p, nthreads=8)
@@ -519,7 +524,8 @@ def test_speculation_across_chunks_and_graph_cycles(R, O):
     p = W.lq4_problem(seed=24, N=256, H=300, dt=0.005, eps=0.01)
     r_seq = W.reference_sequence(5, 23, switch_every=8, lo=-0.8, hi=0.8)
     ref = _gov(R, p, speculate=0).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
-    for max_T in (4, 256):
+    # chunk lengths around the ten draw buffers of the ring as well
+    for max_T in (4, 9, 10, 11, 256):
         out = _gov(R, p, speculate=7, max_T=max_T).closed_loop(np.zeros(4), 0.0, r_seq,
                                                                 use_graph=True)
         for key in ("kappa", "v", "x", "worst"):
