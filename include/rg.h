@@ -192,10 +192,11 @@ typedef struct rg_options {
                               smallest scenario margin (or m_ss if smaller).  0 (default): the
                               robust verdict, every scenario.  > 0: LQ4 FP32 rollouts on
                               quads of lanes (a wave runs until all its scenarios violated
-                              or the candidate died), otherwise one lane per scenario; no
-                              speculation on later steps; bisection or grid search (Newton:
-                              RG_E_NOTSUP), per-scenario margin keys in the workspace
-                              (8 B x 128 x N). */
+                              or the candidate died), otherwise one lane per scenario; a
+                              later step is decided ahead only on certain verdicts (every
+                              scenario at least the band away, or more than chance_q
+                              violating); bisection or grid search (Newton: RG_E_NOTSUP),
+                              per-scenario margin keys in the workspace (8 B x 128 x N). */
 } rg_options;
 
 typedef struct rg_step_info {

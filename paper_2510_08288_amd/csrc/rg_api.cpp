@@ -68,11 +68,10 @@ int fail_hip(rg_handle* h, const char* what, hipError_t e) {
   } while (0)
 
 // How many later steps' probes a probe-only round may also run (closed loop,
-// bisection with first-round prediction, FP32 quad rollouts on streamed draws,
-// robust verdict).
+// bisection with first-round prediction, FP32 quad rollouts on streamed draws).
 int32_t spec_allowed(const rg_handle* h) {
   const bool ok = h->opt.search == RG_SEARCH_BISECT && h->opt.predict &&
-                  h->pr.s.rng_mode == RG_RNG_STREAM && h->opt.chance_q == 0 &&
+                  h->pr.s.rng_mode == RG_RNG_STREAM &&
                   rollout_uses_quad(h->pr, h->cfg, h->opt.precision);
   return ok ? h->opt.speculate : 0;
 }

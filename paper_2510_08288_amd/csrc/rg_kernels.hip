@@ -1785,12 +1785,15 @@ __device__ void setup_body(const typename Plant<KIND, double>::Coef& pc, DevStat
         if (S->dead[c] || S->mss[c] < 0.0) return 0;
         return kall_of(c) >= S->band ? 1 : -1;
       };
+      // certain admission: every scenario's FP32 margin at least the band, so
+      // no scenario violates (also under the chance-constrained verdict, whose
+      // worst margin is the order statistic the round selected)
       auto admit = [&](int c, int passes) {
         decided = true;
         spec_found = 1;
         spec_kappa = S->kappa[c];
         const double kall = kall_of(c);
-        spec_worst = kall < S->mss[c] ? kall : S->mss[c];
+        spec_worst = S->q > 0 ? cand_worst(S, c) : (kall < S->mss[c] ? kall : S->mss[c]);
         spec_passes = passes;
       };
       if (S->spec_kind == 1) {

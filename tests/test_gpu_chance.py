@@ -108,6 +108,31 @@ def test_quad_and_one_lane_layouts_agree(R, N, H, q):
     assert np.allclose(out[4]["worst"], out[1]["worst"], rtol=TOL32, atol=TOL32)
 
 
+@pytest.mark.parametrize("r_args", [(2024, 40, 12, -2.0, 2.0), (5, 23, 8, -0.8, 0.8)])
+def test_speculation_keeps_chance_closed_loop_identical(R, oracle_mod, r_args):
+    # later steps decided ahead (kappa = 1 probes of the next steps; after a
+    # held step, the next step's first round): only verdicts that are certain
+    # without an FP64 recheck count (every scenario at least the band away,
+    # or more than q scenarios violating), and the worst margin is the order
+    # statistic of the round that ran the candidate.  Same results as without
+    # speculation, kappa equal to the oracle's.
+    seed, T, every, lo, hi = r_args
+    p = W.lq4_problem(seed=24, N=256, H=600, dt=0.005, eps=0.01)
+    r_seq = W.reference_sequence(seed, T, switch_every=every, lo=lo, hi=hi)
+    q = 3
+    a = R.Governor(p, chance_q=q, speculate=7).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    b = R.Governor(p, chance_q=q, speculate=0).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    for key in ("kappa", "v", "x", "worst", "status"):
+        assert np.array_equal(a[key], b[key]), key
+    assert int(np.sum(a["rounds"] == 0)) > 0  # some updates decided ahead
+    o = oracle_mod.Oracle(p, nthreads=8)
+    v_prev = 0.0
+    for s in range(len(r_seq)):
+        ref = o.bisect_q(a["x"][s], r_seq[s], v_prev, s, 12, q)
+        assert a["kappa"][s] == ref["kappa"], (s, a["kappa"][s], ref["kappa"])
+        v_prev = a["v"][s]
+
+
 def test_closed_loop_each_update_equals_oracle(R, oracle_mod):
     p = _lq4_wide(N=160, H=250)
     r_seq = W.reference_sequence(11, 12, switch_every=3, lo=-1.5, hi=1.5)
