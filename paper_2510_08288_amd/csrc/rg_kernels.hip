@@ -1315,6 +1315,10 @@ __global__ void __launch_bounds__(256) k_recheck_lq4_quad(const RollArgs<1, doub
   const __amdgpu_buffer_rsrc_t wres = __builtin_amdgcn_make_buffer_rsrc(
       (void*)step_w(a, t), (short)0, (int)(row_bytes * (uint32_t)(H + U)), 0x00020000);
   const int stride = (int)((gridDim.x * blockDim.x) >> 2);
+  // chance-constrained verdict (qv > 0): one FP64 violation refuses the
+  // candidate only once more than qv scenarios violate, so an entry does not
+  // stop on another's, and every entry keeps its margin key
+  const int qv = S->q;
   // every lane of a quad holds the same entry, so all exits are quad-uniform
   for (int i = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 2); i < n; i += stride) {
     const int2 en = a.rlist[i];
@@ -1393,7 +1397,7 @@ __global__ void __launch_bounds__(256) k_recheck_lq4_quad(const RollArgs<1, doub
           ++g;
           break;
         }
-        if ((g & 7) == 7 &&
+        if ((g & 7) == 7 && qv == 0 &&
             __hip_atomic_load(&S->fail64[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
           break;
       }
@@ -1407,7 +1411,13 @@ __global__ void __launch_bounds__(256) k_recheck_lq4_quad(const RollArgs<1, doub
     if (!(bad == 0.0) || m != m) m = -INFINITY;
     if (q == 0) {
       atomicMin(&S->key64[c], ord64(m));
-      if (m < 0.0) __hip_atomic_store(&S->fail64[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (qv > 0) {
+        a.per_key[(size_t)c * a.N + k] = ord64(m);
+        if (m < 0.0 && S->nviol[c] + atomicAdd(&S->nviol64[c], 1) >= qv)
+          __hip_atomic_store(&S->fail64[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else if (m < 0.0) {
+        __hip_atomic_store(&S->fail64[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
   }
   if (decide) last_block_decides<1>(ctl);
@@ -3441,7 +3451,7 @@ hipError_t launch_recheck(const Problem& pr, int early_exit, const LaunchCfg& cf
   // Few workgroups: each of them counts itself on one device-scope counter at
   // the end (the last one decides), and near-band entries are rare; a
   // grid-stride loop takes any excess.
-  if (cfg.lanes == 4 && pr.p.kind == 1 && quad_draws_addressable(pr) && !cfg.chance) {
+  if (cfg.lanes == 4 && pr.p.kind == 1 && quad_draws_addressable(pr)) {
     const int qblocks = div_up((cap < 4096 ? cap : 4096) * 4, 256);
     const QuadCoef64 qc = make_quad_coef64(pr);
     auto a = make_args<1, double>(pr, 0.0, early_exit, 0, b);
