@@ -53,7 +53,7 @@ PEAK_FP32_NONPACKED_TFLOPS = 78.6
 # valid only for the kernel sources they were taken on (SHA-1 of the device sources
 # below, concatenated in this order).
 KERNEL_SOURCES = ("rg_kernels.hip", "rg_device.hpp", "rg_internal.hpp")
-HBM_TRAFFIC = {"kernels_sha1": "a134a1338c212e40d1d5e344d0f10e24f0d6a4b1", "bytes_per_launch": 110232143}
+HBM_TRAFFIC = {"kernels_sha1": "c1d43d815060d5efe28c0b2f2e2ddf994d19b6f6", "bytes_per_launch": 110040372}
 FIXTURE = os.path.join(ROOT, "tests", "golden", "lq4_closed_loop_n4096_h2000.txt")
 
 
