@@ -399,7 +399,11 @@ def paper_sweep_rows(Ns, modes, reps=6, log_every=1024):
     """RG-step time of the 9-state grid search (Alg. 3, M = 32 points, no
     refinement), H = 1024, dt = 0.01, from the nominal equilibrium of v = 0.5
     towards r = 2.0, for each N in Ns: a fresh handle per N and draw mode, the
-    median of reps - 1 blocking steps after one warm-up."""
+    median of reps - 1 blocking steps after one warm-up.  With streamed draws
+    the row also gives `rollout_ms`, the mean time per step of the rollout
+    launches alone (HIP events around them; no draw generation, transfers,
+    recheck or decision), the counterpart of the paper's second GPU timing,
+    which leaves out scenario generation and transfers."""
     import numpy as np
     import torch
 
@@ -422,6 +426,14 @@ def paper_sweep_rows(Ns, modes, reps=6, log_every=1024):
                 res = g.step(x0, 2.0, 0.5)
                 times.append(time.perf_counter() - t0)
             row["lanes"] = int(g.options.lanes)
+            if mode == rg.RNG_STREAM:
+                g.set_profiling(True)
+                for rep in range(reps - 1):
+                    g.set_step(0)
+                    g.step(x0, 2.0, 0.5)
+                pf = g.profile()
+                row["rollout_ms"] = pf["rollout_ms"] / (reps - 1)
+                g.set_profiling(False)
             g.close()
             row[label] = float(np.median(times[1:])) * 1e3
             row["kappa"] = res["kappa"]
