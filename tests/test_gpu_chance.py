@@ -150,3 +150,21 @@ def test_closed_loop_each_update_equals_oracle(R, oracle_mod):
         ref = o.bisect_q(a["x"][s], r_seq[s], v_prev, s, 12, q)
         assert a["kappa"][s] == ref["kappa"], (s, a["kappa"][s], ref["kappa"])
         v_prev = a["v"][s]
+
+
+def test_autotune_with_the_chance_verdict(R):
+    # every schedule the autotuner tries (quads or one lane per scenario,
+    # workgroup, depth, prediction, speculation) gives the same kappa sequence
+    # under the chance-constrained verdict, so the tuner accepts them all and
+    # the tuned handle reproduces the untuned closed loop
+    p = W.lq4_problem(seed=24, N=384, H=300, dt=0.005, eps=0.01)
+    r_seq = W.reference_sequence(5, 16, switch_every=4, lo=-2.5, hi=2.5)
+    ref = R.Governor(p, chance_q=3).closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    g = R.Governor(p, chance_q=3)
+    best = g.autotune(np.zeros(4), 0.0, r_seq[:8])
+    assert best["lanes"] in (1, 4) and best["ms_per_update"] > 0
+    assert g.get_step() == 0
+    out = g.closed_loop(np.zeros(4), 0.0, r_seq, use_graph=True)
+    g.close()
+    for key in ("kappa", "v", "x", "status"):
+        assert np.array_equal(out[key], ref[key]), key
