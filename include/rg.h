@@ -337,8 +337,9 @@ int rg_get_options(const rg_handle* h, rg_options* out);
  * handle's step counter, which is restored afterwards) for every candidate
  * schedule (three runs: the first captures the graphs, the faster of the other
  * two counts): lanes per scenario (FP32 rollouts: 1 or 4 for LQ4, 1 or 16 for
- * FC9 with the robust verdict), rollout workgroup (128 or 256 threads), device search depth (2..5; 1..3 for the grid
- * refinement), first-round prediction (on/off, bisection only) and the
+ * FC9 with the robust verdict), rollout workgroup (128 or 256 threads), device
+ * search depth (2..5; 1..3 for the grid refinement), first-round prediction
+ * (on/off, bisection only) and the
  * speculation depth (7, 3, 1, 0; with prediction and 4 lanes).  Schedules
  * change only which candidates run when, so every one must give the same kappa
  * sequence; a mismatch returns RG_E_STATE.  best_out (nullable) receives the
