@@ -379,6 +379,20 @@ def run_batch(rg, W, np, torch, steps=2):
     el = time.perf_counter() - t0
     depth = bt.options.depth
     bt.close()
+    # the batch autotuner on the whole batch (18 schedules, three steps each),
+    # then the batch under the schedule it chose
+    t2 = time.perf_counter()
+    best = rg.batch_autotune(probs, xs, rs, vps)
+    tune_s = time.perf_counter() - t2
+    bt = rg.Batch(probs, block=best["block"], depth=best["depth"], predict=best["predict"])
+    bt.step(xs, rs, vps, use_graph=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tuned = [bt.step(xs, rs, vps, use_graph=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    el_tuned = time.perf_counter() - t1
+    bt.close()
+    tuned_same = all(np.array_equal(a["kappa"], b["kappa"]) for a, b in zip(outs, tuned))
     NH = np.array([p.N * p.H for p in probs], dtype=np.float64)
     nominal = sum(float(np.sum(o["bisect_passes"] * NH)) for o in outs)
     executed = sum(float(np.sum(o["lane_steps"])) for o in outs)
@@ -392,7 +406,12 @@ def run_batch(rg, W, np, torch, steps=2):
             "mean_kappa_lq4": float(np.mean([np.mean(o["kappa"][0::2]) for o in outs])),
             "mean_kappa_fc9": float(np.mean([np.mean(o["kappa"][1::2]) for o in outs])),
             "first_step_with_capture_s": first,
-            "sum_N_x_H": float(np.sum(NH)), "depth_instance0": int(depth)}
+            "sum_N_x_H": float(np.sum(NH)), "depth_instance0": int(depth),
+            "autotuned": {"schedule": {k: best[k] for k in ("block", "depth", "predict")},
+                          "tuner_ms_per_batched_step": best["ms_per_batched_step"],
+                          "ms_per_batched_step": el_tuned / steps * 1e3,
+                          "same_kappa_as_default": bool(tuned_same),
+                          "tuning_s": tune_s}}
 
 
 def paper_sweep_rows(Ns, modes, reps=6, log_every=1024):

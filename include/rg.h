@@ -426,6 +426,24 @@ int rg_batch_set_stream(rg_batch* b, void* hip_stream);
 int rg_batch_set_step(rg_batch* b, int32_t instance, uint32_t t);
 /* The options in force (depth resolved). */
 int rg_batch_get_options(const rg_batch* b, rg_options* out);
+/* Autotuner of a batch's launch schedule (not in the paper; serving
+ * throughput).  For every candidate schedule — scenario tile, i.e. waves per
+ * workgroup column of an instance (opt.block 64, 128, 256), search depth (1, 2,
+ * 3) and first-round prediction (off, on) — creates the batch of `count`
+ * instances described by descs (other options from opt, NULL: the defaults of
+ * rg_batch_create), runs its steps t = 0, 1, 2 from the states x and references r,
+ * v_prev (as rg_batch_step, graph replay; the first step allocates and
+ * captures) and times the faster of the last two; the batch is then
+ * destroyed.  Lanes per scenario are not a choice: batches run one lane per
+ * scenario.  Schedules change only which candidates run when, so every one must
+ * give the same kappa at every step; a mismatch returns RG_E_STATE.  best_out
+ * (nullable) receives the fastest schedule's options (depth resolved),
+ * best_ms_out (nullable) its time per batched step in ms.  Errors as
+ * rg_batch_create and rg_batch_step (message via rg_batch_last_error(NULL)).
+ * Allocates and frees one batch's device memory per schedule; host-blocking. */
+int rg_batch_autotune(const rg_instance_desc* descs, int32_t count, const rg_options* opt,
+                      const double* x, const double* r, const double* v_prev,
+                      rg_options* best_out, double* best_ms_out);
 /* One RG step of every instance.  x: the instances' states packed in order
  * (n_i values each); r, v_prev, v_out: [count]; kappa_out and info_out
  * ([count]) nullable.  use_graph = 1 captures the step once as a HIP graph

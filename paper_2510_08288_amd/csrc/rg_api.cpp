@@ -1732,6 +1732,67 @@ int rg_batch_step(rg_batch* bt, const double* x, const double* r, const double* 
   return RG_OK;
 }
 
+int rg_batch_autotune(const rg_instance_desc* descs, int32_t count, const rg_options* opt,
+                      const double* x, const double* r, const double* v_prev,
+                      rg_options* best_out, double* best_ms_out) {
+  if (!descs || count < 1 || !x || !r || !v_prev)
+    return bfail(nullptr, RG_E_INVAL, "bad arguments");
+  rg_options base;
+  rg_default_options(&base);
+  base.predict = 0;
+  base.block = 64;
+  if (opt) base = *opt;
+  std::vector<double> v(count), kap(count);
+  std::vector<std::vector<double>> kref;  // kappa of steps 0..2 under the first schedule
+  double best_ms = INFINITY;
+  rg_options best = base;
+  constexpr int kRuns = 3;  // steps t = 0, 1, 2: the first captures the graph
+  for (int block : {64, 128, 256}) {
+    for (int depth : {1, 2, 3}) {
+      for (int predict : {0, 1}) {
+        rg_options o = base;
+        o.block = block;
+        o.depth = depth;
+        o.predict = predict;
+        rg_batch* bt = nullptr;
+        int rc = rg_batch_create(descs, count, &o, &bt);
+        if (rc != RG_OK) return rc;  // message set by rg_batch_create
+        double ms = INFINITY;
+        std::vector<std::vector<double>> ks;
+        for (int run = 0; run < kRuns && rc == RG_OK; ++run) {
+          const auto t0 = std::chrono::steady_clock::now();
+          rc = rg_batch_step(bt, x, r, v_prev, v.data(), kap.data(), nullptr, 1);
+          const double el =
+              std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                  .count();
+          if (run > 0 && el < ms) ms = el;
+          ks.push_back(kap);
+        }
+        rg_options got{};
+        (void)rg_batch_get_options(bt, &got);
+        const std::string err = bt->err;
+        rg_batch_destroy(bt);
+        if (rc != RG_OK) return bfail(nullptr, rc, err);
+        if (kref.empty()) {
+          kref = ks;
+        } else if (ks != kref) {
+          return bfail(nullptr, RG_E_STATE,
+                       "batch schedules disagree on kappa (block " + std::to_string(block) +
+                           ", depth " + std::to_string(depth) + ", predict " +
+                           std::to_string(predict) + ")");
+        }
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = got;
+        }
+      }
+    }
+  }
+  if (best_out) *best_out = best;
+  if (best_ms_out) *best_ms_out = best_ms;
+  return RG_OK;
+}
+
 int rg_batch_get_options(const rg_batch* bt, rg_options* out) {
   if (!bt || !out) return RG_E_INVAL;
   *out = bt->opt;

@@ -135,6 +135,8 @@ def load_library(path: str = LIB_PATH, with_torch: bool = True) -> C.CDLL:
     L.rg_batch_set_step.argtypes = [_vp, C.c_int32, C.c_uint32]
     L.rg_batch_get_options.argtypes = [_vp, C.POINTER(rg_options)]
     L.rg_batch_step.argtypes = [_vp, _dp, _dp, _dp, _dp, _dp, C.POINTER(rg_step_info), C.c_int32]
+    L.rg_batch_autotune.argtypes = [C.POINTER(rg_instance_desc), C.c_int32, C.POINTER(rg_options),
+                                    _dp, _dp, _dp, C.POINTER(rg_options), C.POINTER(C.c_double)]
     L.rg_batch_last_error.argtypes = [_vp]
     L.rg_batch_last_error.restype = C.c_char_p
     L.rg_get_profile.argtypes = [_vp, C.POINTER(rg_profile)]
@@ -398,6 +400,55 @@ class Governor:
         return out
 
 
+def _batch_descs(problems):
+    """Instance descriptors of a batch, and the arrays they point into (keep them alive)."""
+    keep = []
+    descs = (rg_instance_desc * len(problems))()
+    for i, p in enumerate(problems):
+        co, wlo, whi = _f64(p.coeffs), _f64(p.w_lo), _f64(p.w_hi)
+        F, g = _f64(np.asarray(p.F).reshape(-1)), _f64(p.g)
+        keep += [co, wlo, whi, F, g]
+        descs[i].plant = rg_plant(p.kind, p.n, p.n_w, p.n_y, p.n_theta, _ptr(co), co.size)
+        descs[i].scen = rg_scenarios(int(p.N), int(p.seed) & 0xFFFFFFFF,
+                                     int(p.instance) & 0xFFFFFFFF, _ptr(wlo), _ptr(whi),
+                                     float(p.theta_rel), int(p.inject), RNG_INLINE)
+        descs[i].cons = rg_constraints(int(np.asarray(p.F).shape[0]), _ptr(F), _ptr(g),
+                                       float(p.eps), int(p.ss_check))
+        descs[i].H = int(p.H)
+        descs[i].dt = float(p.dt)
+    return descs, keep
+
+
+def _batch_options(K, band, depth, block, persistent_wgs, early_exit, predict, search, M, refine):
+    opt = default_options()
+    opt.K, opt.band, opt.depth, opt.block = K, band, depth, block if block else 64
+    opt.persistent_wgs, opt.early_exit = persistent_wgs, int(early_exit)
+    opt.predict, opt.search, opt.M, opt.refine = int(predict), search, M, refine
+    return opt
+
+
+def batch_autotune(problems, xs, r, v_prev, K: int = 12, band: float = 1e-4,
+                   early_exit: bool = True, search: int = SEARCH_BISECT, M: int = 64,
+                   refine: int = 6) -> dict:
+    """rg_batch_autotune: time steps 0..2 of the batch under every schedule
+    (scenario tile, depth, first-round prediction) and return the fastest one
+    (keyword arguments of Batch) with its time per batched step."""
+    L = load_library()
+    descs, keep = _batch_descs(problems)
+    opt = _batch_options(K, band, 0, 64, 0, early_exit, False, search, M, refine)
+    x = _f64(np.concatenate([np.asarray(v, dtype=np.float64) for v in xs]))
+    r = _f64(r)
+    vp = _f64(v_prev)
+    best = rg_options()
+    ms = C.c_double()
+    rc = L.rg_batch_autotune(descs, len(problems), C.byref(opt), _ptr(x), _ptr(r), _ptr(vp),
+                             C.byref(best), C.byref(ms))
+    if rc < 0:
+        raise RGError(rc, L.rg_batch_last_error(None).decode())
+    return dict(block=best.block, depth=best.depth, predict=bool(best.predict),
+                ms_per_batched_step=ms.value)
+
+
 class Batch:
     """Many independent governors stepped together (``rg_batch_*``)."""
 
@@ -407,24 +458,9 @@ class Batch:
         import torch
         self.L = load_library()
         self.problems = list(problems)
-        self._keep = []
-        descs = (rg_instance_desc * len(self.problems))()
-        for i, p in enumerate(self.problems):
-            co, wlo, whi = _f64(p.coeffs), _f64(p.w_lo), _f64(p.w_hi)
-            F, g = _f64(np.asarray(p.F).reshape(-1)), _f64(p.g)
-            self._keep += [co, wlo, whi, F, g]
-            descs[i].plant = rg_plant(p.kind, p.n, p.n_w, p.n_y, p.n_theta, _ptr(co), co.size)
-            descs[i].scen = rg_scenarios(int(p.N), int(p.seed) & 0xFFFFFFFF,
-                                         int(p.instance) & 0xFFFFFFFF, _ptr(wlo), _ptr(whi),
-                                         float(p.theta_rel), int(p.inject), RNG_INLINE)
-            descs[i].cons = rg_constraints(int(np.asarray(p.F).shape[0]), _ptr(F), _ptr(g),
-                                           float(p.eps), int(p.ss_check))
-            descs[i].H = int(p.H)
-            descs[i].dt = float(p.dt)
-        opt = default_options()
-        opt.K, opt.band, opt.depth, opt.block = K, band, depth, block if block else 64
-        opt.persistent_wgs, opt.early_exit = persistent_wgs, int(early_exit)
-        opt.predict, opt.search, opt.M, opt.refine = int(predict), search, M, refine
+        descs, self._keep = _batch_descs(self.problems)
+        opt = _batch_options(K, band, depth, block, persistent_wgs, early_exit, predict, search,
+                             M, refine)
         h = _vp()
         rc = self.L.rg_batch_create(descs, len(self.problems), C.byref(opt), C.byref(h))
         if rc < 0:

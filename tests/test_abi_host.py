@@ -34,7 +34,8 @@ def test_header_declares_the_boundary():
                      "rg_workspace_size", "rg_bind_workspace", "rg_set_stream", "rg_set_step",
                      "rg_get_step", "rg_draws", "rg_trajectory", "rg_status_string",
                      "rg_last_error", "rg_default_options", "rg_grad", "rg_set_theta",
-                     "rg_get_options", "rg_set_profiling", "rg_get_profile", "rg_autotune"]:
+                     "rg_get_options", "rg_set_profiling", "rg_get_profile", "rg_autotune",
+                     "rg_batch_autotune"]:
         assert required in names
 
 
@@ -233,6 +234,13 @@ def test_batch_create_and_step_validate_on_the_host(lib):
                              v.ctypes.data_as(dp), None, None, 0) == R.RG_E_INVAL
     assert lib.rg_batch_set_step(h, 2, 5) == R.RG_E_INVAL   # two instances
     assert lib.rg_batch_destroy(h) == 0
+    # the batch autotuner checks its arguments before it creates any batch
+    assert lib.rg_batch_autotune(None, 2, None, x.ctypes.data_as(dp), r.ctypes.data_as(dp),
+                                 vp.ctypes.data_as(dp), None, None) == R.RG_E_INVAL
+    assert lib.rg_batch_autotune(descs, 2, None, x.ctypes.data_as(dp), None,
+                                 vp.ctypes.data_as(dp), None, None) == R.RG_E_INVAL
+    assert lib.rg_batch_autotune(descs, 0, None, x.ctypes.data_as(dp), r.ctypes.data_as(dp),
+                                 vp.ctypes.data_as(dp), None, None) == R.RG_E_INVAL
     # Newton, Alg. 2 and the chance-constrained verdict are not batched
     for field, value in [("search", R.SEARCH_NEWTON), ("search", R.SEARCH_ALG2), ("chance_q", 3)]:
         o = R.rg_options()
@@ -243,6 +251,10 @@ def test_batch_create_and_step_validate_on_the_host(lib):
     descs[1].scen.N = 0
     h2 = C.c_void_p()
     assert lib.rg_batch_create(descs, 2, None, C.byref(h2)) == R.RG_E_INVAL
+    assert b"instance 1" in lib.rg_batch_last_error(None)
+    # an invalid descriptor fails in the autotuner's first rg_batch_create
+    assert lib.rg_batch_autotune(descs, 2, None, x.ctypes.data_as(dp), r.ctypes.data_as(dp),
+                                 vp.ctypes.data_as(dp), None, None) == R.RG_E_INVAL
     assert b"instance 1" in lib.rg_batch_last_error(None)
 
 

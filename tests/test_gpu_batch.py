@@ -112,3 +112,21 @@ def test_batch_grid_search_matches_single_governors(R, oracle_mod):
     for i, p in enumerate(probs):
         ref = oracle_mod.Oracle(p, nthreads=8).grid(xs[i], rs[i], vps[i], 0, 17, 3)
         assert out["kappa"][i] == ref["kappa"], (i, out["kappa"][i], ref["kappa"])
+
+
+def test_batch_autotune_keeps_kappa(R, oracle_mod):
+    # every schedule the batch autotuner times (tile, depth, prediction) gives
+    # the same kappa; the batch created with the chosen one reproduces the
+    # default batch's steps
+    probs, xs, rs, vps = _mixed(oracle_mod, count=6, seed=13)
+    best = R.batch_autotune(probs, xs, rs, vps)
+    assert best["block"] in (64, 128, 256) and best["depth"] in (1, 2, 3)
+    assert best["ms_per_batched_step"] > 0
+    a = R.Batch(probs)
+    ka = [a.step(xs, rs, vps, use_graph=True)["kappa"] for _ in range(3)]
+    a.close()
+    b = R.Batch(probs, block=best["block"], depth=best["depth"], predict=best["predict"])
+    assert (b.options.block, b.options.depth) == (best["block"], best["depth"])
+    kb = [b.step(xs, rs, vps, use_graph=True)["kappa"] for _ in range(3)]
+    b.close()
+    assert all(np.array_equal(x, y) for x, y in zip(ka, kb))
