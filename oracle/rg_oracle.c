@@ -1095,9 +1095,9 @@ double orc_candidate_grad(const orc_problem* p, const double* x0, double kappa, 
  * iterate kappa_N, its neighbours kappa_N -/+ delta (delta = 2^-K) and the
  * bracket midpoint; every verdict tightens the bracket [lo, hi] (lo admissible
  * or 0, hi refused).  kappa_N = kappa_c - phi(kappa_c) / phi'(kappa_c) from the
- * last iterate kappa_c (derivative of the active term); a step that is not
- * strictly inside the bracket, or a non-negative slope, falls back to the
- * midpoint.  Stops when hi - lo <= delta and returns lo.  The midpoint makes the
+ * last iterate kappa_c (derivative of the active term); a step at or past a
+ * bracket end moves delta inside that end, and a non-negative or non-finite
+ * slope falls back to the midpoint.  Stops when hi - lo <= delta and returns lo.  The midpoint makes the
  * bracket at least halve per round, so at most K + 1 rounds.
  * ========================================================================= */
 orc_result orc_newton(const orc_problem* p, const double* x0, double r, double v_prev,
