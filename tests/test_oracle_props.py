@@ -12,7 +12,9 @@ plant:
   problem are a prefix of the larger one's);
 * on linear plants from an admissible state, Alg. 2 (per-scenario bisection,
   then the minimum) returns the same kappa as the joint bisection of Alg. 1;
-* kappa = 1 returns v = r exactly, and v = v_prev + kappa (r - v_prev).
+* kappa = 1 returns v = r exactly, and v = v_prev + kappa (r - v_prev);
+* the chance-constrained verdict admits no less as q grows, and q = 0 is the
+  robust verdict.
 """
 import numpy as np
 from hypothesis import assume, given, settings, strategies as st
@@ -79,3 +81,18 @@ def test_alg2_equals_bisection_on_linear_plants(oracle_mod, seed, sseed, N, H, r
     a = o.bisect(x0, r, 0.0, 0, K)
     b = o.alg2(x0, r, 0.0, 0, K)
     assert a["kappa"] == b["kappa"]
+
+
+@SETTINGS
+@given(seed=plant_seed, sseed=scen_seed, N=st.integers(1, 12), H=st.integers(1, 50), r=ref,
+       K=depth, q1=st.integers(0, 6), dq=st.integers(0, 8))
+def test_chance_verdict_monotone_in_q(oracle_mod, seed, sseed, N, H, r, K, q1, dq):
+    # admitting up to q violating scenarios admits at least what q' < q admits,
+    # and q = 0 is the robust verdict
+    o = oracle_mod.Oracle(_problem(seed, sseed, N, H, w_half=0.3))
+    x0 = np.zeros(4)
+    a = o.bisect_q(x0, r, 0.0, 0, K, q1)
+    b = o.bisect_q(x0, r, 0.0, 0, K, q1 + dq)
+    assert a["kappa"] <= b["kappa"]
+    if q1 == 0:
+        assert a["kappa"] == o.bisect(x0, r, 0.0, 0, K)["kappa"]
