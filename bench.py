@@ -232,7 +232,16 @@ def run_extras(args):
         c4[nm]["speedup_vs_fp64_bisection"] = (c4["fp64_sequential_bisection"]["ms_per_update"] /
                                                c4[nm]["ms_per_update"])
     out["fc9_adjoint_n16384_h1000"] = c4
-    # the 9-state grid workload (64-point grid + 6 refinements)
+    out.update(run_fc9_grid(U, rg, W, np, torch))
+    out.update(run_more_extras(rg, W, np, torch))
+    print(json.dumps(out))
+
+
+def run_fc9_grid(U, rg, W, np, torch):
+    """The 9-state grid workload (N = 65536, H = 1000, 64-point grid + 6
+    refinements): U updates at t = 0..U-1 after one warm-up, rollout launches
+    timed with HIP events."""
+    out = {}
     wg = W.workload_fc9_grid()
     pg = wg["problem"]
     g = rg.Governor(pg, search=rg.SEARCH_GRID, M=wg["M"], refine=wg["refine"], band=wg["band"])
@@ -260,8 +269,7 @@ def run_extras(args):
         "rollout_tflops": (prof["lane_steps"] * FLOP_PER_STEP_FC9 / (prof["rollout_ms"] * 1e-3) / 1e12
                            if prof["rollout_ms"] > 0 else 0.0),
         "flop_per_scenario_step": FLOP_PER_STEP_FC9, "unit": "scenario-steps/s"}
-    out.update(run_more_extras(rg, W, np, torch))
-    print(json.dumps(out))
+    return out
 
 
 def _median_ms(fn, reps):
@@ -524,6 +532,8 @@ def main():
     ap.add_argument("--tune-steps", type=int, default=200,
                     help="closed-loop updates the autotuner times each schedule on")
     ap.add_argument("--autotune-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--fc9-grid-only", action="store_true",
+                    help="only the 9-state grid workload (--extra-updates updates) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy one device buffer of BYTES into another three times (the "
                          "reference kernel for scaling HBM counters) and exit")
@@ -542,6 +552,9 @@ def main():
     torch.cuda.set_device(0)
     if args.form is not None:
         return run_form(args)
+    if args.fc9_grid_only:
+        print(json.dumps(run_fc9_grid(args.extra_updates, rg, W, np, torch)))
+        return
     if args.extras_only:
         return run_extras(args)
     if args.paper_sweep:
