@@ -284,6 +284,28 @@ int rg_reset(rg_handle* h);
 int rg_step(rg_handle* h, const double* x, double r, double v_prev, double* v_out,
             double* kappa_out, rg_step_info* info);
 
+/* rg_step with its inputs and outputs in device memory, enqueued on the
+ * handle's stream without waiting: one RG update (Alg. 1-3 inputs x_t,
+ * v_{t-1}, r_t; output kappa_opt, v_t) that a caller can capture into a HIP
+ * graph of its own and replay, or chain behind its own kernels.  All pointers
+ * are device memory on the handle's device, owned by the caller, and must stay
+ * valid until the step has run: x [n] (FP64), r, v_prev (one FP64 each), t
+ * (one uint32: the step index that selects the scenario draws; the step reads
+ * it and writes t + 1, so replays of a captured step advance it), v_out
+ * (FP64), kappa_out (FP64, nullable), status_out (int32, nullable: 0 admitted,
+ * 1 infeasible with kappa = 0 and v = v_prev, 2 Newton fell back to bisection).
+ * Inputs are not checked for finiteness (they are never read on the host).
+ * Same kappa, v and status as rg_step at the same x, r, v_prev and t; the
+ * handle's own step counter (rg_set_step, rg_get_step) is neither read nor
+ * advanced.  No host copies, synchronisation or allocation once the workspace
+ * is in place: the first call on a handle sets it up (allocating unless one is
+ * bound, and synchronising), so make one call (or one rg_step) before
+ * capturing; under capture without it, RG_E_STATE.  RG_E_NOTSUP for Alg. 2,
+ * RG_E_STATE while profiling is on.  Steps on one handle run in stream order;
+ * overlapping steps of one handle on different streams race. */
+int rg_step_async(rg_handle* h, const double* x, const double* r, const double* v_prev,
+                  uint32_t* t, double* v_out, double* kappa_out, int32_t* status_out);
+
 /* For callers that cannot allocate device memory (code that must not call
  * hipMalloc, tight serving loops): rg_step without a workspace.  Same
  * arguments, outputs, status and effect on t as rg_step, and the same kappa, v

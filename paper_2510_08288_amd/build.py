@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librg.so")
-SOURCES = ["rg_kernels.hip", "rg_api.cpp"]
+SOURCES = ["rg_kernels.hip", "rg_async.hip", "rg_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are switched off for every HIP translation unit.

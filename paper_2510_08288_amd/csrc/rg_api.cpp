@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/rg.h"
+#include "rg_async.hpp"
 #include "rg_internal.hpp"
 
 using namespace rg;
@@ -865,6 +866,32 @@ int rg_step(rg_handle* h, const double* x, double r, double v_prev, double* v_ou
   if (kappa_out) *kappa_out = R.kappa;
   fill_info(R, info);
   return R.status == 0 ? RG_OK : (R.status == 2 ? RG_S_FALLBACK : RG_S_INFEASIBLE);
+}
+
+int rg_step_async(rg_handle* h, const double* x, const double* r, const double* v_prev,
+                  uint32_t* t, double* v_out, double* kappa_out, int32_t* status_out) {
+  if (!h) return RG_E_INVAL;
+  if (!x || !r || !v_prev || !t || !v_out) return fail(h, RG_E_INVAL, "NULL device pointer");
+  if (h->opt.search == RG_SEARCH_ALG2)
+    return fail(h, RG_E_NOTSUP, "Alg. 2 runs single RG steps (rg_step)");
+  if (h->profiling) return fail(h, RG_E_STATE, "the asynchronous step does not profile");
+  if (!h->ws_ready) {
+    // setting up the workspace allocates and synchronises: not under capture
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPCHK(h, hipStreamIsCapturing(h->stream, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+      return fail(h, RG_E_STATE,
+                  "workspace not set up: run one step (or bind a workspace and step once) "
+                  "before capturing");
+    int rc = ensure_workspace(h);
+    if (rc) return rc;
+  }
+  hipError_t e = launch_async_in(h->b, x, r, v_prev, t, h->pr.p.n, h->stream);
+  if (e == hipSuccess) e = enqueue_step(h, h->pr, h->b, false);
+  if (e == hipSuccess) e = launch_async_out(h->b, v_out, kappa_out, status_out, t, h->stream);
+  if (e != hipSuccess) return fail_hip(h, "enqueue asynchronous RG step", e);
+  h->gen_t = -1;  // the streamed draw buffer holds the draws of a step only the device knows
+  return RG_OK;
 }
 
 int rg_margin(rg_handle* h, const double* x, double r, double v_prev, const double* kappa,

@@ -115,6 +115,7 @@ def load_library(path: str = LIB_PATH, with_torch: bool = True) -> C.CDLL:
     L.rg_reset.argtypes = [_vp]
     L.rg_get_step.argtypes = [_vp, C.POINTER(C.c_uint32)]
     L.rg_step.argtypes = [_vp, _dp, C.c_double, C.c_double, _dp, _dp, C.POINTER(rg_step_info)]
+    L.rg_step_async.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.rg_step_noalloc.argtypes = [_vp, _dp, C.c_double, C.c_double, _dp, _dp,
                                   C.POINTER(rg_step_info)]
     L.rg_margin.argtypes = [_vp, _dp, C.c_double, C.c_double, _dp, C.c_int32, _dp, _fp, _ip]
@@ -278,6 +279,27 @@ class Governor:
         rc = self._check(self.L.rg_step(self.h, _ptr(x), float(r), float(v_prev), C.byref(v),
                                         C.byref(kap), C.byref(info)))
         return dict(v=v.value, kappa=kap.value, status=rc, **_info_dict(info))
+
+    def step_async(self, x, r, v_prev, t, v_out, kappa_out=None, status_out=None) -> None:
+        """rg_step_async: one RG step on device tensors, enqueued on the handle's
+        stream (set_stream) without waiting; capturable in a CUDA graph.  x: n
+        float64, r, v_prev, v_out, kappa_out: one float64 each, t: one int32
+        holding the step index as uint32 (advanced by one), status_out: one
+        int32; all contiguous on the handle's device."""
+        n = self.problem.n
+        spec = [(x, "float64", n, "x"), (r, "float64", 1, "r"), (v_prev, "float64", 1, "v_prev"),
+                (t, "int32", 1, "t"), (v_out, "float64", 1, "v_out"),
+                (kappa_out, "float64", 1, "kappa_out"), (status_out, "int32", 1, "status_out")]
+        ptrs = []
+        for a, dt, numel, name in spec:
+            if a is None and name in ("kappa_out", "status_out"):
+                ptrs.append(None)
+                continue
+            if (not a.is_cuda or str(a.dtype) != "torch." + dt or a.numel() != numel
+                    or not a.is_contiguous()):
+                raise ValueError(f"{name}: a contiguous {dt} device tensor of {numel} element(s)")
+            ptrs.append(C.c_void_p(a.data_ptr()))
+        self._check(self.L.rg_step_async(self.h, *ptrs))
 
     def step_noalloc(self, x, r: float, v_prev: float) -> dict:
         """rg_step_noalloc: the same RG step with no device allocation (static

@@ -35,7 +35,7 @@ def test_header_declares_the_boundary():
                      "rg_get_step", "rg_draws", "rg_trajectory", "rg_status_string",
                      "rg_last_error", "rg_default_options", "rg_grad", "rg_set_theta",
                      "rg_get_options", "rg_set_profiling", "rg_get_profile", "rg_autotune",
-                     "rg_batch_autotune"]:
+                     "rg_batch_autotune", "rg_step_async"]:
         assert required in names
 
 
@@ -183,6 +183,14 @@ def test_calls_reject_bad_arguments_before_device_work(lib):
     assert lib.rg_step(h, None, 1.0, 0.0, C.byref(v), None, None) == R.RG_E_INVAL
     assert lib.rg_step(h, xn.ctypes.data_as(dp), 1.0, 0.0, C.byref(v), None, None) == R.RG_E_INVAL
     assert lib.rg_step(h, x.ctypes.data_as(dp), float("inf"), 0.0, C.byref(v), None, None) == R.RG_E_INVAL
+    # the asynchronous step rejects null handles and pointers before reading any
+    # of them (its pointers are device memory; these are never dereferenced)
+    vp = C.c_void_p(x.ctypes.data)
+    assert lib.rg_step_async(None, vp, vp, vp, vp, vp, None, None) == R.RG_E_INVAL
+    assert lib.rg_step_async(h, None, vp, vp, vp, vp, None, None) == R.RG_E_INVAL
+    assert lib.rg_step_async(h, vp, vp, vp, None, vp, None, None) == R.RG_E_INVAL
+    assert lib.rg_step_async(h, vp, vp, vp, vp, None, None, None) == R.RG_E_INVAL
+    assert b"NULL" in lib.rg_last_error(h)
     kap = np.array([0.5, 1.5])
     out = np.zeros(2)
     assert lib.rg_margin(h, x.ctypes.data_as(dp), 1.0, 0.0, kap.ctypes.data_as(dp), 2,
