@@ -350,6 +350,41 @@ def run_more_extras(rg, W, np, torch):
                                            "same_kappa": ra["kappa"] == rb["kappa"]}
     ga.close()
     gb.close()
+    # the step on device pointers, captured once as a CUDA graph and replayed,
+    # against rg_step on the same update (both repeat the update without
+    # clearing the search record in between)
+    gc = rg.Governor(wl["problem"], band=wl["band"], K=wl["K"])
+    gd = rg.Governor(wl["problem"], band=wl["band"], K=wl["K"])
+    cap = torch.cuda.Stream()
+    gc.set_stream(cap)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    x_d = torch.from_numpy(np.asarray(xs, dtype=np.float64)).cuda()
+    r_d, vp_d = torch.full((1,), 1.9, **f64), torch.full((1,), 0.4, **f64)
+    v_d, k_d = torch.zeros(1, **f64), torch.zeros(1, **f64)
+    t_d = torch.full((1,), 26, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    with torch.cuda.stream(cap):
+        gc.step_async(x_d, r_d, vp_d, t_d, v_d, k_d)  # sets the workspace up
+    cap.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=cap):
+        gc.step_async(x_d, r_d, vp_d, t_d, v_d, k_d)
+    rd = {}
+
+    def replay():
+        t_d.fill_(26)
+        graph.replay()
+        torch.cuda.synchronize()
+
+    def blocking():
+        gd.set_step(26)
+        rd.update(gd.step(xs, 1.9, 0.4))
+    out["async_step_graph_lq4_n4096_h2000"] = {"graph_replay_ms": _median_ms(replay, 9),
+                                               "rg_step_ms": _median_ms(blocking, 9),
+                                               "same_kappa": k_d.item() == rd["kappa"]}
+    del graph
+    gc.close()
+    gd.close()
     out["batch_1024_lq4_fc9"] = run_batch(rg, W, np, torch)
     # points of the paper-shaped sweep (bench.py --paper-sweep runs all 288)
     ns = [1, 32, 256, 512, 1024, 1312, 2048, 4096, 8192]
