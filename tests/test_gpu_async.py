@@ -1,6 +1,7 @@
 """GPU tests of rg_step_async, the RG step on device pointers: the same kappa,
-v and status as rg_step at every step of a sequence (several searches, both
-plants, the chance-constrained verdict), the device step counter advanced in
+v and status as rg_step at every step of a sequence (bisection, grid, both
+Newton forms, FP32 with FP64 recheck and plain FP64, both plants, the
+chance-constrained verdict), the device step counter advanced in
 place, and a CUDA graph captured around one step and replayed several times,
 with eager work and synchronisation between the replays, every replay checked
 against rg_step."""
@@ -41,10 +42,16 @@ CASES = {
                           dict(rng_mode=1)),
     "lq4_newton": (lambda: W.lq4_problem(seed=24, N=256, H=300, dt=0.005, eps=0.01),
                    dict(search=2)),
+    "lq4_newton_tangent": (lambda: W.lq4_problem(seed=24, N=256, H=300, dt=0.005, eps=0.01),
+                           dict(search=4)),
+    "lq4_fp64": (lambda: W.lq4_problem(seed=24, N=200, H=300, dt=0.005, eps=0.01),
+                 dict(precision=1)),
     "lq4_chance": (lambda: W.lq4_problem(seed=24, N=300, H=400, dt=0.005, eps=0.01, w_half=0.4),
                    dict(chance_q=3)),
     "fc9_grid": (lambda: W.fc9_problem(N=256, H=300, dt=0.002, w_half=0.05),
                  dict(search=1, M=16, refine=3)),
+    "fc9_bisect_fp64": (lambda: W.fc9_problem(N=64, H=200, dt=0.002, w_half=0.05),
+                        dict(precision=1)),
 }
 
 
