@@ -159,6 +159,8 @@ def test_create_rejects_bad_horizon_and_options(lib):
                               v.ctypes.data_as(dp), None, None, None, 0) == R.RG_E_NOTSUP
     assert lib.rg_autotune(h, x.ctypes.data_as(dp), 0.0, r.ctypes.data_as(dp), 3, 1, None,
                            None) == R.RG_E_NOTSUP
+    vp = C.c_void_p(x.ctypes.data)  # refused before any pointer is read
+    assert lib.rg_step_async(h, vp, vp, vp, vp, vp, None, None) == R.RG_E_NOTSUP
     assert lib.rg_destroy(h) == 0
 
 
